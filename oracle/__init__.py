@@ -1,0 +1,166 @@
+"""CPU oracle for the H0 barcode -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never imports, links
+or executes anything here; the two share no code.
+
+``ph0_oracle.cpp`` is a plain, single-threaded C++ implementation of the
+barcode algorithm of Section 2 of the paper (distances, sort, dedupe to
+grades, dense F2 column reduction, read-off).  This wrapper builds it with
+g++ on first use and exposes it on numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ph0_oracle.cpp")
+_LIB = os.path.join(_HERE, "libph0_oracle.so")
+
+INF = 0xFFFFFFFF
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [
+        ("E", ctypes.c_int64),
+        ("E_eff", ctypes.c_int64),
+        ("distinct", ctypes.c_int64),
+        ("additions", ctypes.c_int64),
+        ("pivots", ctypes.c_int64),
+        ("columns", ctypes.c_int64),
+        ("late_nonzero", ctypes.c_int64),
+        ("not_two_sparse", ctypes.c_int64),
+        ("s_dist", ctypes.c_double),
+        ("s_sort", ctypes.c_double),
+        ("s_rank", ctypes.c_double),
+        ("s_reduce", ctypes.c_double),
+        ("s_emit", ctypes.c_double),
+    ]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle shared library with g++ (single-threaded, -O3)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call([
+            "g++", "-O3", "-march=native", "-std=c++17", "-fPIC", "-shared",
+            "-o", tmp, _SRC,
+        ])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        P = ctypes.c_void_p
+        lib.ph0o_barcode.argtypes = [P, ctypes.c_int, ctypes.c_int64, ctypes.c_int32,
+                                     ctypes.c_int, P, P, P, P, ctypes.POINTER(_Stats)]
+        lib.ph0o_barcode.restype = ctypes.c_int
+        lib.ph0o_sorted_edges.argtypes = [P, ctypes.c_int, ctypes.c_int64, ctypes.c_int32,
+                                          P, P, P, P, P, ctypes.POINTER(ctypes.c_int64)]
+        lib.ph0o_sorted_edges.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _points(points: np.ndarray) -> tuple[np.ndarray, int]:
+    x = np.ascontiguousarray(points)
+    if x.ndim != 2:
+        raise ValueError("points must be N x d")
+    if x.dtype == np.int8:
+        return x, 1
+    if x.dtype == np.int16:
+        return x, 2
+    raise TypeError("points must be int8 or int16")
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclass
+class OracleResult:
+    canonical: np.ndarray        # n uint32 deaths ascending, INF last
+    death_by_vertex: np.ndarray  # n uint32
+    killer_pos: np.ndarray       # n int64 sorted position of the killing column
+    partner: np.ndarray          # n int32 other row of the stored column
+    E: int
+    E_eff: int
+    distinct: int
+    additions: int
+    pivots: int
+    columns: int
+    late_nonzero: int
+    not_two_sparse: int
+    seconds: dict
+
+    def bars(self) -> np.ndarray:
+        """n x 2 uint32 (birth, death) in canonical order."""
+        out = np.zeros((self.canonical.size, 2), dtype=np.uint32)
+        out[:, 1] = self.canonical
+        return out
+
+
+def barcode(points: np.ndarray, early_exit: bool = True) -> OracleResult:
+    """Run the full oracle on an N x d int8/int16 cloud."""
+    x, eb = _points(points)
+    n, d = x.shape
+    if n < 1 or d < 1:
+        raise ValueError("need N >= 1 and d >= 1")
+    lib = _load()
+    dv = np.empty(n, np.uint32)
+    can = np.empty(n, np.uint32)
+    kp = np.empty(n, np.int64)
+    par = np.empty(n, np.int32)
+    st = _Stats()
+    rc = lib.ph0o_barcode(_ptr(x), eb, n, d, 1 if early_exit else 0, _ptr(dv), _ptr(can),
+                          _ptr(kp), _ptr(par), ctypes.byref(st))
+    if rc != 0:
+        raise RuntimeError("oracle rejected its arguments")
+    return OracleResult(
+        canonical=can, death_by_vertex=dv, killer_pos=kp, partner=par,
+        E=st.E, E_eff=st.E_eff, distinct=st.distinct, additions=st.additions,
+        pivots=st.pivots, columns=st.columns, late_nonzero=st.late_nonzero,
+        not_two_sparse=st.not_two_sparse,
+        seconds=dict(dist=st.s_dist, sort=st.s_sort, rank=st.s_rank,
+                     reduce=st.s_reduce, emit=st.s_emit),
+    )
+
+
+@dataclass
+class SortedEdges:
+    colex_delta: np.ndarray  # E int64, squared distance of edge (i, j) at j(j-1)/2 + i
+    delta: np.ndarray        # E int64 sorted
+    j: np.ndarray            # E int32
+    i: np.ndarray            # E int32
+    grade: np.ndarray        # E uint32, 1-based index in D
+    distinct: int
+
+
+def sorted_edges(points: np.ndarray) -> SortedEdges:
+    """Steps 1-3 of the oracle: colex distances, the sorted list, the grades."""
+    x, eb = _points(points)
+    n, d = x.shape
+    E = n * (n - 1) // 2
+    lib = _load()
+    cd = np.empty(E, np.int64)
+    de = np.empty(E, np.int64)
+    jj = np.empty(E, np.int32)
+    ii = np.empty(E, np.int32)
+    gg = np.empty(E, np.uint32)
+    nd = ctypes.c_int64(0)
+    rc = lib.ph0o_sorted_edges(_ptr(x), eb, n, d, _ptr(cd), _ptr(de), _ptr(jj), _ptr(ii),
+                               _ptr(gg), ctypes.byref(nd))
+    if rc != 0:
+        raise RuntimeError("oracle rejected its arguments")
+    return SortedEdges(cd, de, jj, ii, gg, int(nd.value))

@@ -1,0 +1,176 @@
+"""Pins for the CPU oracle: every output is checked against something other
+than the oracle itself (hand-derived closed forms, Kruskal/union-find,
+scipy's MST and distance routines, brute-force component counts, the 2-sparse
+pair walk, and invariants of the barcode).  CPU only."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_02527_amd import synth
+from tests import checks
+from tests.conftest import golden_cases, load_fixture
+
+INF = oracle.INF
+
+
+def _cloud(rng, n, d, lo, hi, dtype):
+    return rng.integers(lo, hi + 1, size=(n, d)).astype(dtype)
+
+
+def _invariants(res, n):
+    can = res.canonical
+    assert can.size == n
+    assert (np.diff(can.astype(np.int64)) >= 0).all()  # ascending, INF last
+    assert int((can == INF).sum()) == 1
+    fin = can[can != INF]
+    assert fin.size == n - 1
+    if fin.size:
+        assert fin.min() >= 1 and fin.max() <= res.distinct
+    assert res.pivots == n - 1
+    assert res.not_two_sparse == 0
+    # births are all 0 by construction of bars()
+    assert (res.bars()[:, 0] == 0).all()
+
+
+@pytest.mark.parametrize("name", golden_cases())
+def test_golden_closed_forms(name):
+    pts, deaths, vdeaths = load_fixture(name)
+    res = oracle.barcode(pts)
+    np.testing.assert_array_equal(res.canonical, deaths)
+    if vdeaths is not None:
+        np.testing.assert_array_equal(res.death_by_vertex, vdeaths)
+    _invariants(res, pts.shape[0])
+
+
+def test_collinear_unit_spacing_closed_form():
+    for n in (2, 3, 7, 20, 65, 130):
+        pts = np.zeros((n, 3), np.int16)
+        pts[:, 0] = np.arange(n)
+        res = oracle.barcode(pts)
+        # D = {1, 4, ..., (n-1)^2}; all gaps have grade 1
+        assert res.distinct == n - 1
+        np.testing.assert_array_equal(res.canonical[:-1], np.ones(n - 1, np.uint32))
+        assert res.canonical[-1] == INF
+        # vertex k (k >= 1) dies when the gap (k-1, k) appears; vertex 0 survives
+        np.testing.assert_array_equal(res.death_by_vertex[1:], np.ones(n - 1, np.uint32))
+
+
+def test_stage_outputs_match_library_routines():
+    rng = np.random.default_rng(1)
+    for n, d, lo, hi, dt in [(1, 2, 0, 3, np.int8), (2, 1, -5, 5, np.int16),
+                              (37, 3, -100, 100, np.int16), (80, 16, -128, 127, np.int8),
+                              (64, 5, 0, 2, np.int8), (50, 64, -32768, 32767, np.int16)]:
+        pts = _cloud(rng, n, d, lo, hi, dt)
+        se = oracle.sorted_edges(pts)
+        np.testing.assert_array_equal(se.colex_delta, checks.sqdist_colex(pts))
+        ds, ii, jj, gr = checks.sorted_order(pts)
+        np.testing.assert_array_equal(se.delta, ds)
+        np.testing.assert_array_equal(se.i, ii)
+        np.testing.assert_array_equal(se.j, jj)
+        np.testing.assert_array_equal(se.grade, gr)
+        assert se.distinct == np.unique(ds).size
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_deaths_equal_kruskal_and_scipy_mst(seed):
+    rng = np.random.default_rng(100 + seed)
+    cases = [(300, 3, -100, 100, np.int16), (200, 16, -128, 127, np.int8),
+             (150, 2, 0, 4, np.int8), (120, 64, -20, 20, np.int8)]
+    n, d, lo, hi, dt = cases[seed % len(cases)]
+    pts = _cloud(rng, n, d, lo, hi, dt)
+    res = oracle.barcode(pts)
+    _invariants(res, n)
+    vd, killer = checks.kruskal_minlabel(pts)
+    np.testing.assert_array_equal(res.death_by_vertex, vd)   # per vertex (min-label rule)
+    np.testing.assert_array_equal(res.killer_pos, killer)
+    np.testing.assert_array_equal(res.canonical[:-1], checks.mst_grades_scipy(pts))
+    assert res.E_eff == int(killer.max()) + 1
+
+
+def test_mixture_workload_kruskal():
+    pts = synth.mixture_cloud(1024, 16, 8, 10.0, seed=3)
+    res = oracle.barcode(pts)
+    _invariants(res, 1024)
+    vd, killer = checks.kruskal_minlabel(pts)
+    np.testing.assert_array_equal(res.death_by_vertex, vd)
+    np.testing.assert_array_equal(res.canonical[:-1], checks.mst_grades_scipy(pts))
+
+
+def test_brute_force_small_tie_heavy():
+    rng = np.random.default_rng(7)
+    for trial in range(250):
+        n = int(rng.integers(1, 9))
+        d = int(rng.integers(1, 4))
+        pts = _cloud(rng, n, d, 0, 2, np.int8)
+        res = oracle.barcode(pts)
+        np.testing.assert_array_equal(res.canonical, checks.betti0_brute(pts))
+        _invariants(res, n)
+
+
+def test_canonical_barcode_ignores_tie_order():
+    rng = np.random.default_rng(11)
+    for trial in range(40):
+        n = int(rng.integers(2, 7))
+        pts = _cloud(rng, n, 2, 0, 2, np.int8)
+        res = oracle.barcode(pts)
+        for s in range(5):
+            vd, _ = checks.kruskal_minlabel(pts, tie_perm_seed=s)
+            np.testing.assert_array_equal(res.canonical, np.sort(vd))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_additions_and_partners_match_pair_walk(seed):
+    rng = np.random.default_rng(200 + seed)
+    pts = [_cloud(rng, 256, 3, -100, 100, np.int16),
+           synth.mixture_cloud(300, 16, 4, 10.0, seed=seed),
+           _cloud(rng, 200, 2, 0, 3, np.int8)][seed]
+    res = oracle.barcode(pts)
+    ref = checks.sparse_pair_walk(pts)
+    assert res.additions == ref["additions"]
+    assert res.E_eff == ref["E_eff"]
+    np.testing.assert_array_equal(res.partner, ref["partner"])
+    np.testing.assert_array_equal(res.death_by_vertex, ref["vertex_deaths"])
+
+
+def test_literal_equals_early_exit():
+    rng = np.random.default_rng(5)
+    for pts in [_cloud(rng, 256, 3, -100, 100, np.int16),
+                synth.mixture_cloud(512, 16, 8, 10.0, seed=9),
+                _cloud(rng, 60, 2, 0, 2, np.int8)]:
+        a = oracle.barcode(pts, early_exit=True)
+        b = oracle.barcode(pts, early_exit=False)
+        np.testing.assert_array_equal(a.canonical, b.canonical)
+        np.testing.assert_array_equal(a.death_by_vertex, b.death_by_vertex)
+        np.testing.assert_array_equal(a.partner, b.partner)
+        assert a.E_eff == b.E_eff and a.additions <= b.additions
+        assert b.late_nonzero == 0 and b.columns == b.E
+        ref = checks.sparse_pair_walk(pts, early_exit=False)
+        assert b.additions == ref["additions"]
+
+
+def test_barcode_invariant_under_transformations():
+    rng = np.random.default_rng(3)
+    pts = _cloud(rng, 120, 4, -50, 50, np.int16)
+    base = oracle.barcode(pts).canonical
+    perm = rng.permutation(120)
+    for q in [pts[perm], pts + 17, -pts, pts[:, ::-1].copy(), pts * 3,
+              np.ascontiguousarray(pts[perm][:, [2, 0, 3, 1]])]:
+        np.testing.assert_array_equal(oracle.barcode(q.astype(np.int16)).canonical, base)
+
+
+def test_uniform_workload_against_checks():
+    pts = synth.workload("uniform_n256_d3_i16", seed=0)
+    assert pts.shape == (256, 3) and pts.dtype == np.int16
+    res = oracle.barcode(pts)
+    assert res.E == 32640
+    _invariants(res, 256)
+    np.testing.assert_array_equal(res.canonical[:-1], checks.mst_grades_scipy(pts))
+    ref = checks.sparse_pair_walk(pts)
+    assert res.additions == ref["additions"]
+
+
+def test_bad_arguments_rejected():
+    with pytest.raises(TypeError):
+        oracle.barcode(np.zeros((3, 2), np.int32))
+    with pytest.raises(ValueError):
+        oracle.barcode(np.zeros((0, 2), np.int8))
