@@ -1,0 +1,141 @@
+/* ph0.h -- C ABI of the MI355X (gfx950) library for 0th persistent homology
+ * (H0) barcodes of integer point clouds.
+ *
+ * The computation is the barcode algorithm of Section 2 of Rawson, "Linear
+ * Run Time of Persistent Homology Computation with GPU Parallelization",
+ * in the five GPU steps of Section 4:
+ *   1. squared Euclidean distance of every pair i < j of the N points;
+ *   2. sort the N(N-1)/2 edges by distance (ties: by larger endpoint j, then
+ *      by i);
+ *   3. remove duplicate distances to get D; an edge's grade is the 1-based
+ *      index of its distance in D;
+ *   4. column-reduce the N x N(N-1)/2 vertex-by-edge boundary matrix over F2,
+ *      left to right, until every nonzero column has a distinct lowest entry
+ *      (the low of a column is its largest row index);
+ *   5. each surviving pivot of grade b is the interval (0, b); the vertex whose
+ *      row never becomes a pivot (vertex 0) is the one infinite interval.
+ *
+ * All arithmetic is integer, so results are exact and deterministic: the same
+ * input gives bit-identical output whatever the stream, batch or concurrency.
+ *
+ * Conventions for every entry point:
+ *   - Return value: PH0_OK (0) or a negative ph0_status; on error the output
+ *     buffers hold unspecified data and ph0_last_error() describes the cause.
+ *   - Points are row-major N x d arrays of int8 (PH0_I8) or int16 (PH0_I16).
+ *   - The caller owns every buffer it passes; the library keeps no pointer
+ *     after a call returns.
+ *   - Calls with host pointers block until their results are in host memory.
+ *     Calls taking a `hip_stream` (a hipStream_t, NULL = the null stream)
+ *     enqueue their work on that stream and also return only after it is
+ *     complete (the reduction is steered from the host between rounds).
+ */
+#ifndef PH0_H
+#define PH0_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PH0_INF 0xFFFFFFFFu /* death of the essential (never dying) class */
+
+typedef enum { PH0_I8 = 1, PH0_I16 = 2 } ph0_dtype;
+
+typedef enum {
+  PH0_OK = 0,
+  PH0_EINVAL = -1,  /* NULL pointer, n < 1, d < 1, bad dtype, small workspace */
+  PH0_ERANGE = -2,  /* the packed 64-bit sort key cannot hold distance + edge id */
+  PH0_ENOMEM = -3,  /* device or host allocation failed, or a budget is full */
+  PH0_EDEVICE = -4, /* a HIP call failed or a kernel reported an inconsistency */
+  PH0_EBUSY = -5    /* serving: the request was not admitted now; retry later */
+} ph0_status;
+
+/* One barcode interval (birth, death) in grade units: birth is always 0,
+ * death is the grade b (1-based index in D) or PH0_INF. */
+typedef struct {
+  uint32_t birth;
+  uint32_t death;
+} ph0_bar;
+
+/* Counters and stage timings of one call.  Times are GPU event times in ms
+ * (0 when not measured). */
+typedef struct {
+  int64_t n;             /* points */
+  int64_t E;             /* edges N(N-1)/2 */
+  int64_t E_eff;         /* sorted position of the last pivot + 1 */
+  int64_t distinct_eff;  /* |D| restricted to the first E_eff sorted edges */
+  int64_t additions;     /* column additions of columns < E_eff (the sequential count) */
+  int64_t additions_all; /* column additions performed, incl. columns >= E_eff */
+  int64_t find_steps;    /* root look-ups made by the parallel commit rule */
+  int64_t words_read;    /* 64-bit pivot-table words loaded by the reduction */
+  int64_t rounds;        /* reduction rounds (walk, decide, commit) */
+  int64_t window;        /* columns reduced side by side in one round */
+  int32_t sort_passes;   /* LSD radix passes over the distance bits */
+  int32_t delta_bits;    /* bits of the squared-distance bound */
+  int32_t index_bits;    /* bits per vertex index in the packed key */
+  int32_t keys_path;     /* 0 = vector ALU distances, 1 = int8 MFMA Gram */
+  float ms_keys, ms_sort, ms_reduce, ms_rank, ms_emit, ms_total;
+} ph0_stats;
+
+/* Message for the last non-OK status returned on this thread. */
+const char* ph0_last_error(void);
+
+/* Device workspace needed by ph0_barcodes_device / ph0_pairs_device for a
+ * cloud of n points in d dimensions.  Returns EINVAL / ERANGE like those
+ * calls would.  The size is dominated by two 8-byte keys per edge. */
+int ph0_workspace_bytes(int64_t n, int32_t d, ph0_dtype dt, size_t* bytes);
+
+/* The whole barcode, host memory in and out.  `out` receives n bars sorted
+ * by death ascending, PH0_INF last (the canonical barcode).  `st` may be NULL.
+ * Allocates and frees its own device memory. */
+int ph0_barcodes(const void* points, ph0_dtype dt, int64_t n, int32_t d, ph0_bar* out,
+                 ph0_stats* st);
+
+/* The whole barcode on device memory: d_points (n*d elements), d_out (n bars,
+ * canonical order), d_workspace of at least ph0_workspace_bytes() bytes.  No
+ * device allocation is made.  `st` may be NULL. */
+int ph0_barcodes_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d,
+                        ph0_bar* d_out, void* d_workspace, size_t ws_bytes,
+                        void* hip_stream, ph0_stats* st);
+
+/* Per-vertex detail of the same computation (device pointers, any may be NULL):
+ *   d_death_by_vertex[n] grade at which vertex r dies, PH0_INF for vertex 0
+ *   d_killer_pos[n]      sorted position of the edge whose column became the
+ *                        pivot of row r, -1 for vertex 0
+ *   d_killer_edge[n]     that edge as (j << 32) | i, i < j; UINT64_MAX if none
+ *   d_killer_sqdist[n]   its squared distance D[b]; -1 if none
+ *   d_partner[n]         the other nonzero row of the reduced column stored
+ *                        as the pivot of row r (it has exactly two), -1 if none
+ * Vertex r != 0 dies when the component whose smallest vertex is r joins a
+ * component with a smaller smallest vertex. */
+int ph0_pairs_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d,
+                     uint32_t* d_death_by_vertex, int64_t* d_killer_pos,
+                     uint64_t* d_killer_edge, int64_t* d_killer_sqdist, int32_t* d_partner,
+                     void* d_workspace, size_t ws_bytes, void* hip_stream, ph0_stats* st);
+
+/* Step 1 alone: the packed keys (delta << 2b | j << b | i, b = index_bits) of
+ * all edges i < j at colex position j(j-1)/2 + i.  d_keys holds E entries. */
+int ph0_keys_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d,
+                    uint64_t* d_keys, void* d_workspace, size_t ws_bytes, void* hip_stream);
+
+/* Steps 1-2: the packed keys in sorted (delta, j, i) order.  d_keys holds E. */
+int ph0_sorted_keys_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d,
+                           uint64_t* d_keys, void* d_workspace, size_t ws_bytes,
+                           void* hip_stream);
+
+/* Key layout the library would use: bits per vertex index (b) and bits of the
+ * squared-distance bound.  Returns ERANGE when 2b + delta_bits > 64. */
+int ph0_key_layout(int64_t n, int32_t d, ph0_dtype dt, int32_t* index_bits,
+                   int32_t* delta_bits);
+
+/* Reduction window (columns reduced side by side per round); 0 restores the
+ * built-in choice.  Affects speed only, never results.  Process-wide. */
+int ph0_set_window(int64_t columns);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PH0_H */

@@ -48,7 +48,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call([
-            "g++", "-O3", "-march=native", "-std=c++17", "-fPIC", "-shared",
+            "g++", "-O3", "-std=c++17", "-fPIC", "-shared",
             "-o", tmp, _SRC,
         ])
         os.replace(tmp, _LIB)

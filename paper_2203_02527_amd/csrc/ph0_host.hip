@@ -1,0 +1,492 @@
+// ph0_host.hip -- the C ABI declared in include/ph0.h: argument checks, key
+// layout and sort planning, workspace carving, and the stage sequence
+//   coordinate ranges -> keys -> LSD radix passes -> round-based reduction
+//   -> grades -> per-vertex deaths -> canonical barcode.
+// Every step of the computation runs in the HIP kernels of this library;
+// the host only plans, launches and steers the reduction rounds.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <vector>
+
+#include "../../include/ph0.h"
+#include "ph0_internal.h"
+
+using namespace ph0;
+
+namespace {
+
+thread_local char g_err[512] = "";
+std::atomic<int64_t> g_window{0};
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(PH0_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+  } while (0)
+
+constexpr int64_t kMaxN = 65536;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+int index_bits(int64_t n) { return n <= 1 ? 0 : 64 - __builtin_clzll((uint64_t)(n - 1)); }
+
+int64_t window_for(int64_t n, int64_t E) {
+  int64_t w = g_window.load();
+  if (w <= 0) w = std::max<int64_t>(65536, 64 * n);
+  w = std::min<int64_t>(w, std::max<int64_t>(E, 1));
+  return std::max<int64_t>(w, 1);
+}
+
+struct Layout {
+  int64_t n, E, LW, Wcap, tiles;
+  size_t keysA, keysB, hist, tickets, err, desc, table, killer, lowc, touch, rtag, ra, rr, rrlo,
+      rst, ctl, blockcnt, dbv, minmax, total;
+};
+
+Layout make_layout(int64_t n, int32_t d) {
+  Layout L;
+  L.n = n;
+  L.E = n * (n - 1) / 2;
+  L.LW = (n + 63) / 64;
+  L.Wcap = window_for(n, L.E);
+  const int64_t keys = std::max<int64_t>(L.E, 2 * n + 64);  // room for the bar sort too
+  L.tiles = radix_tiles(keys);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.keysA = take(8 * (size_t)keys);
+  L.keysB = take(8 * (size_t)keys);
+  L.hist = take(4 * 256 * kMaxPasses);
+  L.tickets = take(4 * kMaxPasses);
+  L.err = take(4);
+  L.desc = take(8 * 256 * (size_t)L.tiles);
+  L.table = take(8 * (size_t)(n * L.LW));
+  L.killer = take(8 * (size_t)n);
+  L.lowc = take(8 * (size_t)n);
+  L.touch = take(8 * (size_t)n);
+  L.rtag = take(8 * (size_t)L.Wcap);
+  L.ra = take(4 * (size_t)L.Wcap);
+  L.rr = take(4 * (size_t)L.Wcap);
+  L.rrlo = take(4 * (size_t)L.Wcap);
+  L.rst = take(4 * (size_t)L.Wcap);
+  L.ctl = take(sizeof(RedCtl));
+  L.blockcnt = take(4 * (size_t)(rank_blocks(keys) + 1));
+  L.dbv = take(4 * (size_t)n);
+  L.minmax = take(8 * (size_t)d);
+  L.total = o;
+  (void)d;
+  return L;
+}
+
+int check_args(const void* p, ph0_dtype dt, int64_t n, int32_t d) {
+  if (!p) return fail(PH0_EINVAL, "points pointer is NULL");
+  if (dt != PH0_I8 && dt != PH0_I16) return fail(PH0_EINVAL, "dtype must be PH0_I8 or PH0_I16");
+  if (n < 1) return fail(PH0_EINVAL, "n must be >= 1 (got %lld)", (long long)n);
+  if (n > kMaxN) return fail(PH0_EINVAL, "n must be <= %lld (got %lld)", (long long)kMaxN, (long long)n);
+  if (d < 1) return fail(PH0_EINVAL, "d must be >= 1 (got %d)", d);
+  return PH0_OK;
+}
+
+SortPlan plan_sort(int ib, int dbits) {
+  SortPlan sp = {};
+  sp.passes = (dbits + 7) / 8;
+  int shift = 2 * ib;
+  for (int p = 0; p < sp.passes; ++p) {
+    const int w = dbits / sp.passes + (p < dbits % sp.passes ? 1 : 0);
+    sp.shift[p] = shift;
+    sp.bits[p] = w;
+    shift += w;
+  }
+  return sp;
+}
+
+struct Timer {
+  bool on;
+  hipStream_t s;
+  hipEvent_t ev[8];
+  int k = 0;
+  explicit Timer(bool enabled, hipStream_t st) : on(enabled), s(st) {
+    if (on)
+      for (auto& e : ev) on = on && hipEventCreate(&e) == hipSuccess;
+  }
+  void mark() {
+    if (on && k < 8) hipEventRecord(ev[k++], s);
+  }
+  float ms(int a, int b) {
+    float v = 0;
+    if (on && b < k) hipEventElapsedTime(&v, ev[a], ev[b]);
+    return v;
+  }
+  ~Timer() {
+    if (on)
+      for (auto& e : ev) hipEventDestroy(e);
+  }
+};
+
+RedCtl* pinned_ctl() {
+  thread_local RedCtl* p = nullptr;
+  if (!p && hipHostMalloc((void**)&p, sizeof(RedCtl), hipHostMallocDefault) != hipSuccess)
+    p = nullptr;
+  return p;
+}
+
+enum Stop { kStopKeys = 1, kStopSorted = 2, kStopAll = 3 };
+
+struct Outputs {
+  ph0_bar* bars = nullptr;
+  uint32_t* dbv = nullptr;
+  int64_t* killer_pos = nullptr;
+  uint64_t* killer_edge = nullptr;
+  int64_t* killer_sqdist = nullptr;
+  int32_t* partner = nullptr;
+  uint64_t* keys = nullptr;  // for the stage entry points
+};
+
+int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs& out,
+        void* d_ws, size_t ws_bytes, hipStream_t s, ph0_stats* st, Stop stop) {
+  int rc = check_args(d_points, dt, n, d);
+  if (rc) return rc;
+  if (!d_ws) return fail(PH0_EINVAL, "workspace pointer is NULL");
+  const Layout L = make_layout(n, d);
+  if (ws_bytes < L.total)
+    return fail(PH0_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+  char* ws = static_cast<char*>(d_ws);
+  auto at = [&](size_t off) { return static_cast<void*>(ws + off); };
+  const int eb = dt == PH0_I8 ? 1 : 2;
+  const int ib = index_bits(n);
+  ph0_stats S = {};
+  S.n = n;
+  S.E = L.E;
+  S.index_bits = ib;
+  S.window = L.Wcap;
+
+  if (n == 1) {
+    if (stop != kStopAll) return PH0_OK;
+    if (out.bars) {
+      const ph0_bar one = {0u, PH0_INF};
+      HIPCHK(hipMemcpyAsync(out.bars, &one, sizeof(one), hipMemcpyHostToDevice, s));
+    }
+    if (out.dbv) HIPCHK(launch_fill_u32(out.dbv, kInf, 1, s));
+    if (out.killer_pos) HIPCHK(launch_fill_u64((uint64_t*)out.killer_pos, ~0ull, 1, s));
+    if (out.killer_edge) HIPCHK(launch_fill_u64(out.killer_edge, ~0ull, 1, s));
+    if (out.killer_sqdist) HIPCHK(launch_fill_u64((uint64_t*)out.killer_sqdist, ~0ull, 1, s));
+    if (out.partner) HIPCHK(launch_fill_u32((uint32_t*)out.partner, ~0u, 1, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st) *st = S;
+    return PH0_OK;
+  }
+
+  Timer tm(st != nullptr, s);
+  tm.mark();  // 0
+  // Bound on the squared distance from the per-dimension coordinate ranges.
+  // The range kernel keeps (min, max) interleaved per dimension.
+  int32_t* mm = static_cast<int32_t*>(at(L.minmax));
+  std::vector<int32_t> pairs(2 * (size_t)d);
+  {
+    std::vector<int32_t> init(2 * (size_t)d);
+    for (int32_t k = 0; k < d; ++k) {
+      init[2 * k] = 0x7FFFFFFF;
+      init[2 * k + 1] = (int32_t)0x80000000;
+    }
+    HIPCHK(hipMemcpyAsync(mm, init.data(), 8 * (size_t)d, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_coord_range(d_points, eb, n, d, mm, s));
+    HIPCHK(hipMemcpyAsync(pairs.data(), mm, 8 * (size_t)d, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  unsigned __int128 bound = 0;
+  for (int32_t k = 0; k < d; ++k) {
+    const int64_t w = (int64_t)pairs[2 * k + 1] - pairs[2 * k];
+    bound += (unsigned __int128)(w * w);
+  }
+  int dbits = 0;
+  while (dbits < 100 && (bound >> dbits) != 0) ++dbits;
+  S.delta_bits = dbits;
+  if (2 * ib + dbits > 64)
+    return fail(PH0_ERANGE,
+                "packed key needs %d distance bits + 2 x %d index bits > 64 (reduce the "
+                "coordinate range)",
+                dbits, ib);
+  const SortPlan sp = plan_sort(ib, dbits);
+  S.sort_passes = sp.passes;
+  const bool mfma = (eb == 1) && d >= 8 && d <= 32768;
+  S.keys_path = mfma ? 1 : 0;
+
+  uint64_t* keysA = static_cast<uint64_t*>(at(L.keysA));
+  uint64_t* keysB = static_cast<uint64_t*>(at(L.keysB));
+  uint32_t* hist = static_cast<uint32_t*>(at(L.hist));
+  uint32_t* tickets = static_cast<uint32_t*>(at(L.tickets));
+  int32_t* serr = static_cast<int32_t*>(at(L.err));
+  uint64_t* desc = static_cast<uint64_t*>(at(L.desc));
+
+  HIPCHK(launch_fill_u32(hist, 0u, 256 * kMaxPasses, s));
+  HIPCHK(launch_fill_u32(tickets, 0u, kMaxPasses, s));
+  HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t*>(serr), 0u, 1, s));
+  tm.mark();  // 1
+  HIPCHK(launch_keys(d_points, eb, n, d, ib, sp, keysA, hist, mfma, s));
+  tm.mark();  // 2
+  if (stop == kStopKeys) {
+    HIPCHK(hipMemcpyAsync(out.keys, keysA, 8 * (size_t)L.E, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return PH0_OK;
+  }
+
+  HIPCHK(launch_fill_u64(desc, 0ull, 256 * radix_tiles(L.E), s));
+  uint64_t* src = keysA;
+  uint64_t* dst = keysB;
+  for (int p = 0; p < sp.passes; ++p) {
+    HIPCHK(launch_radix_pass(src, dst, L.E, sp.shift[p], sp.bits[p], hist + 256 * p, desc,
+                             tickets + p, serr, (uint32_t)(p + 1), s));
+    std::swap(src, dst);
+  }
+  uint64_t* skeys = src;  // sorted
+  uint64_t* spare = dst;  // free ping-pong buffer
+  tm.mark();  // 3
+  if (stop == kStopSorted) {
+    int32_t herr = 0;
+    HIPCHK(hipMemcpyAsync(out.keys, skeys, 8 * (size_t)L.E, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(&herr, serr, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (herr) return fail(PH0_EDEVICE, "radix sort look-back did not complete");
+    return PH0_OK;
+  }
+
+  // Reduction rounds.
+  RedArgs ra;
+  ra.skeys = skeys;
+  ra.ib = ib;
+  ra.n = n;
+  ra.E = L.E;
+  ra.LW = L.LW;
+  ra.Wcap = L.Wcap;
+  ra.table = static_cast<uint64_t*>(at(L.table));
+  ra.killer = static_cast<int64_t*>(at(L.killer));
+  ra.lowc = static_cast<uint64_t*>(at(L.lowc));
+  ra.touch = static_cast<uint64_t*>(at(L.touch));
+  ra.ring.tag = static_cast<int64_t*>(at(L.rtag));
+  ra.ring.a = static_cast<int32_t*>(at(L.ra));
+  ra.ring.r = static_cast<int32_t*>(at(L.rr));
+  ra.ring.rlo = static_cast<int32_t*>(at(L.rrlo));
+  ra.ring.st = static_cast<int32_t*>(at(L.rst));
+  ra.ctl = static_cast<RedCtl*>(at(L.ctl));
+  RedCtl* hc = pinned_ctl();
+  if (!hc) return fail(PH0_ENOMEM, "pinned host allocation failed");
+  HIPCHK(launch_reduce_init(ra, s));
+  // Every round finalizes at least the first unfinished column (it either
+  // reduces to zero or commits), so the window start must advance.
+  int64_t prevF = -1;
+  const int burst = 8;
+  while (true) {
+    for (int t = 0; t < burst; ++t) HIPCHK(launch_reduce_round(ra, s));
+    HIPCHK(hipMemcpyAsync(hc, ra.ctl, sizeof(RedCtl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hc->done) break;
+    if (hc->F <= prevF || hc->err) {
+      HIPCHK(hipStreamSynchronize(s));
+      return fail(PH0_EDEVICE, "reduction stalled at column %lld (err %d)", (long long)hc->F,
+                  hc->err);
+    }
+    prevF = hc->F;
+  }
+  HIPCHK(launch_reduce_finish(ra, s));
+  HIPCHK(hipMemcpyAsync(hc, ra.ctl, sizeof(RedCtl), hipMemcpyDeviceToHost, s));
+  int32_t herr = 0;
+  HIPCHK(hipMemcpyAsync(&herr, serr, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  tm.mark();  // 4
+  if (herr) return fail(PH0_EDEVICE, "radix sort look-back did not complete");
+  if (hc->err & 1) return fail(PH0_EDEVICE, "a reduced column did not have exactly two rows");
+  if (hc->err & 2 || hc->pivots != n - 1)
+    return fail(PH0_EDEVICE, "reduction ended with %lld pivots, expected %lld",
+                (long long)hc->pivots, (long long)(n - 1));
+  S.E_eff = hc->E_eff;
+  S.additions_all = hc->additions_all;
+  S.additions = hc->additions_all - hc->additions_overshoot;
+  S.find_steps = hc->find_steps;
+  S.words_read = hc->words_read;
+  S.rounds = hc->round;
+
+  // Grades over [0, E_eff) into the spare buffer, then per-vertex deaths.
+  uint32_t* rank = reinterpret_cast<uint32_t*>(spare);
+  HIPCHK(launch_rank(skeys, ra.ctl, 2 * ib, static_cast<uint32_t*>(at(L.blockcnt)), L.E, rank,
+                     s));
+  uint32_t* dbv = out.dbv ? out.dbv : static_cast<uint32_t*>(at(L.dbv));
+  HIPCHK(launch_vertex_deaths(ra.killer, rank, n, dbv, s));
+  uint32_t last_rank = 0;
+  HIPCHK(hipMemcpyAsync(&last_rank, rank + (hc->E_eff - 1), 4, hipMemcpyDeviceToHost, s));
+  tm.mark();  // 5
+  if (out.bars) {
+    if (n <= kSmallSortMax) {
+      HIPCHK(launch_sort_bars_small(dbv, n, reinterpret_cast<uint32_t*>(out.bars), s));
+    } else {
+      // Larger barcodes: the same LSD passes over the 32 death bits.
+      uint64_t* ka = spare;
+      uint64_t* kb = spare + n;
+      SortPlan bp = {};
+      bp.passes = 4;
+      for (int p = 0; p < 4; ++p) {
+        bp.shift[p] = 8 * p;
+        bp.bits[p] = 8;
+      }
+      HIPCHK(launch_u32_to_keys(dbv, n, ka, s));
+      HIPCHK(launch_fill_u32(hist, 0u, 256 * kMaxPasses, s));
+      HIPCHK(launch_fill_u32(tickets, 0u, kMaxPasses, s));
+      HIPCHK(launch_histogram(ka, n, bp, hist, s));
+      HIPCHK(launch_fill_u64(desc, 0ull, 256 * radix_tiles(n), s));
+      for (int p = 0; p < 4; ++p) {
+        HIPCHK(launch_radix_pass(ka, kb, n, bp.shift[p], 8, hist + 256 * p, desc, tickets + p,
+                                 serr, (uint32_t)(p + 1), s));
+        std::swap(ka, kb);
+      }
+      HIPCHK(launch_keys_to_bars(ka, n, reinterpret_cast<uint32_t*>(out.bars), s));
+    }
+  }
+  if (out.killer_pos || out.killer_edge || out.killer_sqdist || out.partner)
+    HIPCHK(launch_pairs_detail(ra.killer, skeys, ib, ra.table, L.LW, n, out.killer_pos,
+                               out.killer_edge, out.killer_sqdist, out.partner, s));
+  tm.mark();  // 6
+  HIPCHK(hipMemcpyAsync(&herr, serr, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (herr) return fail(PH0_EDEVICE, "barcode sort look-back did not complete");
+  S.distinct_eff = last_rank;
+  if (st) {
+    S.ms_keys = tm.ms(1, 2);
+    S.ms_sort = tm.ms(2, 3);
+    S.ms_reduce = tm.ms(3, 4);
+    S.ms_rank = tm.ms(4, 5);
+    S.ms_emit = tm.ms(5, 6);
+    S.ms_total = tm.ms(0, 6);
+    *st = S;
+  }
+  return PH0_OK;
+}
+
+struct DeviceBuffer {
+  void* p = nullptr;
+  ~DeviceBuffer() {
+    if (p) hipFree(p);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* ph0_last_error(void) { return g_err; }
+
+int ph0_workspace_bytes(int64_t n, int32_t d, ph0_dtype dt, size_t* bytes) {
+  static const char probe = 0;
+  int rc = check_args(&probe, dt, n, d);
+  if (rc) return rc;
+  if (!bytes) return fail(PH0_EINVAL, "bytes pointer is NULL");
+  *bytes = make_layout(n, d).total;
+  return PH0_OK;
+}
+
+int ph0_key_layout(int64_t n, int32_t d, ph0_dtype dt, int32_t* ibits, int32_t* dbits) {
+  static const char probe = 0;
+  int rc = check_args(&probe, dt, n, d);
+  if (rc) return rc;
+  const int ib = index_bits(n);
+  const uint64_t span = dt == PH0_I8 ? 255 : 65535;
+  unsigned __int128 bound = (unsigned __int128)d * span * span;
+  int db = 0;
+  while (db < 100 && (bound >> db) != 0) ++db;
+  if (ibits) *ibits = ib;
+  if (dbits) *dbits = db;
+  if (2 * ib + db > 64)
+    return fail(PH0_ERANGE, "full-range coordinates need %d + 2 x %d > 64 key bits", db, ib);
+  return PH0_OK;
+}
+
+int ph0_set_window(int64_t columns) {
+  if (columns < 0) return fail(PH0_EINVAL, "window must be >= 0");
+  g_window.store(columns);
+  return PH0_OK;
+}
+
+int ph0_barcodes_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d,
+                        ph0_bar* d_out, void* d_ws, size_t ws_bytes, void* hip_stream,
+                        ph0_stats* st) {
+  if (!d_out) return fail(PH0_EINVAL, "output pointer is NULL");
+  Outputs o;
+  o.bars = d_out;
+  return run(d_points, dt, n, d, o, d_ws, ws_bytes, static_cast<hipStream_t>(hip_stream), st,
+             kStopAll);
+}
+
+int ph0_pairs_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d,
+                     uint32_t* d_death_by_vertex, int64_t* d_killer_pos,
+                     uint64_t* d_killer_edge, int64_t* d_killer_sqdist, int32_t* d_partner,
+                     void* d_ws, size_t ws_bytes, void* hip_stream, ph0_stats* st) {
+  Outputs o;
+  o.dbv = d_death_by_vertex;
+  o.killer_pos = d_killer_pos;
+  o.killer_edge = d_killer_edge;
+  o.killer_sqdist = d_killer_sqdist;
+  o.partner = d_partner;
+  return run(d_points, dt, n, d, o, d_ws, ws_bytes, static_cast<hipStream_t>(hip_stream), st,
+             kStopAll);
+}
+
+int ph0_keys_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, uint64_t* d_keys,
+                    void* d_ws, size_t ws_bytes, void* hip_stream) {
+  if (!d_keys && n > 1) return fail(PH0_EINVAL, "keys pointer is NULL");
+  Outputs o;
+  o.keys = d_keys;
+  return run(d_points, dt, n, d, o, d_ws, ws_bytes, static_cast<hipStream_t>(hip_stream),
+             nullptr, kStopKeys);
+}
+
+int ph0_sorted_keys_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d,
+                           uint64_t* d_keys, void* d_ws, size_t ws_bytes, void* hip_stream) {
+  if (!d_keys && n > 1) return fail(PH0_EINVAL, "keys pointer is NULL");
+  Outputs o;
+  o.keys = d_keys;
+  return run(d_points, dt, n, d, o, d_ws, ws_bytes, static_cast<hipStream_t>(hip_stream),
+             nullptr, kStopSorted);
+}
+
+int ph0_barcodes(const void* points, ph0_dtype dt, int64_t n, int32_t d, ph0_bar* out,
+                 ph0_stats* st) {
+  int rc = check_args(points, dt, n, d);
+  if (rc) return rc;
+  if (!out) return fail(PH0_EINVAL, "output pointer is NULL");
+  size_t ws = 0;
+  if ((rc = ph0_workspace_bytes(n, d, dt, &ws))) return rc;
+  const size_t pbytes = (size_t)n * d * (dt == PH0_I8 ? 1 : 2);
+  DeviceBuffer dp, dout, dws;
+  if (hipMalloc(&dp.p, pbytes) != hipSuccess || hipMalloc(&dout.p, 8 * (size_t)n) != hipSuccess ||
+      hipMalloc(&dws.p, ws) != hipSuccess)
+    return fail(PH0_ENOMEM, "device allocation of %zu bytes failed", ws + pbytes + 8 * n);
+  hipStream_t s;
+  HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  rc = PH0_OK;
+  if (hipMemcpyAsync(dp.p, points, pbytes, hipMemcpyHostToDevice, s) != hipSuccess)
+    rc = fail(PH0_EDEVICE, "copy of points to the device failed");
+  if (!rc)
+    rc = ph0_barcodes_device(dp.p, dt, n, d, static_cast<ph0_bar*>(dout.p), dws.p, ws, s, st);
+  if (!rc && (hipMemcpyAsync(out, dout.p, 8 * (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+              hipStreamSynchronize(s) != hipSuccess))
+    rc = fail(PH0_EDEVICE, "copy of the barcode to the host failed");
+  hipStreamDestroy(s);
+  return rc;
+}
+
+}  // extern "C"

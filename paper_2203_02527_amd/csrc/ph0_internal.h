@@ -1,0 +1,112 @@
+// ph0_internal.h -- declarations shared by the HIP translation units of the
+// library (kernels and their launchers).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ph0 {
+
+constexpr int kMaxPasses = 8;
+constexpr uint32_t kInf = 0xFFFFFFFFu;
+constexpr uint64_t kU64Max = ~0ull;
+
+// Which key bits each LSD radix pass sorts on.
+struct SortPlan {
+  int passes;
+  int shift[kMaxPasses];  // first key bit of the pass's digit
+  int bits[kMaxPasses];   // digit width (1..8)
+};
+
+// Control block of the round-based reduction, resident in device memory.
+struct RedCtl {
+  int64_t F;        // first column that is not final
+  int64_t Wend;     // end of the current window [F, Wend)
+  int64_t maxWend;  // largest Wend ever used
+  int64_t pivots;   // committed pivots
+  int64_t E_eff;    // largest committed column + 1
+  int64_t round;
+  uint64_t firstdup[2];  // per round parity: first survivor whose low repeats
+  uint64_t newF[2];      // per round parity: first survivor left active
+  int64_t additions_all;
+  int64_t find_steps;
+  int64_t words_read;
+  int64_t additions_overshoot;  // additions of walked columns >= E_eff
+  int32_t done;
+  int32_t err;  // bit 0: a reduced column had weight != 2; bit 1: ran out of columns
+};
+
+// Per-column state of the reduction window, a ring indexed by p % Wcap.
+struct Ring {
+  int64_t* tag;  // column p that owns the entry (-1 = none)
+  int32_t* a;    // smaller nonzero row of the partially reduced column
+  int32_t* r;    // its low (larger nonzero row)
+  int32_t* rlo;  // root of row a in the pivot forest seen last round
+  int32_t* st;   // status (low 2 bits) | additions so far << 2
+};
+
+enum : int32_t { kActive = 0, kZero = 1, kCommitted = 2 };
+
+// ---- launchers (each enqueues on `s`, returns hipError_t) ----
+
+hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
+
+// Per-dimension coordinate range -> bound on the squared distance.
+hipError_t launch_coord_range(const void* pts, int elem_bytes, int64_t n, int32_t d,
+                              int32_t* minmax /* 2*d, zeroed to +-inf by caller */,
+                              hipStream_t s);
+
+// Step 1: keys of all edges at colex positions + per-pass digit histograms.
+hipError_t launch_keys(const void* pts, int elem_bytes, int64_t n, int32_t d, int ib,
+                       const SortPlan& sp, uint64_t* keys, uint32_t* hist, bool use_mfma,
+                       hipStream_t s);
+
+// Step 2: global digit histograms of an arbitrary key array (used for the
+// small sort of the barcode's deaths).
+hipError_t launch_histogram(const uint64_t* keys, int64_t count, const SortPlan& sp,
+                            uint32_t* hist, hipStream_t s);
+
+// One stable LSD pass: in -> out by digit (key >> shift) & ((1<<bits)-1).
+int64_t radix_tiles(int64_t count);
+hipError_t launch_radix_pass(const uint64_t* in, uint64_t* out, int64_t count, int shift,
+                             int bits, const uint32_t* hist_pass, uint64_t* desc,
+                             uint32_t* ticket, int32_t* err, uint32_t epoch, hipStream_t s);
+
+// Steps 4-5: round-based reduction.
+struct RedArgs {
+  const uint64_t* skeys;
+  int ib;
+  int64_t n, E, LW, Wcap;
+  uint64_t* table;
+  int64_t* killer;
+  uint64_t* lowc;
+  uint64_t* touch;
+  Ring ring;
+  RedCtl* ctl;
+};
+hipError_t launch_reduce_init(const RedArgs& a, hipStream_t s);
+hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s);
+hipError_t launch_reduce_finish(const RedArgs& a, hipStream_t s);
+
+// Step 3 (dense grades) over the first E_eff sorted keys.
+int64_t rank_blocks(int64_t count);
+hipError_t launch_rank(const uint64_t* skeys, const RedCtl* ctl, int shift, uint32_t* blockcnt,
+                       int64_t max_count, uint32_t* rank_out, hipStream_t s);
+
+// Step 5: per-vertex deaths and the canonical barcode.
+hipError_t launch_vertex_deaths(const int64_t* killer, const uint32_t* rank, int64_t n,
+                                uint32_t* dbv, hipStream_t s);
+hipError_t launch_sort_bars_small(const uint32_t* dbv, int64_t n, uint32_t* out_bars,
+                                  hipStream_t s);
+hipError_t launch_u32_to_keys(const uint32_t* v, int64_t n, uint64_t* keys, hipStream_t s);
+hipError_t launch_keys_to_bars(const uint64_t* keys, int64_t n, uint32_t* out_bars,
+                               hipStream_t s);
+hipError_t launch_pairs_detail(const int64_t* killer, const uint64_t* skeys, int ib,
+                               const uint64_t* table, int64_t LW, int64_t n,
+                               int64_t* killer_pos, uint64_t* killer_edge,
+                               int64_t* killer_sqdist, int32_t* partner, hipStream_t s);
+
+constexpr int kSmallSortMax = 16384;  // barcode sorts up to this size run in LDS
+
+}  // namespace ph0

@@ -1,0 +1,253 @@
+"""Thin ctypes binding of the C ABI in include/ph0.h (same names).
+
+Only argument marshalling lives here: every step of the barcode computation
+runs in the HIP kernels of libph0.so.  There is no CPU fallback: loading
+fails loudly when the library has not been built.
+
+Device entry points take torch tensors on a HIP device and enqueue on the
+current torch stream (or the one given); host entry points take numpy.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libph0.so")
+
+PH0_INF = 0xFFFFFFFF
+PH0_I8 = 1
+PH0_I16 = 2
+STATUS = {0: "PH0_OK", -1: "PH0_EINVAL", -2: "PH0_ERANGE", -3: "PH0_ENOMEM",
+          -4: "PH0_EDEVICE", -5: "PH0_EBUSY"}
+
+
+class Ph0Error(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+class ph0_stats(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("E", ctypes.c_int64),
+        ("E_eff", ctypes.c_int64),
+        ("distinct_eff", ctypes.c_int64),
+        ("additions", ctypes.c_int64),
+        ("additions_all", ctypes.c_int64),
+        ("find_steps", ctypes.c_int64),
+        ("words_read", ctypes.c_int64),
+        ("rounds", ctypes.c_int64),
+        ("window", ctypes.c_int64),
+        ("sort_passes", ctypes.c_int32),
+        ("delta_bits", ctypes.c_int32),
+        ("index_bits", ctypes.c_int32),
+        ("keys_path", ctypes.c_int32),
+        ("ms_keys", ctypes.c_float),
+        ("ms_sort", ctypes.c_float),
+        ("ms_reduce", ctypes.c_float),
+        ("ms_rank", ctypes.c_float),
+        ("ms_emit", ctypes.c_float),
+        ("ms_total", ctypes.c_float),
+    ]
+
+    def to_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_SIGS = {
+    "ph0_last_error": ([], ctypes.c_char_p),
+    "ph0_workspace_bytes": ([_I64, _I32, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "ph0_key_layout": ([_I64, _I32, ctypes.c_int, ctypes.POINTER(_I32), ctypes.POINTER(_I32)], ctypes.c_int),
+    "ph0_set_window": ([_I64], ctypes.c_int),
+    "ph0_barcodes": ([_P, ctypes.c_int, _I64, _I32, _P, ctypes.POINTER(ph0_stats)], ctypes.c_int),
+    "ph0_barcodes_device": ([_P, ctypes.c_int, _I64, _I32, _P, _P, ctypes.c_size_t, _P,
+                             ctypes.POINTER(ph0_stats)], ctypes.c_int),
+    "ph0_pairs_device": ([_P, ctypes.c_int, _I64, _I32, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P,
+                          ctypes.POINTER(ph0_stats)], ctypes.c_int),
+    "ph0_keys_device": ([_P, ctypes.c_int, _I64, _I32, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "ph0_sorted_keys_device": ([_P, ctypes.c_int, _I64, _I32, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Load libph0.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libph0.so is not built; run `python -m paper_2203_02527_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def ph0_last_error() -> str:
+    return lib().ph0_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise Ph0Error(rc, ph0_last_error())
+
+
+def _dtype_code(dtype) -> int:
+    s = str(dtype).replace("<class '", "").rstrip("'>")
+    if s.endswith("uint8") or s.endswith("uint16"):
+        raise TypeError("points must be signed int8 or int16, got %s" % s)
+    if s.endswith("int8"):
+        return PH0_I8
+    if s.endswith("int16"):
+        return PH0_I16
+    raise TypeError("points must be int8 or int16, got %s" % s)
+
+
+def ph0_workspace_bytes(n: int, d: int, dtype) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().ph0_workspace_bytes(n, d, _dtype_code(dtype), ctypes.byref(out)))
+    return out.value
+
+
+def ph0_key_layout(n: int, d: int, dtype) -> tuple[int, int, int]:
+    """(status, index_bits, delta_bits) for full-range coordinates."""
+    ib, db = _I32(0), _I32(0)
+    rc = lib().ph0_key_layout(n, d, _dtype_code(dtype), ctypes.byref(ib), ctypes.byref(db))
+    return rc, ib.value, db.value
+
+
+def ph0_set_window(columns: int) -> None:
+    _check(lib().ph0_set_window(columns))
+
+
+def ph0_barcodes(points: np.ndarray, with_stats: bool = False):
+    """Host API: N x d int8/int16 numpy array -> N x 2 uint32 (birth, death)."""
+    x = np.ascontiguousarray(points)
+    if x.ndim != 2:
+        raise ValueError("points must be N x d")
+    n, d = x.shape
+    out = np.empty((n, 2), np.uint32)
+    st = ph0_stats()
+    _check(lib().ph0_barcodes(x.ctypes.data_as(_P), _dtype_code(x.dtype), n, d,
+                              out.ctypes.data_as(_P), ctypes.byref(st)))
+    return (out, st.to_dict()) if with_stats else out
+
+
+# ---- device (torch) entry points ----
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _points_dev(points):
+    if not points.is_cuda:
+        raise ValueError("points must be a device tensor")
+    if points.dim() != 2:
+        raise ValueError("points must be N x d")
+    return points.contiguous()
+
+
+def alloc_workspace(n: int, d: int, dtype, device=None):
+    """A byte tensor large enough for ph0_barcodes_device on this cloud shape."""
+    torch = _torch()
+    nbytes = ph0_workspace_bytes(n, d, dtype)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def ph0_barcodes_device(points, out=None, workspace=None, stream=None, with_stats=False):
+    """Device API: returns an N x 2 int32 tensor holding the uint32 bars.
+
+    View it as uint32 on the host (``out.cpu().numpy().view(np.uint32)``);
+    PH0_INF reads as -1 in int32.
+    """
+    torch = _torch()
+    x = _points_dev(points)
+    n, d = x.shape
+    if out is None:
+        out = torch.empty((n, 2), dtype=torch.int32, device=x.device)
+    if workspace is None:
+        workspace = alloc_workspace(n, d, x.dtype, x.device)
+    st = ph0_stats()
+    _check(lib().ph0_barcodes_device(_ptr(x), _dtype_code(x.dtype), n, d, _ptr(out),
+                                     _ptr(workspace), workspace.numel(), _stream_ptr(stream),
+                                     ctypes.byref(st)))
+    return (out, st.to_dict()) if with_stats else out
+
+
+@dataclass
+class Pairs:
+    death_by_vertex: object  # int32 tensor holding uint32 grades (PH0_INF = -1)
+    killer_pos: object       # int64
+    killer_edge: object      # int64 holding (j << 32) | i
+    killer_sqdist: object    # int64
+    partner: object          # int32
+    stats: dict
+
+
+def ph0_pairs_device(points, workspace=None, stream=None) -> Pairs:
+    torch = _torch()
+    x = _points_dev(points)
+    n, d = x.shape
+    dev = x.device
+    dbv = torch.empty(n, dtype=torch.int32, device=dev)
+    kp = torch.empty(n, dtype=torch.int64, device=dev)
+    ke = torch.empty(n, dtype=torch.int64, device=dev)
+    ks = torch.empty(n, dtype=torch.int64, device=dev)
+    par = torch.empty(n, dtype=torch.int32, device=dev)
+    if workspace is None:
+        workspace = alloc_workspace(n, d, x.dtype, dev)
+    st = ph0_stats()
+    _check(lib().ph0_pairs_device(_ptr(x), _dtype_code(x.dtype), n, d, _ptr(dbv), _ptr(kp),
+                                  _ptr(ke), _ptr(ks), _ptr(par), _ptr(workspace),
+                                  workspace.numel(), _stream_ptr(stream), ctypes.byref(st)))
+    return Pairs(dbv, kp, ke, ks, par, st.to_dict())
+
+
+def ph0_keys_device(points, workspace=None, stream=None):
+    """Unsorted packed keys (int64 tensor of E entries, colex order)."""
+    torch = _torch()
+    x = _points_dev(points)
+    n, d = x.shape
+    keys = torch.empty(max(n * (n - 1) // 2, 1), dtype=torch.int64, device=x.device)
+    if workspace is None:
+        workspace = alloc_workspace(n, d, x.dtype, x.device)
+    _check(lib().ph0_keys_device(_ptr(x), _dtype_code(x.dtype), n, d, _ptr(keys),
+                                 _ptr(workspace), workspace.numel(), _stream_ptr(stream)))
+    return keys[: n * (n - 1) // 2]
+
+
+def ph0_sorted_keys_device(points, workspace=None, stream=None):
+    """Packed keys in sorted (delta, j, i) order (int64 tensor of E entries)."""
+    torch = _torch()
+    x = _points_dev(points)
+    n, d = x.shape
+    keys = torch.empty(max(n * (n - 1) // 2, 1), dtype=torch.int64, device=x.device)
+    if workspace is None:
+        workspace = alloc_workspace(n, d, x.dtype, x.device)
+    _check(lib().ph0_sorted_keys_device(_ptr(x), _dtype_code(x.dtype), n, d, _ptr(keys),
+                                        _ptr(workspace), workspace.numel(), _stream_ptr(stream)))
+    return keys[: n * (n - 1) // 2]

@@ -1,0 +1,60 @@
+"""Write oracle_<workload>_s<seed>.json: expected values at full workload size.
+
+Calls only the CPU oracle (oracle/) on the seeded generators; no value here
+comes from the GPU library.  Run from the repository root:
+
+    python tests/golden/make_golden.py [workload ...]
+"""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2203_02527_amd import synth  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def digest(a: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def record(name: str, seed: int) -> dict:
+    pts = synth.workload(name, seed=seed)
+    res = oracle.barcode(pts, early_exit=True)
+    return {
+        "workload": name,
+        "seed": seed,
+        "n": int(pts.shape[0]),
+        "d": int(pts.shape[1]),
+        "points_sha256": digest(pts),
+        "E": res.E,
+        "E_eff": res.E_eff,
+        "additions": res.additions,
+        "pivots": res.pivots,
+        "canonical_sha256": digest(res.canonical.astype("<u4")),
+        "death_by_vertex_sha256": digest(res.death_by_vertex.astype("<u4")),
+        "killer_pos_sha256": digest(res.killer_pos.astype("<i8")),
+        "partner_sha256": digest(res.partner.astype("<i4")),
+        "max_finite_death": int(res.canonical[-2]) if res.canonical.size > 1 else None,
+        "oracle_seconds": res.seconds,
+    }
+
+
+def main(names):
+    for name in names:
+        rec = record(name, 0)
+        with open(os.path.join(HERE, "oracle_%s_s0.json" % name), "w") as f:
+            json.dump(rec, f, indent=1, sort_keys=True)
+            f.write("\n")
+        print(name, rec["E_eff"], rec["additions"], flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or list(synth.WORKLOADS))

@@ -1,0 +1,61 @@
+"""The C-ABI library loads, exports every declared symbol, and its argument
+checks (which run before any device call) behave as documented.  CPU only."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2203_02527_amd import ph0
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "ph0.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ph0_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ph0.lib()
+    names = _declared()
+    assert "ph0_barcodes_device" in names and len(names) >= 9
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(ph0.EXPORTED)
+
+
+def test_workspace_bytes_and_arguments():
+    ws = ph0.ph0_workspace_bytes(16384, 64, np.int8)
+    E = 16384 * 16383 // 2
+    assert ws >= 2 * 8 * E  # two key buffers dominate
+    assert ws < 3 * 8 * E
+    for n, d in [(0, 3), (-1, 3), (5, 0), (70000, 3)]:
+        with pytest.raises(ph0.Ph0Error) as ei:
+            ph0.ph0_workspace_bytes(n, d, np.int8)
+        assert ei.value.code == -1
+    with pytest.raises(TypeError):
+        ph0.ph0_workspace_bytes(5, 3, np.int32)
+
+
+def test_key_layout_bit_budget():
+    rc, ib, db = ph0.ph0_key_layout(16384, 64, np.int8)
+    assert rc == 0 and ib == 14 and db == 22  # 64 * 255^2 < 2^22
+    rc, ib, db = ph0.ph0_key_layout(256, 3, np.int16)
+    assert rc == 0 and ib == 8 and db == 34
+    rc, ib, db = ph0.ph0_key_layout(16384, 64, np.int16)
+    assert rc == -2 and 2 * ib + db > 64  # full-range int16 does not fit
+    rc, ib, _ = ph0.ph0_key_layout(2, 1, np.int8)
+    assert rc == 0 and ib == 1
+
+
+def test_host_entry_rejects_bad_arguments_before_device_use():
+    with pytest.raises(ph0.Ph0Error) as ei:
+        ph0.ph0_barcodes(np.zeros((0, 3), np.int8))
+    assert ei.value.code == -1
+    with pytest.raises(TypeError):
+        ph0.ph0_barcodes(np.zeros((4, 3), np.float32))
+    assert ph0.ph0_set_window(0) is None
+    with pytest.raises(ph0.Ph0Error):
+        ph0.ph0_set_window(-5)

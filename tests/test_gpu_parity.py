@@ -1,0 +1,219 @@
+"""GPU parity: the HIP path against the CPU oracle, stage by stage, through
+the C ABI.  Everything is integer, so every comparison is exact (tolerance 0).
+"""
+import hashlib
+import json
+import os
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_02527_amd import ph0, synth
+from tests.conftest import GOLDEN, golden_cases, load_fixture
+
+pytestmark = pytest.mark.gpu
+
+INF = 0xFFFFFFFF
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    assert t.cuda.is_available(), "GPU tests need a HIP device"
+    ph0.lib()
+    return t
+
+
+def _cloud(seed, n, d, lo, hi, dtype):
+    rng = np.random.default_rng(seed)
+    return rng.integers(lo, hi + 1, size=(n, d)).astype(dtype)
+
+
+# (name, n, d, lo, hi, dtype): ragged tile tails, both distance paths, ties.
+CASES = [
+    ("n2_d1_i8", 2, 1, -5, 5, np.int8),
+    ("n3_d2_i16", 3, 2, -100, 100, np.int16),
+    ("n65_d3_i16", 65, 3, -100, 100, np.int16),
+    ("n130_d3_tie", 130, 3, 0, 2, np.int8),
+    ("n200_d8_i8_mfma", 200, 8, -128, 127, np.int8),
+    ("n257_d16_i8", 257, 16, -128, 127, np.int8),
+    ("n300_d64_i8", 300, 64, -20, 20, np.int8),
+    ("n190_d100_i8", 190, 100, -128, 127, np.int8),
+    ("n150_d300_i8", 150, 300, -128, 127, np.int8),
+    ("n333_d5_i16", 333, 5, -16000, 16000, np.int16),
+    ("n1000_d3_i16", 1000, 3, -1000, 1000, np.int16),
+    ("n700_d2_tie", 700, 2, 0, 6, np.int8),
+]
+
+
+def _unpack(keys, n):
+    k = keys.cpu().numpy().view(np.uint64)
+    ib = (n - 1).bit_length()
+    m = np.uint64((1 << ib) - 1)
+    return (k >> np.uint64(2 * ib)).astype(np.int64), ((k >> np.uint64(ib)) & m).astype(np.int64), \
+        (k & m).astype(np.int64)
+
+
+def _dev(torch, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_keys_match_oracle_distances(torch, case):
+    name, n, d, lo, hi, dt = case
+    x = _cloud(zlib.crc32(name.encode()) % 1000, n, d, lo, hi, dt)
+    keys = ph0.ph0_keys_device(_dev(torch, x))
+    torch.cuda.synchronize()
+    delta, j, i = _unpack(keys, n)
+    ref = oracle.sorted_edges(x)
+    np.testing.assert_array_equal(delta, ref.colex_delta)
+    jj = np.repeat(np.arange(n), np.arange(n))
+    ii = np.arange(jj.size) - jj * (jj - 1) // 2
+    np.testing.assert_array_equal(j, jj)
+    np.testing.assert_array_equal(i, ii)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_sorted_keys_match_oracle(torch, case):
+    name, n, d, lo, hi, dt = case
+    x = _cloud(zlib.crc32(name.encode()) % 1000 + 1, n, d, lo, hi, dt)
+    keys = ph0.ph0_sorted_keys_device(_dev(torch, x))
+    torch.cuda.synchronize()
+    delta, j, i = _unpack(keys, n)
+    ref = oracle.sorted_edges(x)
+    np.testing.assert_array_equal(delta, ref.delta)
+    np.testing.assert_array_equal(j, ref.j)
+    np.testing.assert_array_equal(i, ref.i)
+
+
+def _check_full(torch, x, early=True):
+    n = x.shape[0]
+    ref = oracle.barcode(x)
+    bars, st = ph0.ph0_barcodes_device(_dev(torch, x), with_stats=True)
+    pr = ph0.ph0_pairs_device(_dev(torch, x))
+    torch.cuda.synchronize()
+    b = bars.cpu().numpy().view(np.uint32)
+    assert (b[:, 0] == 0).all()
+    np.testing.assert_array_equal(b[:, 1], ref.canonical)
+    np.testing.assert_array_equal(pr.death_by_vertex.cpu().numpy().view(np.uint32),
+                                  ref.death_by_vertex)
+    np.testing.assert_array_equal(pr.killer_pos.cpu().numpy(), ref.killer_pos)
+    np.testing.assert_array_equal(pr.partner.cpu().numpy(), ref.partner)
+    if n > 1:
+        assert st["E_eff"] == ref.E_eff
+        assert st["additions"] == ref.additions
+        assert st["distinct_eff"] == int(ref.canonical[-2])
+        kp = ref.killer_pos
+        se = oracle.sorted_edges(x)
+        has = kp >= 0
+        ke = pr.killer_edge.cpu().numpy().view(np.uint64)
+        np.testing.assert_array_equal(ke[has] >> np.uint64(32), se.j[kp[has]].astype(np.uint64))
+        np.testing.assert_array_equal(ke[has] & np.uint64(0xFFFFFFFF),
+                                      se.i[kp[has]].astype(np.uint64))
+        np.testing.assert_array_equal(pr.killer_sqdist.cpu().numpy()[has], se.delta[kp[has]])
+    return st
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_barcode_matches_oracle(torch, case):
+    name, n, d, lo, hi, dt = case
+    x = _cloud(zlib.crc32(name.encode()) % 1000 + 2, n, d, lo, hi, dt)
+    _check_full(torch, x)
+
+
+@pytest.mark.parametrize("name", golden_cases())
+def test_closed_form_cases(torch, name):
+    pts, deaths, vdeaths = load_fixture(name)
+    bars = ph0.ph0_barcodes_device(_dev(torch, pts)).cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(bars[:, 1], deaths)
+    pr = ph0.ph0_pairs_device(_dev(torch, pts))
+    if vdeaths is not None:
+        np.testing.assert_array_equal(pr.death_by_vertex.cpu().numpy().view(np.uint32), vdeaths)
+
+
+def test_degenerate_inputs(torch):
+    same = np.full((300, 4), 9, np.int8)  # all distances 0 -> no radix pass
+    st = _check_full(torch, same)
+    assert st["sort_passes"] == 0
+    line = np.zeros((129, 1), np.int16)
+    line[:, 0] = np.arange(129)
+    _check_full(torch, line)
+    ext = np.array([[-128] * 64, [127] * 64, [0] * 64, [-128] * 32 + [127] * 32], np.int8)
+    _check_full(torch, ext)
+
+
+def test_windows_give_identical_results(torch):
+    x = synth.mixture_cloud(700, 16, 6, 10.0, seed=4)
+    ref = oracle.barcode(x)
+    try:
+        for w in (1, 3, 64, 1000, 1 << 20):
+            ph0.ph0_set_window(w)
+            pr = ph0.ph0_pairs_device(_dev(torch, x))
+            np.testing.assert_array_equal(pr.partner.cpu().numpy(), ref.partner)
+            np.testing.assert_array_equal(pr.death_by_vertex.cpu().numpy().view(np.uint32),
+                                          ref.death_by_vertex)
+            assert pr.stats["additions"] == ref.additions
+    finally:
+        ph0.ph0_set_window(0)
+
+
+def test_repeat_runs_are_bit_identical(torch):
+    x = synth.mixture_cloud(2000, 16, 8, 10.0, seed=11)
+    xd = _dev(torch, x)
+    ws = ph0.alloc_workspace(2000, 16, x.dtype)
+    first = ph0.ph0_pairs_device(xd, workspace=ws)
+    for _ in range(3):
+        again = ph0.ph0_pairs_device(xd, workspace=ws)
+        assert torch.equal(first.partner, again.partner)
+        assert torch.equal(first.death_by_vertex, again.death_by_vertex)
+
+
+def test_host_entry_point(torch):
+    x = _cloud(5, 400, 3, -100, 100, np.int16)
+    bars, st = ph0.ph0_barcodes(x, with_stats=True)
+    np.testing.assert_array_equal(bars[:, 1], oracle.barcode(x).canonical)
+    one = ph0.ph0_barcodes(np.array([[1, 2, 3]], np.int16))
+    assert one.tolist() == [[0, INF]]
+
+
+def test_key_budget_error(torch):
+    x = np.zeros((4097, 128), np.int16)
+    x[0, :] = -32768
+    x[1, :] = 32767
+    with pytest.raises(ph0.Ph0Error) as ei:
+        ph0.ph0_barcodes_device(_dev(torch, x))
+    assert ei.value.code == -2
+
+
+def test_uniform_workload_n256(torch):
+    _check_full(torch, synth.workload("uniform_n256_d3_i16", seed=0))
+
+
+def test_mixture_workload_n4096(torch):
+    st = _check_full(torch, synth.workload("mixture_n4096_d16_i8", seed=0))
+    assert st["keys_path"] == 1
+
+
+def _sha(a, dt):
+    return hashlib.sha256(np.ascontiguousarray(a).astype(dt).tobytes()).hexdigest()
+
+
+def test_mixture_workload_n16384_against_stored_oracle(torch):
+    rec = json.load(open(os.path.join(GOLDEN, "oracle_mixture_n16384_d64_i8_s0.json")))
+    x = synth.workload("mixture_n16384_d64_i8", seed=0)
+    assert _sha(x, x.dtype) == rec["points_sha256"]
+    xd = _dev(torch, x)
+    bars, st = ph0.ph0_barcodes_device(xd, with_stats=True)
+    pr = ph0.ph0_pairs_device(xd)
+    torch.cuda.synchronize()
+    b = bars.cpu().numpy().view(np.uint32)
+    assert _sha(b[:, 1], "<u4") == rec["canonical_sha256"]
+    assert _sha(pr.death_by_vertex.cpu().numpy().view(np.uint32), "<u4") == \
+        rec["death_by_vertex_sha256"]
+    assert _sha(pr.killer_pos.cpu().numpy(), "<i8") == rec["killer_pos_sha256"]
+    assert _sha(pr.partner.cpu().numpy(), "<i4") == rec["partner_sha256"]
+    assert st["E_eff"] == rec["E_eff"] and st["additions"] == rec["additions"]
+    assert st["E"] == rec["E"]
