@@ -1,0 +1,174 @@
+"""Benchmark of the H0 barcode hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+A step is one whole barcode -- distances, LSD radix sort, grades, F2 column
+reduction, read-off -- of the N=16384, d=64 int8 Gaussian-mixture cloud (32
+clusters, std 12, seed 0), from points already resident in HBM to the
+canonical barcode in HBM, through ph0_barcodes_device.
+
+value = E_eff / step time: sorted edge columns up to the last pivot, i.e. the
+columns the reduction actually processes (the remaining E - E_eff columns are
+zero by the early-exit argument and cost nothing), per second of the whole
+step.  One JSON line is printed.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "mixture_n16384_d64_i8"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--window", type=int, default=0, help="reduction window (0 = built-in)")
+    ap.add_argument("--lanes", type=int, default=0, help="walk lanes per column (0 = built-in)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(points, n_sample):
+    """The CPU oracle (single-threaded) on the first n_sample points."""
+    import oracle
+
+    sub = points[:n_sample].copy()
+    t0 = time.perf_counter()
+    res = oracle.barcode(sub)
+    t = time.perf_counter() - t0
+    return {
+        "value": res.E_eff / t,
+        "unit": "edge columns/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "first %d points of the same cloud (E=%d, E_eff=%d), whole oracle run "
+                  "(distances, std::sort, grades, dense F2 reduction, read-off) in %.2f s"
+                  % (n_sample, res.E, res.E_eff, t),
+        "seconds": res.seconds,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU; this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2203_02527_amd import ph0, synth
+
+    if not os.path.exists(ph0.LIB_PATH):
+        import __graft_entry__
+
+        __graft_entry__.build()
+    if args.window:
+        ph0.ph0_set_window(args.window)
+    if args.lanes:
+        ph0.ph0_set_walk_lanes(args.lanes)
+    pts = synth.workload(args.workload, seed=args.seed)
+    n, d = pts.shape
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(pts).to(dev)
+    ws = ph0.alloc_workspace(n, d, pts.dtype, dev)
+    out = torch.empty((n, 2), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        ph0.ph0_barcodes_device(x, out=out, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st = ph0.ph0_barcodes_device(x, out=out, workspace=ws, stream=stream, with_stats=True)
+        stats.append(st)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    ms_step = 1000.0 * t / args.steps
+    st0 = stats[-1]
+    E, E_eff = st0["E"], st0["E_eff"]
+
+    def mean(k):
+        return float(np.mean([s[k] for s in stats]))
+
+    # Kernel rooflines from the library's event timings over the timed steps.
+    walk_ms = mean("ms_walk_kernel")
+    walk_launches = mean("walk_launches")
+    walk_bytes = 8.0 * mean("words_read")  # pivot-table words the walks load
+    radix_ms = mean("ms_radix_kernel")
+    radix_launches = mean("radix_launches")
+    radix_bytes = 16.0 * E * st0["sort_passes"]  # every pass reads and writes each key
+    kern = {
+        "reduce_walk": dict(ms=walk_ms, launches=walk_launches, bytes=walk_bytes,
+                            per_launch_ms=walk_ms / max(walk_launches, 1)),
+        "radix_pass": dict(ms=radix_ms, launches=radix_launches, bytes=radix_bytes,
+                           per_launch_ms=radix_ms / max(radix_launches, 1)),
+    }
+    for k in kern.values():
+        k["achieved_gbs"] = k["bytes"] / max(k["ms"], 1e-9) / 1e6
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    kd = kern[dom]
+    roofline = {
+        "kernel": dom,
+        "bound": "hbm",
+        "achieved": round(kd["achieved_gbs"], 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(kd["achieved_gbs"] / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "avg_launch_ms": round(kd["per_launch_ms"], 4),
+        "algorithmic_bytes_per_launch": kd["bytes"] / max(kd["launches"], 1),
+    }
+    others = {k: {"achieved_gbs": round(v["achieved_gbs"], 1), "ms_per_step": round(v["ms"], 3),
+                  "launches": v["launches"]} for k, v in kern.items()}
+
+    rec = {
+        "metric": "edge columns reduced/s at N=16384",
+        "value": E_eff / (ms_step / 1000.0),
+        "unit": "edge columns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "n": int(n), "d": int(d), "seed": args.seed,
+            "E": int(E), "E_eff": int(E_eff),
+            "edges_per_s_all_E": E / (ms_step / 1000.0),
+            "window": st0["window"],
+        },
+        "stages_ms": {k: round(mean(k), 4) for k in
+                      ("ms_keys", "ms_sort", "ms_reduce", "ms_rank", "ms_emit", "ms_total")},
+        "reduction": {k: st0[k] for k in ("additions", "additions_all", "find_steps",
+                                          "words_read", "rounds", "distinct_eff",
+                                          "sort_passes", "delta_bits", "keys_path")},
+        "roofline": roofline,
+        "kernels": others,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(pts, n // 2)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -77,6 +77,11 @@ typedef struct {
   int32_t index_bits;    /* bits per vertex index in the packed key */
   int32_t keys_path;     /* 0 = vector ALU distances, 1 = int8 MFMA Gram */
   float ms_keys, ms_sort, ms_reduce, ms_rank, ms_emit, ms_total;
+  /* Kernel-level event times (sum over launches) and launch counts. */
+  float ms_walk_kernel;    /* reduction walk kernel (one launch per round) */
+  float ms_radix_kernel;   /* LSD radix pass kernel (one launch per pass) */
+  int32_t walk_launches;
+  int32_t radix_launches;
 } ph0_stats;
 
 /* Message for the last non-OK status returned on this thread. */
@@ -133,6 +138,12 @@ int ph0_key_layout(int64_t n, int32_t d, ph0_dtype dt, int32_t* index_bits,
 /* Reduction window (columns reduced side by side per round); 0 restores the
  * built-in choice.  Affects speed only, never results.  Process-wide. */
 int ph0_set_window(int64_t columns);
+
+/* Lanes of a wavefront that reduce one column together (a power of two up to
+ * 64; 0 restores the built-in choice, the fewest lanes that cover a pivot
+ * row, at most 64).  Fewer lanes put more columns in flight per wavefront.
+ * Affects speed only, never results.  Process-wide. */
+int ph0_set_walk_lanes(int32_t lanes);
 
 #ifdef __cplusplus
 }

@@ -4,8 +4,7 @@
 // written at the edge's colex position j(j-1)/2 + i, so that the array is
 // already in (j, i) order and a stable sort on the delta bits alone yields the
 // (delta, j, i) order.  delta is the exact squared Euclidean distance of two
-// integer points.  Each workgroup also adds its keys' radix digits into the
-// global histograms of every LSD pass, so the sort needs no counting pass.
+// integer points.
 //
 // Two paths:
 //  * vector ALU, direct differences (any d, int8 or int16; int64 sums);
@@ -26,39 +25,6 @@ __device__ inline void tile_coords(int64_t t, int64_t* jb, int64_t* ib) {
   while ((j + 1) * (j + 2) / 2 <= t) ++j;
   *jb = j;
   *ib = t - j * (j + 1) / 2;
-}
-
-struct HistSpec {
-  int passes;
-  int dshift[kMaxPasses];  // shift of the digit inside delta
-  int bits[kMaxPasses];
-};
-
-HistSpec hist_spec(const SortPlan& sp, int ib) {
-  HistSpec h;
-  h.passes = sp.passes;
-  for (int p = 0; p < kMaxPasses; ++p) {
-    h.dshift[p] = p < sp.passes ? sp.shift[p] - 2 * ib : 0;
-    h.bits[p] = p < sp.passes ? sp.bits[p] : 0;
-  }
-  return h;
-}
-
-__device__ inline void hist_add(uint32_t (*lh)[256], const HistSpec& hs, uint64_t delta) {
-  for (int p = 0; p < hs.passes; ++p) {
-    uint32_t dg = (uint32_t)(delta >> hs.dshift[p]) & ((1u << hs.bits[p]) - 1u);
-    atomicAdd(&lh[p][dg], 1u);
-  }
-}
-
-__device__ inline void hist_flush(uint32_t (*lh)[256], const HistSpec& hs, uint32_t* hist) {
-  for (int p = 0; p < hs.passes; ++p) {
-    int nb = 1 << hs.bits[p];
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-      uint32_t c = lh[p][b];
-      if (c) atomicAdd(&hist[p * 256 + b], c);
-    }
-  }
 }
 
 __global__ void k_fill_u64(uint64_t* p, uint64_t v, int64_t count) {
@@ -96,12 +62,8 @@ constexpr int kChunk = 32;  // dimensions staged per LDS round
 template <typename T>
 __global__ __launch_bounds__(256) void k_keys_alu(const T* __restrict__ x, int64_t n, int32_t d,
                                                   int ib, uint64_t* __restrict__ keys,
-                                                  uint32_t* __restrict__ hist, HistSpec hs,
                                                   int64_t ntiles) {
   __shared__ int32_t xs[2][kTile][kChunk + 1];
-  __shared__ uint32_t lh[kMaxPasses][256];
-  for (int p = 0; p < hs.passes; ++p)
-    for (int b = threadIdx.x; b < 256; b += blockDim.x) lh[p][b] = 0;
 
   const int il = threadIdx.x & 63;   // i inside the tile (one per lane)
   const int jl0 = threadIdx.x >> 6;  // first j of this wave; j = jl0 + 4q
@@ -139,12 +101,9 @@ __global__ __launch_bounds__(256) void k_keys_alu(const T* __restrict__ x, int64
         const uint64_t delta = (uint64_t)acc[q];
         keys[j * (j - 1) / 2 + i] =
             (delta << (2 * ib)) | ((uint64_t)j << ib) | (uint64_t)i;
-        hist_add(lh, hs, delta);
       }
     }
   }
-  __syncthreads();
-  hist_flush(lh, hs, hist);
 }
 
 // ---- int8 MFMA Gram path ----
@@ -156,16 +115,12 @@ constexpr int kMaxDpad = 256;  // int8 dims staged per LDS round (multiple of 32
 __global__ __launch_bounds__(256) void k_keys_mfma(const int8_t* __restrict__ x, int64_t n,
                                                    int32_t d, int ib,
                                                    uint64_t* __restrict__ keys,
-                                                   uint32_t* __restrict__ hist, HistSpec hs,
                                                    int64_t ntiles) {
   // Rows padded by 16 bytes so that the 32 row reads of a half-wave spread
   // over the LDS banks.
   constexpr int kRow = kMaxDpad + 16;
   __shared__ __attribute__((aligned(16))) int8_t xs[2][kTile][kRow];
   __shared__ int32_t nrm[2][kTile];
-  __shared__ uint32_t lh[kMaxPasses][256];
-  for (int p = 0; p < hs.passes; ++p)
-    for (int b = threadIdx.x; b < 256; b += blockDim.x) lh[p][b] = 0;
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -223,32 +178,8 @@ __global__ __launch_bounds__(256) void k_keys_mfma(const int8_t* __restrict__ x,
         const uint64_t delta = (uint64_t)(int64_t)(nrm[1][jl] + ni - 2 * c[r]);
         keys[j * (j - 1) / 2 + i] =
             (delta << (2 * ib)) | ((uint64_t)j << ib) | (uint64_t)i;
-        hist_add(lh, hs, delta);
       }
     }
-  }
-  __syncthreads();
-  hist_flush(lh, hs, hist);
-}
-
-__global__ __launch_bounds__(256) void k_histogram(const uint64_t* __restrict__ keys,
-                                                   int64_t count, SortPlan sp,
-                                                   uint32_t* __restrict__ hist) {
-  __shared__ uint32_t lh[kMaxPasses][256];
-  for (int p = 0; p < sp.passes; ++p)
-    for (int b = threadIdx.x; b < 256; b += blockDim.x) lh[p][b] = 0;
-  __syncthreads();
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t k = keys[i];
-    for (int p = 0; p < sp.passes; ++p)
-      atomicAdd(&lh[p][(uint32_t)(k >> sp.shift[p]) & ((1u << sp.bits[p]) - 1u)], 1u);
-  }
-  __syncthreads();
-  for (int p = 0; p < sp.passes; ++p) {
-    const int nb = 1 << sp.bits[p];
-    for (int b = threadIdx.x; b < nb; b += blockDim.x)
-      if (lh[p][b]) atomicAdd(&hist[p * 256 + b], lh[p][b]);
   }
 }
 
@@ -285,29 +216,20 @@ hipError_t launch_coord_range(const void* pts, int elem_bytes, int64_t n, int32_
 }
 
 hipError_t launch_keys(const void* pts, int elem_bytes, int64_t n, int32_t d, int ib,
-                       const SortPlan& sp, uint64_t* keys, uint32_t* hist, bool use_mfma,
-                       hipStream_t s) {
+                       uint64_t* keys, bool use_mfma, hipStream_t s) {
   const int64_t nb = (n + kTile - 1) / kTile;
   const int64_t ntiles = nb * (nb + 1) / 2;
-  const HistSpec hs = hist_spec(sp, ib);
   const int grid = (int)(ntiles < 65536 ? ntiles : 65536);
   if (use_mfma && elem_bytes == 1) {
     hipLaunchKernelGGL(k_keys_mfma, dim3(grid), dim3(256), 0, s,
-                       static_cast<const int8_t*>(pts), n, d, ib, keys, hist, hs, ntiles);
+                       static_cast<const int8_t*>(pts), n, d, ib, keys, ntiles);
   } else if (elem_bytes == 1) {
     hipLaunchKernelGGL(k_keys_alu<int8_t>, dim3(grid), dim3(256), 0, s,
-                       static_cast<const int8_t*>(pts), n, d, ib, keys, hist, hs, ntiles);
+                       static_cast<const int8_t*>(pts), n, d, ib, keys, ntiles);
   } else {
     hipLaunchKernelGGL(k_keys_alu<int16_t>, dim3(grid), dim3(256), 0, s,
-                       static_cast<const int16_t*>(pts), n, d, ib, keys, hist, hs, ntiles);
+                       static_cast<const int16_t*>(pts), n, d, ib, keys, ntiles);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_histogram(const uint64_t* keys, int64_t count, const SortPlan& sp,
-                            uint32_t* hist, hipStream_t s) {
-  hipLaunchKernelGGL(k_histogram, dim3(grid_for(count, 256 * 16, 1024)), dim3(256), 0, s, keys,
-                     count, sp, hist);
   return hipGetLastError();
 }
 

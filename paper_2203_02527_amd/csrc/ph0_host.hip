@@ -21,6 +21,7 @@ namespace {
 
 thread_local char g_err[512] = "";
 std::atomic<int64_t> g_window{0};
+std::atomic<int32_t> g_walk_lanes{0};
 
 int fail(int code, const char* fmt, ...) {
   va_list ap;
@@ -44,16 +45,20 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 int index_bits(int64_t n) { return n <= 1 ? 0 : 64 - __builtin_clzll((uint64_t)(n - 1)); }
 
+// Columns in flight per reduction round; a power of two (the per-column
+// state is a ring indexed by column & (window - 1)).
 int64_t window_for(int64_t n, int64_t E) {
   int64_t w = g_window.load();
   if (w <= 0) w = std::max<int64_t>(65536, 64 * n);
   w = std::min<int64_t>(w, std::max<int64_t>(E, 1));
-  return std::max<int64_t>(w, 1);
+  int64_t p = 1;
+  while (p < w) p <<= 1;
+  return p;
 }
 
 struct Layout {
   int64_t n, E, LW, Wcap, tiles;
-  size_t keysA, keysB, hist, tickets, err, desc, table, killer, lowc, touch, rtag, ra, rr, rrlo,
+  size_t keysA, keysB, counts, err, table, killer, lowc, touch, act0, act1, rtag, ra, rr, rrlo,
       rst, ctl, blockcnt, dbv, minmax, total;
 };
 
@@ -73,14 +78,14 @@ Layout make_layout(int64_t n, int32_t d) {
   };
   L.keysA = take(8 * (size_t)keys);
   L.keysB = take(8 * (size_t)keys);
-  L.hist = take(4 * 256 * kMaxPasses);
-  L.tickets = take(4 * kMaxPasses);
+  L.counts = take(4 * (size_t)radix_count_entries(keys));
   L.err = take(4);
-  L.desc = take(8 * 256 * (size_t)L.tiles);
   L.table = take(8 * (size_t)(n * L.LW));
   L.killer = take(8 * (size_t)n);
   L.lowc = take(8 * (size_t)n);
   L.touch = take(8 * (size_t)n);
+  L.act0 = take(8 * (size_t)L.Wcap);
+  L.act1 = take(8 * (size_t)L.Wcap);
   L.rtag = take(8 * (size_t)L.Wcap);
   L.ra = take(4 * (size_t)L.Wcap);
   L.rr = take(4 * (size_t)L.Wcap);
@@ -137,6 +142,39 @@ struct Timer {
   ~Timer() {
     if (on)
       for (auto& e : ev) hipEventDestroy(e);
+  }
+};
+
+// Event pairs around individual kernel launches (stats only).
+struct KernelClock {
+  bool on;
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  explicit KernelClock(bool enabled) : on(enabled) {}
+  hipEvent_t* pair() {
+    if (!on) return nullptr;
+    if (used + 2 > ev.size()) {
+      for (int k = 0; k < 2; ++k) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        ev.push_back(e);
+      }
+    }
+    hipEvent_t* p = &ev[used];
+    used += 2;
+    return p;
+  }
+  float total_ms() const {
+    float t = 0;
+    for (size_t k = 0; k + 1 < used; k += 2) {
+      float v = 0;
+      if (hipEventElapsedTime(&v, ev[k], ev[k + 1]) == hipSuccess) t += v;
+    }
+    return t;
+  }
+  int launches() const { return (int)(used / 2); }
+  ~KernelClock() {
+    for (auto e : ev) hipEventDestroy(e);
   }
 };
 
@@ -230,16 +268,12 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
 
   uint64_t* keysA = static_cast<uint64_t*>(at(L.keysA));
   uint64_t* keysB = static_cast<uint64_t*>(at(L.keysB));
-  uint32_t* hist = static_cast<uint32_t*>(at(L.hist));
-  uint32_t* tickets = static_cast<uint32_t*>(at(L.tickets));
+  uint32_t* counts = static_cast<uint32_t*>(at(L.counts));
   int32_t* serr = static_cast<int32_t*>(at(L.err));
-  uint64_t* desc = static_cast<uint64_t*>(at(L.desc));
 
-  HIPCHK(launch_fill_u32(hist, 0u, 256 * kMaxPasses, s));
-  HIPCHK(launch_fill_u32(tickets, 0u, kMaxPasses, s));
   HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t*>(serr), 0u, 1, s));
   tm.mark();  // 1
-  HIPCHK(launch_keys(d_points, eb, n, d, ib, sp, keysA, hist, mfma, s));
+  HIPCHK(launch_keys(d_points, eb, n, d, ib, keysA, mfma, s));
   tm.mark();  // 2
   if (stop == kStopKeys) {
     HIPCHK(hipMemcpyAsync(out.keys, keysA, 8 * (size_t)L.E, hipMemcpyDeviceToDevice, s));
@@ -247,12 +281,14 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     return PH0_OK;
   }
 
-  HIPCHK(launch_fill_u64(desc, 0ull, 256 * radix_tiles(L.E), s));
   uint64_t* src = keysA;
   uint64_t* dst = keysB;
+  KernelClock radix_clock(st != nullptr), walk_clock(st != nullptr);
   for (int p = 0; p < sp.passes; ++p) {
-    HIPCHK(launch_radix_pass(src, dst, L.E, sp.shift[p], sp.bits[p], hist + 256 * p, desc,
-                             tickets + p, serr, (uint32_t)(p + 1), s));
+    hipEvent_t* ev = radix_clock.pair();
+    if (ev) hipEventRecord(ev[0], s);
+    HIPCHK(launch_radix_pass(src, dst, L.E, sp.shift[p], sp.bits[p], counts, serr, s));
+    if (ev) hipEventRecord(ev[1], s);
     std::swap(src, dst);
   }
   uint64_t* skeys = src;  // sorted
@@ -263,7 +299,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     HIPCHK(hipMemcpyAsync(out.keys, skeys, 8 * (size_t)L.E, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(&herr, serr, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (herr) return fail(PH0_EDEVICE, "radix sort look-back did not complete");
+    if (herr) return fail(PH0_EDEVICE, "radix sort digit counts were inconsistent");
     return PH0_OK;
   }
 
@@ -275,6 +311,9 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   ra.E = L.E;
   ra.LW = L.LW;
   ra.Wcap = L.Wcap;
+  ra.lanes = g_walk_lanes.load();
+  ra.act[0] = static_cast<int64_t*>(at(L.act0));
+  ra.act[1] = static_cast<int64_t*>(at(L.act1));
   ra.table = static_cast<uint64_t*>(at(L.table));
   ra.killer = static_cast<int64_t*>(at(L.killer));
   ra.lowc = static_cast<uint64_t*>(at(L.lowc));
@@ -293,7 +332,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   int64_t prevF = -1;
   const int burst = 8;
   while (true) {
-    for (int t = 0; t < burst; ++t) HIPCHK(launch_reduce_round(ra, s));
+    for (int t = 0; t < burst; ++t) HIPCHK(launch_reduce_round(ra, s, walk_clock.pair()));
     HIPCHK(hipMemcpyAsync(hc, ra.ctl, sizeof(RedCtl), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (hc->done) break;
@@ -310,7 +349,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   HIPCHK(hipMemcpyAsync(&herr, serr, 4, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   tm.mark();  // 4
-  if (herr) return fail(PH0_EDEVICE, "radix sort look-back did not complete");
+  if (herr) return fail(PH0_EDEVICE, "radix sort digit counts were inconsistent");
   if (hc->err & 1) return fail(PH0_EDEVICE, "a reduced column did not have exactly two rows");
   if (hc->err & 2 || hc->pivots != n - 1)
     return fail(PH0_EDEVICE, "reduction ended with %lld pivots, expected %lld",
@@ -338,20 +377,9 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
       // Larger barcodes: the same LSD passes over the 32 death bits.
       uint64_t* ka = spare;
       uint64_t* kb = spare + n;
-      SortPlan bp = {};
-      bp.passes = 4;
-      for (int p = 0; p < 4; ++p) {
-        bp.shift[p] = 8 * p;
-        bp.bits[p] = 8;
-      }
       HIPCHK(launch_u32_to_keys(dbv, n, ka, s));
-      HIPCHK(launch_fill_u32(hist, 0u, 256 * kMaxPasses, s));
-      HIPCHK(launch_fill_u32(tickets, 0u, kMaxPasses, s));
-      HIPCHK(launch_histogram(ka, n, bp, hist, s));
-      HIPCHK(launch_fill_u64(desc, 0ull, 256 * radix_tiles(n), s));
       for (int p = 0; p < 4; ++p) {
-        HIPCHK(launch_radix_pass(ka, kb, n, bp.shift[p], 8, hist + 256 * p, desc, tickets + p,
-                                 serr, (uint32_t)(p + 1), s));
+        HIPCHK(launch_radix_pass(ka, kb, n, 8 * p, 8, counts, serr, s));
         std::swap(ka, kb);
       }
       HIPCHK(launch_keys_to_bars(ka, n, reinterpret_cast<uint32_t*>(out.bars), s));
@@ -363,7 +391,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   tm.mark();  // 6
   HIPCHK(hipMemcpyAsync(&herr, serr, 4, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (herr) return fail(PH0_EDEVICE, "barcode sort look-back did not complete");
+  if (herr) return fail(PH0_EDEVICE, "barcode sort digit counts were inconsistent");
   S.distinct_eff = last_rank;
   if (st) {
     S.ms_keys = tm.ms(1, 2);
@@ -372,6 +400,10 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     S.ms_rank = tm.ms(4, 5);
     S.ms_emit = tm.ms(5, 6);
     S.ms_total = tm.ms(0, 6);
+    S.ms_walk_kernel = walk_clock.total_ms();
+    S.walk_launches = walk_clock.launches();
+    S.ms_radix_kernel = radix_clock.total_ms();
+    S.radix_launches = radix_clock.launches();
     *st = S;
   }
   return PH0_OK;
@@ -418,6 +450,13 @@ int ph0_key_layout(int64_t n, int32_t d, ph0_dtype dt, int32_t* ibits, int32_t* 
 int ph0_set_window(int64_t columns) {
   if (columns < 0) return fail(PH0_EINVAL, "window must be >= 0");
   g_window.store(columns);
+  return PH0_OK;
+}
+
+int ph0_set_walk_lanes(int32_t lanes) {
+  if (lanes < 0 || lanes > 64 || (lanes & (lanes - 1)))
+    return fail(PH0_EINVAL, "lanes must be 0 or a power of two <= 64");
+  g_walk_lanes.store(lanes);
   return PH0_OK;
 }
 

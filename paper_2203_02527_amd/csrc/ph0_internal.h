@@ -19,21 +19,30 @@ struct SortPlan {
 };
 
 // Control block of the round-based reduction, resident in device memory.
+// A round works on "items": first the nA columns carried over in the active
+// list act[cur], then the fresh columns [fresh_lo, fresh_hi) entering the
+// window this round.
 struct RedCtl {
-  int64_t F;        // first column that is not final
-  int64_t Wend;     // end of the current window [F, Wend)
-  int64_t maxWend;  // largest Wend ever used
-  int64_t pivots;   // committed pivots
-  int64_t E_eff;    // largest committed column + 1
+  int64_t F;         // first column that is not final
+  int64_t Wend;      // end of the window [F, Wend); Wend - F <= Wcap
+  int64_t maxWend;   // largest Wend ever used
+  int64_t fresh_lo;  // columns entering this round
+  int64_t fresh_hi;
+  int64_t nA;        // carried-over active columns in act[cur]
+  int64_t nA_next;   // columns appended to act[cur ^ 1] by this round's commit
+  int64_t pivots;    // committed pivots
+  int64_t E_eff;     // largest committed column + 1
   int64_t round;
   uint64_t firstdup[2];  // per round parity: first survivor whose low repeats
-  uint64_t newF[2];      // per round parity: first survivor left active
+  uint64_t newF[2];      // per round parity: first column left active
   int64_t additions_all;
   int64_t find_steps;
   int64_t words_read;
   int64_t additions_overshoot;  // additions of walked columns >= E_eff
+  int32_t cur;
   int32_t done;
   int32_t err;  // bit 0: a reduced column had weight != 2; bit 1: ran out of columns
+  int32_t pad;
 };
 
 // Per-column state of the reduction window, a ring indexed by p % Wcap.
@@ -57,36 +66,35 @@ hipError_t launch_coord_range(const void* pts, int elem_bytes, int64_t n, int32_
                               int32_t* minmax /* 2*d, zeroed to +-inf by caller */,
                               hipStream_t s);
 
-// Step 1: keys of all edges at colex positions + per-pass digit histograms.
+// Step 1: keys of all edges at colex positions.
 hipError_t launch_keys(const void* pts, int elem_bytes, int64_t n, int32_t d, int ib,
-                       const SortPlan& sp, uint64_t* keys, uint32_t* hist, bool use_mfma,
-                       hipStream_t s);
+                       uint64_t* keys, bool use_mfma, hipStream_t s);
 
-// Step 2: global digit histograms of an arbitrary key array (used for the
-// small sort of the barcode's deaths).
-hipError_t launch_histogram(const uint64_t* keys, int64_t count, const SortPlan& sp,
-                            uint32_t* hist, hipStream_t s);
-
-// One stable LSD pass: in -> out by digit (key >> shift) & ((1<<bits)-1).
+// Step 2: one stable LSD pass in -> out by digit (key >> shift) & ((1<<bits)-1).
+// `counts` holds radix_count_entries(count) words of scratch.
 int64_t radix_tiles(int64_t count);
+int64_t radix_count_entries(int64_t count);
 hipError_t launch_radix_pass(const uint64_t* in, uint64_t* out, int64_t count, int shift,
-                             int bits, const uint32_t* hist_pass, uint64_t* desc,
-                             uint32_t* ticket, int32_t* err, uint32_t epoch, hipStream_t s);
+                             int bits, uint32_t* counts, int32_t* err, hipStream_t s);
 
 // Steps 4-5: round-based reduction.
 struct RedArgs {
   const uint64_t* skeys;
   int ib;
   int64_t n, E, LW, Wcap;
+  int lanes;  // lanes per column in the walk (0 = built-in choice)
   uint64_t* table;
   int64_t* killer;
   uint64_t* lowc;
   uint64_t* touch;
+  int64_t* act[2];  // active lists, Wcap entries each
   Ring ring;
   RedCtl* ctl;
 };
 hipError_t launch_reduce_init(const RedArgs& a, hipStream_t s);
-hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s);
+// One round: walk, decide, commit, advance.  When `ev_walk` is non-null its
+// two events are recorded around the walk kernel.
+hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_walk);
 hipError_t launch_reduce_finish(const RedArgs& a, hipStream_t s);
 
 // Step 3 (dense grades) over the first E_eff sorted keys.

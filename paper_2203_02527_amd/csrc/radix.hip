@@ -1,19 +1,18 @@
 // radix.hip -- step 2 of the GPU pipeline (Section 4, step 2: sort the edges):
-// one stable least-significant-digit radix pass over 64-bit keys.
+// stable least-significant-digit radix passes over 64-bit keys.
 //
-// A pass reads every key once and writes it once.  Global digit counts come
-// precomputed (from the distance kernel), so each workgroup only needs the
-// counts of the tiles before it: tiles take their index from an atomic
-// ticket, publish their own digit counts, and look back over earlier tiles'
-// published counts (decoupled look-back).  A tile waits only on tiles with
-// smaller tickets, which have already started, so every wait ends.
-//
-// Inside a tile (4 waves x 16 rounds x 64 lanes = 4096 keys) each wave owns a
-// contiguous quarter; a key's rank among equal digits comes from wave ballots
-// on the digit bits, so the order of equal digits is preserved (stability is
-// what turns sorting on the distance bits into the (delta, j, i) order).  The
-// tile is reordered by digit in LDS before it is written, so that each digit's
-// run leaves as consecutive addresses.
+// Each pass is reduce-then-scan, with no workgroup ever waiting on another:
+//   count   -- every 4096-key tile counts its digits;
+//   scan    -- one exclusive scan over the counts laid out digit-major
+//              (all tiles' counts of digit 0, then digit 1, ...) gives every
+//              (digit, tile) its first output position;
+//   scatter -- every tile ranks its keys among equal digits and writes them.
+// Inside a tile (4 waves x 16 rounds x 64 lanes) each wave owns a contiguous
+// quarter; a key's rank among equal digits comes from wave ballots on the
+// digit bits, so equal digits keep their order.  That stability is what turns
+// sorting on the distance bits alone into the (delta, j, i) order.  The tile
+// is reordered by digit in LDS before it is written, so each digit's run
+// leaves as consecutive addresses.
 #include "ph0_internal.h"
 
 namespace ph0 {
@@ -24,16 +23,7 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kRounds = 16;
 constexpr int kTileKeys = kThreads * kRounds;  // 4096
-
-constexpr uint64_t kFlagShift = 54;  // descriptor: epoch (8b) | state (2b) | value (54b)
-constexpr uint64_t kValueMask = (1ull << kFlagShift) - 1;
-constexpr uint64_t kAggregate = 1;
-constexpr uint64_t kInclusive = 2;
-constexpr int64_t kSpinLimit = 1ll << 26;
-
-__device__ inline uint64_t desc_make(uint32_t epoch, uint64_t state, uint64_t value) {
-  return ((uint64_t)(epoch & 0xFF) << 56) | (state << kFlagShift) | value;
-}
+constexpr int kScanBlock = 4096;                // counts scanned per block
 
 // Exclusive scan of one value per thread over a 256-thread block.
 __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* >= 4 */) {
@@ -41,7 +31,7 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* >= 4 *
   uint32_t x = v;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = __shfl_up(x, o, 64);
+    const uint32_t y = __shfl_up(x, o, 64);
     if (lane >= o) x += y;
   }
   if (lane == 63) scratch[wave] = x;
@@ -52,35 +42,22 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* >= 4 *
   return base + x - v;
 }
 
-__global__ __launch_bounds__(kThreads) void k_radix_pass(
-    const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int64_t count, int shift,
-    int bits, const uint32_t* __restrict__ ghist, uint64_t* desc, uint32_t* ticket,
-    int32_t* err, uint32_t epoch) {
-  __shared__ uint32_t s_ticket;
-  __shared__ uint32_t wcnt[kWaves][256];
-  __shared__ uint32_t tile_start[256];  // first LDS slot of each digit in the tile
-  __shared__ uint64_t gbase[256];       // global position of the digit's first key here
-  __shared__ uint32_t scan_tmp[kWaves];
-  __shared__ uint64_t skeys[kTileKeys];
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const uint32_t nbins = 1u << bits, dmask = nbins - 1u;
-  if (tid == 0) s_ticket = atomicAdd(ticket, 1u);
-  for (int b = tid; b < 256; b += kThreads)
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) wcnt[w][b] = 0;
-  __syncthreads();
-  const int64_t tile = s_ticket;
-  const int64_t base = tile * kTileKeys + (int64_t)wave * 64 * kRounds;
-
-  uint64_t key[kRounds];
-  uint32_t rank[kRounds];
+// Load this wave's 16 x 64 keys of the tile and rank each among equal
+// digits inside the wave (running counts per wave in wcnt).
+__device__ inline void load_and_rank(const uint64_t* __restrict__ in, int64_t count, int64_t base,
+                                     int shift, int bits, uint32_t dmask, uint64_t (&key)[kRounds],
+                                     uint32_t (&rank)[kRounds], uint32_t* wcnt_wave) {
+  const int lane = threadIdx.x & 63;
   const uint64_t lt_mask = (1ull << lane) - 1ull;
 #pragma unroll
   for (int k = 0; k < kRounds; ++k) {
     const int64_t idx = base + k * 64 + lane;
     const bool valid = idx < count;
     key[k] = valid ? in[idx] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kRounds; ++k) {
+    const bool valid = base + k * 64 + lane < count;
     const uint32_t dg = (uint32_t)(key[k] >> shift) & dmask;
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < bits; ++b) {
@@ -90,20 +67,120 @@ __global__ __launch_bounds__(kThreads) void k_radix_pass(
     uint32_t before = 0, cnt = 0;
     if (valid) {
       before = __popcll(peers & lt_mask);
-      cnt = wcnt[wave][dg];
+      cnt = wcnt_wave[dg];
     }
     rank[k] = cnt + before;
-    // All lanes have read the running count; the first lane of each digit
-    // group advances it (LDS operations of one wave complete in order).
+    // Every lane has read the running count before the first lane of each
+    // digit group advances it (LDS operations of one wave complete in order).
     __builtin_amdgcn_wave_barrier();
-    if (valid && before == 0) wcnt[wave][dg] = cnt + (uint32_t)__popcll(peers);
+    if (valid && before == 0) wcnt_wave[dg] = cnt + (uint32_t)__popcll(peers);
     __builtin_amdgcn_wave_barrier();
   }
+}
+
+__global__ __launch_bounds__(kThreads) void k_radix_count(const uint64_t* __restrict__ in,
+                                                          int64_t count, int shift, int bits,
+                                                          int64_t ntiles,
+                                                          uint32_t* __restrict__ counts) {
+  __shared__ uint32_t wcnt[kWaves][256];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const uint32_t nbins = 1u << bits, dmask = nbins - 1u;
+  for (int b = tid; b < 256; b += kThreads)
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) wcnt[w][b] = 0;
+  __syncthreads();
+  const int64_t tile = blockIdx.x;
+  const int64_t base = tile * kTileKeys + (int64_t)wave * 64 * kRounds;
+  uint64_t key[kRounds];
+  uint32_t rank[kRounds];
+  load_and_rank(in, count, base, shift, bits, dmask, key, rank, wcnt[wave]);
+  __syncthreads();
+  if ((uint32_t)tid < nbins) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) c += wcnt[w][tid];
+    counts[(int64_t)tid * ntiles + tile] = c;
+  }
+}
+
+// Exclusive scan of `len` counts: per-block totals, a scan of the totals,
+// then each block scans its part with its offset.
+__global__ __launch_bounds__(kThreads) void k_scan_totals(const uint32_t* __restrict__ v,
+                                                          int64_t len,
+                                                          uint32_t* __restrict__ totals) {
+  __shared__ uint32_t tmp[4];
+  const int64_t b0 = blockIdx.x * (int64_t)kScanBlock;
+  uint32_t s = 0;
+  for (int k = threadIdx.x; k < kScanBlock; k += kThreads)
+    if (b0 + k < len) s += v[b0 + k];
+  const uint32_t ex = block_exclusive_scan(s, tmp);
+  if (threadIdx.x == kThreads - 1) totals[blockIdx.x] = ex + s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_top(uint32_t* totals, int64_t nblocks) {
+  __shared__ uint32_t tmp[4];
+  __shared__ uint32_t last;
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nblocks; b0 += kThreads) {
+    const int64_t b = b0 + threadIdx.x;
+    const uint32_t x = b < nblocks ? totals[b] : 0;
+    const uint32_t ex = block_exclusive_scan(x, tmp);
+    if (threadIdx.x == kThreads - 1) last = ex + x;
+    __syncthreads();
+    if (b < nblocks) totals[b] = carry + ex;
+    carry += last;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_apply(uint32_t* __restrict__ v, int64_t len,
+                                                         const uint32_t* __restrict__ totals) {
+  __shared__ uint32_t tmp[4];
+  constexpr int kPer = kScanBlock / kThreads;  // 16 consecutive counts per thread
+  const int64_t p0 = blockIdx.x * (int64_t)kScanBlock + threadIdx.x * kPer;
+  uint32_t x[kPer];
+  uint32_t s = 0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    x[q] = p0 + q < len ? v[p0 + q] : 0;
+    s += x[q];
+  }
+  uint32_t run = totals[blockIdx.x] + block_exclusive_scan(s, tmp);
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    if (p0 + q < len) v[p0 + q] = run;
+    run += x[q];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint64_t* __restrict__ in,
+                                                            uint64_t* __restrict__ out,
+                                                            int64_t count, int shift, int bits,
+                                                            int64_t ntiles,
+                                                            const uint32_t* __restrict__ offsets,
+                                                            int32_t* err) {
+  __shared__ uint32_t wcnt[kWaves][256];
+  __shared__ uint32_t tile_start[256];  // first LDS slot of each digit in the tile
+  __shared__ uint32_t gbase[256];       // output position of the digit's first key here
+  __shared__ uint32_t scan_tmp[kWaves];
+  __shared__ uint64_t skeys[kTileKeys];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t nbins = 1u << bits, dmask = nbins - 1u;
+  for (int b = tid; b < 256; b += kThreads)
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) wcnt[w][b] = 0;
+  __syncthreads();
+  const int64_t tile = blockIdx.x;
+  const int64_t base = tile * kTileKeys + (int64_t)wave * 64 * kRounds;
+  uint64_t key[kRounds];
+  uint32_t rank[kRounds];
+  load_and_rank(in, count, base, shift, bits, dmask, key, rank, wcnt[wave]);
   __syncthreads();
 
-  // Per digit: prefix over waves, the tile total, and its start in the tile.
+  // Per digit: prefix over waves, the tile total, its start in the tile.
   uint32_t total = 0;
-  if (tid < 256) {
+  {
     uint32_t run = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) {
@@ -114,50 +191,13 @@ __global__ __launch_bounds__(kThreads) void k_radix_pass(
     total = (uint32_t)tid < nbins ? run : 0;
   }
   const uint32_t start = block_exclusive_scan(total, scan_tmp);
-  const uint32_t gh = (uint32_t)tid < nbins ? ghist[tid] : 0;
-  const uint32_t gexcl = block_exclusive_scan(gh, scan_tmp);
-  if (tid < 256) tile_start[tid] = start;
-
-  // Decoupled look-back: thread `tid` owns digit `tid`.
-  if ((uint32_t)tid < nbins) {
-    uint64_t* mine = desc + tile * 256 + tid;
-    uint64_t prefix = 0;
-    if (tile == 0) {
-      __hip_atomic_store(mine, desc_make(epoch, kInclusive, total), __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      __hip_atomic_store(mine, desc_make(epoch, kAggregate, total), __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
-      int64_t t = tile - 1;
-      int64_t spins = 0;
-      while (t >= 0) {
-        const uint64_t v = __hip_atomic_load(desc + t * 256 + tid, __ATOMIC_ACQUIRE,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t state = (v >> kFlagShift) & 3u;
-        if ((uint32_t)(v >> 56) != (epoch & 0xFF) || state == 0) {
-          if (++spins > kSpinLimit) {
-            atomicOr(err, 1);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        prefix += v & kValueMask;
-        if (state == kInclusive) break;
-        --t;
-      }
-      __hip_atomic_store(mine, desc_make(epoch, kInclusive, prefix + total), __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    }
-    gbase[tid] = (uint64_t)gexcl + prefix;
-  }
+  tile_start[tid] = start;
+  gbase[tid] = (uint32_t)tid < nbins ? offsets[(int64_t)tid * ntiles + tile] : 0;
   __syncthreads();
 
-  // Reorder the tile by digit in LDS.
 #pragma unroll
   for (int k = 0; k < kRounds; ++k) {
-    const int64_t idx = base + k * 64 + lane;
-    if (idx < count) {
+    if (base + k * 64 + lane < count) {
       const uint32_t dg = (uint32_t)(key[k] >> shift) & dmask;
       skeys[tile_start[dg] + wcnt[wave][dg] + rank[k]] = key[k];
     }
@@ -169,11 +209,11 @@ __global__ __launch_bounds__(kThreads) void k_radix_pass(
   for (int pos = tid; pos < valid_n; pos += kThreads) {
     const uint64_t k = skeys[pos];
     const uint32_t dg = (uint32_t)(k >> shift) & dmask;
-    const uint64_t dst = gbase[dg] + (uint64_t)(pos - tile_start[dg]);
+    const uint64_t dst = (uint64_t)gbase[dg] + (uint64_t)(pos - tile_start[dg]);
     if (dst < (uint64_t)count)
       out[dst] = k;
     else
-      oob = true;  // inconsistent digit counts: report, never write outside
+      oob = true;  // inconsistent counts: report, never write outside
   }
   if (oob) atomicOr(err, 2);
 }
@@ -182,13 +222,27 @@ __global__ __launch_bounds__(kThreads) void k_radix_pass(
 
 int64_t radix_tiles(int64_t count) { return (count + kTileKeys - 1) / kTileKeys; }
 
+int64_t radix_count_entries(int64_t count) {
+  const int64_t len = 256 * radix_tiles(count);
+  return len + (len + kScanBlock - 1) / kScanBlock + 1;
+}
+
 hipError_t launch_radix_pass(const uint64_t* in, uint64_t* out, int64_t count, int shift,
-                             int bits, const uint32_t* hist_pass, uint64_t* desc,
-                             uint32_t* ticket, int32_t* err, uint32_t epoch, hipStream_t s) {
+                             int bits, uint32_t* counts, int32_t* err, hipStream_t s) {
   const int64_t tiles = radix_tiles(count);
   if (tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_radix_pass, dim3((unsigned)tiles), dim3(kThreads), 0, s, in, out, count,
-                     shift, bits, hist_pass, desc, ticket, err, epoch);
+  const int64_t len = (int64_t)(1 << bits) * tiles;
+  const int64_t nblocks = (len + kScanBlock - 1) / kScanBlock;
+  uint32_t* totals = counts + 256 * tiles;
+  hipLaunchKernelGGL(k_radix_count, dim3((unsigned)tiles), dim3(kThreads), 0, s, in, count,
+                     shift, bits, tiles, counts);
+  hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)nblocks), dim3(kThreads), 0, s, counts, len,
+                     totals);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, s, totals, nblocks);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblocks), dim3(kThreads), 0, s, counts, len,
+                     totals);
+  hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)tiles), dim3(kThreads), 0, s, in, out,
+                     count, shift, bits, tiles, counts, err);
   return hipGetLastError();
 }
 

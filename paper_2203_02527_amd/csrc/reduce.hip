@@ -8,12 +8,15 @@
 // reads words 0 .. r/64 only.  Bit r of row r doubles as the "slot r is
 // taken" flag (the table starts zeroed).
 //
-// One column, one lane group.  A group of G lanes (G = 64 for N > 2048)
-// holds the current column as a dense register bitset, WPL words per lane.
-// Each step loads the stored column of the current low, XORs it in, and
-// finds the new low: per-lane highest set bit, a ballot over the group, and
-// a shuffle from the highest nonzero lane.  Over F2 every column met on the
-// way has exactly two nonzero rows, which the kernel checks.
+// One column, one lane group.  A group of G lanes holds the current column
+// as a dense register bitset, WPL words per lane (G * WPL >= LW); a wave
+// reduces 64/G columns side by side.  Each step XORs the stored column of the
+// current low into the register column and finds the new low: per-lane
+// highest set bit, a ballot over the group, and a lane read from the highest
+// nonzero lane.  The step is speculative: an untaken slot's row is all zero,
+// so "the low did not move" is how a free slot is recognised, and no separate
+// presence check sits on the dependent chain.  Over F2 every column met on
+// the way has exactly two nonzero rows, which the kernel checks.
 //
 // Rounds.  A window of consecutive sorted columns [F, Wend) is reduced side
 // by side against the table as committed so far (every slot there belongs to
@@ -23,9 +26,9 @@
 //   * survivors before the first survivor whose low repeats an earlier
 //     survivor's low commit (none of them would have met another's slot);
 //   * a later survivor also commits if no earlier survivor touches the
-//     component of its low r, i.e. neither low nor the root of its other row
-//     equals r: then no earlier column can take slot r first, and its walk
-//     is final;
+//     component of its low r -- no earlier survivor has low r, and none has
+//     r as the root of its other row: then no earlier column can take slot r
+//     first, and its walk is final;
 //   * every other survivor stays and continues next round against the
 //     grown table.
 // The result -- every stored column, every pivot, the number of additions
@@ -44,29 +47,47 @@ __device__ inline uint64_t enc(int64_t round, int64_t p) {
   return ((uint64_t)(0xFFFFFF - (round & 0xFFFFFF)) << 40) | (uint64_t)p;
 }
 
+// Column layout inside a group of G lanes: word w lives in lane w % G, slot
+// w / G, so one load instruction covers G consecutive words of a row.
+
+__device__ inline uint64_t readlane64(uint64_t v, int lane) {
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, lane);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t shfl64_down(uint64_t v, int delta) {
+  const uint32_t lo = __shfl_down((uint32_t)v, delta, 64);
+  const uint32_t hi = __shfl_down((uint32_t)(v >> 32), delta, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ inline uint64_t shfl64(uint64_t v, int src) {
   const uint32_t lo = __shfl((uint32_t)v, src, 64);
   const uint32_t hi = __shfl((uint32_t)(v >> 32), src, 64);
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Largest value of `hb` (>= 0 means present) across the lanes of a group.
-template <int G>
-__device__ inline int group_max_index(int hb, int gbase) {
-  uint64_t m = __ballot(hb >= 0);
-  if constexpr (G < 64) m = (m >> gbase) & ((1ull << G) - 1ull);
-  if (m == 0) return -1;
-  const int top = 63 - __clzll(m);
-  return __shfl(hb, gbase + top, 64);
-}
-
-template <int WPL>
-__device__ inline int lane_highest(const uint64_t (&w)[WPL], int gl) {
-  int hb = -1;
+// Highest set bit of the group's column, looking only at slots <= qmax
+// (words above are known to be zero), or -1 for the zero column.
+template <int G, int WPL>
+__device__ inline int group_top_bit(const uint64_t (&w)[WPL], int gbase, int qmax) {
 #pragma unroll
-  for (int k = WPL - 1; k >= 0; --k)
-    if (hb < 0 && w[k] != 0) hb = (gl * WPL + k) * 64 + 63 - __clzll(w[k]);
-  return hb;
+  for (int q = WPL - 1; q >= 0; --q) {
+    if (q > qmax) continue;
+    uint64_t m = __ballot(w[q] != 0);
+    if constexpr (G < 64) m = (m >> gbase) & ((1ull << G) - 1ull);
+    if (m) {
+      const int top = 63 - __clzll(m);
+      uint64_t word;
+      if constexpr (G == 64)
+        word = readlane64(w[q], top);
+      else
+        word = shfl64(w[q], gbase + top);
+      return (q * G + top) * 64 + 63 - __clzll(word);
+    }
+  }
+  return -1;
 }
 
 template <int G>
@@ -76,38 +97,76 @@ __device__ inline bool group_any(bool v, int gbase) {
   return m != 0;
 }
 
-// Load words 0..r/64 of stored column r into the group's registers; return
-// whether slot r is taken (bit r set).
 template <int G, int WPL>
-__device__ inline bool load_row(const uint64_t* __restrict__ table, int64_t LW, int r, int gl,
-                                int gbase, uint64_t (&row)[WPL]) {
-  const int top = r >> 6;
-  const uint64_t* rp = table + (int64_t)r * LW;
-  uint64_t mine = 0;
+__device__ inline void flip_bit(uint64_t (&w)[WPL], int gl, int bit) {
+  const int word = bit >> 6;
+  if (gl == word % G) {
 #pragma unroll
-  for (int k = 0; k < WPL; ++k) {
-    const int widx = gl * WPL + k;
-    row[k] = widx <= top ? rp[widx] : 0ull;
-    if (widx == top) mine = row[k];
+    for (int q = 0; q < WPL; ++q)
+      if (q == word / G) w[q] ^= 1ull << (bit & 63);
   }
-  const uint64_t topword = shfl64(mine, gbase + top / WPL);
-  return (topword >> (r & 63)) & 1ull;
 }
 
-template <int WPL>
+template <int G, int WPL>
 __device__ inline void clear_bit(uint64_t (&w)[WPL], int gl, int bit) {
+  const int word = bit >> 6;
+  if (gl == word % G) {
 #pragma unroll
-  for (int k = 0; k < WPL; ++k)
-    if (gl * WPL + k == (bit >> 6)) w[k] &= ~(1ull << (bit & 63));
+    for (int q = 0; q < WPL; ++q)
+      if (q == word / G) w[q] &= ~(1ull << (bit & 63));
+  }
+}
+
+// XOR words 0..(r >> 6) of stored column r into w (the rest are zero).
+template <int G, int WPL>
+__device__ inline void xor_row(uint64_t (&w)[WPL], const uint64_t* __restrict__ table,
+                               int64_t LW, int r, int gl) {
+  const int top = r >> 6;
+  const uint64_t* rp = table + (int64_t)r * LW;
+#pragma unroll
+  for (int q = 0; q < WPL; ++q) {
+    const int widx = q * G + gl;
+    if (widx <= top) w[q] ^= rp[widx];
+  }
+}
+
+__device__ inline uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t w = shfl64_down(v, o);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+
+__device__ inline int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += (int64_t)shfl64_down((uint64_t)v, o);
+  return v;
+}
+
+// atomicMin that first looks at the current value: rows that many survivors
+// share would otherwise serialize on one address.  A stale read only costs
+// an unneeded atomic.
+__device__ inline void filtered_min(uint64_t* addr, uint64_t v) {
+  if (*(volatile uint64_t*)addr > v)
+    atomicMin((unsigned long long*)addr, (unsigned long long)v);
+}
+
+__device__ inline int64_t item_column(const RedCtl* ctl, const int64_t* act, int64_t t) {
+  return t < ctl->nA ? act[t] : ctl->fresh_lo + (t - ctl->nA);
 }
 
 template <int G, int WPL>
 __global__ __launch_bounds__(256) void k_walk(const uint64_t* __restrict__ skeys, int ib,
                                               int64_t LW, const uint64_t* __restrict__ table,
-                                              Ring ring, int64_t Wcap, uint64_t* lowc,
+                                              Ring ring, int64_t Wcap, const int64_t* act0,
+                                              const int64_t* act1, uint64_t* lowc,
                                               uint64_t* touch, RedCtl* ctl) {
   if (ctl->done) return;
-  const int64_t F = ctl->F, Wend = ctl->Wend, round = ctl->round;
+  const int64_t nA = ctl->nA, round = ctl->round;
+  const int64_t items = nA + (ctl->fresh_hi - ctl->fresh_lo);
+  const int64_t* act = ctl->cur ? act1 : act0;
   const int lane = threadIdx.x & 63;
   const int gl = lane & (G - 1);
   const int gbase = lane & ~(G - 1);
@@ -118,44 +177,42 @@ __global__ __launch_bounds__(256) void k_walk(const uint64_t* __restrict__ skeys
 
   int64_t adds = 0, finds = 0, words = 0;
   int32_t bad = 0;
-  for (int64_t p = F + gid; p < Wend; p += gtotal) {
-    const int64_t k = p % Wcap;
-    int32_t a, r, rlo, st;
-    if (ring.tag[k] != p) {
+  for (int64_t t = gid; t < items; t += gtotal) {
+    int64_t p;
+    int32_t a, r, rlo, prev_steps;
+    if (t < nA) {
+      p = act[t];
+      const int64_t k = p & (Wcap - 1);
+      a = ring.a[k];
+      r = ring.r[k];
+      rlo = ring.rlo[k];
+      prev_steps = ring.st[k] >> 2;
+    } else {
+      p = ctl->fresh_lo + (t - nA);
       const uint64_t key = skeys[p];
       a = (int32_t)(key & imask);
       r = (int32_t)((key >> ib) & imask);
       rlo = a;
-      st = kActive;
-    } else {
-      st = ring.st[k];
-      if ((st & 3) != kActive) continue;
-      a = ring.a[k];
-      r = ring.r[k];
-      rlo = ring.rlo[k];
+      prev_steps = 0;
     }
     uint64_t col[WPL];
 #pragma unroll
-    for (int q = 0; q < WPL; ++q) {
-      const int widx = gl * WPL + q;
-      col[q] = (widx == (a >> 6) ? 1ull << (a & 63) : 0ull) ^
-               (widx == (r >> 6) ? 1ull << (r & 63) : 0ull);
-    }
+    for (int q = 0; q < WPL; ++q) col[q] = 0;
+    flip_bit<G, WPL>(col, gl, a);
+    flip_bit<G, WPL>(col, gl, r);
     int moved = 0;
     bool zero = false;
     while (true) {
-      uint64_t row[WPL];
+      xor_row<G, WPL>(col, table, LW, r, gl);
       words += (r >> 6) + 1;
-      if (!load_row<G, WPL>(table, LW, r, gl, gbase, row)) break;
-#pragma unroll
-      for (int q = 0; q < WPL; ++q) col[q] ^= row[q];
+      const int nr = group_top_bit<G, WPL>(col, gbase, (r >> 6) / G);
+      if (nr == r) break;  // row r is empty: slot r is free
       ++moved;
-      const int nr = group_max_index<G>(lane_highest<WPL>(col, gl), gbase);
       if (nr < 0) {
         zero = true;
         break;
       }
-      if (nr >= r) {  // lows must strictly decrease; a corrupt table ends the walk
+      if (nr > r) {  // lows must decrease; a corrupt table ends the walk
         bad = 1;
         zero = true;
         break;
@@ -167,24 +224,27 @@ __global__ __launch_bounds__(256) void k_walk(const uint64_t* __restrict__ skeys
     if (zero) {
       status = kZero;
     } else {
-      clear_bit<WPL>(col, gl, r);
-      const int na = group_max_index<G>(lane_highest<WPL>(col, gl), gbase);
-      if (na >= 0) clear_bit<WPL>(col, gl, na);
+      flip_bit<G, WPL>(col, gl, r);
+      const int na = group_top_bit<G, WPL>(col, gbase, (r >> 6) / G);
+      if (na >= 0) flip_bit<G, WPL>(col, gl, na);
       bool rest = false;
 #pragma unroll
       for (int q = 0; q < WPL; ++q) rest |= col[q] != 0;
       if (na < 0 || group_any<G>(rest, gbase)) bad = 1;
       a = na < 0 ? 0 : na;
-      // Root of row a in the current forest: follow stored columns down.
+      // Root of row a in the current forest: follow stored columns down
+      // (col is all zero here and serves as the row buffer).
       int v = moved ? a : rlo;
       while (true) {
-        uint64_t row[WPL];
+#pragma unroll
+        for (int q = 0; q < WPL; ++q) col[q] = 0;
+        xor_row<G, WPL>(col, table, LW, v, gl);
         words += (v >> 6) + 1;
-        if (!load_row<G, WPL>(table, LW, v, gl, gbase, row)) break;
-        clear_bit<WPL>(row, gl, v);
-        const int c = group_max_index<G>(lane_highest<WPL>(row, gl), gbase);
+        clear_bit<G, WPL>(col, gl, v);
+        const int c = group_top_bit<G, WPL>(col, gbase, (v >> 6) / G);
+        if (c < 0) break;  // empty row: v is a root
         ++finds;
-        if (c < 0 || c >= v) {  // a stored column needs a second, smaller row
+        if (c >= v) {  // a stored column needs a second, smaller row
           bad = 1;
           break;
         }
@@ -193,81 +253,131 @@ __global__ __launch_bounds__(256) void k_walk(const uint64_t* __restrict__ skeys
       rlo = v;
       if (gl == 0) {
         const uint64_t e = enc(round, p);
-        atomicMin((unsigned long long*)&lowc[r], (unsigned long long)e);
-        atomicMin((unsigned long long*)&touch[r], (unsigned long long)e);
-        atomicMin((unsigned long long*)&touch[rlo], (unsigned long long)e);
+        filtered_min(&lowc[r], e);
+        filtered_min(&touch[rlo], e);
       }
     }
     if (gl == 0) {
-      const int32_t steps = (ring.tag[k] == p ? (st >> 2) : 0) + moved;
+      const int64_t k = p & (Wcap - 1);
       ring.a[k] = a;
       ring.r[k] = r;
       ring.rlo[k] = rlo;
-      ring.st[k] = status | (steps << 2);
+      ring.st[k] = status | ((prev_steps + moved) << 2);
       ring.tag[k] = p;
     }
   }
-  // One atomic per group leader with work.
-  if (gl == 0 && (adds | finds | words)) {
-    atomicAdd((unsigned long long*)&ctl->additions_all, (unsigned long long)adds);
-    atomicAdd((unsigned long long*)&ctl->find_steps, (unsigned long long)finds);
-    atomicAdd((unsigned long long*)&ctl->words_read, (unsigned long long)words);
+  // Counters: group leaders -> block totals in LDS -> one atomic per block.
+  __shared__ unsigned long long s_cnt[3];
+  __shared__ int s_bad;
+  if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  if (gl == 0) {
+    if (adds) atomicAdd(&s_cnt[0], (unsigned long long)adds);
+    if (finds) atomicAdd(&s_cnt[1], (unsigned long long)finds);
+    if (words) atomicAdd(&s_cnt[2], (unsigned long long)words);
+    if (bad) s_bad = 1;
   }
-  if (gl == 0 && bad) atomicOr(&ctl->err, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_cnt[0]) atomicAdd((unsigned long long*)&ctl->additions_all, s_cnt[0]);
+    if (s_cnt[1]) atomicAdd((unsigned long long*)&ctl->find_steps, s_cnt[1]);
+    if (s_cnt[2]) atomicAdd((unsigned long long*)&ctl->words_read, s_cnt[2]);
+    if (s_bad) atomicOr(&ctl->err, 1);
+  }
 }
 
-__global__ __launch_bounds__(256) void k_decide(Ring ring, int64_t Wcap, const uint64_t* lowc,
+__global__ __launch_bounds__(256) void k_decide(Ring ring, int64_t Wcap, const int64_t* act0,
+                                                const int64_t* act1, const uint64_t* lowc,
                                                 RedCtl* ctl) {
   if (ctl->done) return;
-  const int64_t F = ctl->F, Wend = ctl->Wend, round = ctl->round;
+  const int64_t round = ctl->round;
+  const int64_t items = ctl->nA + (ctl->fresh_hi - ctl->fresh_lo);
+  const int64_t* act = ctl->cur ? act1 : act0;
   uint64_t best = kNoValue;
-  for (int64_t p = F + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < Wend;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t k = p % Wcap;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < items;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = item_column(ctl, act, t);
+    const int64_t k = p & (Wcap - 1);
     if ((ring.st[k] & 3) != kActive) continue;
     if (lowc[ring.r[k]] != enc(round, p) && (uint64_t)p < best) best = (uint64_t)p;
   }
-  if (best != kNoValue)
+  best = wave_min_u64(best);
+  if ((threadIdx.x & 63) == 0 && best != kNoValue)
     atomicMin((unsigned long long*)&ctl->firstdup[round & 1], (unsigned long long)best);
 }
 
-__global__ __launch_bounds__(256) void k_commit(Ring ring, int64_t Wcap, const uint64_t* touch,
+__global__ __launch_bounds__(256) void k_commit(Ring ring, int64_t Wcap, int64_t* act0,
+                                                int64_t* act1, const uint64_t* lowc,
+                                                const uint64_t* touch,
                                                 uint64_t* table, int64_t LW, int64_t* killer,
                                                 RedCtl* ctl) {
   if (ctl->done) return;
-  const int64_t F = ctl->F, Wend = ctl->Wend, round = ctl->round;
+  const int64_t round = ctl->round;
+  const int64_t items = ctl->nA + (ctl->fresh_hi - ctl->fresh_lo);
+  const int64_t* act = ctl->cur ? act1 : act0;
+  int64_t* next = ctl->cur ? act0 : act1;
   const uint64_t fd = ctl->firstdup[round & 1];
-  uint64_t stay = kNoValue;
+  const int lane = threadIdx.x & 63;
+  uint64_t stay_min = kNoValue;
   int64_t npiv = 0, last = -1;
-  for (int64_t p = F + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < Wend;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t k = p % Wcap;
-    const int32_t st = ring.st[k];
-    if ((st & 3) != kActive) continue;
-    const int32_t r = ring.r[k];
-    if ((uint64_t)p < fd || touch[r] == enc(round, p)) {
-      const int32_t a = ring.a[k];
-      uint64_t* row = table + (int64_t)r * LW;
-      if ((a >> 6) == (r >> 6)) {
-        row[r >> 6] = (1ull << (r & 63)) | (1ull << (a & 63));
-      } else {
-        row[a >> 6] = 1ull << (a & 63);
-        row[r >> 6] = 1ull << (r & 63);
+  // Every lane of a wave runs the same number of iterations, so the wave can
+  // append its staying columns with one atomic.
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t iters = (items + stride - 1 - (t0 - lane)) / stride;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t t = t0 + it * stride;
+    bool stay = false;
+    int64_t p = -1;
+    if (t < items) {
+      p = item_column(ctl, act, t);
+      const int64_t k = p & (Wcap - 1);
+      const int32_t st = ring.st[k];
+      if ((st & 3) == kActive) {
+        const int32_t r = ring.r[k];
+        const uint64_t e = enc(round, p);
+        if ((uint64_t)p < fd || (lowc[r] == e && touch[r] > e)) {
+          const int32_t a = ring.a[k];
+          uint64_t* row = table + (int64_t)r * LW;
+          if ((a >> 6) == (r >> 6)) {
+            row[r >> 6] = (1ull << (r & 63)) | (1ull << (a & 63));
+          } else {
+            row[a >> 6] = 1ull << (a & 63);
+            row[r >> 6] = 1ull << (r & 63);
+          }
+          killer[r] = p;
+          ring.st[k] = (st & ~3) | kCommitted;
+          ++npiv;
+          last = p > last ? p : last;
+        } else {
+          stay = true;
+          if ((uint64_t)p < stay_min) stay_min = (uint64_t)p;
+        }
       }
-      killer[r] = p;
-      ring.st[k] = (st & ~3) | kCommitted;
-      ++npiv;
-      last = p > last ? p : last;
-    } else if ((uint64_t)p < stay) {
-      stay = (uint64_t)p;
+    }
+    const uint64_t m = __ballot(stay);
+    if (m) {
+      int64_t base = 0;
+      if (lane == 0)
+        base = (int64_t)atomicAdd((unsigned long long*)&ctl->nA_next,
+                                  (unsigned long long)__popcll(m));
+      base = __shfl(base, 0, 64);
+      if (stay) next[base + __popcll(m & ((1ull << lane) - 1ull))] = p;
     }
   }
-  if (npiv) {
-    atomicAdd((unsigned long long*)&ctl->pivots, (unsigned long long)npiv);
-    atomicMax((long long*)&ctl->E_eff, (long long)(last + 1));
+  npiv = wave_sum_i64(npiv);
+  // max of (last + 1) as a min of its complement
+  const uint64_t last_c = wave_min_u64(~(uint64_t)(last + 1));
+  stay_min = wave_min_u64(stay_min);
+  if (lane == 0) {
+    if (npiv) {
+      atomicAdd((unsigned long long*)&ctl->pivots, (unsigned long long)npiv);
+      atomicMax((long long*)&ctl->E_eff, (long long)~last_c);
+    }
+    if (stay_min != kNoValue)
+      atomicMin((unsigned long long*)&ctl->newF[round & 1], (unsigned long long)stay_min);
   }
-  if (stay != kNoValue)
-    atomicMin((unsigned long long*)&ctl->newF[round & 1], (unsigned long long)stay);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl->firstdup[(round + 1) & 1] = kNoValue;
     ctl->newF[(round + 1) & 1] = kNoValue;
@@ -278,10 +388,11 @@ __global__ void k_advance(RedCtl* ctl, int64_t n, int64_t E, int64_t Wcap) {
   if (ctl->done) return;
   const int64_t round = ctl->round;
   const uint64_t nf = ctl->newF[round & 1];
-  int64_t F = nf == kNoValue ? ctl->Wend : (int64_t)nf;
-  int64_t Wend;
+  const int64_t F = nf == kNoValue ? ctl->Wend : (int64_t)nf;
+  int64_t Wend = ctl->Wend;
   if (ctl->pivots >= n - 1) {
-    Wend = ctl->Wend < ctl->E_eff ? ctl->Wend : ctl->E_eff;
+    // Every later column reduces to zero; only columns before the last
+    // pivot still need finishing (for the exact addition count).
     if (F >= ctl->E_eff) ctl->done = 1;
   } else {
     Wend = F + Wcap < E ? F + Wcap : E;
@@ -290,6 +401,11 @@ __global__ void k_advance(RedCtl* ctl, int64_t n, int64_t E, int64_t Wcap) {
       ctl->err |= 2;
     }
   }
+  ctl->fresh_lo = ctl->Wend;
+  ctl->fresh_hi = Wend;
+  ctl->nA = ctl->nA_next;
+  ctl->nA_next = 0;
+  ctl->cur ^= 1;
   ctl->F = F;
   ctl->Wend = Wend;
   if (Wend > ctl->maxWend) ctl->maxWend = Wend;
@@ -301,6 +417,8 @@ __global__ void k_reduce_init(RedCtl* ctl, int64_t E, int64_t Wcap, int64_t n) {
   c.F = 0;
   c.Wend = Wcap < E ? Wcap : E;
   c.maxWend = c.Wend;
+  c.fresh_lo = 0;
+  c.fresh_hi = c.Wend;
   c.firstdup[0] = c.firstdup[1] = kNoValue;
   c.newF[0] = c.newF[1] = kNoValue;
   c.done = (n <= 1 || E == 0) ? 1 : 0;
@@ -314,26 +432,70 @@ __global__ __launch_bounds__(256) void k_overshoot(Ring ring, int64_t Wcap, RedC
   int64_t s = 0;
   for (int64_t p = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < hi;
        p += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t k = p % Wcap;
+    const int64_t k = p & (Wcap - 1);
     if (ring.tag[k] == p) s += ring.st[k] >> 2;
   }
-  if (s) atomicAdd((unsigned long long*)&ctl->additions_overshoot, (unsigned long long)s);
+  s = wave_sum_i64(s);
+  if ((threadIdx.x & 63) == 0 && s)
+    atomicAdd((unsigned long long*)&ctl->additions_overshoot, (unsigned long long)s);
+}
+
+// Resident-sized grids: the walk keeps about 32 waves per CU busy and loops.
+int device_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+      cus = 256;
+    else
+      cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  }
+  return cus;
 }
 
 template <int G, int WPL>
 void walk_launch(const RedArgs& a, hipStream_t s) {
   const int64_t gpb = 256 / G;
   int64_t blocks = (a.Wcap + gpb - 1) / gpb;
-  if (blocks > 8192) blocks = 8192;
+  const int64_t cap = 8 * (int64_t)device_cus();
+  if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL((k_walk<G, WPL>), dim3((unsigned)blocks), dim3(256), 0, s, a.skeys, a.ib,
-                     a.LW, a.table, a.ring, a.Wcap, a.lowc, a.touch, a.ctl);
+                     a.LW, a.table, a.ring, a.Wcap, a.act[0], a.act[1], a.lowc, a.touch, a.ctl);
 }
 
 int scan_blocks(int64_t Wcap) {
   int64_t b = (Wcap + 255) / 256;
-  if (b > 2048) b = 2048;
+  const int64_t cap = 4 * (int64_t)device_cus();
+  if (b > cap) b = cap;
   return (int)(b < 1 ? 1 : b);
+}
+
+// Lanes per column: enough words per lane to cover a row, and at most
+// 64 lanes; `want` (a power of two) asks for fewer lanes and more words each.
+bool launch_walk_shape(const RedArgs& a, hipStream_t s) {
+  const int64_t LW = a.LW;
+  int G = 1;
+  while (G < 64 && G < LW) G <<= 1;
+  if (a.lanes > 0 && a.lanes < G) G = a.lanes;
+  const int64_t wpl = (LW + G - 1) / G;
+#define PH0_WALK(g, w)                      \
+  if (G == g && wpl <= w) {                 \
+    walk_launch<g, w>(a, s);                \
+    return true;                            \
+  }
+  PH0_WALK(1, 1) PH0_WALK(2, 1) PH0_WALK(4, 1) PH0_WALK(8, 1) PH0_WALK(16, 1)
+  PH0_WALK(32, 1) PH0_WALK(64, 1) PH0_WALK(64, 2) PH0_WALK(64, 4) PH0_WALK(64, 8)
+  PH0_WALK(64, 16) PH0_WALK(32, 2) PH0_WALK(32, 4) PH0_WALK(32, 8) PH0_WALK(32, 16)
+  PH0_WALK(16, 2) PH0_WALK(16, 4) PH0_WALK(16, 8) PH0_WALK(16, 16)
+#undef PH0_WALK
+  if (a.lanes > 0) {  // requested shape not built: use the default one
+    RedArgs d = a;
+    d.lanes = 0;
+    return launch_walk_shape(d, s);
+  }
+  return false;
 }
 
 }  // namespace
@@ -352,27 +514,17 @@ hipError_t launch_reduce_init(const RedArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s) {
-  // Lane-group shape: G lanes per column, WPL words per lane, G * WPL >= LW.
-  const int64_t LW = a.LW;
-  if (LW <= 1) walk_launch<1, 1>(a, s);
-  else if (LW <= 2) walk_launch<2, 1>(a, s);
-  else if (LW <= 4) walk_launch<4, 1>(a, s);
-  else if (LW <= 8) walk_launch<8, 1>(a, s);
-  else if (LW <= 16) walk_launch<16, 1>(a, s);
-  else if (LW <= 32) walk_launch<32, 1>(a, s);
-  else if (LW <= 64) walk_launch<64, 1>(a, s);
-  else if (LW <= 128) walk_launch<64, 2>(a, s);
-  else if (LW <= 256) walk_launch<64, 4>(a, s);
-  else if (LW <= 512) walk_launch<64, 8>(a, s);
-  else if (LW <= 1024) walk_launch<64, 16>(a, s);
-  else return hipErrorInvalidValue;
+hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_walk) {
+  if (ev_walk) hipEventRecord(ev_walk[0], s);
+  if (!launch_walk_shape(a, s)) return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (ev_walk) hipEventRecord(ev_walk[1], s);
   const int sb = scan_blocks(a.Wcap);
-  hipLaunchKernelGGL(k_decide, dim3(sb), dim3(256), 0, s, a.ring, a.Wcap, a.lowc, a.ctl);
-  hipLaunchKernelGGL(k_commit, dim3(sb), dim3(256), 0, s, a.ring, a.Wcap, a.touch, a.table,
-                     a.LW, a.killer, a.ctl);
+  hipLaunchKernelGGL(k_decide, dim3(sb), dim3(256), 0, s, a.ring, a.Wcap, a.act[0], a.act[1],
+                     a.lowc, a.ctl);
+  hipLaunchKernelGGL(k_commit, dim3(sb), dim3(256), 0, s, a.ring, a.Wcap, a.act[0], a.act[1],
+                     a.lowc, a.touch, a.table, a.LW, a.killer, a.ctl);
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, a.ctl, a.n, a.E, a.Wcap);
   return hipGetLastError();
 }
