@@ -135,6 +135,68 @@ int ph0_sorted_keys_device(const void* d_points, ph0_dtype dt, int64_t n, int32_
 int ph0_key_layout(int64_t n, int32_t d, ph0_dtype dt, int32_t* index_bits,
                    int32_t* delta_bits);
 
+/* ---- Many clouds in one launch ---------------------------------------- */
+
+/* Speed-only tuning of the batched path (never changes results).  A zero
+ * field takes the built-in value. */
+typedef struct {
+  int32_t chunk_mult[4];  /* first sorted chunk holds about chunk_mult * n edges,
+                             per cloud size bucket n <= 64, <= 128, <= 256, <= 512 */
+  int32_t blocks_per_cu;  /* workgroups launched per compute unit (1 or 2) */
+} ph0_batch_tuning;
+
+/* Device workspace for ph0_barcodes_batched_device on these clouds.
+ * offsets: host array of nclouds + 1 row offsets into the concatenated
+ * points (offsets[0] = 0, non-decreasing). */
+int ph0_batched_workspace_bytes(const int64_t* offsets, int64_t nclouds, int32_t d,
+                                ph0_dtype dt, const ph0_batch_tuning* tune, size_t* bytes);
+
+/* Barcodes of nclouds clouds in one persistent launch.  d_points holds the
+ * clouds' rows back to back (offsets[nclouds] x d, device); cloud c owns rows
+ * offsets[c] .. offsets[c+1]-1 and gets its canonical barcode in the same
+ * rows of d_out (offsets[nclouds] bars, device).  Each workgroup takes whole
+ * clouds from a work queue, largest first, with its pivot table in LDS.
+ * Clouds with n > 512 or n * d > 8192 run through the single-cloud path after
+ * the launch.  Results are identical to ph0_barcodes_device on each cloud.
+ * `tune` and `st` may be NULL. */
+int ph0_barcodes_batched_device(const void* d_points, ph0_dtype dt, const int64_t* offsets,
+                                int64_t nclouds, int32_t d, ph0_bar* d_out, void* d_workspace,
+                                size_t ws_bytes, const ph0_batch_tuning* tune,
+                                void* hip_stream, ph0_stats* st);
+
+/* ---- Serving: continuous batching of independent requests -------------- */
+
+/* A server owns one device memory pool of mem_budget_bytes and up to
+ * max_slots request slots, each a host worker thread with its own HIP stream.
+ * A request is admitted only when a slot is free and its device footprint
+ * (points + bars + ph0_workspace_bytes) fits in the pool, so admission is by
+ * memory; admitted requests run concurrently on their streams and overlap on
+ * the device.  Results are bit-identical to ph0_barcodes on the same cloud. */
+typedef struct ph0_server ph0_server;
+
+int ph0_server_create(size_t mem_budget_bytes, int32_t max_slots, ph0_server** srv);
+
+/* Device bytes a request of this shape reserves while it runs. */
+int ph0_server_request_bytes(int64_t n, int32_t d, ph0_dtype dt, size_t* bytes);
+
+/* Offer one cloud (host memory, copied before return).  Returns PH0_OK when
+ * admitted, PH0_EBUSY when no slot or not enough pool memory is free now
+ * (retry later), PH0_ENOMEM when it could never fit the pool, or EINVAL. */
+int ph0_server_submit(ph0_server* srv, const void* points, ph0_dtype dt, int64_t n, int32_t d,
+                      uint64_t tag);
+
+/* Non-blocking.  Returns 1 and fills tag / status / n_out (and up to out_cap
+ * bars of the canonical barcode into out) for one finished request, or 0 when
+ * none is finished.  status is the request's ph0_status. */
+int ph0_server_poll(ph0_server* srv, uint64_t* tag, int32_t* status, ph0_bar* out,
+                    int64_t out_cap, int64_t* n_out);
+
+/* Requests admitted and not yet polled. */
+int64_t ph0_server_in_flight(ph0_server* srv);
+
+/* Waits for running requests, then frees the server. */
+void ph0_server_destroy(ph0_server* srv);
+
 /* Reduction window (columns reduced side by side per round); 0 restores the
  * built-in choice.  Affects speed only, never results.  Process-wide. */
 int ph0_set_window(int64_t columns);

@@ -8,8 +8,15 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <cstring>
+
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 #include "../../include/ph0.h"
@@ -49,7 +56,7 @@ int index_bits(int64_t n) { return n <= 1 ? 0 : 64 - __builtin_clzll((uint64_t)(
 // state is a ring indexed by column & (window - 1)).
 int64_t window_for(int64_t n, int64_t E) {
   int64_t w = g_window.load();
-  if (w <= 0) w = std::max<int64_t>(65536, 64 * n);
+  if (w <= 0) w = std::max<int64_t>(65536, 16 * n);
   w = std::min<int64_t>(w, std::max<int64_t>(E, 1));
   int64_t p = 1;
   while (p < w) p <<= 1;
@@ -409,6 +416,77 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   return PH0_OK;
 }
 
+// ---- batched path ----
+
+struct BatchPlan {
+  int64_t nclouds = 0, emax = 0, big_n = 0, blocks = 0;
+  std::vector<int32_t> order;  // fused clouds, largest first
+  std::vector<int32_t> big;    // clouds for the single-cloud path
+  size_t offs = 0, ord = 0, errs = 0, queue = 0, scratch = 0, grades = 0, plain = 0,
+         plain_bytes = 0, total = 0;
+};
+
+int device_cu_count() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      cus = prop.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
+}
+
+int plan_batch(const int64_t* offsets, int64_t nclouds, int32_t d, ph0_dtype dt,
+               const ph0_batch_tuning* tune, BatchPlan* P) {
+  if (!offsets) return fail(PH0_EINVAL, "offsets pointer is NULL");
+  if (nclouds < 1) return fail(PH0_EINVAL, "nclouds must be >= 1");
+  if (d < 1) return fail(PH0_EINVAL, "d must be >= 1");
+  if (dt != PH0_I8 && dt != PH0_I16) return fail(PH0_EINVAL, "dtype must be PH0_I8 or PH0_I16");
+  if (offsets[0] != 0) return fail(PH0_EINVAL, "offsets[0] must be 0");
+  P->nclouds = nclouds;
+  std::vector<std::pair<int64_t, int32_t>> bysize;
+  for (int64_t c = 0; c < nclouds; ++c) {
+    const int64_t n = offsets[c + 1] - offsets[c];
+    if (n < 0) return fail(PH0_EINVAL, "offsets must be non-decreasing (cloud %lld)", (long long)c);
+    if (n > kMaxN) return fail(PH0_EINVAL, "cloud %lld has n > %lld", (long long)c, (long long)kMaxN);
+    if (n > kBatchMaxN || n * d > kBatchMaxPts || d > 64) {
+      P->big.push_back((int32_t)c);
+      P->big_n = std::max(P->big_n, n);
+    } else {
+      bysize.push_back({n, (int32_t)c});
+      P->emax = std::max(P->emax, n * (n - 1) / 2);
+    }
+  }
+  std::stable_sort(bysize.begin(), bysize.end(),
+                   [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
+                     return x.first > y.first;
+                   });
+  for (auto& e : bysize) P->order.push_back(e.second);
+  const int bpc = tune && tune->blocks_per_cu > 0 ? std::min(tune->blocks_per_cu, 2) : 1;
+  P->blocks = std::min<int64_t>((int64_t)device_cu_count() * bpc,
+                                std::max<int64_t>((int64_t)P->order.size(), 1));
+  if (P->big_n > 0) {
+    if (ph0_workspace_bytes(P->big_n, d, dt, &P->plain_bytes) != PH0_OK) return PH0_EINVAL;
+  }
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  P->offs = take(8 * (size_t)(nclouds + 1));
+  P->ord = take(4 * std::max<size_t>(P->order.size(), 1));
+  P->errs = take(4 * (size_t)nclouds);
+  P->queue = take(4);
+  P->scratch = take(16 * (size_t)std::max<int64_t>(P->emax, 1) * (size_t)P->blocks);
+  P->grades = take(4 * (size_t)std::max<int64_t>(P->emax, 1) * (size_t)P->blocks);
+  P->plain = take(P->plain_bytes);
+  P->total = o;
+  return PH0_OK;
+}
+
 struct DeviceBuffer {
   void* p = nullptr;
   ~DeviceBuffer() {
@@ -502,6 +580,88 @@ int ph0_sorted_keys_device(const void* d_points, ph0_dtype dt, int64_t n, int32_
              nullptr, kStopSorted);
 }
 
+int ph0_batched_workspace_bytes(const int64_t* offsets, int64_t nclouds, int32_t d,
+                                ph0_dtype dt, const ph0_batch_tuning* tune, size_t* bytes) {
+  if (!bytes) return fail(PH0_EINVAL, "bytes pointer is NULL");
+  BatchPlan P;
+  int rc = plan_batch(offsets, nclouds, d, dt, tune, &P);
+  if (rc) return rc;
+  *bytes = P.total;
+  return PH0_OK;
+}
+
+int ph0_barcodes_batched_device(const void* d_points, ph0_dtype dt, const int64_t* offsets,
+                                int64_t nclouds, int32_t d, ph0_bar* d_out, void* d_ws,
+                                size_t ws_bytes, const ph0_batch_tuning* tune,
+                                void* hip_stream, ph0_stats* st) {
+  if (!d_points) return fail(PH0_EINVAL, "points pointer is NULL");
+  if (!d_out) return fail(PH0_EINVAL, "output pointer is NULL");
+  if (!d_ws) return fail(PH0_EINVAL, "workspace pointer is NULL");
+  BatchPlan P;
+  int rc = plan_batch(offsets, nclouds, d, dt, tune, &P);
+  if (rc) return rc;
+  if (ws_bytes < P.total)
+    return fail(PH0_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, P.total);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  char* ws = static_cast<char*>(d_ws);
+  const int eb = dt == PH0_I8 ? 1 : 2;
+  Timer tm(st != nullptr, s);
+  tm.mark();
+  HIPCHK(hipMemcpyAsync(ws + P.offs, offsets, 8 * (size_t)(nclouds + 1), hipMemcpyHostToDevice, s));
+  if (!P.order.empty())
+    HIPCHK(hipMemcpyAsync(ws + P.ord, P.order.data(), 4 * P.order.size(), hipMemcpyHostToDevice,
+                          s));
+  HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t*>(ws + P.errs), 0u, nclouds, s));
+  HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t*>(ws + P.queue), 0u, 1, s));
+  if (!P.order.empty()) {
+    BatchArgs A;
+    A.pts = d_points;
+    A.elem_bytes = eb;
+    A.d = d;
+    A.offsets = reinterpret_cast<const int64_t*>(ws + P.offs);
+    A.order = reinterpret_cast<const int32_t*>(ws + P.ord);
+    A.nclouds = (int64_t)P.order.size();
+    A.bars = reinterpret_cast<uint32_t*>(d_out);
+    A.scratch = reinterpret_cast<uint64_t*>(ws + P.scratch);
+    A.grades = reinterpret_cast<uint32_t*>(ws + P.grades);
+    A.emax = std::max<int64_t>(P.emax, 1);
+    A.queue = reinterpret_cast<uint32_t*>(ws + P.queue);
+    A.errs = reinterpret_cast<int32_t*>(ws + P.errs);
+    // One chunk multiplier per launch: the size bucket of the largest cloud
+    // decides (clouds run largest first).
+    const int64_t n0 = offsets[P.order[0] + 1] - offsets[P.order[0]];
+    const int bucket = n0 <= 64 ? 0 : n0 <= 128 ? 1 : n0 <= 256 ? 2 : 3;
+    A.chunk_mult = tune && tune->chunk_mult[bucket] > 0 ? tune->chunk_mult[bucket] : 24;
+    HIPCHK(launch_batched(A, (int)P.blocks, s));
+  }
+  tm.mark();
+  for (int32_t c : P.big) {
+    const int64_t n = offsets[c + 1] - offsets[c];
+    Outputs o;
+    o.bars = d_out + offsets[c];
+    rc = run(static_cast<const char*>(d_points) + offsets[c] * d * eb, dt, n, d, o, ws + P.plain,
+             P.plain_bytes, s, nullptr, kStopAll);
+    if (rc) return rc;
+  }
+  tm.mark();
+  std::vector<int32_t> errs((size_t)nclouds);
+  HIPCHK(hipMemcpyAsync(errs.data(), ws + P.errs, 4 * (size_t)nclouds, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int64_t c = 0; c < nclouds; ++c)
+    if (errs[c])
+      return fail(errs[c] == 3 ? PH0_ERANGE : PH0_EDEVICE,
+                  "cloud %lld failed in the batched kernel (code %d)", (long long)c, errs[c]);
+  if (st) {
+    ph0_stats S = {};
+    S.n = offsets[nclouds];
+    S.ms_reduce = tm.ms(0, 1);
+    S.ms_emit = tm.ms(1, 2);
+    S.ms_total = tm.ms(0, 2);
+    *st = S;
+  }
+  return PH0_OK;
+}
+
 int ph0_barcodes(const void* points, ph0_dtype dt, int64_t n, int32_t d, ph0_bar* out,
                  ph0_stats* st) {
   int rc = check_args(points, dt, n, d);
@@ -526,6 +686,227 @@ int ph0_barcodes(const void* points, ph0_dtype dt, int64_t n, int32_t d, ph0_bar
     rc = fail(PH0_EDEVICE, "copy of the barcode to the host failed");
   hipStreamDestroy(s);
   return rc;
+}
+
+}  // extern "C"
+
+// ---- serving ----
+
+namespace {
+
+struct Request {
+  uint64_t tag = 0;
+  int64_t n = 0;
+  int32_t d = 0;
+  ph0_dtype dt = PH0_I8;
+  std::vector<char> pts;
+  std::vector<ph0_bar> bars;
+  int32_t status = PH0_OK;
+  size_t off = 0, bytes = 0;  // pool region
+};
+
+// First-fit allocator over [0, size) of the device pool.
+class PoolAllocator {
+ public:
+  explicit PoolAllocator(size_t size) { free_[0] = size; }
+  bool take(size_t bytes, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes;
+        const size_t at = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void give(size_t off, size_t bytes) {
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+
+ private:
+  std::map<size_t, size_t> free_;
+};
+
+size_t request_bytes(int64_t n, int32_t d, ph0_dtype dt) {
+  size_t ws = 0;
+  if (ph0_workspace_bytes(n, d, dt, &ws) != PH0_OK) return 0;
+  return align_up((size_t)n * d * (dt == PH0_I8 ? 1 : 2)) + align_up(8 * (size_t)n) + ws;
+}
+
+}  // namespace
+
+struct ph0_server {
+  size_t budget = 0;
+  char* pool = nullptr;
+  PoolAllocator* alloc = nullptr;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Request*> pending;   // admitted, waiting for a worker
+  std::deque<Request*> finished;  // done, waiting for poll
+  std::vector<std::thread> workers;
+  int32_t slots = 0;
+  int32_t busy = 0;  // admitted and not finished
+  int64_t in_flight = 0;
+  bool stop = false;
+};
+
+namespace {
+
+void serve_worker(ph0_server* S) {
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+  while (true) {
+    Request* R = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv.wait(lk, [&] { return S->stop || !S->pending.empty(); });
+      if (S->pending.empty()) break;
+      R = S->pending.front();
+      S->pending.pop_front();
+    }
+    char* base = S->pool + R->off;
+    const size_t pbytes = (size_t)R->n * R->d * (R->dt == PH0_I8 ? 1 : 2);
+    char* dpts = base;
+    ph0_bar* dout = reinterpret_cast<ph0_bar*>(base + align_up(pbytes));
+    char* ws = base + align_up(pbytes) + align_up(8 * (size_t)R->n);
+    const size_t ws_bytes = R->bytes - align_up(pbytes) - align_up(8 * (size_t)R->n);
+    int rc = PH0_OK;
+    if (!s) rc = fail(PH0_EDEVICE, "stream creation failed");
+    if (!rc && hipMemcpyAsync(dpts, R->pts.data(), pbytes, hipMemcpyHostToDevice, s) != hipSuccess)
+      rc = fail(PH0_EDEVICE, "copy of points failed");
+    if (!rc) {
+      Outputs o;
+      o.bars = dout;
+      rc = run(dpts, R->dt, R->n, R->d, o, ws, ws_bytes, s, nullptr, kStopAll);
+    }
+    R->bars.resize((size_t)R->n);
+    if (!rc && (hipMemcpyAsync(R->bars.data(), dout, 8 * (size_t)R->n, hipMemcpyDeviceToHost, s) !=
+                    hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess))
+      rc = fail(PH0_EDEVICE, "copy of the barcode failed");
+    R->status = rc;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->alloc->give(R->off, R->bytes);
+      S->busy -= 1;
+      S->finished.push_back(R);
+    }
+  }
+  if (s) hipStreamDestroy(s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ph0_server_request_bytes(int64_t n, int32_t d, ph0_dtype dt, size_t* bytes) {
+  static const char probe = 0;
+  int rc = check_args(&probe, dt, n, d);
+  if (rc) return rc;
+  if (!bytes) return fail(PH0_EINVAL, "bytes pointer is NULL");
+  *bytes = request_bytes(n, d, dt);
+  return PH0_OK;
+}
+
+int ph0_server_create(size_t mem_budget_bytes, int32_t max_slots, ph0_server** srv) {
+  if (!srv) return fail(PH0_EINVAL, "server pointer is NULL");
+  if (max_slots < 1 || max_slots > 64) return fail(PH0_EINVAL, "max_slots must be in 1..64");
+  if (mem_budget_bytes < 4096) return fail(PH0_EINVAL, "memory budget too small");
+  ph0_server* S = new ph0_server();
+  S->budget = mem_budget_bytes;
+  if (hipMalloc((void**)&S->pool, mem_budget_bytes) != hipSuccess) {
+    delete S;
+    return fail(PH0_ENOMEM, "device pool of %zu bytes could not be allocated", mem_budget_bytes);
+  }
+  S->alloc = new PoolAllocator(mem_budget_bytes);
+  S->slots = max_slots;
+  for (int k = 0; k < max_slots; ++k) S->workers.emplace_back(serve_worker, S);
+  *srv = S;
+  return PH0_OK;
+}
+
+int ph0_server_submit(ph0_server* S, const void* points, ph0_dtype dt, int64_t n, int32_t d,
+                      uint64_t tag) {
+  if (!S) return fail(PH0_EINVAL, "server is NULL");
+  int rc = check_args(points, dt, n, d);
+  if (rc) return rc;
+  const size_t need = request_bytes(n, d, dt);
+  if (need > S->budget)
+    return fail(PH0_ENOMEM, "request needs %zu bytes, the pool holds %zu", need, S->budget);
+  std::unique_lock<std::mutex> lk(S->mu);
+  if (S->busy >= S->slots) return fail(PH0_EBUSY, "all %d slots are busy", S->slots);
+  size_t off = 0;
+  if (!S->alloc->take(need, &off)) return fail(PH0_EBUSY, "not enough free pool memory now");
+  Request* R = new Request();
+  R->tag = tag;
+  R->n = n;
+  R->d = d;
+  R->dt = dt;
+  R->off = off;
+  R->bytes = need;
+  const size_t pbytes = (size_t)n * d * (dt == PH0_I8 ? 1 : 2);
+  R->pts.assign(static_cast<const char*>(points), static_cast<const char*>(points) + pbytes);
+  S->busy += 1;
+  S->in_flight += 1;
+  S->pending.push_back(R);
+  lk.unlock();
+  S->cv.notify_one();
+  return PH0_OK;
+}
+
+int ph0_server_poll(ph0_server* S, uint64_t* tag, int32_t* status, ph0_bar* out, int64_t out_cap,
+                    int64_t* n_out) {
+  if (!S) return fail(PH0_EINVAL, "server is NULL");
+  Request* R = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->finished.empty()) return 0;
+    R = S->finished.front();
+    S->finished.pop_front();
+    S->in_flight -= 1;
+  }
+  if (tag) *tag = R->tag;
+  if (status) *status = R->status;
+  if (n_out) *n_out = R->n;
+  if (out && R->status == PH0_OK)
+    std::memcpy(out, R->bars.data(), 8 * (size_t)std::min<int64_t>(out_cap, R->n));
+  delete R;
+  return 1;
+}
+
+int64_t ph0_server_in_flight(ph0_server* S) {
+  if (!S) return 0;
+  std::lock_guard<std::mutex> lk(S->mu);
+  return S->in_flight;
+}
+
+void ph0_server_destroy(ph0_server* S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv.notify_all();
+  for (auto& t : S->workers) t.join();
+  for (Request* R : S->finished) delete R;
+  if (S->pool) hipFree(S->pool);
+  delete S->alloc;
+  delete S;
 }
 
 }  // extern "C"

@@ -117,4 +117,25 @@ hipError_t launch_pairs_detail(const int64_t* killer, const uint64_t* skeys, int
 
 constexpr int kSmallSortMax = 16384;  // barcode sorts up to this size run in LDS
 
+// Many small clouds, one persistent launch (one workgroup per cloud).
+constexpr int kBatchMaxN = 512;     // largest cloud the fused kernel takes
+constexpr int kBatchMaxPts = 8192;  // largest n * d it stages in LDS
+struct BatchArgs {
+  const void* pts;          // concatenated rows, n_total x d
+  int elem_bytes;
+  int32_t d;
+  const int64_t* offsets;   // nclouds + 1 row offsets (device)
+  const int32_t* order;     // processing order, largest first (device)
+  int64_t nclouds;
+  uint32_t* bars;           // 2 x n_total: (birth, death) per row
+  uint64_t* scratch;        // per workgroup: 2 x emax keys
+  uint32_t* grades;         // per workgroup: emax grades
+  int64_t emax;             // largest edge count of any cloud
+  uint32_t* queue;          // work counter, zero at launch
+  int32_t* errs;            // per cloud, zero at launch
+  int32_t chunk_mult;       // first chunk holds about chunk_mult * n edges
+};
+size_t batched_shared_bytes();
+hipError_t launch_batched(const BatchArgs& a, int blocks, hipStream_t s);
+
 }  // namespace ph0

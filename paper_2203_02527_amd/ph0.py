@@ -79,6 +79,17 @@ _SIGS = {
                              ctypes.POINTER(ph0_stats)], ctypes.c_int),
     "ph0_pairs_device": ([_P, ctypes.c_int, _I64, _I32, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P,
                           ctypes.POINTER(ph0_stats)], ctypes.c_int),
+    "ph0_batched_workspace_bytes": ([_P, _I64, _I32, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_size_t)],
+                                    ctypes.c_int),
+    "ph0_barcodes_batched_device": ([_P, ctypes.c_int, _P, _I64, _I32, _P, _P, ctypes.c_size_t, _P, _P,
+                                     ctypes.POINTER(ph0_stats)], ctypes.c_int),
+    "ph0_server_create": ([ctypes.c_size_t, _I32, ctypes.POINTER(_P)], ctypes.c_int),
+    "ph0_server_request_bytes": ([_I64, _I32, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "ph0_server_submit": ([_P, _P, ctypes.c_int, _I64, _I32, ctypes.c_uint64], ctypes.c_int),
+    "ph0_server_poll": ([_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_I32), _P, _I64,
+                         ctypes.POINTER(_I64)], ctypes.c_int),
+    "ph0_server_in_flight": ([_P], _I64),
+    "ph0_server_destroy": ([_P], None),
     "ph0_keys_device": ([_P, ctypes.c_int, _I64, _I32, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "ph0_sorted_keys_device": ([_P, ctypes.c_int, _I64, _I32, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
 }
@@ -260,3 +271,122 @@ def ph0_sorted_keys_device(points, workspace=None, stream=None):
     _check(lib().ph0_sorted_keys_device(_ptr(x), _dtype_code(x.dtype), n, d, _ptr(keys),
                                         _ptr(workspace), workspace.numel(), _stream_ptr(stream)))
     return keys[: n * (n - 1) // 2]
+
+
+class ph0_batch_tuning(ctypes.Structure):
+    _fields_ = [("chunk_mult", ctypes.c_int32 * 4), ("blocks_per_cu", ctypes.c_int32)]
+
+
+def make_tuning(chunk_mult=(0, 0, 0, 0), blocks_per_cu=0) -> ph0_batch_tuning:
+    t = ph0_batch_tuning()
+    for k, v in enumerate(chunk_mult):
+        t.chunk_mult[k] = int(v)
+    t.blocks_per_cu = int(blocks_per_cu)
+    return t
+
+
+def _offsets(offsets) -> np.ndarray:
+    o = np.ascontiguousarray(offsets, dtype=np.int64)
+    if o.ndim != 1 or o.size < 2:
+        raise ValueError("offsets must hold nclouds + 1 entries")
+    return o
+
+
+def ph0_batched_workspace_bytes(offsets, d: int, dtype, tuning=None) -> int:
+    o = _offsets(offsets)
+    out = ctypes.c_size_t(0)
+    _check(lib().ph0_batched_workspace_bytes(o.ctypes.data_as(_P), o.size - 1, d, _dtype_code(dtype),
+                                             None if tuning is None else ctypes.byref(tuning),
+                                             ctypes.byref(out)))
+    return out.value
+
+
+def ph0_barcodes_batched_device(points, offsets, out=None, workspace=None, tuning=None,
+                                stream=None, with_stats=False):
+    """Barcodes of many clouds (rows offsets[c]:offsets[c+1] of `points`).
+
+    Returns an (offsets[-1], 2) int32 tensor of uint32 bars, each cloud's
+    canonical barcode in its own rows.
+    """
+    torch = _torch()
+    x = _points_dev(points)
+    o = _offsets(offsets)
+    if int(o[-1]) != x.shape[0]:
+        raise ValueError("offsets[-1] must equal the number of rows")
+    d = x.shape[1]
+    if out is None:
+        out = torch.empty((x.shape[0], 2), dtype=torch.int32, device=x.device)
+    if workspace is None:
+        nbytes = ph0_batched_workspace_bytes(o, d, x.dtype, tuning)
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    st = ph0_stats()
+    _check(lib().ph0_barcodes_batched_device(
+        _ptr(x), _dtype_code(x.dtype), o.ctypes.data_as(_P), o.size - 1, d, _ptr(out),
+        _ptr(workspace), workspace.numel(), None if tuning is None else ctypes.byref(tuning),
+        _stream_ptr(stream), ctypes.byref(st)))
+    return (out, st.to_dict()) if with_stats else out
+
+
+# ---- serving ----
+
+def ph0_server_request_bytes(n: int, d: int, dtype) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().ph0_server_request_bytes(n, d, _dtype_code(dtype), ctypes.byref(out)))
+    return out.value
+
+
+class Server:
+    """Continuous-batching server (ph0_server_* entry points).
+
+    submit() admits a cloud when a slot and pool memory are free (else it
+    returns False: retry later); admitted clouds run concurrently on their own
+    streams; poll() returns finished (tag, status, bars) without blocking.
+    """
+
+    def __init__(self, mem_budget_bytes: int, max_slots: int = 4):
+        h = _P()
+        _check(lib().ph0_server_create(int(mem_budget_bytes), int(max_slots), ctypes.byref(h)))
+        self._h = h
+        self.max_slots = max_slots
+        self._buf = np.empty((65536, 2), np.uint32)
+
+    def submit(self, points: np.ndarray, tag: int) -> bool:
+        x = np.ascontiguousarray(points)
+        rc = lib().ph0_server_submit(self._h, x.ctypes.data_as(_P), _dtype_code(x.dtype),
+                                     x.shape[0], x.shape[1], int(tag))
+        if rc == -5:
+            return False
+        _check(rc)
+        return True
+
+    def poll(self, max_n: int = 65536):
+        tag = ctypes.c_uint64(0)
+        status = _I32(0)
+        n_out = _I64(0)
+        buf = self._buf
+        got = lib().ph0_server_poll(self._h, ctypes.byref(tag), ctypes.byref(status),
+                                    buf.ctypes.data_as(_P), min(max_n, buf.shape[0]),
+                                    ctypes.byref(n_out))
+        if got <= 0:
+            return None
+        return tag.value, status.value, buf[: n_out.value].copy()
+
+    def in_flight(self) -> int:
+        return int(lib().ph0_server_in_flight(self._h))
+
+    def close(self):
+        if self._h:
+            lib().ph0_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
