@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--window", type=int, default=0, help="reduction window (0 = built-in)")
     ap.add_argument("--lanes", type=int, default=0, help="walk lanes per column (0 = built-in)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=200)
     return ap.parse_args()
 
 
@@ -57,6 +60,72 @@ def cpu_baseline(points, n_sample):
                   "(distances, std::sort, grades, dense F2 reduction, read-off) in %.2f s"
                   % (n_sample, res.E, res.E_eff, t),
         "seconds": res.seconds,
+    }
+
+
+def bench_batched(torch, ph0, synth, reps=3):
+    """10,000 uneven clouds: one persistent launch vs one cloud per call."""
+    import numpy as np
+
+    pts, offsets = synth.batch_clouds(count=10000, seed=0)
+    x = torch.from_numpy(pts).to("cuda:0")
+    out = torch.empty((pts.shape[0], 2), dtype=torch.int32, device="cuda:0")
+    nbytes = ph0.ph0_batched_workspace_bytes(offsets, 3, pts.dtype)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    ph0.ph0_barcodes_batched_device(x, offsets, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ph0.ph0_barcodes_batched_device(x, offsets, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    t_batched = (time.perf_counter() - t0) / reps
+    # plain path: the first 500 clouds, one ph0_barcodes_device call each
+    k = 500
+    pws = ph0.alloc_workspace(512, 3, pts.dtype, "cuda:0")
+    pout = torch.empty((512, 2), dtype=torch.int32, device="cuda:0")
+    for c in range(5):
+        ph0.ph0_barcodes_device(x[offsets[c]:offsets[c + 1]], out=pout[: offsets[c + 1] - offsets[c]],
+                                workspace=pws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(k):
+        n = int(offsets[c + 1] - offsets[c])
+        ph0.ph0_barcodes_device(x[offsets[c]:offsets[c + 1]], out=pout[:n], workspace=pws)
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / k
+    return {
+        "workload": "10000 clouds, N uniform in [32,512], d=3 int16, circles or 2-4 blobs, seed 0",
+        "clouds_per_s": 10000 / t_batched,
+        "ms_per_launch": round(1000 * t_batched, 3),
+        "plain_clouds_per_s": 1.0 / t_plain,
+        "plain_sample": "first %d clouds, one ph0_barcodes_device call each" % k,
+        "speedup_vs_plain": (10000 / t_batched) * t_plain,
+        "edges_total": int(np.sum(np.diff(offsets) * (np.diff(offsets) - 1) // 2)),
+    }
+
+
+def bench_serving(ph0, synth, count):
+    """Mixed request stream: closed-loop saturation, then Poisson at 0.8x."""
+    from paper_2203_02527_amd import serve
+
+    reqs = synth.serving_requests(count, seed=0)
+    serve.serve(reqs[:8], rate=None, mem_budget=8 << 30, slots=4)  # warm-up
+    sat = serve.serve(reqs, rate=None, mem_budget=8 << 30, slots=4)
+    rate = 0.8 * sat["clouds_per_s"]
+    pois = serve.serve(reqs, rate=rate, mem_budget=8 << 30, slots=4, seed=1)
+    pl = serve.plain(reqs)
+    pl.pop("results")
+    return {
+        "workload": "%d requests, N log-uniform in [64,8192], d in {3,16,64}, int8/int16 "
+                    "mixtures, seed 0; 4 slots, 8 GiB pool" % count,
+        "saturation_clouds_per_s": sat["clouds_per_s"],
+        "poisson_rate": rate,
+        "clouds_per_s": pois["clouds_per_s"],
+        "p50_ms": pois["p50_ms"],
+        "p99_ms": pois["p99_ms"],
+        "plain_clouds_per_s": pl["clouds_per_s"],
+        "plain_p50_ms": pl["p50_ms"],
+        "plain_p99_ms": pl["p99_ms"],
     }
 
 
@@ -165,6 +234,10 @@ def main():
         "roofline": roofline,
         "kernels": others,
     }
+    if not args.no_batched:
+        rec["batched"] = bench_batched(torch, ph0, synth)
+    if not args.no_serving:
+        rec["serving"] = bench_serving(ph0, synth, args.serve_requests)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(pts, n // 2)
     print(json.dumps(rec), flush=True)

@@ -139,16 +139,16 @@ struct Timer {
       for (auto& e : ev) on = on && hipEventCreate(&e) == hipSuccess;
   }
   void mark() {
-    if (on && k < 8) hipEventRecord(ev[k++], s);
+    if (on && k < 8) (void)hipEventRecord(ev[k++], s);
   }
   float ms(int a, int b) {
     float v = 0;
-    if (on && b < k) hipEventElapsedTime(&v, ev[a], ev[b]);
+    if (on && b < k) (void)hipEventElapsedTime(&v, ev[a], ev[b]);
     return v;
   }
   ~Timer() {
     if (on)
-      for (auto& e : ev) hipEventDestroy(e);
+      for (auto& e : ev) (void)hipEventDestroy(e);
   }
 };
 
@@ -181,7 +181,7 @@ struct KernelClock {
   }
   int launches() const { return (int)(used / 2); }
   ~KernelClock() {
-    for (auto e : ev) hipEventDestroy(e);
+    for (auto e : ev) (void)hipEventDestroy(e);
   }
 };
 
@@ -293,9 +293,9 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   KernelClock radix_clock(st != nullptr), walk_clock(st != nullptr);
   for (int p = 0; p < sp.passes; ++p) {
     hipEvent_t* ev = radix_clock.pair();
-    if (ev) hipEventRecord(ev[0], s);
+    if (ev) (void)hipEventRecord(ev[0], s);
     HIPCHK(launch_radix_pass(src, dst, L.E, sp.shift[p], sp.bits[p], counts, serr, s));
-    if (ev) hipEventRecord(ev[1], s);
+    if (ev) (void)hipEventRecord(ev[1], s);
     std::swap(src, dst);
   }
   uint64_t* skeys = src;  // sorted
@@ -490,7 +490,7 @@ int plan_batch(const int64_t* offsets, int64_t nclouds, int32_t d, ph0_dtype dt,
 struct DeviceBuffer {
   void* p = nullptr;
   ~DeviceBuffer() {
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   }
 };
 
@@ -684,7 +684,7 @@ int ph0_barcodes(const void* points, ph0_dtype dt, int64_t n, int32_t d, ph0_bar
   if (!rc && (hipMemcpyAsync(out, dout.p, 8 * (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess ||
               hipStreamSynchronize(s) != hipSuccess))
     rc = fail(PH0_EDEVICE, "copy of the barcode to the host failed");
-  hipStreamDestroy(s);
+  (void)hipStreamDestroy(s);
   return rc;
 }
 
@@ -807,7 +807,7 @@ void serve_worker(ph0_server* S) {
       S->finished.push_back(R);
     }
   }
-  if (s) hipStreamDestroy(s);
+  if (s) (void)hipStreamDestroy(s);
 }
 
 }  // namespace
@@ -904,7 +904,7 @@ void ph0_server_destroy(ph0_server* S) {
   S->cv.notify_all();
   for (auto& t : S->workers) t.join();
   for (Request* R : S->finished) delete R;
-  if (S->pool) hipFree(S->pool);
+  if (S->pool) (void)hipFree(S->pool);
   delete S->alloc;
   delete S;
 }

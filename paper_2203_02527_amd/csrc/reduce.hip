@@ -62,6 +62,12 @@ __device__ inline uint64_t shfl64_down(uint64_t v, int delta) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+__device__ inline uint64_t shfl64_up(uint64_t v, int delta) {
+  const uint32_t lo = __shfl_up((uint32_t)v, delta, 64);
+  const uint32_t hi = __shfl_up((uint32_t)(v >> 32), delta, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ inline uint64_t shfl64(uint64_t v, int src) {
   const uint32_t lo = __shfl((uint32_t)v, src, 64);
   const uint32_t hi = __shfl((uint32_t)(v >> 32), src, 64);
@@ -118,16 +124,35 @@ __device__ inline void clear_bit(uint64_t (&w)[WPL], int gl, int bit) {
 }
 
 // XOR words 0..(r >> 6) of stored column r into w (the rest are zero).
+// Every lane issues all WPL loads unconditionally (addresses past the top
+// word are clamped to it and the value masked), so the loads of one step are
+// in flight together and wait once.
 template <int G, int WPL>
 __device__ inline void xor_row(uint64_t (&w)[WPL], const uint64_t* __restrict__ table,
                                int64_t LW, int r, int gl) {
   const int top = r >> 6;
   const uint64_t* rp = table + (int64_t)r * LW;
+  uint64_t v[WPL];
 #pragma unroll
   for (int q = 0; q < WPL; ++q) {
     const int widx = q * G + gl;
-    if (widx <= top) w[q] ^= rp[widx];
+    v[q] = rp[widx <= top ? widx : top];
   }
+#pragma unroll
+  for (int q = 0; q < WPL; ++q) {
+    const int widx = q * G + gl;
+    w[q] ^= widx <= top ? v[q] : 0ull;
+  }
+}
+
+// A value the whole group agrees on; for a full-wave group it is moved to a
+// scalar register so that branches on it are scalar.
+template <int G>
+__device__ inline int group_uniform(int x) {
+  if constexpr (G == 64)
+    return __builtin_amdgcn_readfirstlane(x);
+  else
+    return x;
 }
 
 __device__ inline uint64_t wave_min_u64(uint64_t v) {
@@ -202,10 +227,11 @@ __global__ __launch_bounds__(256) void k_walk(const uint64_t* __restrict__ skeys
     flip_bit<G, WPL>(col, gl, r);
     int moved = 0;
     bool zero = false;
+    r = group_uniform<G>(r);
     while (true) {
       xor_row<G, WPL>(col, table, LW, r, gl);
       words += (r >> 6) + 1;
-      const int nr = group_top_bit<G, WPL>(col, gbase, (r >> 6) / G);
+      const int nr = group_uniform<G>(group_top_bit<G, WPL>(col, gbase, (r >> 6) / G));
       if (nr == r) break;  // row r is empty: slot r is free
       ++moved;
       if (nr < 0) {
@@ -234,14 +260,14 @@ __global__ __launch_bounds__(256) void k_walk(const uint64_t* __restrict__ skeys
       a = na < 0 ? 0 : na;
       // Root of row a in the current forest: follow stored columns down
       // (col is all zero here and serves as the row buffer).
-      int v = moved ? a : rlo;
+      int v = group_uniform<G>(moved ? a : rlo);
       while (true) {
 #pragma unroll
         for (int q = 0; q < WPL; ++q) col[q] = 0;
         xor_row<G, WPL>(col, table, LW, v, gl);
         words += (v >> 6) + 1;
         clear_bit<G, WPL>(col, gl, v);
-        const int c = group_top_bit<G, WPL>(col, gbase, (v >> 6) / G);
+        const int c = group_uniform<G>(group_top_bit<G, WPL>(col, gbase, (v >> 6) / G));
         if (c < 0) break;  // empty row: v is a root
         ++finds;
         if (c >= v) {  // a stored column needs a second, smaller row
@@ -287,9 +313,49 @@ __global__ __launch_bounds__(256) void k_walk(const uint64_t* __restrict__ skeys
   }
 }
 
+// Block-wide reductions for the 256-thread decide/commit kernels.
+__device__ inline uint64_t block_min_u64(uint64_t v, uint64_t* tmp /* 4 */) {
+  v = wave_min_u64(v);
+  if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint64_t r = tmp[0];
+#pragma unroll
+  for (int w = 1; w < 4; ++w) r = tmp[w] < r ? tmp[w] : r;
+  __syncthreads();
+  return r;
+}
+
+__device__ inline int64_t block_sum_i64(int64_t v, int64_t* tmp /* 4 */) {
+  v = wave_sum_i64(v);
+  if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const int64_t r = tmp[0] + tmp[1] + tmp[2] + tmp[3];
+  __syncthreads();
+  return r;
+}
+
+// Exclusive prefix of v over the block (and the block total).
+__device__ inline int64_t block_excl_i64(int64_t v, int64_t* tmp /* 4 */, int64_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = (int64_t)shfl64_up((uint64_t)x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) tmp[wave] = x;
+  __syncthreads();
+  int64_t base = 0;
+  for (int w = 0; w < wave; ++w) base += tmp[w];
+  *total = tmp[0] + tmp[1] + tmp[2] + tmp[3];
+  __syncthreads();
+  return base + x - v;
+}
+
 __global__ __launch_bounds__(256) void k_decide(Ring ring, int64_t Wcap, const int64_t* act0,
                                                 const int64_t* act1, const uint64_t* lowc,
                                                 RedCtl* ctl) {
+  __shared__ uint64_t tmp[4];
   if (ctl->done) return;
   const int64_t round = ctl->round;
   const int64_t items = ctl->nA + (ctl->fresh_hi - ctl->fresh_lo);
@@ -302,85 +368,83 @@ __global__ __launch_bounds__(256) void k_decide(Ring ring, int64_t Wcap, const i
     if ((ring.st[k] & 3) != kActive) continue;
     if (lowc[ring.r[k]] != enc(round, p) && (uint64_t)p < best) best = (uint64_t)p;
   }
-  best = wave_min_u64(best);
-  if ((threadIdx.x & 63) == 0 && best != kNoValue)
+  best = block_min_u64(best, tmp);
+  if (threadIdx.x == 0 && best != kNoValue)
     atomicMin((unsigned long long*)&ctl->firstdup[round & 1], (unsigned long long)best);
 }
 
+// Commit the survivors the rule allows; append the rest to the next active
+// list.  Two phases per block so that the list needs one atomic per block:
+// commit and count, then (after one block-wide scan) write the stayers.
 __global__ __launch_bounds__(256) void k_commit(Ring ring, int64_t Wcap, int64_t* act0,
                                                 int64_t* act1, const uint64_t* lowc,
                                                 const uint64_t* touch,
                                                 uint64_t* table, int64_t LW, int64_t* killer,
                                                 RedCtl* ctl) {
+  __shared__ int64_t itmp[4];
+  __shared__ uint64_t utmp[4];
+  __shared__ int64_t s_base;
   if (ctl->done) return;
   const int64_t round = ctl->round;
   const int64_t items = ctl->nA + (ctl->fresh_hi - ctl->fresh_lo);
   const int64_t* act = ctl->cur ? act1 : act0;
   int64_t* next = ctl->cur ? act0 : act1;
   const uint64_t fd = ctl->firstdup[round & 1];
-  const int lane = threadIdx.x & 63;
-  uint64_t stay_min = kNoValue;
-  int64_t npiv = 0, last = -1;
-  // Every lane of a wave runs the same number of iterations, so the wave can
-  // append its staying columns with one atomic.
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t iters = (items + stride - 1 - (t0 - lane)) / stride;
-  for (int64_t it = 0; it < iters; ++it) {
-    const int64_t t = t0 + it * stride;
-    bool stay = false;
-    int64_t p = -1;
-    if (t < items) {
-      p = item_column(ctl, act, t);
-      const int64_t k = p & (Wcap - 1);
-      const int32_t st = ring.st[k];
-      if ((st & 3) == kActive) {
-        const int32_t r = ring.r[k];
-        const uint64_t e = enc(round, p);
-        if ((uint64_t)p < fd || (lowc[r] == e && touch[r] > e)) {
-          const int32_t a = ring.a[k];
-          uint64_t* row = table + (int64_t)r * LW;
-          if ((a >> 6) == (r >> 6)) {
-            row[r >> 6] = (1ull << (r & 63)) | (1ull << (a & 63));
-          } else {
-            row[a >> 6] = 1ull << (a & 63);
-            row[r >> 6] = 1ull << (r & 63);
-          }
-          killer[r] = p;
-          ring.st[k] = (st & ~3) | kCommitted;
-          ++npiv;
-          last = p > last ? p : last;
-        } else {
-          stay = true;
-          if ((uint64_t)p < stay_min) stay_min = (uint64_t)p;
-        }
+  uint64_t stay_min = kNoValue;
+  int64_t npiv = 0, last = -1, nstay = 0;
+  for (int64_t t = t0; t < items; t += stride) {
+    const int64_t p = item_column(ctl, act, t);
+    const int64_t k = p & (Wcap - 1);
+    const int32_t st = ring.st[k];
+    if ((st & 3) != kActive) continue;
+    const int32_t r = ring.r[k];
+    const uint64_t e = enc(round, p);
+    if ((uint64_t)p < fd || (lowc[r] == e && touch[r] > e)) {
+      const int32_t a = ring.a[k];
+      uint64_t* row = table + (int64_t)r * LW;
+      if ((a >> 6) == (r >> 6)) {
+        row[r >> 6] = (1ull << (r & 63)) | (1ull << (a & 63));
+      } else {
+        row[a >> 6] = 1ull << (a & 63);
+        row[r >> 6] = 1ull << (r & 63);
       }
-    }
-    const uint64_t m = __ballot(stay);
-    if (m) {
-      int64_t base = 0;
-      if (lane == 0)
-        base = (int64_t)atomicAdd((unsigned long long*)&ctl->nA_next,
-                                  (unsigned long long)__popcll(m));
-      base = __shfl(base, 0, 64);
-      if (stay) next[base + __popcll(m & ((1ull << lane) - 1ull))] = p;
+      killer[r] = p;
+      ring.st[k] = (st & ~3) | kCommitted;
+      ++npiv;
+      last = p > last ? p : last;
+    } else {
+      ++nstay;
+      if ((uint64_t)p < stay_min) stay_min = (uint64_t)p;
     }
   }
-  npiv = wave_sum_i64(npiv);
-  // max of (last + 1) as a min of its complement
-  const uint64_t last_c = wave_min_u64(~(uint64_t)(last + 1));
-  stay_min = wave_min_u64(stay_min);
-  if (lane == 0) {
+  int64_t total;
+  const int64_t mine = block_excl_i64(nstay, itmp, &total);
+  if (threadIdx.x == 0 && total)
+    s_base = (int64_t)atomicAdd((unsigned long long*)&ctl->nA_next, (unsigned long long)total);
+  __syncthreads();
+  if (nstay) {
+    int64_t at = s_base + mine;
+    for (int64_t t = t0; t < items; t += stride) {
+      const int64_t p = item_column(ctl, act, t);
+      if ((ring.st[p & (Wcap - 1)] & 3) == kActive) next[at++] = p;
+    }
+  }
+  npiv = block_sum_i64(npiv, itmp);
+  const uint64_t last_c = block_min_u64(~(uint64_t)(last + 1), utmp);
+  stay_min = block_min_u64(stay_min, utmp);
+  if (threadIdx.x == 0) {
     if (npiv) {
       atomicAdd((unsigned long long*)&ctl->pivots, (unsigned long long)npiv);
       atomicMax((long long*)&ctl->E_eff, (long long)~last_c);
     }
     if (stay_min != kNoValue)
       atomicMin((unsigned long long*)&ctl->newF[round & 1], (unsigned long long)stay_min);
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctl->firstdup[(round + 1) & 1] = kNoValue;
-    ctl->newF[(round + 1) & 1] = kNoValue;
+    if (blockIdx.x == 0) {
+      ctl->firstdup[(round + 1) & 1] = kNoValue;
+      ctl->newF[(round + 1) & 1] = kNoValue;
+    }
   }
 }
 
@@ -515,11 +579,11 @@ hipError_t launch_reduce_init(const RedArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_walk) {
-  if (ev_walk) hipEventRecord(ev_walk[0], s);
+  if (ev_walk) (void)hipEventRecord(ev_walk[0], s);
   if (!launch_walk_shape(a, s)) return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (ev_walk) hipEventRecord(ev_walk[1], s);
+  if (ev_walk) (void)hipEventRecord(ev_walk[1], s);
   const int sb = scan_blocks(a.Wcap);
   hipLaunchKernelGGL(k_decide, dim3(sb), dim3(256), 0, s, a.ring, a.Wcap, a.act[0], a.act[1],
                      a.lowc, a.ctl);
