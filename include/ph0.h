@@ -82,6 +82,8 @@ typedef struct {
   float ms_radix_kernel;   /* LSD radix pass kernel (one launch per pass) */
   int32_t walk_launches;
   int32_t radix_launches;
+  int32_t sort_chunks;     /* distance ranges sorted (1 = only the first) */
+  int32_t reserved;
 } ph0_stats;
 
 /* Message for the last non-OK status returned on this thread. */

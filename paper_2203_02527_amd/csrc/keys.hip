@@ -4,7 +4,10 @@
 // written at the edge's colex position j(j-1)/2 + i, so that the array is
 // already in (j, i) order and a stable sort on the delta bits alone yields the
 // (delta, j, i) order.  delta is the exact squared Euclidean distance of two
-// integer points.
+// integer points.  Each workgroup also counts its distances into a histogram
+// of `delta >> hist_shift` (kHistBins bins, LDS across all the workgroup's
+// tiles, one flush per workgroup), from which the host picks the distance
+// ranges the sort has to order.
 //
 // Two paths:
 //  * vector ALU, direct differences (any d, int8 or int16; int64 sums);
@@ -59,11 +62,24 @@ __global__ void k_coord_range(const T* __restrict__ x, int64_t n, int32_t d,
 // ---- vector ALU path ----
 constexpr int kChunk = 32;  // dimensions staged per LDS round
 
+__device__ inline void hist_zero(uint32_t* lh) {
+  for (int b = threadIdx.x; b < kHistBins; b += blockDim.x) lh[b] = 0;
+}
+
+__device__ inline void hist_flush(const uint32_t* lh, uint32_t* hist) {
+  __syncthreads();
+  for (int b = threadIdx.x; b < kHistBins; b += blockDim.x)
+    if (lh[b]) atomicAdd(&hist[b], lh[b]);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_keys_alu(const T* __restrict__ x, int64_t n, int32_t d,
                                                   int ib, uint64_t* __restrict__ keys,
-                                                  int64_t ntiles) {
+                                                  int64_t ntiles, int hist_shift,
+                                                  uint32_t* __restrict__ hist) {
   __shared__ int32_t xs[2][kTile][kChunk + 1];
+  __shared__ uint32_t lh[kHistBins];
+  hist_zero(lh);
 
   const int il = threadIdx.x & 63;   // i inside the tile (one per lane)
   const int jl0 = threadIdx.x >> 6;  // first j of this wave; j = jl0 + 4q
@@ -101,9 +117,11 @@ __global__ __launch_bounds__(256) void k_keys_alu(const T* __restrict__ x, int64
         const uint64_t delta = (uint64_t)acc[q];
         keys[j * (j - 1) / 2 + i] =
             (delta << (2 * ib)) | ((uint64_t)j << ib) | (uint64_t)i;
+        atomicAdd(&lh[delta >> hist_shift], 1u);
       }
     }
   }
+  hist_flush(lh, hist);
 }
 
 // ---- int8 MFMA Gram path ----
@@ -115,12 +133,15 @@ constexpr int kMaxDpad = 256;  // int8 dims staged per LDS round (multiple of 32
 __global__ __launch_bounds__(256) void k_keys_mfma(const int8_t* __restrict__ x, int64_t n,
                                                    int32_t d, int ib,
                                                    uint64_t* __restrict__ keys,
-                                                   int64_t ntiles) {
+                                                   int64_t ntiles, int hist_shift,
+                                                   uint32_t* __restrict__ hist) {
   // Rows padded by 16 bytes so that the 32 row reads of a half-wave spread
   // over the LDS banks.
   constexpr int kRow = kMaxDpad + 16;
   __shared__ __attribute__((aligned(16))) int8_t xs[2][kTile][kRow];
   __shared__ int32_t nrm[2][kTile];
+  __shared__ uint32_t lh[kHistBins];
+  hist_zero(lh);
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -178,9 +199,11 @@ __global__ __launch_bounds__(256) void k_keys_mfma(const int8_t* __restrict__ x,
         const uint64_t delta = (uint64_t)(int64_t)(nrm[1][jl] + ni - 2 * c[r]);
         keys[j * (j - 1) / 2 + i] =
             (delta << (2 * ib)) | ((uint64_t)j << ib) | (uint64_t)i;
+        atomicAdd(&lh[delta >> hist_shift], 1u);
       }
     }
   }
+  hist_flush(lh, hist);
 }
 
 int grid_for(int64_t count, int per_block, int cap) {
@@ -216,19 +239,31 @@ hipError_t launch_coord_range(const void* pts, int elem_bytes, int64_t n, int32_
 }
 
 hipError_t launch_keys(const void* pts, int elem_bytes, int64_t n, int32_t d, int ib,
-                       uint64_t* keys, bool use_mfma, hipStream_t s) {
+                       uint64_t* keys, bool use_mfma, int hist_shift, uint32_t* hist,
+                       hipStream_t s) {
   const int64_t nb = (n + kTile - 1) / kTile;
   const int64_t ntiles = nb * (nb + 1) / 2;
-  const int grid = (int)(ntiles < 65536 ? ntiles : 65536);
+  // Resident-sized grid: each workgroup loops over tiles, so its histogram
+  // is flushed once.
+  int cus = 256;
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+        prop.multiProcessorCount > 0)
+      cus = prop.multiProcessorCount;
+  }
+  const int64_t cap = 8 * (int64_t)cus;
+  const int grid = (int)(ntiles < cap ? ntiles : cap);
   if (use_mfma && elem_bytes == 1) {
     hipLaunchKernelGGL(k_keys_mfma, dim3(grid), dim3(256), 0, s,
-                       static_cast<const int8_t*>(pts), n, d, ib, keys, ntiles);
+                       static_cast<const int8_t*>(pts), n, d, ib, keys, ntiles, hist_shift, hist);
   } else if (elem_bytes == 1) {
     hipLaunchKernelGGL(k_keys_alu<int8_t>, dim3(grid), dim3(256), 0, s,
-                       static_cast<const int8_t*>(pts), n, d, ib, keys, ntiles);
+                       static_cast<const int8_t*>(pts), n, d, ib, keys, ntiles, hist_shift, hist);
   } else {
     hipLaunchKernelGGL(k_keys_alu<int16_t>, dim3(grid), dim3(256), 0, s,
-                       static_cast<const int16_t*>(pts), n, d, ib, keys, ntiles);
+                       static_cast<const int16_t*>(pts), n, d, ib, keys, ntiles, hist_shift, hist);
   }
   return hipGetLastError();
 }

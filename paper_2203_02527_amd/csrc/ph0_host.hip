@@ -65,7 +65,7 @@ int64_t window_for(int64_t n, int64_t E) {
 
 struct Layout {
   int64_t n, E, LW, Wcap, tiles;
-  size_t keysA, keysB, counts, err, table, killer, lowc, touch, act0, act1, rtag, ra, rr, rrlo,
+  size_t keysA, keysB, counts, hist, err, table, killer, lowc, touch, act0, act1, rtag, ra, rr, rrlo,
       rst, ctl, blockcnt, dbv, minmax, total;
 };
 
@@ -86,6 +86,7 @@ Layout make_layout(int64_t n, int32_t d) {
   L.keysA = take(8 * (size_t)keys);
   L.keysB = take(8 * (size_t)keys);
   L.counts = take(4 * (size_t)radix_count_entries(keys));
+  L.hist = take(4 * (size_t)kHistBins);
   L.err = take(4);
   L.table = take(8 * (size_t)(n * L.LW));
   L.killer = take(8 * (size_t)n);
@@ -276,11 +277,14 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   uint64_t* keysA = static_cast<uint64_t*>(at(L.keysA));
   uint64_t* keysB = static_cast<uint64_t*>(at(L.keysB));
   uint32_t* counts = static_cast<uint32_t*>(at(L.counts));
+  uint32_t* hist = static_cast<uint32_t*>(at(L.hist));
   int32_t* serr = static_cast<int32_t*>(at(L.err));
+  const int hist_shift = dbits > 11 ? dbits - 11 : 0;
 
   HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t*>(serr), 0u, 1, s));
+  HIPCHK(launch_fill_u32(hist, 0u, kHistBins, s));
   tm.mark();  // 1
-  HIPCHK(launch_keys(d_points, eb, n, d, ib, keysA, mfma, s));
+  HIPCHK(launch_keys(d_points, eb, n, d, ib, keysA, mfma, hist_shift, hist, s));
   tm.mark();  // 2
   if (stop == kStopKeys) {
     HIPCHK(hipMemcpyAsync(out.keys, keysA, 8 * (size_t)L.E, hipMemcpyDeviceToDevice, s));
@@ -288,20 +292,35 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     return PH0_OK;
   }
 
-  uint64_t* src = keysA;
-  uint64_t* dst = keysB;
   KernelClock radix_clock(st != nullptr), walk_clock(st != nullptr);
-  for (int p = 0; p < sp.passes; ++p) {
+  // One LSD pass, timed when stats are requested.
+  auto pass = [&](const uint64_t* in, uint64_t* outk, int64_t count, int p, KeyFilter f,
+                  int64_t expect) -> hipError_t {
     hipEvent_t* ev = radix_clock.pair();
     if (ev) (void)hipEventRecord(ev[0], s);
-    HIPCHK(launch_radix_pass(src, dst, L.E, sp.shift[p], sp.bits[p], counts, serr, s));
+    const hipError_t e =
+        launch_radix_pass(in, outk, count, sp.shift[p], sp.bits[p], counts, serr, s, f, expect);
     if (ev) (void)hipEventRecord(ev[1], s);
-    std::swap(src, dst);
-  }
-  uint64_t* skeys = src;  // sorted
-  uint64_t* spare = dst;  // free ping-pong buffer
-  tm.mark();  // 3
+    return e;
+  };
+  // Every key, in sorted order, ping-ponging between the two key buffers.
+  uint64_t* skeys = keysA;  // sorted order (a prefix of it while chunked)
+  uint64_t* spare = keysB;  // the other buffer
+  auto full_sort = [&]() -> hipError_t {
+    uint64_t* src = keysA;
+    uint64_t* dst = keysB;
+    for (int p = 0; p < sp.passes; ++p) {
+      const hipError_t e = pass(src, dst, L.E, p, KeyFilter(), -1);
+      if (e != hipSuccess) return e;
+      std::swap(src, dst);
+    }
+    skeys = src;
+    spare = dst;
+    return hipSuccess;
+  };
   if (stop == kStopSorted) {
+    HIPCHK(full_sort());
+    tm.mark();  // 3
     int32_t herr = 0;
     HIPCHK(hipMemcpyAsync(out.keys, skeys, 8 * (size_t)L.E, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(&herr, serr, 4, hipMemcpyDeviceToHost, s));
@@ -309,6 +328,51 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     if (herr) return fail(PH0_EDEVICE, "radix sort digit counts were inconsistent");
     return PH0_OK;
   }
+
+  // The reduction only ever needs the sorted order up to its last pivot, so
+  // the sort proceeds in distance ranges (chunks of histogram bins, growing
+  // geometrically): a chunk's keys are picked out of all keys by the first
+  // LSD pass and sorted into the next positions of the sorted array, which
+  // therefore always holds an exact prefix of the full order.
+  std::vector<uint32_t> h(kHistBins);
+  HIPCHK(hipMemcpyAsync(h.data(), hist, 4 * (size_t)kHistBins, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int64_t E_lim = 0;
+  int bin_next = 0, chunks = 0;
+  bool whole = false;
+  auto next_chunk = [&]() -> hipError_t {
+    const int64_t target = std::max<int64_t>(L.E / 16, 8 * n) << std::min(chunks, 20);
+    int b = bin_next;
+    int64_t cnt = 0;
+    while (b < kHistBins && (cnt == 0 || cnt < target)) cnt += h[b++];
+    ++chunks;
+    if (sp.passes == 0 || E_lim + 2 * cnt > L.E) {
+      // The rest in one full sort; its prefix equals the chunks sorted so far.
+      whole = true;
+      E_lim = L.E;
+      return full_sort();
+    }
+    KeyFilter f;
+    f.fshift = 2 * ib + hist_shift;
+    f.flo = (uint64_t)bin_next;
+    f.fhi = (uint64_t)b;
+    uint64_t* D = keysB + E_lim;        // the chunk's final place
+    uint64_t* T = keysB + E_lim + cnt;  // scratch for the ping-pong
+    const uint64_t* in = keysA;
+    for (int p = 0; p < sp.passes; ++p) {
+      uint64_t* o = ((sp.passes - 1 - p) % 2 == 0) ? D : T;
+      const hipError_t e = pass(in, o, p == 0 ? L.E : cnt, p, p == 0 ? f : KeyFilter(), cnt);
+      if (e != hipSuccess) return e;
+      in = o;
+    }
+    skeys = keysB;
+    spare = keysA;
+    E_lim += cnt;
+    bin_next = b;
+    return hipSuccess;
+  };
+  HIPCHK(next_chunk());
+  tm.mark();  // 3
 
   // Reduction rounds.
   RedArgs ra;
@@ -333,7 +397,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   ra.ctl = static_cast<RedCtl*>(at(L.ctl));
   RedCtl* hc = pinned_ctl();
   if (!hc) return fail(PH0_ENOMEM, "pinned host allocation failed");
-  HIPCHK(launch_reduce_init(ra, s));
+  HIPCHK(launch_reduce_init(ra, E_lim, s));
   // Every round finalizes at least the first unfinished column (it either
   // reduces to zero or commits), so the window start must advance.
   int64_t prevF = -1;
@@ -343,6 +407,14 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     HIPCHK(hipMemcpyAsync(hc, ra.ctl, sizeof(RedCtl), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (hc->done) break;
+    if (hc->need_more && !hc->err) {
+      if (whole) return fail(PH0_EDEVICE, "reduction asked for columns past the last one");
+      HIPCHK(next_chunk());
+      ra.skeys = skeys;
+      HIPCHK(launch_reduce_extend(ra, E_lim, s));
+      prevF = -1;
+      continue;
+    }
     if (hc->F <= prevF || hc->err) {
       HIPCHK(hipStreamSynchronize(s));
       return fail(PH0_EDEVICE, "reduction stalled at column %lld (err %d)", (long long)hc->F,
@@ -350,6 +422,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     }
     prevF = hc->F;
   }
+  S.sort_chunks = chunks;
   HIPCHK(launch_reduce_finish(ra, s));
   HIPCHK(hipMemcpyAsync(hc, ra.ctl, sizeof(RedCtl), hipMemcpyDeviceToHost, s));
   int32_t herr = 0;

@@ -39,10 +39,11 @@ struct RedCtl {
   int64_t find_steps;
   int64_t words_read;
   int64_t additions_overshoot;  // additions of walked columns >= E_eff
+  int64_t E_lim;     // sorted columns available so far (a prefix of the order)
   int32_t cur;
   int32_t done;
   int32_t err;  // bit 0: a reduced column had weight != 2; bit 1: ran out of columns
-  int32_t pad;
+  int32_t need_more;  // every available column is final and pivots are missing
 };
 
 // Per-column state of the reduction window, a ring indexed by p % Wcap.
@@ -66,16 +67,26 @@ hipError_t launch_coord_range(const void* pts, int elem_bytes, int64_t n, int32_
                               int32_t* minmax /* 2*d, zeroed to +-inf by caller */,
                               hipStream_t s);
 
-// Step 1: keys of all edges at colex positions.
+// Step 1: keys of all edges at colex positions, and the histogram of
+// delta >> hist_shift over kHistBins bins (added into `hist`).
+constexpr int kHistBins = 2048;
 hipError_t launch_keys(const void* pts, int elem_bytes, int64_t n, int32_t d, int ib,
-                       uint64_t* keys, bool use_mfma, hipStream_t s);
+                       uint64_t* keys, bool use_mfma, int hist_shift, uint32_t* hist,
+                       hipStream_t s);
 
 // Step 2: one stable LSD pass in -> out by digit (key >> shift) & ((1<<bits)-1).
 // `counts` holds radix_count_entries(count) words of scratch.
 int64_t radix_tiles(int64_t count);
 int64_t radix_count_entries(int64_t count);
+// Keys with (key >> fshift) outside [flo, fhi) are skipped (neither counted
+// nor written); `expect` is how many keys are kept (the output length).
+struct KeyFilter {
+  int fshift = 0;
+  uint64_t flo = 0, fhi = ~0ull;
+};
 hipError_t launch_radix_pass(const uint64_t* in, uint64_t* out, int64_t count, int shift,
-                             int bits, uint32_t* counts, int32_t* err, hipStream_t s);
+                             int bits, uint32_t* counts, int32_t* err, hipStream_t s,
+                             KeyFilter f = KeyFilter(), int64_t expect = -1);
 
 // Steps 4-5: round-based reduction.
 struct RedArgs {
@@ -91,7 +102,9 @@ struct RedArgs {
   Ring ring;
   RedCtl* ctl;
 };
-hipError_t launch_reduce_init(const RedArgs& a, hipStream_t s);
+hipError_t launch_reduce_init(const RedArgs& a, int64_t E_lim, hipStream_t s);
+// More sorted columns are available: [old E_lim, E_lim).
+hipError_t launch_reduce_extend(const RedArgs& a, int64_t E_lim, hipStream_t s);
 // One round: walk, decide, commit, advance.  When `ev_walk` is non-null its
 // two events are recorded around the walk kernel.
 hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_walk);

@@ -25,8 +25,10 @@ constexpr int kRounds = 16;
 constexpr int kTileKeys = kThreads * kRounds;  // 4096
 constexpr int kScanBlock = 4096;                // counts scanned per block
 
-// Exclusive scan of one value per thread over a 256-thread block.
-__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* >= 4 */) {
+// Exclusive scan of one value per thread over a 256-thread block (the block
+// total goes to *total when given).
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* >= 4 */,
+                                         uint32_t* total = nullptr) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t x = v;
 #pragma unroll
@@ -38,15 +40,22 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* >= 4 *
   __syncthreads();
   uint32_t base = 0;
   for (int w = 0; w < wave; ++w) base += scratch[w];
+  if (total) *total = scratch[0] + scratch[1] + scratch[2] + scratch[3];
   __syncthreads();
   return base + x - v;
 }
 
 // Load this wave's 16 x 64 keys of the tile and rank each among equal
 // digits inside the wave (running counts per wave in wcnt).
+__device__ inline bool kept(uint64_t key, const KeyFilter& f) {
+  const uint64_t v = key >> f.fshift;
+  return v >= f.flo && v < f.fhi;
+}
+
 __device__ inline void load_and_rank(const uint64_t* __restrict__ in, int64_t count, int64_t base,
-                                     int shift, int bits, uint32_t dmask, uint64_t (&key)[kRounds],
-                                     uint32_t (&rank)[kRounds], uint32_t* wcnt_wave) {
+                                     int shift, int bits, uint32_t dmask, const KeyFilter& f,
+                                     uint64_t (&key)[kRounds], uint32_t (&rank)[kRounds],
+                                     uint32_t* wcnt_wave) {
   const int lane = threadIdx.x & 63;
   const uint64_t lt_mask = (1ull << lane) - 1ull;
 #pragma unroll
@@ -57,7 +66,7 @@ __device__ inline void load_and_rank(const uint64_t* __restrict__ in, int64_t co
   }
 #pragma unroll
   for (int k = 0; k < kRounds; ++k) {
-    const bool valid = base + k * 64 + lane < count;
+    const bool valid = base + k * 64 + lane < count && kept(key[k], f);
     const uint32_t dg = (uint32_t)(key[k] >> shift) & dmask;
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < bits; ++b) {
@@ -81,7 +90,8 @@ __device__ inline void load_and_rank(const uint64_t* __restrict__ in, int64_t co
 __global__ __launch_bounds__(kThreads) void k_radix_count(const uint64_t* __restrict__ in,
                                                           int64_t count, int shift, int bits,
                                                           int64_t ntiles,
-                                                          uint32_t* __restrict__ counts) {
+                                                          uint32_t* __restrict__ counts,
+                                                          KeyFilter f) {
   __shared__ uint32_t wcnt[kWaves][256];
   const int tid = threadIdx.x, wave = tid >> 6;
   const uint32_t nbins = 1u << bits, dmask = nbins - 1u;
@@ -93,7 +103,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_count(const uint64_t* __rest
   const int64_t base = tile * kTileKeys + (int64_t)wave * 64 * kRounds;
   uint64_t key[kRounds];
   uint32_t rank[kRounds];
-  load_and_rank(in, count, base, shift, bits, dmask, key, rank, wcnt[wave]);
+  load_and_rank(in, count, base, shift, bits, dmask, f, key, rank, wcnt[wave]);
   __syncthreads();
   if ((uint32_t)tid < nbins) {
     uint32_t c = 0;
@@ -158,7 +168,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint64_t* __re
                                                             int64_t count, int shift, int bits,
                                                             int64_t ntiles,
                                                             const uint32_t* __restrict__ offsets,
-                                                            int32_t* err) {
+                                                            int32_t* err, KeyFilter f,
+                                                            int64_t out_count) {
   __shared__ uint32_t wcnt[kWaves][256];
   __shared__ uint32_t tile_start[256];  // first LDS slot of each digit in the tile
   __shared__ uint32_t gbase[256];       // output position of the digit's first key here
@@ -175,7 +186,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint64_t* __re
   const int64_t base = tile * kTileKeys + (int64_t)wave * 64 * kRounds;
   uint64_t key[kRounds];
   uint32_t rank[kRounds];
-  load_and_rank(in, count, base, shift, bits, dmask, key, rank, wcnt[wave]);
+  load_and_rank(in, count, base, shift, bits, dmask, f, key, rank, wcnt[wave]);
   __syncthreads();
 
   // Per digit: prefix over waves, the tile total, its start in the tile.
@@ -190,27 +201,26 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint64_t* __re
     }
     total = (uint32_t)tid < nbins ? run : 0;
   }
-  const uint32_t start = block_exclusive_scan(total, scan_tmp);
+  uint32_t tile_kept;
+  const uint32_t start = block_exclusive_scan(total, scan_tmp, &tile_kept);
   tile_start[tid] = start;
   gbase[tid] = (uint32_t)tid < nbins ? offsets[(int64_t)tid * ntiles + tile] : 0;
   __syncthreads();
 
 #pragma unroll
   for (int k = 0; k < kRounds; ++k) {
-    if (base + k * 64 + lane < count) {
+    if (base + k * 64 + lane < count && kept(key[k], f)) {
       const uint32_t dg = (uint32_t)(key[k] >> shift) & dmask;
       skeys[tile_start[dg] + wcnt[wave][dg] + rank[k]] = key[k];
     }
   }
   __syncthreads();
-  const int64_t tile_base = tile * kTileKeys;
-  const int64_t valid_n = count - tile_base < kTileKeys ? count - tile_base : kTileKeys;
   bool oob = false;
-  for (int pos = tid; pos < valid_n; pos += kThreads) {
+  for (int pos = tid; pos < (int)tile_kept; pos += kThreads) {
     const uint64_t k = skeys[pos];
     const uint32_t dg = (uint32_t)(k >> shift) & dmask;
     const uint64_t dst = (uint64_t)gbase[dg] + (uint64_t)(pos - tile_start[dg]);
-    if (dst < (uint64_t)count)
+    if (dst < (uint64_t)out_count)
       out[dst] = k;
     else
       oob = true;  // inconsistent counts: report, never write outside
@@ -228,21 +238,23 @@ int64_t radix_count_entries(int64_t count) {
 }
 
 hipError_t launch_radix_pass(const uint64_t* in, uint64_t* out, int64_t count, int shift,
-                             int bits, uint32_t* counts, int32_t* err, hipStream_t s) {
+                             int bits, uint32_t* counts, int32_t* err, hipStream_t s,
+                             KeyFilter f, int64_t expect) {
+  const int64_t out_count = expect >= 0 ? expect : count;
   const int64_t tiles = radix_tiles(count);
   if (tiles == 0) return hipSuccess;
   const int64_t len = (int64_t)(1 << bits) * tiles;
   const int64_t nblocks = (len + kScanBlock - 1) / kScanBlock;
   uint32_t* totals = counts + 256 * tiles;
   hipLaunchKernelGGL(k_radix_count, dim3((unsigned)tiles), dim3(kThreads), 0, s, in, count,
-                     shift, bits, tiles, counts);
+                     shift, bits, tiles, counts, f);
   hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)nblocks), dim3(kThreads), 0, s, counts, len,
                      totals);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, s, totals, nblocks);
   hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblocks), dim3(kThreads), 0, s, counts, len,
                      totals);
   hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)tiles), dim3(kThreads), 0, s, in, out,
-                     count, shift, bits, tiles, counts, err);
+                     count, shift, bits, tiles, counts, err, f, out_count);
   return hipGetLastError();
 }
 

@@ -459,10 +459,15 @@ __global__ void k_advance(RedCtl* ctl, int64_t n, int64_t E, int64_t Wcap) {
     // pivot still need finishing (for the exact addition count).
     if (F >= ctl->E_eff) ctl->done = 1;
   } else {
-    Wend = F + Wcap < E ? F + Wcap : E;
-    if (F >= E) {
-      ctl->done = 1;
-      ctl->err |= 2;
+    const int64_t lim = ctl->E_lim;
+    Wend = F + Wcap < lim ? F + Wcap : lim;
+    if (F >= lim) {
+      if (lim < E) {
+        ctl->need_more = 1;  // the host sorts the next distance range
+      } else {
+        ctl->done = 1;
+        ctl->err |= 2;
+      }
     }
   }
   ctl->fresh_lo = ctl->Wend;
@@ -476,16 +481,29 @@ __global__ void k_advance(RedCtl* ctl, int64_t n, int64_t E, int64_t Wcap) {
   ctl->round = round + 1;
 }
 
-__global__ void k_reduce_init(RedCtl* ctl, int64_t E, int64_t Wcap, int64_t n) {
+__global__ void k_reduce_extend(RedCtl* ctl, int64_t E_lim, int64_t Wcap) {
+  // All columns before the old limit are final here (F == old limit).
+  ctl->E_lim = E_lim;
+  ctl->need_more = 0;
+  const int64_t F = ctl->F;
+  const int64_t Wend = F + Wcap < E_lim ? F + Wcap : E_lim;
+  ctl->fresh_lo = ctl->Wend;
+  ctl->fresh_hi = Wend;
+  ctl->Wend = Wend;
+  if (Wend > ctl->maxWend) ctl->maxWend = Wend;
+}
+
+__global__ void k_reduce_init(RedCtl* ctl, int64_t E_lim, int64_t Wcap, int64_t n) {
   RedCtl c = {};
   c.F = 0;
-  c.Wend = Wcap < E ? Wcap : E;
+  c.E_lim = E_lim;
+  c.Wend = Wcap < E_lim ? Wcap : E_lim;
   c.maxWend = c.Wend;
   c.fresh_lo = 0;
   c.fresh_hi = c.Wend;
   c.firstdup[0] = c.firstdup[1] = kNoValue;
   c.newF[0] = c.newF[1] = kNoValue;
-  c.done = (n <= 1 || E == 0) ? 1 : 0;
+  c.done = (n <= 1 || E_lim == 0) ? 1 : 0;
   *ctl = c;
 }
 
@@ -564,7 +582,12 @@ bool launch_walk_shape(const RedArgs& a, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_reduce_init(const RedArgs& a, hipStream_t s) {
+hipError_t launch_reduce_extend(const RedArgs& a, int64_t E_lim, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_extend, dim3(1), dim3(1), 0, s, a.ctl, E_lim, a.Wcap);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_init(const RedArgs& a, int64_t E_lim, hipStream_t s) {
   hipError_t e;
   if ((e = launch_fill_u64(a.table, 0ull, a.n * a.LW, s)) != hipSuccess) return e;
   if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(a.killer), ~0ull, a.n, s)) != hipSuccess)
@@ -574,7 +597,7 @@ hipError_t launch_reduce_init(const RedArgs& a, hipStream_t s) {
   if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(a.ring.tag), ~0ull, a.Wcap, s)) !=
       hipSuccess)
     return e;
-  hipLaunchKernelGGL(k_reduce_init, dim3(1), dim3(1), 0, s, a.ctl, a.E, a.Wcap, a.n);
+  hipLaunchKernelGGL(k_reduce_init, dim3(1), dim3(1), 0, s, a.ctl, E_lim, a.Wcap, a.n);
   return hipGetLastError();
 }
 

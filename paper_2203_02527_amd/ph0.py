@@ -57,6 +57,8 @@ class ph0_stats(ctypes.Structure):
         ("ms_radix_kernel", ctypes.c_float),
         ("walk_launches", ctypes.c_int32),
         ("radix_launches", ctypes.c_int32),
+        ("sort_chunks", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def to_dict(self) -> dict:
