@@ -27,6 +27,10 @@ WORKLOAD = "mixture_n16384_d64_i8"
 HBM_PEAK_GBS = 8000.0
 
 
+def note(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +133,22 @@ def bench_serving(ph0, synth, count):
     }
 
 
+def sort_bytes(st):
+    """Algorithmic bytes of one call's radix passes: a pass reads its input
+    keys once and writes its output keys once (8 bytes each).  A distance
+    chunk's first pass reads all E keys and keeps the chunk's; its later
+    passes read and write the chunk's keys only.  When the sort finished
+    with one whole sort, that sort moves all E keys in every pass (the
+    chunks sorted before it are then not counted, which only lowers the
+    figure)."""
+    E, P, k, c = st["E"], st["sort_passes"], st["sorted_keys"], st["sort_chunks"]
+    if P == 0:
+        return 0.0
+    if k < E:
+        return 8.0 * E * c + 8.0 * k + 16.0 * (P - 1) * k
+    return 8.0 * E * (c - 1) + 16.0 * E * P
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -165,6 +185,7 @@ def main():
     t0 = time.perf_counter()
     for _ in range(args.steps):
         _, st = ph0.ph0_barcodes_device(x, out=out, workspace=ws, stream=stream, with_stats=True)
+        st["radix_bytes"] = sort_bytes(st)
         stats.append(st)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
@@ -181,7 +202,10 @@ def main():
     walk_bytes = 8.0 * mean("words_read")  # pivot-table words the walks load
     radix_ms = mean("ms_radix_kernel")
     radix_launches = mean("radix_launches")
-    radix_bytes = 16.0 * E * st0["sort_passes"]  # every pass reads and writes each key
+    # A radix pass reads its input keys once and writes its output keys once.
+    # Each distance chunk's first pass reads all E keys and keeps the chunk;
+    # its later passes read and write only the chunk's keys.
+    radix_bytes = mean("radix_bytes")
     kern = {
         "reduce_walk": dict(ms=walk_ms, launches=walk_launches, bytes=walk_bytes,
                             per_launch_ms=walk_ms / max(walk_launches, 1)),
@@ -234,12 +258,16 @@ def main():
         "roofline": roofline,
         "kernels": others,
     }
+    note("timed %d steps: %.3f ms/step" % (args.steps, ms_step))
     if not args.no_batched:
         rec["batched"] = bench_batched(torch, ph0, synth)
+        note("batched done")
     if not args.no_serving:
         rec["serving"] = bench_serving(ph0, synth, args.serve_requests)
+        note("serving done")
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(pts, n // 2)
+        note("cpu baseline done")
     print(json.dumps(rec), flush=True)
 
 

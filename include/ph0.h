@@ -84,6 +84,7 @@ typedef struct {
   int32_t radix_launches;
   int32_t sort_chunks;     /* distance ranges sorted (1 = only the first) */
   int32_t reserved;
+  int64_t sorted_keys;     /* keys put in sorted order: the sorted prefix length */
 } ph0_stats;
 
 /* Message for the last non-OK status returned on this thread. */
@@ -208,6 +209,11 @@ int ph0_set_window(int64_t columns);
  * row, at most 64).  Fewer lanes put more columns in flight per wavefront.
  * Affects speed only, never results.  Process-wide. */
 int ph0_set_walk_lanes(int32_t lanes);
+
+/* Columns one full wavefront walks side by side (1..4; 0 restores the
+ * built-in 1): more keeps more pivot-table fetches in flight per wavefront.
+ * Used when a pivot row needs all 64 lanes (N > 2048).  Speed only. */
+int ph0_set_walk_per_wave(int32_t columns);
 
 #ifdef __cplusplus
 }

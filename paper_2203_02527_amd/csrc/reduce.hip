@@ -313,6 +313,371 @@ __global__ __launch_bounds__(256) void k_walk(const uint64_t* __restrict__ skeys
   }
 }
 
+// ---- full-wave walk (N > 2048: a pivot row needs all 64 lanes) ----
+//
+// The walk is bound by instruction issue, not by memory, so this version
+// keeps every per-step quantity scalar: the current low r is wave-uniform,
+// the row's address and length go into a buffer resource (words past the
+// row's top word come back as zero from the hardware range check), only the
+// word slots at or below the low's slot are loaded, and the top-bit search
+// starts at that slot.  Word w of a column lives in lane w % 64, slot w / 64.
+
+__device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const uint64_t* table, int64_t LW, int r) {
+  const int top = r >> 6;
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(table + (int64_t)r * LW), 0, (top + 1) * 8,
+                                           0x00020000);
+}
+
+template <int WPL>
+__device__ inline void wide_load(uint64_t (&v)[WPL], __amdgpu_buffer_rsrc_t rs, int qmax,
+                                 int lane) {
+#pragma unroll
+  for (int q = 0; q < WPL; ++q) {
+    if (q <= qmax) {
+      const auto x = __builtin_amdgcn_raw_buffer_load_b64(rs, lane * 8, q * 512, 0);
+      v[q] = ((uint64_t)x[1] << 32) | x[0];
+    } else {
+      v[q] = 0;
+    }
+  }
+}
+
+// Highest set bit among slots 0..qmax, or -1.
+template <int WPL>
+__device__ inline int wide_top(const uint64_t (&w)[WPL], int qmax) {
+#pragma unroll
+  for (int q = WPL - 1; q >= 0; --q) {
+    if (q > qmax) continue;
+    const uint64_t m = __ballot(w[q] != 0);
+    if (m) {
+      const int L = 63 - __clzll(m);
+      const uint64_t word = readlane64(w[q], L);
+      return (q * 64 + L) * 64 + 63 - __clzll(word);
+    }
+  }
+  return -1;
+}
+
+template <int WPL>
+__device__ inline void wide_flip(uint64_t (&w)[WPL], int lane, int bit) {
+  const int word = bit >> 6;
+  const uint64_t b = (lane == (word & 63)) ? (1ull << (bit & 63)) : 0ull;
+#pragma unroll
+  for (int q = 0; q < WPL; ++q)
+    if (q == (word >> 6)) w[q] ^= b;
+}
+
+template <int WPL>
+__global__ __launch_bounds__(256) void k_walk_wide(const uint64_t* __restrict__ skeys, int ib,
+                                                   int64_t LW, const uint64_t* __restrict__ table,
+                                                   Ring ring, int64_t Wcap, const int64_t* act0,
+                                                   const int64_t* act1, uint64_t* lowc,
+                                                   uint64_t* touch, RedCtl* ctl) {
+  if (ctl->done) return;
+  const int64_t nA = ctl->nA, round = ctl->round, fresh_lo = ctl->fresh_lo;
+  const int64_t items = nA + (ctl->fresh_hi - fresh_lo);
+  const int64_t* act = ctl->cur ? act1 : act0;
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64;
+  const int64_t wtotal = (int64_t)gridDim.x * (blockDim.x / 64);
+  const uint64_t imask = (1ull << ib) - 1ull;
+
+  int64_t adds = 0, finds = 0, words = 0;
+  int32_t bad = 0;
+  for (int64_t t = wid; t < items; t += wtotal) {
+    int64_t p;
+    int a, r, rlo, prev;
+    if (t < nA) {
+      p = act[t];
+      const int64_t q = p & (Wcap - 1);
+      a = ring.a[q];
+      r = ring.r[q];
+      rlo = ring.rlo[q];
+      prev = ring.st[q] >> 2;
+    } else {
+      p = fresh_lo + (t - nA);
+      const uint64_t key = skeys[p];
+      a = (int)(key & imask);
+      r = (int)((key >> ib) & imask);
+      rlo = a;
+      prev = 0;
+    }
+    a = __builtin_amdgcn_readfirstlane(a);
+    r = __builtin_amdgcn_readfirstlane(r);
+    rlo = __builtin_amdgcn_readfirstlane(rlo);
+    uint64_t col[WPL];
+#pragma unroll
+    for (int q = 0; q < WPL; ++q) col[q] = 0;
+    wide_flip<WPL>(col, lane, a);
+    wide_flip<WPL>(col, lane, r);
+    int moved = 0;
+    bool zero = false;
+    while (true) {
+      const int top = r >> 6, qmax = top >> 6;
+      uint64_t v[WPL];
+      wide_load<WPL>(v, row_rsrc(table, LW, r), qmax, lane);
+#pragma unroll
+      for (int q = 0; q < WPL; ++q) col[q] ^= v[q];
+      words += top + 1;
+      const int nr = __builtin_amdgcn_readfirstlane(wide_top<WPL>(col, qmax));
+      if (nr == r) break;  // row r is empty: slot r is free
+      ++moved;
+      if (nr < 0) {
+        zero = true;
+        break;
+      }
+      if (nr > r) {  // lows must decrease; a corrupt table ends the walk
+        bad = 1;
+        zero = true;
+        break;
+      }
+      r = nr;
+    }
+    adds += moved;
+    int32_t status = kActive;
+    if (zero) {
+      status = kZero;
+    } else {
+      const int qmax = (r >> 6) >> 6;
+      wide_flip<WPL>(col, lane, r);
+      const int na = __builtin_amdgcn_readfirstlane(wide_top<WPL>(col, qmax));
+      if (na >= 0) wide_flip<WPL>(col, lane, na);
+      bool rest = false;
+#pragma unroll
+      for (int q = 0; q < WPL; ++q) rest |= col[q] != 0;
+      if (na < 0 || __ballot(rest) != 0) bad = 1;
+      a = na < 0 ? 0 : na;
+      // Root of row a in the current forest: follow stored columns down.
+      int v = moved ? a : rlo;
+      while (true) {
+        const int top = v >> 6, qmax_v = top >> 6;
+        uint64_t row[WPL];
+        wide_load<WPL>(row, row_rsrc(table, LW, v), qmax_v, lane);
+        words += top + 1;
+        const uint64_t own = (lane == (top & 63)) ? (1ull << (v & 63)) : 0ull;
+#pragma unroll
+        for (int q = 0; q < WPL; ++q)
+          if (q == qmax_v) row[q] &= ~own;
+        const int c = __builtin_amdgcn_readfirstlane(wide_top<WPL>(row, qmax_v));
+        if (c < 0) break;  // empty row: v is a root
+        ++finds;
+        if (c >= v) {
+          bad = 1;
+          break;
+        }
+        v = c;
+      }
+      rlo = v;
+      if (lane == 0) {
+        const uint64_t e = enc(round, p);
+        filtered_min(&lowc[r], e);
+        filtered_min(&touch[rlo], e);
+      }
+    }
+    if (lane == 0) {
+      const int64_t q = p & (Wcap - 1);
+      ring.a[q] = a;
+      ring.r[q] = r;
+      ring.rlo[q] = rlo;
+      ring.st[q] = status | ((prev + moved) << 2);
+      ring.tag[q] = p;
+    }
+  }
+  __shared__ unsigned long long s_cnt[3];
+  __shared__ int s_bad;
+  if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  if (lane == 0) {
+    if (adds) atomicAdd(&s_cnt[0], (unsigned long long)adds);
+    if (finds) atomicAdd(&s_cnt[1], (unsigned long long)finds);
+    if (words) atomicAdd(&s_cnt[2], (unsigned long long)words);
+    if (bad) s_bad = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_cnt[0]) atomicAdd((unsigned long long*)&ctl->additions_all, s_cnt[0]);
+    if (s_cnt[1]) atomicAdd((unsigned long long*)&ctl->find_steps, s_cnt[1]);
+    if (s_cnt[2]) atomicAdd((unsigned long long*)&ctl->words_read, s_cnt[2]);
+    if (s_bad) atomicOr(&ctl->err, 1);
+  }
+}
+
+// The same walk for full-wave groups, with K columns per wave side by side.
+// Each column is a small state machine -- WALK (XOR the stored column of the
+// current low in), FIND (follow the root of the other row), then done -- and
+// one pass of the loop first issues the row loads of all K columns, then
+// consumes them, so a wave keeps K row fetches in flight instead of one.
+// Every step is the same as in k_walk; only the interleaving differs.
+template <int WPL, int K>
+__global__ __launch_bounds__(256) void k_walk_multi(const uint64_t* __restrict__ skeys, int ib,
+                                                    int64_t LW,
+                                                    const uint64_t* __restrict__ table,
+                                                    Ring ring, int64_t Wcap, const int64_t* act0,
+                                                    const int64_t* act1, uint64_t* lowc,
+                                                    uint64_t* touch, RedCtl* ctl) {
+  constexpr int G = 64;
+  constexpr int kIdle = 0, kWalk = 1, kFind = 2;
+  if (ctl->done) return;
+  const int64_t nA = ctl->nA, round = ctl->round, fresh_lo = ctl->fresh_lo;
+  const int64_t items = nA + (ctl->fresh_hi - fresh_lo);
+  const int64_t* act = ctl->cur ? act1 : act0;
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64;
+  const int64_t wtotal = (int64_t)gridDim.x * (blockDim.x / 64);
+  const uint64_t imask = (1ull << ib) - 1ull;
+
+  int64_t next_t = wid;
+  int64_t adds = 0, finds = 0, words = 0;
+  int32_t bad = 0;
+  uint64_t col[K][WPL];
+  int mode[K], r[K], a[K], rlo[K], v[K], moved[K], prev[K];
+  int64_t pcol[K];
+
+  auto start = [&](int k) {
+    mode[k] = kIdle;
+    r[k] = v[k] = a[k] = rlo[k] = moved[k] = prev[k] = 0;
+    pcol[k] = 0;
+    if (next_t >= items) return;
+    const int64_t t = next_t;
+    next_t += wtotal;
+    int64_t p;
+    int aa, rr, ll, ps;
+    if (t < nA) {
+      p = act[t];
+      const int64_t q = p & (Wcap - 1);
+      aa = ring.a[q];
+      rr = ring.r[q];
+      ll = ring.rlo[q];
+      ps = ring.st[q] >> 2;
+    } else {
+      p = fresh_lo + (t - nA);
+      const uint64_t key = skeys[p];
+      aa = (int)(key & imask);
+      rr = (int)((key >> ib) & imask);
+      ll = aa;
+      ps = 0;
+    }
+    pcol[k] = p;
+    a[k] = __builtin_amdgcn_readfirstlane(aa);
+    r[k] = __builtin_amdgcn_readfirstlane(rr);
+    rlo[k] = __builtin_amdgcn_readfirstlane(ll);
+    prev[k] = __builtin_amdgcn_readfirstlane(ps);
+    moved[k] = 0;
+#pragma unroll
+    for (int q = 0; q < WPL; ++q) col[k][q] = 0;
+    flip_bit<G, WPL>(col[k], lane, a[k]);
+    flip_bit<G, WPL>(col[k], lane, r[k]);
+    mode[k] = kWalk;
+  };
+  auto finish = [&](int k, int32_t status) {
+    if (lane == 0) {
+      const int64_t q = pcol[k] & (Wcap - 1);
+      ring.a[q] = a[k];
+      ring.r[q] = r[k];
+      ring.rlo[q] = rlo[k];
+      ring.st[q] = status | ((prev[k] + moved[k]) << 2);
+      ring.tag[q] = pcol[k];
+      if (status == kActive) {
+        const uint64_t e = enc(round, pcol[k]);
+        filtered_min(&lowc[r[k]], e);
+        filtered_min(&touch[rlo[k]], e);
+      }
+    }
+    adds += moved[k];
+    start(k);
+  };
+
+#pragma unroll
+  for (int k = 0; k < K; ++k) start(k);
+  while (true) {
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) any |= mode[k] != kIdle;
+    if (!any) break;
+    // Issue every active column's row loads.
+    uint64_t rv[K][WPL];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int row = mode[k] == kFind ? v[k] : r[k];
+      const int top = row >> 6;
+      const uint64_t* rp = table + (int64_t)row * LW;
+#pragma unroll
+      for (int q = 0; q < WPL; ++q) {
+        const int widx = q * G + lane;
+        rv[k][q] = mode[k] != kIdle ? rp[widx <= top ? widx : top] : 0ull;
+      }
+    }
+    // Consume them.
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (mode[k] == kWalk) {
+        const int top = r[k] >> 6;
+#pragma unroll
+        for (int q = 0; q < WPL; ++q) col[k][q] ^= (q * G + lane <= top) ? rv[k][q] : 0ull;
+        words += top + 1;
+        const int nr = __builtin_amdgcn_readfirstlane(group_top_bit<G, WPL>(col[k], 0, top / G));
+        if (nr == r[k]) {  // slot r is free: a survivor; find the other row's root
+          flip_bit<G, WPL>(col[k], lane, r[k]);
+          const int na = __builtin_amdgcn_readfirstlane(group_top_bit<G, WPL>(col[k], 0, top / G));
+          if (na >= 0) flip_bit<G, WPL>(col[k], lane, na);
+          bool rest = false;
+#pragma unroll
+          for (int q = 0; q < WPL; ++q) rest |= col[k][q] != 0;
+          if (na < 0 || group_any<G>(rest, 0)) bad = 1;
+          a[k] = na < 0 ? 0 : na;
+          v[k] = moved[k] ? a[k] : rlo[k];
+          mode[k] = kFind;
+        } else if (nr < 0 || nr > r[k]) {  // zero column (or a corrupt table)
+          if (nr > r[k]) bad = 1;
+          ++moved[k];
+          finish(k, kZero);
+        } else {
+          ++moved[k];
+          r[k] = nr;
+        }
+      } else if (mode[k] == kFind) {
+        const int top = v[k] >> 6;
+        uint64_t row[WPL];
+#pragma unroll
+        for (int q = 0; q < WPL; ++q) row[q] = (q * G + lane <= top) ? rv[k][q] : 0ull;
+        words += top + 1;
+        clear_bit<G, WPL>(row, lane, v[k]);
+        const int c = __builtin_amdgcn_readfirstlane(group_top_bit<G, WPL>(row, 0, top / G));
+        if (c < 0) {  // empty row: v is the root
+          rlo[k] = v[k];
+          finish(k, kActive);
+        } else if (c >= v[k]) {
+          bad = 1;
+          rlo[k] = v[k];
+          finish(k, kActive);
+        } else {
+          ++finds;
+          v[k] = c;
+        }
+      }
+    }
+  }
+  __shared__ unsigned long long s_cnt[3];
+  __shared__ int s_bad;
+  if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  if (lane == 0) {
+    if (adds) atomicAdd(&s_cnt[0], (unsigned long long)adds);
+    if (finds) atomicAdd(&s_cnt[1], (unsigned long long)finds);
+    if (words) atomicAdd(&s_cnt[2], (unsigned long long)words);
+    if (bad) s_bad = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_cnt[0]) atomicAdd((unsigned long long*)&ctl->additions_all, s_cnt[0]);
+    if (s_cnt[1]) atomicAdd((unsigned long long*)&ctl->find_steps, s_cnt[1]);
+    if (s_cnt[2]) atomicAdd((unsigned long long*)&ctl->words_read, s_cnt[2]);
+    if (s_bad) atomicOr(&ctl->err, 1);
+  }
+}
+
 // Block-wide reductions for the 256-thread decide/commit kernels.
 __device__ inline uint64_t block_min_u64(uint64_t v, uint64_t* tmp /* 4 */) {
   v = wave_min_u64(v);
@@ -543,6 +908,25 @@ void walk_launch(const RedArgs& a, hipStream_t s) {
   const int64_t cap = 8 * (int64_t)device_cus();
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
+  if constexpr (G == 64) {
+    if (a.per_wave <= 1) {
+      hipLaunchKernelGGL((k_walk_wide<WPL>), dim3((unsigned)blocks), dim3(256), 0, s, a.skeys,
+                         a.ib, a.LW, a.table, a.ring, a.Wcap, a.act[0], a.act[1], a.lowc,
+                         a.touch, a.ctl);
+      return;
+    }
+    if (a.per_wave > 1) {
+#define PH0_MULTI(k)                                                                           \
+  if (a.per_wave == k) {                                                                      \
+    hipLaunchKernelGGL((k_walk_multi<WPL, k>), dim3((unsigned)blocks), dim3(256), 0, s,        \
+                       a.skeys, a.ib, a.LW, a.table, a.ring, a.Wcap, a.act[0], a.act[1],      \
+                       a.lowc, a.touch, a.ctl);                                               \
+    return;                                                                                   \
+  }
+      PH0_MULTI(2) PH0_MULTI(3) PH0_MULTI(4)
+#undef PH0_MULTI
+    }
+  }
   hipLaunchKernelGGL((k_walk<G, WPL>), dim3((unsigned)blocks), dim3(256), 0, s, a.skeys, a.ib,
                      a.LW, a.table, a.ring, a.Wcap, a.act[0], a.act[1], a.lowc, a.touch, a.ctl);
 }
