@@ -44,7 +44,24 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device 5 times (a reference kernel of "
+                         "known traffic for hardware byte counters) and exit")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    """Five device-to-device copies of mib MiB: each reads and writes exactly
+    mib MiB, which scales the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+
+    a = torch.empty(mib << 20, dtype=torch.uint8, device="cuda:0").fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": mib << 20, "copies": 5}), flush=True)
 
 
 def cpu_baseline(points, n_sample):
@@ -155,6 +172,9 @@ def main():
         print("bench.py runs on exactly one GPU; this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     import numpy as np
     import torch
 

@@ -57,7 +57,7 @@ int index_bits(int64_t n) { return n <= 1 ? 0 : 64 - __builtin_clzll((uint64_t)(
 // state is a ring indexed by column & (window - 1)).
 int64_t window_for(int64_t n, int64_t E) {
   int64_t w = g_window.load();
-  if (w <= 0) w = std::max<int64_t>(65536, 16 * n);
+  if (w <= 0) w = std::max<int64_t>(65536, 8 * n);
   w = std::min<int64_t>(w, std::max<int64_t>(E, 1));
   int64_t p = 1;
   while (p < w) p <<= 1;

@@ -315,12 +315,14 @@ __global__ __launch_bounds__(256) void k_walk(const uint64_t* __restrict__ skeys
 
 // ---- full-wave walk (N > 2048: a pivot row needs all 64 lanes) ----
 //
-// The walk is bound by instruction issue, not by memory, so this version
-// keeps every per-step quantity scalar: the current low r is wave-uniform,
-// the row's address and length go into a buffer resource (words past the
-// row's top word come back as zero from the hardware range check), only the
-// word slots at or below the low's slot are loaded, and the top-bit search
-// starts at that slot.  Word w of a column lives in lane w % 64, slot w / 64.
+// The walk is bound by instruction issue and load latency, not by HBM
+// bandwidth, so this version keeps every per-step quantity scalar: the
+// current low r is wave-uniform, the row's address and length go into a
+// buffer resource (words past the row's top word come back as zero from the
+// hardware range check), and the loop runs in stages by the number S of
+// 64-word slots the row prefix spans (S = r / 4096 + 1, which only falls as
+// r falls), so each stage loads, XORs and searches exactly S slots with no
+// per-slot tests.  Word w of a column lives in lane w % 64, slot w / 64.
 
 __device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const uint64_t* table, int64_t LW, int r) {
   const int top = r >> 6;
@@ -358,13 +360,85 @@ __device__ inline int wide_top(const uint64_t (&w)[WPL], int qmax) {
   return -1;
 }
 
+// One walk step against row r, whose prefix spans S slots: XOR the row's
+// words 0..r/64 into the column and return the column's new top bit (-1 if
+// the column became zero).  Slots >= S of the column are zero already (its
+// bits are <= r), so only S slots are loaded and searched.  The search takes
+// one ballot per slot and picks the highest non-empty slot with scalar
+// selects; the row's byte offset r * rowb is 32-bit (the table stays below
+// 4 GiB for every supported N).
+template <int WPL, int S>
+__device__ inline int wide_step(uint64_t (&col)[WPL], const char* tbase, uint32_t rowb, int r,
+                                int lane) {
+  const uint32_t nrec = (((uint32_t)r | 63u) >> 3) + 1u;  // (r / 64 + 1) words
+  const auto rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(tbase + (uint32_t)r * rowb), 0, (int)nrec, 0x00020000);
+  uint64_t v[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    const auto x = __builtin_amdgcn_raw_buffer_load_b64(rs, lane * 8, q * 512, 0);
+    v[q] = ((uint64_t)x[1] << 32) | x[0];
+  }
+#pragma unroll
+  for (int q = 0; q < S; ++q) col[q] ^= v[q];
+  uint64_t m = __ballot(col[0] != 0);
+  int qs = 0;
+#pragma unroll
+  for (int q = 1; q < S; ++q) {
+    const uint64_t mq = __ballot(col[q] != 0);
+    qs = mq ? q : qs;
+    m = mq ? mq : m;
+  }
+  if (m == 0) return -1;
+  const int L = 63 - __clzll(m);
+  uint64_t word = readlane64(col[0], L);
+#pragma unroll
+  for (int q = 1; q < S; ++q) {
+    const uint64_t wq = readlane64(col[q], L);
+    word = qs == q ? wq : word;
+  }
+  return (qs * 64 + L) * 64 + 63 - __clzll(word);
+}
+
+struct WalkState {
+  int r;      // current low (wave-uniform)
+  int moved;  // additions made
+  int words;  // table words loaded
+  bool stop, zero, bad;
+};
+
+// Steps on rows whose prefix spans S slots -- r >= (S - 1) * 4096; r < S *
+// 4096 holds already since r only decreases -- then the stages below.
+template <int WPL, int S>
+__device__ inline void wide_stages(uint64_t (&col)[WPL], const char* tbase, uint32_t rowb,
+                                   int lane, WalkState& w) {
+  while (!w.stop && w.r >= (S - 1) * 4096) {
+    const int r = w.r;
+    const int nr = __builtin_amdgcn_readfirstlane(wide_step<WPL, S>(col, tbase, rowb, r, lane));
+    w.words += (r >> 6) + 1;
+    if ((unsigned)nr >= (unsigned)r) {  // rare: row empty, zero column, or corrupt
+      w.stop = true;
+      if (nr == r) break;  // row r is empty: slot r is free
+      ++w.moved;
+      w.zero = true;
+      if (nr > r) w.bad = true;  // lows must decrease; a corrupt table ends the walk
+      break;
+    }
+    ++w.moved;
+    w.r = nr;
+  }
+  if constexpr (S > 1) wide_stages<WPL, S - 1>(col, tbase, rowb, lane, w);
+}
+
+// Every slot is XORed with a masked value (zero except in the bit's slot):
+// a conditional update of one slot would let the compiler turn the array
+// access into a dynamic index and move the column out of registers.
 template <int WPL>
 __device__ inline void wide_flip(uint64_t (&w)[WPL], int lane, int bit) {
   const int word = bit >> 6;
   const uint64_t b = (lane == (word & 63)) ? (1ull << (bit & 63)) : 0ull;
 #pragma unroll
-  for (int q = 0; q < WPL; ++q)
-    if (q == (word >> 6)) w[q] ^= b;
+  for (int q = 0; q < WPL; ++q) w[q] ^= b & (0ull - (uint64_t)(q == (word >> 6)));
 }
 
 template <int WPL>
@@ -381,6 +455,8 @@ __global__ __launch_bounds__(256) void k_walk_wide(const uint64_t* __restrict__ 
   const int64_t wid = blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64;
   const int64_t wtotal = (int64_t)gridDim.x * (blockDim.x / 64);
   const uint64_t imask = (1ull << ib) - 1ull;
+  const char* tbase = reinterpret_cast<const char*>(table);
+  const uint32_t rowb = (uint32_t)LW * 8u;
 
   int64_t adds = 0, finds = 0, words = 0;
   int32_t bad = 0;
@@ -410,30 +486,15 @@ __global__ __launch_bounds__(256) void k_walk_wide(const uint64_t* __restrict__ 
     for (int q = 0; q < WPL; ++q) col[q] = 0;
     wide_flip<WPL>(col, lane, a);
     wide_flip<WPL>(col, lane, r);
-    int moved = 0;
-    bool zero = false;
-    while (true) {
-      const int top = r >> 6, qmax = top >> 6;
-      uint64_t v[WPL];
-      wide_load<WPL>(v, row_rsrc(table, LW, r), qmax, lane);
-#pragma unroll
-      for (int q = 0; q < WPL; ++q) col[q] ^= v[q];
-      words += top + 1;
-      const int nr = __builtin_amdgcn_readfirstlane(wide_top<WPL>(col, qmax));
-      if (nr == r) break;  // row r is empty: slot r is free
-      ++moved;
-      if (nr < 0) {
-        zero = true;
-        break;
-      }
-      if (nr > r) {  // lows must decrease; a corrupt table ends the walk
-        bad = 1;
-        zero = true;
-        break;
-      }
-      r = nr;
-    }
+    WalkState w{r, 0, 0, false, false, false};
+    wide_stages<WPL, WPL>(col, tbase, rowb, lane, w);
+    r = w.r;
+    const int moved = w.moved;
+    const bool zero = w.zero;
+    bad |= w.bad;
+    const int cwords = w.words;
     adds += moved;
+    words += cwords;
     int32_t status = kActive;
     if (zero) {
       status = kZero;
@@ -456,8 +517,7 @@ __global__ __launch_bounds__(256) void k_walk_wide(const uint64_t* __restrict__ 
         words += top + 1;
         const uint64_t own = (lane == (top & 63)) ? (1ull << (v & 63)) : 0ull;
 #pragma unroll
-        for (int q = 0; q < WPL; ++q)
-          if (q == qmax_v) row[q] &= ~own;
+        for (int q = 0; q < WPL; ++q) row[q] &= ~(own & (0ull - (uint64_t)(q == qmax_v)));
         const int c = __builtin_amdgcn_readfirstlane(wide_top<WPL>(row, qmax_v));
         if (c < 0) break;  // empty row: v is a root
         ++finds;
