@@ -77,9 +77,11 @@ def cpu_baseline(points, n_sample):
         "unit": "edge columns/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": "first %d points of the same cloud (E=%d, E_eff=%d), whole oracle run "
-                  "(distances, std::sort, grades, dense F2 reduction, read-off) in %.2f s"
-                  % (n_sample, res.E, res.E_eff, t),
+        "sample": "%s (N=%d, E=%d, E_eff=%d), one whole oracle run (distances, std::sort, "
+                  "grades, dense F2 reduction with early exit, read-off) in %.2f s"
+                  % ("the whole benchmark cloud" if n_sample >= len(points) else
+                     "the first %d points of the benchmark cloud" % n_sample,
+                     n_sample, res.E, res.E_eff, t),
         "seconds": res.seconds,
     }
 
@@ -150,6 +152,35 @@ def bench_serving(ph0, synth, count):
     }
 
 
+KERNEL_SOURCES = {"reduce_walk": "reduce.hip", "radix_pass": "radix.hip"}
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    profiles/traffic_<kernel>_<workload>.txt (FETCH_SIZE and WRITE_SIZE per
+    dispatch, each scaled by what the counter reads for a copy of known
+    size), or None when there is no summary or the kernel's source has
+    changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (kernel, workload))
+    src = os.path.join(ROOT, "paper_2203_02527_amd", "csrc", KERNEL_SOURCES[kernel])
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != fields.get("source_sha256"):
+            return None
+    try:
+        return int(float(fields["hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def sort_bytes(st):
     """Algorithmic bytes of one call's radix passes: a pass reads its input
     keys once and writes its output keys once (8 bytes each).  A distance
@@ -217,14 +248,19 @@ def main():
         return float(np.mean([s[k] for s in stats]))
 
     # Kernel rooflines from the library's event timings over the timed steps.
+    # Walk: the algorithmic bytes are those of the dense method -- one N-bit
+    # pivot column (LW 64-bit words) per column addition of the sequential
+    # reduction, plus the 8-byte key of each column up to the last pivot.
+    # The kernel itself loads only the words of a stored column at or below
+    # its low (a stored column has no bits above it), which it reports as
+    # words_read; both rates are given.
+    LW = (n + 63) // 64
     walk_ms = mean("ms_walk_kernel")
     walk_launches = mean("walk_launches")
-    walk_bytes = 8.0 * mean("words_read")  # pivot-table words the walks load
+    walk_bytes = 8.0 * LW * mean("additions") + 8.0 * mean("E_eff")
+    walk_loaded = 8.0 * mean("words_read")
     radix_ms = mean("ms_radix_kernel")
     radix_launches = mean("radix_launches")
-    # A radix pass reads its input keys once and writes its output keys once.
-    # Each distance chunk's first pass reads all E keys and keeps the chunk;
-    # its later passes read and write only the chunk's keys.
     radix_bytes = mean("radix_bytes")
     kern = {
         "reduce_walk": dict(ms=walk_ms, launches=walk_launches, bytes=walk_bytes,
@@ -236,6 +272,8 @@ def main():
         k["achieved_gbs"] = k["bytes"] / max(k["ms"], 1e-9) / 1e6
     dom = max(kern, key=lambda k: kern[k]["ms"])
     kd = kern[dom]
+    per_launch = kd["bytes"] / max(kd["launches"], 1)
+    traffic = measured_traffic(dom, args.workload)
     roofline = {
         "kernel": dom,
         "bound": "hbm",
@@ -243,10 +281,15 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(kd["achieved_gbs"] / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": traffic,
         "avg_launch_ms": round(kd["per_launch_ms"], 4),
-        "algorithmic_bytes_per_launch": kd["bytes"] / max(kd["launches"], 1),
+        "algorithmic_bytes_per_launch": round(per_launch),
     }
+    if dom == "reduce_walk":
+        roofline["loaded_bytes_per_launch"] = round(walk_loaded / max(walk_launches, 1))
+        roofline["loaded_gbs"] = round(walk_loaded / max(walk_ms, 1e-9) / 1e6, 1)
+    if traffic is not None:
+        roofline["traffic_gbs"] = round(traffic / (kd["per_launch_ms"] * 1e6), 1)
     others = {k: {"achieved_gbs": round(v["achieved_gbs"], 1), "ms_per_step": round(v["ms"], 3),
                   "launches": v["launches"]} for k, v in kern.items()}
 
@@ -277,6 +320,13 @@ def main():
                                           "sort_passes", "delta_bits", "keys_path")},
         "roofline": roofline,
         "kernels": others,
+        "rates": {
+            # E_eff over the reduce stage alone (ranks + reduction + read-off)
+            "edge_columns_per_s_reduce_stage": E_eff / ((mean("ms_rank") + mean("ms_reduce")
+                                                          + mean("ms_emit")) / 1000.0),
+            "additions_per_s": mean("additions") / (ms_step / 1000.0),
+            "all_edges_per_s": E / (ms_step / 1000.0),
+        },
     }
     note("timed %d steps: %.3f ms/step" % (args.steps, ms_step))
     if not args.no_batched:
@@ -286,7 +336,7 @@ def main():
         rec["serving"] = bench_serving(ph0, synth, args.serve_requests)
         note("serving done")
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(pts, n // 2)
+        rec["cpu_baseline"] = cpu_baseline(pts, n)
         note("cpu baseline done")
     print(json.dumps(rec), flush=True)
 
