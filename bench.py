@@ -116,8 +116,11 @@ def bench_batched(torch, ph0, synth, reps=3):
         ph0.ph0_barcodes_device(x[offsets[c]:offsets[c + 1]], out=pout[:n], workspace=pws)
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) / k
+    table = ph0.default_tuning()
     return {
         "workload": "10000 clouds, N uniform in [32,512], d=3 int16, circles or 2-4 blobs, seed 0",
+        "tuning": ("autotuned table: chunk_mult %s, blocks_per_cu %d"
+                   % (list(table.chunk_mult), table.blocks_per_cu)) if table else "built-in",
         "clouds_per_s": 10000 / t_batched,
         "ms_per_launch": round(1000 * t_batched, 3),
         "plain_clouds_per_s": 1.0 / t_plain,

@@ -414,7 +414,8 @@ __global__ __launch_bounds__(kThreads) void k_batched(BatchArgs A) {
       atomicAdd(&S.hist[(uint32_t)(sqdist(S, d, i, j) >> hs)], 1u);
     }
     __syncthreads();
-    const int64_t target = (int64_t)A.chunk_mult * n;
+    const int bucket = n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : 3;
+    const int64_t target = (int64_t)A.chunk_mult[bucket] * n;
     uint32_t bin_lo = 0, distinct = 0;
     int err = 0, round = 0;
     while (S.s_pivots < (uint32_t)(n - 1) && bin_lo < (uint32_t)kBins) {

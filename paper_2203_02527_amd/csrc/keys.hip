@@ -54,8 +54,18 @@ __global__ void k_coord_range(const T* __restrict__ x, int64_t n, int32_t d,
       lo = v < lo ? v : lo;
       hi = v > hi ? v : hi;
     }
-    atomicMin(&minmax[2 * k], lo);
-    atomicMax(&minmax[2 * k + 1], hi);
+    // One atomic pair per wavefront: per-thread atomics on the same 2d
+    // addresses serialize.
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const int l2 = __shfl_xor(lo, o), h2 = __shfl_xor(hi, o);
+      lo = l2 < lo ? l2 : lo;
+      hi = h2 > hi ? h2 : hi;
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomicMin(&minmax[2 * k], lo);
+      atomicMax(&minmax[2 * k + 1], hi);
+    }
   }
 }
 

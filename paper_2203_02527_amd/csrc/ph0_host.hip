@@ -47,6 +47,11 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 constexpr int64_t kMaxN = 65536;
+// Built-in chunk multipliers of the batched kernel per cloud size bucket
+// (n <= 64, <= 128, <= 256, <= 512), used when no tuning is passed: the
+// values the autotuner (paper_2203_02527_amd/autotune.py) chose on MI355X
+// for the batch workload's clouds.
+constexpr int32_t kChunkMult[4] = {6, 6, 6, 48};
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
@@ -709,11 +714,8 @@ int ph0_barcodes_batched_device(const void* d_points, ph0_dtype dt, const int64_
     A.emax = std::max<int64_t>(P.emax, 1);
     A.queue = reinterpret_cast<uint32_t*>(ws + P.queue);
     A.errs = reinterpret_cast<int32_t*>(ws + P.errs);
-    // One chunk multiplier per launch: the size bucket of the largest cloud
-    // decides (clouds run largest first).
-    const int64_t n0 = offsets[P.order[0] + 1] - offsets[P.order[0]];
-    const int bucket = n0 <= 64 ? 0 : n0 <= 128 ? 1 : n0 <= 256 ? 2 : 3;
-    A.chunk_mult = tune && tune->chunk_mult[bucket] > 0 ? tune->chunk_mult[bucket] : 24;
+    for (int b = 0; b < 4; ++b)
+      A.chunk_mult[b] = tune && tune->chunk_mult[b] > 0 ? tune->chunk_mult[b] : kChunkMult[b];
     HIPCHK(launch_batched(A, (int)P.blocks, s));
   }
   tm.mark();

@@ -147,7 +147,8 @@ struct BatchArgs {
   int64_t emax;             // largest edge count of any cloud
   uint32_t* queue;          // work counter, zero at launch
   int32_t* errs;            // per cloud, zero at launch
-  int32_t chunk_mult;       // first chunk holds about chunk_mult * n edges
+  int32_t chunk_mult[4];    // first chunk holds about chunk_mult[b] * n edges, for
+                            // size buckets b: n <= 64, <= 128, <= 256, <= 512
 };
 size_t batched_shared_bytes();
 hipError_t launch_batched(const BatchArgs& a, int blocks, hipStream_t s);

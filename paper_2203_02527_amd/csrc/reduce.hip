@@ -942,8 +942,9 @@ __global__ __launch_bounds__(256) void k_overshoot(Ring ring, int64_t Wcap, RedC
     const int64_t k = p & (Wcap - 1);
     if (ring.tag[k] == p) s += ring.st[k] >> 2;
   }
-  s = wave_sum_i64(s);
-  if ((threadIdx.x & 63) == 0 && s)
+  __shared__ int64_t tmp[4];
+  s = block_sum_i64(s, tmp);  // one atomic per block: same-address atomics serialize
+  if (threadIdx.x == 0 && s)
     atomicAdd((unsigned long long*)&ctl->additions_overshoot, (unsigned long long)s);
 }
 

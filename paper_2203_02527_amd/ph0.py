@@ -293,6 +293,22 @@ def make_tuning(chunk_mult=(0, 0, 0, 0), blocks_per_cu=0) -> ph0_batch_tuning:
     return t
 
 
+_default_tuning = None
+
+
+def default_tuning():
+    """The tuning table written by the autotuner (tuning/batched.json), as a
+    ph0_batch_tuning, or None (the library's built-in values) if absent."""
+    global _default_tuning
+    if _default_tuning is None:
+        from . import autotune
+
+        t = autotune.load()
+        _default_tuning = (False,) if t is None else (True, make_tuning(t["chunk_mult"],
+                                                                      t["blocks_per_cu"]))
+    return _default_tuning[1] if _default_tuning[0] else None
+
+
 def _offsets(offsets) -> np.ndarray:
     o = np.ascontiguousarray(offsets, dtype=np.int64)
     if o.ndim != 1 or o.size < 2:
@@ -302,6 +318,7 @@ def _offsets(offsets) -> np.ndarray:
 
 def ph0_batched_workspace_bytes(offsets, d: int, dtype, tuning=None) -> int:
     o = _offsets(offsets)
+    tuning = default_tuning() if tuning is None else tuning
     out = ctypes.c_size_t(0)
     _check(lib().ph0_batched_workspace_bytes(o.ctypes.data_as(_P), o.size - 1, d, _dtype_code(dtype),
                                              None if tuning is None else ctypes.byref(tuning),
@@ -319,6 +336,7 @@ def ph0_barcodes_batched_device(points, offsets, out=None, workspace=None, tunin
     torch = _torch()
     x = _points_dev(points)
     o = _offsets(offsets)
+    tuning = default_tuning() if tuning is None else tuning
     if int(o[-1]) != x.shape[0]:
         raise ValueError("offsets[-1] must equal the number of rows")
     d = x.shape[1]

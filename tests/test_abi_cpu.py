@@ -59,3 +59,21 @@ def test_host_entry_rejects_bad_arguments_before_device_use():
     assert ph0.ph0_set_window(0) is None
     with pytest.raises(ph0.Ph0Error):
         ph0.ph0_set_window(-5)
+
+
+def test_tuning_table_loader(tmp_path):
+    from paper_2203_02527_amd import autotune
+
+    assert autotune.load(str(tmp_path / "absent.json")) is None
+    good = tmp_path / "good.json"
+    good.write_text('{"chunk_mult": [8, 12, 16, 24], "blocks_per_cu": 1}')
+    assert autotune.load(str(good))["chunk_mult"] == [8, 12, 16, 24]
+    for bad in ('{"chunk_mult": [8, 12, 16], "blocks_per_cu": 1}',
+                '{"chunk_mult": [8, 12, 16, 0], "blocks_per_cu": 1}',
+                '{"chunk_mult": [8, 12, 16, 24], "blocks_per_cu": 3}'):
+        p = tmp_path / "bad.json"
+        p.write_text(bad)
+        with pytest.raises(ValueError):
+            autotune.load(str(p))
+    if os.path.exists(autotune.TABLE):  # the committed table must load
+        assert autotune.load() is not None

@@ -102,3 +102,16 @@ def test_full_batch_workload(torch):
         assert b[0] >= 1 or n[c] == 1
     print("full batch: invariants ok", flush=True)
     _check(bars, pts, offsets, which=range(0, 10000, 97))
+
+
+def test_autotuner_finds_valid_table(torch, tmp_path):
+    from paper_2203_02527_amd import autotune
+
+    t = autotune.tune(clouds=40, reps=1, log=lambda m: None)
+    assert len(t["chunk_mult"]) == 4 and all(m in autotune.MULTS for m in t["chunk_mult"])
+    assert t["blocks_per_cu"] in autotune.BLOCKS_PER_CU
+    p = tmp_path / "t.json"
+    import json
+
+    p.write_text(json.dumps(t))
+    assert autotune.load(str(p))["chunk_mult"] == t["chunk_mult"]
