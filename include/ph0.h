@@ -214,11 +214,6 @@ int ph0_set_window(int64_t columns);
  * Affects speed only, never results.  Process-wide. */
 int ph0_set_walk_lanes(int32_t lanes);
 
-/* Columns one full wavefront walks side by side (1..4; 0 restores the
- * built-in 1): more keeps more pivot-table fetches in flight per wavefront.
- * Used when a pivot row needs all 64 lanes (N > 2048).  Speed only. */
-int ph0_set_walk_per_wave(int32_t columns);
-
 #ifdef __cplusplus
 }
 #endif

@@ -32,13 +32,19 @@ FLAGS = [
 ]
 
 
+# Per-source extra flags.  reduce.hip aggregates its atomics per block by
+# hand; the compiler's atomic optimizer would wrap every remaining
+# single-lane atomic (the walk's per-column minima) in a lane-scan loop.
+EXTRA = {"reduce.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+
+
 def sources() -> list[str]:
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed on %s:\n%s" % (src, r.stderr))

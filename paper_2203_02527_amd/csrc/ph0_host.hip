@@ -29,7 +29,6 @@ namespace {
 thread_local char g_err[512] = "";
 std::atomic<int64_t> g_window{0};
 std::atomic<int32_t> g_walk_lanes{0};
-std::atomic<int32_t> g_walk_per_wave{0};
 
 int fail(int code, const char* fmt, ...) {
   va_list ap;
@@ -389,7 +388,6 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   ra.LW = L.LW;
   ra.Wcap = L.Wcap;
   ra.lanes = g_walk_lanes.load();
-  ra.per_wave = g_walk_per_wave.load() > 0 ? g_walk_per_wave.load() : 1;
   ra.act[0] = static_cast<int64_t*>(at(L.act0));
   ra.act[1] = static_cast<int64_t*>(at(L.act1));
   ra.table = static_cast<uint64_t*>(at(L.table));
@@ -609,12 +607,6 @@ int ph0_key_layout(int64_t n, int32_t d, ph0_dtype dt, int32_t* ibits, int32_t* 
 int ph0_set_window(int64_t columns) {
   if (columns < 0) return fail(PH0_EINVAL, "window must be >= 0");
   g_window.store(columns);
-  return PH0_OK;
-}
-
-int ph0_set_walk_per_wave(int32_t columns) {
-  if (columns < 0 || columns > 4) return fail(PH0_EINVAL, "columns per wave must be 0..4");
-  g_walk_per_wave.store(columns);
   return PH0_OK;
 }
 

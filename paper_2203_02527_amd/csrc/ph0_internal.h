@@ -94,7 +94,6 @@ struct RedArgs {
   int ib;
   int64_t n, E, LW, Wcap;
   int lanes;     // lanes per column in the walk (0 = built-in choice)
-  int per_wave;  // columns a full-wave group walks side by side (1..4)
   uint64_t* table;
   int64_t* killer;
   uint64_t* lowc;

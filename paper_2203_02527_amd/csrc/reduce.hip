@@ -367,37 +367,94 @@ __device__ inline int wide_top(const uint64_t (&w)[WPL], int qmax) {
 // one ballot per slot and picks the highest non-empty slot with scalar
 // selects; the row's byte offset r * rowb is 32-bit (the table stays below
 // 4 GiB for every supported N).
-template <int WPL, int S>
-__device__ inline int wide_step(uint64_t (&col)[WPL], const char* tbase, uint32_t rowb, int r,
-                                int lane) {
+__device__ inline __amdgpu_buffer_rsrc_t wide_rsrc(const char* tbase, uint32_t rowb, int r) {
   const uint32_t nrec = (((uint32_t)r | 63u) >> 3) + 1u;  // (r / 64 + 1) words
-  const auto rs = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)(tbase + (uint32_t)r * rowb), 0, (int)nrec, 0x00020000);
-  uint64_t v[S];
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(tbase + (uint32_t)r * rowb), 0, (int)nrec,
+                                           0x00020000);
+}
+
+template <int S>
+__device__ inline void wide_issue(uint64_t (&v)[S], __amdgpu_buffer_rsrc_t rs, int lane) {
 #pragma unroll
   for (int q = 0; q < S; ++q) {
     const auto x = __builtin_amdgcn_raw_buffer_load_b64(rs, lane * 8, q * 512, 0);
     v[q] = ((uint64_t)x[1] << 32) | x[0];
   }
-#pragma unroll
-  for (int q = 0; q < S; ++q) col[q] ^= v[q];
-  uint64_t m = __ballot(col[0] != 0);
+}
+
+// XOR S loaded slots into the column and return its new top bit (-1 if the
+// column became zero).  Slots >= S of the column are zero already (its bits
+// are <= r), so only S slots are searched: one ballot per slot, the highest
+// non-empty slot picked with scalar selects, one lane read.
+// Highest set bit among slots 0..S-1 of w (-1 if none): one ballot per slot,
+// the highest non-empty slot picked with scalar selects, one lane read.
+template <int S, int N>
+__device__ inline int slots_top(const uint64_t (&w)[N]) {
+  static_assert(S <= N, "slot count");
+  uint64_t m = __ballot(w[0] != 0);
   int qs = 0;
 #pragma unroll
   for (int q = 1; q < S; ++q) {
-    const uint64_t mq = __ballot(col[q] != 0);
+    const uint64_t mq = __ballot(w[q] != 0);
     qs = mq ? q : qs;
     m = mq ? mq : m;
   }
   if (m == 0) return -1;
   const int L = 63 - __clzll(m);
-  uint64_t word = readlane64(col[0], L);
+  uint64_t word = readlane64(w[0], L);
 #pragma unroll
   for (int q = 1; q < S; ++q) {
-    const uint64_t wq = readlane64(col[q], L);
+    const uint64_t wq = readlane64(w[q], L);
     word = qs == q ? wq : word;
   }
   return (qs * 64 + L) * 64 + 63 - __clzll(word);
+}
+
+// slots_top with the slot count S = s chosen at run time (1 <= s <= WPL).
+template <int WPL, int S = WPL>
+__device__ inline int slots_top_n(int s, const uint64_t (&w)[WPL]) {
+  if constexpr (S > 1) {
+    if (s < S) return slots_top_n<WPL, S - 1>(s, w);
+  }
+  return slots_top<S>(w);
+}
+
+template <int WPL, int S>
+__device__ inline int wide_xor_top(uint64_t (&col)[WPL], const uint64_t (&v)[S]) {
+#pragma unroll
+  for (int q = 0; q < S; ++q) col[q] ^= v[q];
+  return slots_top<S>(col);
+}
+
+// Highest set bit of stored row v below v itself (-1 if the row holds only
+// its slot flag or is empty): the row's prefix spans S = v / 4096 + 1 slots,
+// and bit v sits in slot S - 1.
+template <int S>
+__device__ inline int row_below(const char* tbase, uint32_t rowb, int v, int lane) {
+  uint64_t row[S];
+  wide_issue<S>(row, wide_rsrc(tbase, rowb, v), lane);
+  row[S - 1] &= ~((lane == ((v >> 6) & 63)) ? (1ull << (v & 63)) : 0ull);
+  return slots_top<S>(row);
+}
+
+template <int WPL, int S = WPL>
+__device__ inline int row_below_n(const char* tbase, uint32_t rowb, int v, int lane) {
+  if constexpr (S > 1) {
+    if (v < (S - 1) * 4096) return row_below_n<WPL, S - 1>(tbase, rowb, v, lane);
+  }
+  return row_below<S>(tbase, rowb, v, lane);
+}
+
+// One walk step against row r, whose prefix spans S slots: XOR the row's
+// words 0..r/64 into the column and return the column's new top bit.  The
+// row's byte offset r * rowb is 32-bit (the table stays below 4 GiB for every
+// supported N); the buffer's length ends the row at word r/64.
+template <int WPL, int S>
+__device__ inline int wide_step(uint64_t (&col)[WPL], const char* tbase, uint32_t rowb, int r,
+                                int lane) {
+  uint64_t v[S];
+  wide_issue<S>(v, wide_rsrc(tbase, rowb, r), lane);
+  return wide_xor_top<WPL, S>(col, v);
 }
 
 struct WalkState {
@@ -407,26 +464,29 @@ struct WalkState {
   bool stop, zero, bad;
 };
 
+// Apply a step's result nr (the column's new top bit) to the walk state.
+__device__ inline void wide_advance(WalkState& w, int nr) {
+  const int r = w.r;
+  w.words += (r >> 6) + 1;
+  if ((unsigned)nr >= (unsigned)r) {  // rare: row empty, zero column, or corrupt
+    w.stop = true;
+    if (nr == r) return;  // row r is empty: slot r is free
+    ++w.moved;
+    w.zero = true;
+    if (nr > r) w.bad = true;  // lows must decrease; a corrupt table ends the walk
+    return;
+  }
+  ++w.moved;
+  w.r = nr;
+}
+
 // Steps on rows whose prefix spans S slots -- r >= (S - 1) * 4096; r < S *
 // 4096 holds already since r only decreases -- then the stages below.
 template <int WPL, int S>
 __device__ inline void wide_stages(uint64_t (&col)[WPL], const char* tbase, uint32_t rowb,
                                    int lane, WalkState& w) {
-  while (!w.stop && w.r >= (S - 1) * 4096) {
-    const int r = w.r;
-    const int nr = __builtin_amdgcn_readfirstlane(wide_step<WPL, S>(col, tbase, rowb, r, lane));
-    w.words += (r >> 6) + 1;
-    if ((unsigned)nr >= (unsigned)r) {  // rare: row empty, zero column, or corrupt
-      w.stop = true;
-      if (nr == r) break;  // row r is empty: slot r is free
-      ++w.moved;
-      w.zero = true;
-      if (nr > r) w.bad = true;  // lows must decrease; a corrupt table ends the walk
-      break;
-    }
-    ++w.moved;
-    w.r = nr;
-  }
+  while (!w.stop && w.r >= (S - 1) * 4096)
+    wide_advance(w, __builtin_amdgcn_readfirstlane(wide_step<WPL, S>(col, tbase, rowb, w.r, lane)));
   if constexpr (S > 1) wide_stages<WPL, S - 1>(col, tbase, rowb, lane, w);
 }
 
@@ -441,302 +501,228 @@ __device__ inline void wide_flip(uint64_t (&w)[WPL], int lane, int bit) {
   for (int q = 0; q < WPL; ++q) w[q] ^= b & (0ull - (uint64_t)(q == (word >> 6)));
 }
 
+// Per-launch context of the full-wave walk kernels.
+struct WideCtx {
+  const uint64_t* skeys;
+  const int64_t* act;
+  Ring ring;
+  uint64_t* lowc;
+  uint64_t* touch;
+  const char* tbase;
+  const uint64_t* table;
+  int64_t LW, Wcap, nA, fresh_lo, round;
+  uint64_t imask;
+  uint32_t rowb;
+  int ib, lane;
+  // per-wave tallies
+  int64_t adds, finds, words;
+  int32_t bad;
+};
+
+// A column in flight: sorted position, other row a, root of a, earlier
+// additions, and the walk state (current low, this launch's additions).
+struct WideCol {
+  int64_t p;
+  int a, rlo, prev;
+  WalkState w;
+};
+
+// The wave's next work item, fetched while the current one walks: stage 1
+// (at the start of the walk) reads the active-list entry or the fresh key,
+// stage 2 (after the walk) the ring entry of a resumed column, so neither
+// dependent load sits on the path between two columns.
+struct WideNext {
+  int64_t t;
+  uint64_t raw;  // the column p (resumed item) or the key (fresh item)
+  int32_t a, r, rlo, st;
+};
+
+// One load from one of two places (a single destination keeps the compiler
+// from merging two conditional stores into a dynamically indexed one).
+__device__ inline void next_fetch1(const WideCtx& x, WideNext& nx, int64_t items) {
+  if (nx.t < items) {
+    const uint64_t* src = nx.t < x.nA ? reinterpret_cast<const uint64_t*>(x.act) + nx.t
+                                      : x.skeys + x.fresh_lo + (nx.t - x.nA);
+    nx.raw = *src;
+  }
+}
+
+__device__ inline void next_fetch2(const WideCtx& x, WideNext& nx) {
+  if (nx.t < x.nA) {
+    const int64_t q = (int64_t)nx.raw & (x.Wcap - 1);
+    nx.a = x.ring.a[q];
+    nx.r = x.ring.r[q];
+    nx.rlo = x.ring.rlo[q];
+    nx.st = x.ring.st[q];
+  }
+}
+
+// Start the prefetched item: an active column resumed from its ring entry,
+// or a fresh column from its key.  Sets the column's two bits.
+template <int WPL>
+__device__ inline void wide_begin(const WideCtx& x, const WideNext& nx, WideCol& c,
+                                  uint64_t (&col)[WPL]) {
+  int a, r, rlo;
+  if (nx.t < x.nA) {
+    c.p = (int64_t)nx.raw;
+    a = nx.a;
+    r = nx.r;
+    rlo = nx.rlo;
+    c.prev = nx.st >> 2;
+  } else {
+    c.p = x.fresh_lo + (nx.t - x.nA);
+    a = (int)(nx.raw & x.imask);
+    r = (int)((nx.raw >> x.ib) & x.imask);
+    rlo = a;
+    c.prev = 0;
+  }
+  c.a = __builtin_amdgcn_readfirstlane(a);
+  c.rlo = __builtin_amdgcn_readfirstlane(rlo);
+  c.w = WalkState{__builtin_amdgcn_readfirstlane(r), 0, 0, false, false, false};
+#pragma unroll
+  for (int q = 0; q < WPL; ++q) col[q] = 0;
+  wide_flip<WPL>(col, x.lane, c.a);
+  wide_flip<WPL>(col, x.lane, c.w.r);
+}
+
+// A column whose walk stopped: a zero column, or a survivor on free slot r.
+// A survivor's other row a is read off the column (which must hold exactly
+// the two bits {a, r}), the root of a in the current forest is found by
+// following stored columns down, and the round-tagged minima for slot r and
+// that root are lowered (both current values are read before either atomic,
+// so the wave waits once).  The column's state goes back to the ring.
+template <int WPL>
+__device__ inline void wide_finish(WideCtx& x, WideCol& c, uint64_t (&col)[WPL]) {
+  const int lane = x.lane;
+  const int r = c.w.r;
+  int a = c.a, rlo = c.rlo;
+  x.adds += c.w.moved;
+  x.words += c.w.words;
+  if (c.w.bad) x.bad = 1;
+  int32_t status = kActive;
+  if (c.w.zero) {
+    status = kZero;
+  } else {
+    const int s = (r >> 12) + 1;
+    wide_flip<WPL>(col, lane, r);
+    const int na = __builtin_amdgcn_readfirstlane(slots_top_n<WPL>(s, col));
+    if (na >= 0) wide_flip<WPL>(col, lane, na);
+    bool rest = false;
+#pragma unroll
+    for (int q = 0; q < WPL; ++q) rest |= col[q] != 0;
+    if (na < 0 || __ballot(rest) != 0) x.bad = 1;
+    a = na < 0 ? 0 : na;
+    // Root of row a in the current forest: follow stored columns down.
+    int v = c.w.moved ? a : rlo;
+    while (true) {
+      x.words += (v >> 6) + 1;
+      const int cb = __builtin_amdgcn_readfirstlane(row_below_n<WPL>(x.tbase, x.rowb, v, lane));
+      if (cb < 0) break;  // empty row: v is a root
+      ++x.finds;
+      if (cb >= v) {
+        x.bad = 1;
+        break;
+      }
+      v = cb;
+    }
+    rlo = v;
+    if (lane == 0) {
+      const uint64_t e = enc(x.round, c.p);
+      const uint64_t cur_l = *(volatile uint64_t*)&x.lowc[r];
+      const uint64_t cur_t = *(volatile uint64_t*)&x.touch[rlo];
+      if (cur_l > e) atomicMin((unsigned long long*)&x.lowc[r], (unsigned long long)e);
+      if (cur_t > e) atomicMin((unsigned long long*)&x.touch[rlo], (unsigned long long)e);
+    }
+  }
+  if (lane == 0) {
+    const int64_t q = c.p & (x.Wcap - 1);
+    x.ring.a[q] = a;
+    x.ring.r[q] = r;
+    x.ring.rlo[q] = rlo;
+    x.ring.st[q] = status | ((c.prev + c.w.moved) << 2);
+    x.ring.tag[q] = c.p;
+  }
+}
+
+__device__ inline bool wide_setup(WideCtx& x, const uint64_t* skeys, int ib, int64_t LW,
+                                  const uint64_t* table, Ring ring, int64_t Wcap,
+                                  const int64_t* act0, const int64_t* act1, uint64_t* lowc,
+                                  uint64_t* touch, const RedCtl* ctl, int64_t* items) {
+  if (ctl->done) return false;
+  x.nA = ctl->nA;
+  x.round = ctl->round;
+  x.fresh_lo = ctl->fresh_lo;
+  *items = x.nA + (ctl->fresh_hi - x.fresh_lo);
+  x.act = ctl->cur ? act1 : act0;
+  x.skeys = skeys;
+  x.ring = ring;
+  x.lowc = lowc;
+  x.touch = touch;
+  x.table = table;
+  x.tbase = reinterpret_cast<const char*>(table);
+  x.LW = LW;
+  x.Wcap = Wcap;
+  x.imask = (1ull << ib) - 1ull;
+  x.rowb = (uint32_t)LW * 8u;
+  x.ib = ib;
+  x.lane = threadIdx.x & 63;
+  x.adds = x.finds = x.words = 0;
+  x.bad = 0;
+  return true;
+}
+
+// Block-level flush of the per-wave tallies: one global atomic per counter
+// and block.
+__device__ inline void wide_flush(const WideCtx& x, RedCtl* ctl) {
+  __shared__ unsigned long long s_cnt[3];
+  __shared__ int s_bad;
+  if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  if (x.lane == 0) {
+    if (x.adds) atomicAdd(&s_cnt[0], (unsigned long long)x.adds);
+    if (x.finds) atomicAdd(&s_cnt[1], (unsigned long long)x.finds);
+    if (x.words) atomicAdd(&s_cnt[2], (unsigned long long)x.words);
+    if (x.bad) s_bad = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_cnt[0]) atomicAdd((unsigned long long*)&ctl->additions_all, s_cnt[0]);
+    if (s_cnt[1]) atomicAdd((unsigned long long*)&ctl->find_steps, s_cnt[1]);
+    if (s_cnt[2]) atomicAdd((unsigned long long*)&ctl->words_read, s_cnt[2]);
+    if (s_bad) atomicOr(&ctl->err, 1);
+  }
+}
+
 template <int WPL>
 __global__ __launch_bounds__(256) void k_walk_wide(const uint64_t* __restrict__ skeys, int ib,
                                                    int64_t LW, const uint64_t* __restrict__ table,
                                                    Ring ring, int64_t Wcap, const int64_t* act0,
                                                    const int64_t* act1, uint64_t* lowc,
                                                    uint64_t* touch, RedCtl* ctl) {
-  if (ctl->done) return;
-  const int64_t nA = ctl->nA, round = ctl->round, fresh_lo = ctl->fresh_lo;
-  const int64_t items = nA + (ctl->fresh_hi - fresh_lo);
-  const int64_t* act = ctl->cur ? act1 : act0;
-  const int lane = threadIdx.x & 63;
+  WideCtx x;
+  int64_t items;
+  if (!wide_setup(x, skeys, ib, LW, table, ring, Wcap, act0, act1, lowc, touch, ctl, &items))
+    return;
   const int64_t wid = blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64;
   const int64_t wtotal = (int64_t)gridDim.x * (blockDim.x / 64);
-  const uint64_t imask = (1ull << ib) - 1ull;
-  const char* tbase = reinterpret_cast<const char*>(table);
-  const uint32_t rowb = (uint32_t)LW * 8u;
-
-  int64_t adds = 0, finds = 0, words = 0;
-  int32_t bad = 0;
-  for (int64_t t = wid; t < items; t += wtotal) {
-    int64_t p;
-    int a, r, rlo, prev;
-    if (t < nA) {
-      p = act[t];
-      const int64_t q = p & (Wcap - 1);
-      a = ring.a[q];
-      r = ring.r[q];
-      rlo = ring.rlo[q];
-      prev = ring.st[q] >> 2;
-    } else {
-      p = fresh_lo + (t - nA);
-      const uint64_t key = skeys[p];
-      a = (int)(key & imask);
-      r = (int)((key >> ib) & imask);
-      rlo = a;
-      prev = 0;
-    }
-    a = __builtin_amdgcn_readfirstlane(a);
-    r = __builtin_amdgcn_readfirstlane(r);
-    rlo = __builtin_amdgcn_readfirstlane(rlo);
+  WideNext nx;
+  nx.t = wid;
+  next_fetch1(x, nx, items);
+  next_fetch2(x, nx);
+  while (nx.t < items) {
+    WideCol c;
     uint64_t col[WPL];
-#pragma unroll
-    for (int q = 0; q < WPL; ++q) col[q] = 0;
-    wide_flip<WPL>(col, lane, a);
-    wide_flip<WPL>(col, lane, r);
-    WalkState w{r, 0, 0, false, false, false};
-    wide_stages<WPL, WPL>(col, tbase, rowb, lane, w);
-    r = w.r;
-    const int moved = w.moved;
-    const bool zero = w.zero;
-    bad |= w.bad;
-    const int cwords = w.words;
-    adds += moved;
-    words += cwords;
-    int32_t status = kActive;
-    if (zero) {
-      status = kZero;
-    } else {
-      const int qmax = (r >> 6) >> 6;
-      wide_flip<WPL>(col, lane, r);
-      const int na = __builtin_amdgcn_readfirstlane(wide_top<WPL>(col, qmax));
-      if (na >= 0) wide_flip<WPL>(col, lane, na);
-      bool rest = false;
-#pragma unroll
-      for (int q = 0; q < WPL; ++q) rest |= col[q] != 0;
-      if (na < 0 || __ballot(rest) != 0) bad = 1;
-      a = na < 0 ? 0 : na;
-      // Root of row a in the current forest: follow stored columns down.
-      int v = moved ? a : rlo;
-      while (true) {
-        const int top = v >> 6, qmax_v = top >> 6;
-        uint64_t row[WPL];
-        wide_load<WPL>(row, row_rsrc(table, LW, v), qmax_v, lane);
-        words += top + 1;
-        const uint64_t own = (lane == (top & 63)) ? (1ull << (v & 63)) : 0ull;
-#pragma unroll
-        for (int q = 0; q < WPL; ++q) row[q] &= ~(own & (0ull - (uint64_t)(q == qmax_v)));
-        const int c = __builtin_amdgcn_readfirstlane(wide_top<WPL>(row, qmax_v));
-        if (c < 0) break;  // empty row: v is a root
-        ++finds;
-        if (c >= v) {
-          bad = 1;
-          break;
-        }
-        v = c;
-      }
-      rlo = v;
-      if (lane == 0) {
-        const uint64_t e = enc(round, p);
-        filtered_min(&lowc[r], e);
-        filtered_min(&touch[rlo], e);
-      }
-    }
-    if (lane == 0) {
-      const int64_t q = p & (Wcap - 1);
-      ring.a[q] = a;
-      ring.r[q] = r;
-      ring.rlo[q] = rlo;
-      ring.st[q] = status | ((prev + moved) << 2);
-      ring.tag[q] = p;
-    }
+    wide_begin<WPL>(x, nx, c, col);
+    nx.t += wtotal;
+    next_fetch1(x, nx, items);
+    wide_stages<WPL, WPL>(col, x.tbase, x.rowb, x.lane, c.w);
+    next_fetch2(x, nx);
+    wide_finish<WPL>(x, c, col);
   }
-  __shared__ unsigned long long s_cnt[3];
-  __shared__ int s_bad;
-  if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
-  if (threadIdx.x == 0) s_bad = 0;
-  __syncthreads();
-  if (lane == 0) {
-    if (adds) atomicAdd(&s_cnt[0], (unsigned long long)adds);
-    if (finds) atomicAdd(&s_cnt[1], (unsigned long long)finds);
-    if (words) atomicAdd(&s_cnt[2], (unsigned long long)words);
-    if (bad) s_bad = 1;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (s_cnt[0]) atomicAdd((unsigned long long*)&ctl->additions_all, s_cnt[0]);
-    if (s_cnt[1]) atomicAdd((unsigned long long*)&ctl->find_steps, s_cnt[1]);
-    if (s_cnt[2]) atomicAdd((unsigned long long*)&ctl->words_read, s_cnt[2]);
-    if (s_bad) atomicOr(&ctl->err, 1);
-  }
+  wide_flush(x, ctl);
 }
 
-// The same walk for full-wave groups, with K columns per wave side by side.
-// Each column is a small state machine -- WALK (XOR the stored column of the
-// current low in), FIND (follow the root of the other row), then done -- and
-// one pass of the loop first issues the row loads of all K columns, then
-// consumes them, so a wave keeps K row fetches in flight instead of one.
-// Every step is the same as in k_walk; only the interleaving differs.
-template <int WPL, int K>
-__global__ __launch_bounds__(256) void k_walk_multi(const uint64_t* __restrict__ skeys, int ib,
-                                                    int64_t LW,
-                                                    const uint64_t* __restrict__ table,
-                                                    Ring ring, int64_t Wcap, const int64_t* act0,
-                                                    const int64_t* act1, uint64_t* lowc,
-                                                    uint64_t* touch, RedCtl* ctl) {
-  constexpr int G = 64;
-  constexpr int kIdle = 0, kWalk = 1, kFind = 2;
-  if (ctl->done) return;
-  const int64_t nA = ctl->nA, round = ctl->round, fresh_lo = ctl->fresh_lo;
-  const int64_t items = nA + (ctl->fresh_hi - fresh_lo);
-  const int64_t* act = ctl->cur ? act1 : act0;
-  const int lane = threadIdx.x & 63;
-  const int64_t wid = blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64;
-  const int64_t wtotal = (int64_t)gridDim.x * (blockDim.x / 64);
-  const uint64_t imask = (1ull << ib) - 1ull;
-
-  int64_t next_t = wid;
-  int64_t adds = 0, finds = 0, words = 0;
-  int32_t bad = 0;
-  uint64_t col[K][WPL];
-  int mode[K], r[K], a[K], rlo[K], v[K], moved[K], prev[K];
-  int64_t pcol[K];
-
-  auto start = [&](int k) {
-    mode[k] = kIdle;
-    r[k] = v[k] = a[k] = rlo[k] = moved[k] = prev[k] = 0;
-    pcol[k] = 0;
-    if (next_t >= items) return;
-    const int64_t t = next_t;
-    next_t += wtotal;
-    int64_t p;
-    int aa, rr, ll, ps;
-    if (t < nA) {
-      p = act[t];
-      const int64_t q = p & (Wcap - 1);
-      aa = ring.a[q];
-      rr = ring.r[q];
-      ll = ring.rlo[q];
-      ps = ring.st[q] >> 2;
-    } else {
-      p = fresh_lo + (t - nA);
-      const uint64_t key = skeys[p];
-      aa = (int)(key & imask);
-      rr = (int)((key >> ib) & imask);
-      ll = aa;
-      ps = 0;
-    }
-    pcol[k] = p;
-    a[k] = __builtin_amdgcn_readfirstlane(aa);
-    r[k] = __builtin_amdgcn_readfirstlane(rr);
-    rlo[k] = __builtin_amdgcn_readfirstlane(ll);
-    prev[k] = __builtin_amdgcn_readfirstlane(ps);
-    moved[k] = 0;
-#pragma unroll
-    for (int q = 0; q < WPL; ++q) col[k][q] = 0;
-    flip_bit<G, WPL>(col[k], lane, a[k]);
-    flip_bit<G, WPL>(col[k], lane, r[k]);
-    mode[k] = kWalk;
-  };
-  auto finish = [&](int k, int32_t status) {
-    if (lane == 0) {
-      const int64_t q = pcol[k] & (Wcap - 1);
-      ring.a[q] = a[k];
-      ring.r[q] = r[k];
-      ring.rlo[q] = rlo[k];
-      ring.st[q] = status | ((prev[k] + moved[k]) << 2);
-      ring.tag[q] = pcol[k];
-      if (status == kActive) {
-        const uint64_t e = enc(round, pcol[k]);
-        filtered_min(&lowc[r[k]], e);
-        filtered_min(&touch[rlo[k]], e);
-      }
-    }
-    adds += moved[k];
-    start(k);
-  };
-
-#pragma unroll
-  for (int k = 0; k < K; ++k) start(k);
-  while (true) {
-    bool any = false;
-#pragma unroll
-    for (int k = 0; k < K; ++k) any |= mode[k] != kIdle;
-    if (!any) break;
-    // Issue every active column's row loads.
-    uint64_t rv[K][WPL];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int row = mode[k] == kFind ? v[k] : r[k];
-      const int top = row >> 6;
-      const uint64_t* rp = table + (int64_t)row * LW;
-#pragma unroll
-      for (int q = 0; q < WPL; ++q) {
-        const int widx = q * G + lane;
-        rv[k][q] = mode[k] != kIdle ? rp[widx <= top ? widx : top] : 0ull;
-      }
-    }
-    // Consume them.
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (mode[k] == kWalk) {
-        const int top = r[k] >> 6;
-#pragma unroll
-        for (int q = 0; q < WPL; ++q) col[k][q] ^= (q * G + lane <= top) ? rv[k][q] : 0ull;
-        words += top + 1;
-        const int nr = __builtin_amdgcn_readfirstlane(group_top_bit<G, WPL>(col[k], 0, top / G));
-        if (nr == r[k]) {  // slot r is free: a survivor; find the other row's root
-          flip_bit<G, WPL>(col[k], lane, r[k]);
-          const int na = __builtin_amdgcn_readfirstlane(group_top_bit<G, WPL>(col[k], 0, top / G));
-          if (na >= 0) flip_bit<G, WPL>(col[k], lane, na);
-          bool rest = false;
-#pragma unroll
-          for (int q = 0; q < WPL; ++q) rest |= col[k][q] != 0;
-          if (na < 0 || group_any<G>(rest, 0)) bad = 1;
-          a[k] = na < 0 ? 0 : na;
-          v[k] = moved[k] ? a[k] : rlo[k];
-          mode[k] = kFind;
-        } else if (nr < 0 || nr > r[k]) {  // zero column (or a corrupt table)
-          if (nr > r[k]) bad = 1;
-          ++moved[k];
-          finish(k, kZero);
-        } else {
-          ++moved[k];
-          r[k] = nr;
-        }
-      } else if (mode[k] == kFind) {
-        const int top = v[k] >> 6;
-        uint64_t row[WPL];
-#pragma unroll
-        for (int q = 0; q < WPL; ++q) row[q] = (q * G + lane <= top) ? rv[k][q] : 0ull;
-        words += top + 1;
-        clear_bit<G, WPL>(row, lane, v[k]);
-        const int c = __builtin_amdgcn_readfirstlane(group_top_bit<G, WPL>(row, 0, top / G));
-        if (c < 0) {  // empty row: v is the root
-          rlo[k] = v[k];
-          finish(k, kActive);
-        } else if (c >= v[k]) {
-          bad = 1;
-          rlo[k] = v[k];
-          finish(k, kActive);
-        } else {
-          ++finds;
-          v[k] = c;
-        }
-      }
-    }
-  }
-  __shared__ unsigned long long s_cnt[3];
-  __shared__ int s_bad;
-  if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
-  if (threadIdx.x == 0) s_bad = 0;
-  __syncthreads();
-  if (lane == 0) {
-    if (adds) atomicAdd(&s_cnt[0], (unsigned long long)adds);
-    if (finds) atomicAdd(&s_cnt[1], (unsigned long long)finds);
-    if (words) atomicAdd(&s_cnt[2], (unsigned long long)words);
-    if (bad) s_bad = 1;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (s_cnt[0]) atomicAdd((unsigned long long*)&ctl->additions_all, s_cnt[0]);
-    if (s_cnt[1]) atomicAdd((unsigned long long*)&ctl->find_steps, s_cnt[1]);
-    if (s_cnt[2]) atomicAdd((unsigned long long*)&ctl->words_read, s_cnt[2]);
-    if (s_bad) atomicOr(&ctl->err, 1);
-  }
-}
 
 // Block-wide reductions for the 256-thread decide/commit kernels.
 __device__ inline uint64_t block_min_u64(uint64_t v, uint64_t* tmp /* 4 */) {
@@ -970,23 +956,10 @@ void walk_launch(const RedArgs& a, hipStream_t s) {
   if (blocks > cap) blocks = cap;
   if (blocks < 1) blocks = 1;
   if constexpr (G == 64) {
-    if (a.per_wave <= 1) {
-      hipLaunchKernelGGL((k_walk_wide<WPL>), dim3((unsigned)blocks), dim3(256), 0, s, a.skeys,
-                         a.ib, a.LW, a.table, a.ring, a.Wcap, a.act[0], a.act[1], a.lowc,
-                         a.touch, a.ctl);
-      return;
-    }
-    if (a.per_wave > 1) {
-#define PH0_MULTI(k)                                                                           \
-  if (a.per_wave == k) {                                                                      \
-    hipLaunchKernelGGL((k_walk_multi<WPL, k>), dim3((unsigned)blocks), dim3(256), 0, s,        \
-                       a.skeys, a.ib, a.LW, a.table, a.ring, a.Wcap, a.act[0], a.act[1],      \
-                       a.lowc, a.touch, a.ctl);                                               \
-    return;                                                                                   \
-  }
-      PH0_MULTI(2) PH0_MULTI(3) PH0_MULTI(4)
-#undef PH0_MULTI
-    }
+    hipLaunchKernelGGL((k_walk_wide<WPL>), dim3((unsigned)blocks), dim3(256), 0, s, a.skeys, a.ib,
+                       a.LW, a.table, a.ring, a.Wcap, a.act[0], a.act[1], a.lowc, a.touch,
+                       a.ctl);
+    return;
   }
   hipLaunchKernelGGL((k_walk<G, WPL>), dim3((unsigned)blocks), dim3(256), 0, s, a.skeys, a.ib,
                      a.LW, a.table, a.ring, a.Wcap, a.act[0], a.act[1], a.lowc, a.touch, a.ctl);

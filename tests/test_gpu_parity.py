@@ -173,21 +173,6 @@ def test_walk_lane_shapes_give_identical_results(torch):
         ph0.ph0_set_walk_lanes(0)
 
 
-def test_columns_per_wave_give_identical_results(torch):
-    x = synth.mixture_cloud(4500, 16, 8, 10.0, seed=8)  # N > 2048: full-wave rows
-    ref = oracle.barcode(x)
-    try:
-        for k in (1, 2, 3, 4):
-            ph0.ph0_set_walk_per_wave(k)
-            pr = ph0.ph0_pairs_device(_dev(torch, x))
-            np.testing.assert_array_equal(pr.partner.cpu().numpy(), ref.partner)
-            np.testing.assert_array_equal(pr.death_by_vertex.cpu().numpy().view(np.uint32),
-                                          ref.death_by_vertex)
-            assert pr.stats["additions"] == ref.additions
-    finally:
-        ph0.ph0_set_walk_per_wave(0)
-
-
 def test_repeat_runs_are_bit_identical(torch):
     x = synth.mixture_cloud(2000, 16, 8, 10.0, seed=11)
     xd = _dev(torch, x)
