@@ -82,18 +82,32 @@ __device__ inline void hist_flush(const uint32_t* lh, uint32_t* hist) {
     if (lh[b]) atomicAdd(&hist[b], lh[b]);
 }
 
-template <typename T>
+// Flattened index of the count of (64-row band J, row jl of the band, tile
+// I <= J): bands in order, then rows, then tiles, so that an exclusive scan
+// of the counts gives each (row, tile) the colex position of its first kept
+// key among all kept keys.
+__device__ inline int64_t key_count_index(int64_t J, int jl, int64_t I) {
+  return 64 * (J * (J + 1) / 2) + (int64_t)jl * (J + 1) + I;
+}
+
+// Tiles a pass visits: all, or every kp.sample-th one for the sampled
+// histogram.
+__device__ inline int64_t tile_step(const KeyPass& kp, int mode) {
+  return (int64_t)gridDim.x * (mode == kKeysHist ? kp.sample : 1);
+}
+
+template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_keys_alu(const T* __restrict__ x, int64_t n, int32_t d,
-                                                  int ib, uint64_t* __restrict__ keys,
-                                                  int64_t ntiles, int hist_shift,
-                                                  uint32_t* __restrict__ hist) {
+                                                  int ib, int64_t ntiles, KeyPass kp) {
   __shared__ int32_t xs[2][kTile][kChunk + 1];
   __shared__ uint32_t lh[kHistBins];
-  hist_zero(lh);
+  constexpr bool kHist = MODE == kKeysFull || MODE == kKeysHist;
+  if (kHist) hist_zero(lh);
 
   const int il = threadIdx.x & 63;   // i inside the tile (one per lane)
   const int jl0 = threadIdx.x >> 6;  // first j of this wave; j = jl0 + 4q
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  const int64_t step = tile_step(kp, MODE);
+  for (int64_t t = blockIdx.x * (MODE == kKeysHist ? kp.sample : 1); t < ntiles; t += step) {
     int64_t jb, ibk;
     tile_coords(t, &jb, &ibk);
     const int64_t i0 = ibk * kTile, j0 = jb * kTile;
@@ -122,16 +136,31 @@ __global__ __launch_bounds__(256) void k_keys_alu(const T* __restrict__ x, int64
     const int64_t i = i0 + il;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int64_t j = j0 + jl0 + 4 * q;
-      if (j < n && i < j) {
-        const uint64_t delta = (uint64_t)acc[q];
-        keys[j * (j - 1) / 2 + i] =
-            (delta << (2 * ib)) | ((uint64_t)j << ib) | (uint64_t)i;
-        atomicAdd(&lh[delta >> hist_shift], 1u);
+      const int jl = jl0 + 4 * q;
+      const int64_t j = j0 + jl;
+      const bool valid = j < n && i < j;
+      const uint64_t delta = (uint64_t)acc[q];
+      const uint64_t key = (delta << (2 * ib)) | ((uint64_t)j << ib) | (uint64_t)i;
+      if constexpr (kHist) {
+        if (valid) {
+          if (MODE == kKeysFull) kp.keys[j * (j - 1) / 2 + i] = key;
+          atomicAdd(&lh[delta >> kp.hist_shift], 1u);
+        }
+      } else {
+        // One wave covers the 64 i of row j: a ballot counts and ranks.
+        const bool kept = valid && delta >= kp.dlo && delta < kp.dhi;
+        const uint64_t m = __ballot(kept);
+        const int64_t ci = key_count_index(jb, jl, ibk);
+        if (MODE == kKeysCount) {
+          if (il == 0) kp.cnt[ci] = (uint32_t)__popcll(m);
+        } else if (kept) {
+          const uint32_t below = __popcll(m & ((1ull << il) - 1ull));
+          kp.keys[kp.cnt[ci] + below] = key;
+        }
       }
     }
   }
-  hist_flush(lh, hist);
+  if (kHist) hist_flush(lh, kp.hist);
 }
 
 // ---- int8 MFMA Gram path ----
@@ -140,51 +169,80 @@ typedef int32_t v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kMaxDpad = 256;  // int8 dims staged per LDS round (multiple of 32)
 
+// Squared norms |x_i|^2 of int8 points (exact int32 for d <= 32768).
+__global__ void k_norms_i8(const int8_t* __restrict__ x, int64_t n, int32_t d,
+                           int32_t* __restrict__ norms) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t s = 0;
+    for (int32_t k = 0; k < d; ++k) {
+      const int32_t v = x[i * d + k];
+      s += v * v;
+    }
+    norms[i] = s;
+  }
+}
+
+// KMAX int8 dimensions are staged per LDS round (64 for d <= 64, else 256);
+// rows are padded by 16 bytes so that the 32 row reads of a half-wave spread
+// over the LDS banks.  With vec16 (d a multiple of 16 and 16-byte aligned
+// points) the rows are copied with 16-byte loads.
+template <int MODE, int KMAX>
 __global__ __launch_bounds__(256) void k_keys_mfma(const int8_t* __restrict__ x, int64_t n,
-                                                   int32_t d, int ib,
-                                                   uint64_t* __restrict__ keys,
-                                                   int64_t ntiles, int hist_shift,
-                                                   uint32_t* __restrict__ hist) {
-  // Rows padded by 16 bytes so that the 32 row reads of a half-wave spread
-  // over the LDS banks.
-  constexpr int kRow = kMaxDpad + 16;
+                                                   int32_t d, int ib, int64_t ntiles,
+                                                   const int32_t* __restrict__ norms,
+                                                   bool vec16, KeyPass kp) {
+  constexpr int kRow = KMAX + 16;
+  constexpr bool kHist = MODE == kKeysFull || MODE == kKeysHist;
   __shared__ __attribute__((aligned(16))) int8_t xs[2][kTile][kRow];
   __shared__ int32_t nrm[2][kTile];
-  __shared__ uint32_t lh[kHistBins];
-  hist_zero(lh);
+  __shared__ uint32_t lh[kHist ? kHistBins : 1];
+  __shared__ uint32_t half_cnt[kTile][2];  // kept keys per (row, half of the tile's i)
+  __shared__ uint32_t rbase[kTile];        // emit: colex base of each row's kept keys
+  if (kHist) hist_zero(lh);
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int jsub = wave >> 1, isub = wave & 1;  // 32 x 32 sub-tile of this wave
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  const int64_t step = tile_step(kp, MODE);
+  for (int64_t t = blockIdx.x * (MODE == kKeysHist ? kp.sample : 1); t < ntiles; t += step) {
     int64_t jb, ibk;
     tile_coords(t, &jb, &ibk);
     const int64_t i0 = ibk * kTile, j0 = jb * kTile;
     v16i c;
 #pragma unroll
     for (int r = 0; r < 16; ++r) c[r] = 0;
-    __syncthreads();  // the previous tile's readers of nrm are done
-    if (threadIdx.x < 2 * kTile) nrm[threadIdx.x >> 6][threadIdx.x & 63] = 0;
-    for (int k0 = 0; k0 < d; k0 += kMaxDpad) {
-      const int kc = d - k0 < kMaxDpad ? d - k0 : kMaxDpad;
+    __syncthreads();  // the previous tile's readers of LDS are done
+    if (threadIdx.x < 2 * kTile) {
+      const int side = threadIdx.x >> 6, pt = threadIdx.x & 63;
+      const int64_t g = (side ? j0 : i0) + pt;
+      nrm[side][pt] = g < n ? norms[g] : 0;
+    }
+    if (MODE == kKeysEmit && threadIdx.x < kTile)
+      rbase[threadIdx.x] = kp.cnt[key_count_index(jb, threadIdx.x, ibk)];
+    for (int k0 = 0; k0 < d; k0 += KMAX) {
+      const int kc = d - k0 < KMAX ? d - k0 : KMAX;
       const int kpad = (kc + 31) & ~31;
-      __syncthreads();
-      for (int e = threadIdx.x; e < kTile * kpad; e += blockDim.x) {
-        const int pt = e / kpad, kk = e - pt * kpad;
-        const int64_t gi = i0 + pt, gj = j0 + pt;
-        xs[0][pt][kk] = (gi < n && kk < kc) ? x[gi * d + k0 + kk] : (int8_t)0;
-        xs[1][pt][kk] = (gj < n && kk < kc) ? x[gj * d + k0 + kk] : (int8_t)0;
-      }
-      __syncthreads();
-      if (threadIdx.x < 2 * kTile) {
-        const int side = threadIdx.x >> 6, pt = threadIdx.x & 63;
-        int32_t s = 0;
-        for (int kk = 0; kk < kc; ++kk) {
-          const int32_t v = xs[side][pt][kk];
-          s += v * v;
+      if (k0 > 0) __syncthreads();
+      if (vec16) {
+        const int segs = kpad >> 4;  // 16-byte segments per row
+        for (int e = threadIdx.x; e < 2 * kTile * segs; e += blockDim.x) {
+          const int side = e / (kTile * segs), rem = e - side * kTile * segs;
+          const int pt = rem / segs, sg = rem - pt * segs;
+          const int64_t g = (side ? j0 : i0) + pt;
+          int4 v = make_int4(0, 0, 0, 0);
+          if (g < n && 16 * sg < kc) v = *reinterpret_cast<const int4*>(x + g * d + k0 + 16 * sg);
+          *reinterpret_cast<int4*>(&xs[side][pt][16 * sg]) = v;
         }
-        nrm[side][pt] += s;
+      } else {
+        for (int e = threadIdx.x; e < kTile * kpad; e += blockDim.x) {
+          const int pt = e / kpad, kk = e - pt * kpad;
+          const int64_t gi = i0 + pt, gj = j0 + pt;
+          xs[0][pt][kk] = (gi < n && kk < kc) ? x[gi * d + k0 + kk] : (int8_t)0;
+          xs[1][pt][kk] = (gj < n && kk < kc) ? x[gj * d + k0 + kk] : (int8_t)0;
+        }
       }
+      __syncthreads();
       // A = rows j (m = lane % 32), B = rows i (n = lane % 32); each lane
       // supplies 16 consecutive k of its row: k = 16 * (lane / 32) + 0..15.
       for (int kk = 0; kk < kpad; kk += 32) {
@@ -195,25 +253,57 @@ __global__ __launch_bounds__(256) void k_keys_mfma(const int8_t* __restrict__ x,
         c = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
       }
     }
-    __syncthreads();
     // D layout of a 32x32 MFMA: lane holds column n = lane % 32 and rows
-    // m = 8 * (r / 4) + 4 * (lane / 32) + r % 4 for r = 0..15.
+    // m = 8 * (r / 4) + 4 * (lane / 32) + r % 4 for r = 0..15.  So for one
+    // r, each half-wave holds one row j and 32 consecutive i.
     const int il = isub * 32 + (lane & 31);
     const int64_t i = i0 + il;
     const int32_t ni = nrm[0][il];
+    const int half = lane >> 5;
+    const uint64_t half_mask = half ? 0xFFFFFFFF00000000ull : 0x00000000FFFFFFFFull;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int jl = jsub * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int jl = jsub * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
       const int64_t j = j0 + jl;
-      if (j < n && i < j) {
+      const bool valid = j < n && i < j;
+      const uint64_t delta = (uint64_t)(int64_t)(nrm[1][jl] + ni - 2 * c[r]);
+      if constexpr (kHist) {
+        if (valid) {
+          if (MODE == kKeysFull)
+            kp.keys[j * (j - 1) / 2 + i] =
+                (delta << (2 * ib)) | ((uint64_t)j << ib) | (uint64_t)i;
+          atomicAdd(&lh[delta >> kp.hist_shift], 1u);
+        }
+      } else {
+        const bool kept = valid && delta >= kp.dlo && delta < kp.dhi;
+        const uint64_t m = __ballot(kept) & half_mask;
+        if ((lane & 31) == 0) half_cnt[jl][isub] = (uint32_t)__popcll(m);
+      }
+    }
+    if constexpr (MODE == kKeysCount) {
+      __syncthreads();
+      if (threadIdx.x < kTile)
+        kp.cnt[key_count_index(jb, threadIdx.x, ibk)] =
+            half_cnt[threadIdx.x][0] + half_cnt[threadIdx.x][1];
+    } else if constexpr (MODE == kKeysEmit) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int jl = jsub * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+        const int64_t j = j0 + jl;
+        const bool valid = j < n && i < j;
         const uint64_t delta = (uint64_t)(int64_t)(nrm[1][jl] + ni - 2 * c[r]);
-        keys[j * (j - 1) / 2 + i] =
-            (delta << (2 * ib)) | ((uint64_t)j << ib) | (uint64_t)i;
-        atomicAdd(&lh[delta >> hist_shift], 1u);
+        const bool kept = valid && delta >= kp.dlo && delta < kp.dhi;
+        const uint64_t m = __ballot(kept) & half_mask;
+        if (kept) {
+          const uint32_t below = __popcll(m & ((1ull << lane) - 1ull));
+          const uint32_t pos = rbase[jl] + (isub ? half_cnt[jl][0] : 0u) + below;
+          kp.keys[pos] = (delta << (2 * ib)) | ((uint64_t)j << ib) | (uint64_t)i;
+        }
       }
     }
   }
-  hist_flush(lh, hist);
+  if (kHist) hist_flush(lh, kp.hist);
 }
 
 int grid_for(int64_t count, int per_block, int cap) {
@@ -248,9 +338,36 @@ hipError_t launch_coord_range(const void* pts, int elem_bytes, int64_t n, int32_
   return hipGetLastError();
 }
 
-hipError_t launch_keys(const void* pts, int elem_bytes, int64_t n, int32_t d, int ib,
-                       uint64_t* keys, bool use_mfma, int hist_shift, uint32_t* hist,
-                       hipStream_t s) {
+int64_t key_count_len(int64_t n) {
+  const int64_t nb = (n + kTile - 1) / kTile;
+  return 64 * (nb * (nb + 1) / 2);
+}
+
+template <int MODE>
+void keys_launch(const void* pts, int elem_bytes, int64_t n, int32_t d, int ib, bool use_mfma,
+                 int64_t ntiles, int grid, const KeyPass& kp, hipStream_t s) {
+  if (use_mfma && elem_bytes == 1) {
+    const bool vec16 = (d % 16) == 0 && (reinterpret_cast<uintptr_t>(pts) % 16) == 0;
+    hipLaunchKernelGGL(k_norms_i8, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s,
+                       static_cast<const int8_t*>(pts), n, d, kp.norms);
+    if (d <= 64)
+      hipLaunchKernelGGL((k_keys_mfma<MODE, 64>), dim3(grid), dim3(256), 0, s,
+                         static_cast<const int8_t*>(pts), n, d, ib, ntiles,
+                         (const int32_t*)kp.norms, vec16, kp);
+    else
+      hipLaunchKernelGGL((k_keys_mfma<MODE, 256>), dim3(grid), dim3(256), 0, s,
+                         static_cast<const int8_t*>(pts), n, d, ib, ntiles,
+                         (const int32_t*)kp.norms, vec16, kp);
+  } else if (elem_bytes == 1)
+    hipLaunchKernelGGL((k_keys_alu<int8_t, MODE>), dim3(grid), dim3(256), 0, s,
+                       static_cast<const int8_t*>(pts), n, d, ib, ntiles, kp);
+  else
+    hipLaunchKernelGGL((k_keys_alu<int16_t, MODE>), dim3(grid), dim3(256), 0, s,
+                       static_cast<const int16_t*>(pts), n, d, ib, ntiles, kp);
+}
+
+hipError_t launch_keys_pass(const void* pts, int elem_bytes, int64_t n, int32_t d, int ib,
+                            bool use_mfma, const KeyPass& kp, hipStream_t s) {
   const int64_t nb = (n + kTile - 1) / kTile;
   const int64_t ntiles = nb * (nb + 1) / 2;
   // Resident-sized grid: each workgroup loops over tiles, so its histogram
@@ -263,19 +380,31 @@ hipError_t launch_keys(const void* pts, int elem_bytes, int64_t n, int32_t d, in
         prop.multiProcessorCount > 0)
       cus = prop.multiProcessorCount;
   }
+  const int64_t sample = kp.mode == kKeysHist ? (kp.sample > 0 ? kp.sample : 1) : 1;
+  const int64_t visited = (ntiles + sample - 1) / sample;
   const int64_t cap = 8 * (int64_t)cus;
-  const int grid = (int)(ntiles < cap ? ntiles : cap);
-  if (use_mfma && elem_bytes == 1) {
-    hipLaunchKernelGGL(k_keys_mfma, dim3(grid), dim3(256), 0, s,
-                       static_cast<const int8_t*>(pts), n, d, ib, keys, ntiles, hist_shift, hist);
-  } else if (elem_bytes == 1) {
-    hipLaunchKernelGGL(k_keys_alu<int8_t>, dim3(grid), dim3(256), 0, s,
-                       static_cast<const int8_t*>(pts), n, d, ib, keys, ntiles, hist_shift, hist);
-  } else {
-    hipLaunchKernelGGL(k_keys_alu<int16_t>, dim3(grid), dim3(256), 0, s,
-                       static_cast<const int16_t*>(pts), n, d, ib, keys, ntiles, hist_shift, hist);
+  const int grid = (int)(visited < cap ? visited : cap);
+  KeyPass k = kp;
+  k.sample = sample;
+  switch (kp.mode) {
+    case kKeysFull: keys_launch<kKeysFull>(pts, elem_bytes, n, d, ib, use_mfma, ntiles, grid, k, s); break;
+    case kKeysHist: keys_launch<kKeysHist>(pts, elem_bytes, n, d, ib, use_mfma, ntiles, grid, k, s); break;
+    case kKeysCount: keys_launch<kKeysCount>(pts, elem_bytes, n, d, ib, use_mfma, ntiles, grid, k, s); break;
+    default: keys_launch<kKeysEmit>(pts, elem_bytes, n, d, ib, use_mfma, ntiles, grid, k, s); break;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_keys(const void* pts, int elem_bytes, int64_t n, int32_t d, int ib,
+                       uint64_t* keys, bool use_mfma, int hist_shift, uint32_t* hist,
+                       int32_t* norms, hipStream_t s) {
+  KeyPass kp;
+  kp.mode = kKeysFull;
+  kp.keys = keys;
+  kp.hist = hist;
+  kp.hist_shift = hist_shift;
+  kp.norms = norms;
+  return launch_keys_pass(pts, elem_bytes, n, d, ib, use_mfma, kp, s);
 }
 
 }  // namespace ph0

@@ -51,6 +51,10 @@ constexpr int64_t kMaxN = 65536;
 // values the autotuner (paper_2203_02527_amd/autotune.py) chose on MI355X
 // for the batch workload's clouds.
 constexpr int32_t kChunkMult[4] = {6, 6, 6, 48};
+// Edge count from which the single-cloud path recomputes keys per distance
+// range instead of storing all of them (below it, the extra passes and host
+// round trips cost more than the stored keys).
+constexpr int64_t kRecomputeMinE = int64_t(1) << 22;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
@@ -71,7 +75,7 @@ int64_t window_for(int64_t n, int64_t E) {
 struct Layout {
   int64_t n, E, LW, Wcap, tiles;
   size_t keysA, keysB, counts, hist, err, table, killer, lowc, touch, act0, act1, rtag, ra, rr, rrlo,
-      rst, ctl, blockcnt, dbv, minmax, total;
+      rst, ctl, blockcnt, dbv, minmax, kcnt, kcnt_tot, norms, total;
 };
 
 Layout make_layout(int64_t n, int32_t d) {
@@ -108,6 +112,10 @@ Layout make_layout(int64_t n, int32_t d) {
   L.blockcnt = take(4 * (size_t)(rank_blocks(keys) + 1));
   L.dbv = take(4 * (size_t)n);
   L.minmax = take(8 * (size_t)d);
+  const int64_t kc = key_count_len(n) + 1;  // + 1: the scan leaves the total there
+  L.kcnt = take(4 * (size_t)kc);
+  L.kcnt_tot = take(4 * (size_t)scan_totals_len(kc));
+  L.norms = take(4 * (size_t)n);
   L.total = o;
   (void)d;
   return L;
@@ -285,11 +293,30 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   uint32_t* hist = static_cast<uint32_t*>(at(L.hist));
   int32_t* serr = static_cast<int32_t*>(at(L.err));
   const int hist_shift = dbits > 11 ? dbits - 11 : 0;
+  int32_t* norms = static_cast<int32_t*>(at(L.norms));
 
+  // Large problems never store all keys: a sampled histogram picks the
+  // distance ranges, and each range's keys are recomputed and written, in
+  // colex order, only when the reduction needs them.
+  const bool recompute = stop == kStopAll && L.E >= kRecomputeMinE;
+  const int64_t nbk = (n + 63) / 64;
+  const int64_t sample = std::max<int64_t>(1, nbk * (nbk + 1) / 2 / 2048);
+  bool keys_full = false;  // keysA holds every key at its colex position
   HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t*>(serr), 0u, 1, s));
   HIPCHK(launch_fill_u32(hist, 0u, kHistBins, s));
   tm.mark();  // 1
-  HIPCHK(launch_keys(d_points, eb, n, d, ib, keysA, mfma, hist_shift, hist, s));
+  if (recompute) {
+    KeyPass kp;
+    kp.mode = kKeysHist;
+    kp.norms = norms;
+    kp.hist = hist;
+    kp.hist_shift = hist_shift;
+    kp.sample = sample;
+    HIPCHK(launch_keys_pass(d_points, eb, n, d, ib, mfma, kp, s));
+  } else {
+    HIPCHK(launch_keys(d_points, eb, n, d, ib, keysA, mfma, hist_shift, hist, norms, s));
+    keys_full = true;
+  }
   tm.mark();  // 2
   if (stop == kStopKeys) {
     HIPCHK(hipMemcpyAsync(out.keys, keysA, 8 * (size_t)L.E, hipMemcpyDeviceToDevice, s));
@@ -312,6 +339,11 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   uint64_t* skeys = keysA;  // sorted order (a prefix of it while chunked)
   uint64_t* spare = keysB;  // the other buffer
   auto full_sort = [&]() -> hipError_t {
+    if (!keys_full) {
+      const hipError_t e = launch_keys(d_points, eb, n, d, ib, keysA, mfma, hist_shift, hist, norms, s);
+      if (e != hipSuccess) return e;
+      keys_full = true;
+    }
     uint64_t* src = keysA;
     uint64_t* dst = keysB;
     for (int p = 0; p < sp.passes; ++p) {
@@ -345,12 +377,44 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   int64_t E_lim = 0;
   int bin_next = 0, chunks = 0;
   bool whole = false;
+  uint32_t* kcnt = static_cast<uint32_t*>(at(L.kcnt));
+  const int64_t kcnt_len = key_count_len(n);
+  // Exact number of keys in bins [blo, bhi), with their colex bases left in
+  // kcnt for the emit pass.
+  auto count_range = [&](int blo, int bhi, int64_t* cnt) -> hipError_t {
+    KeyPass kp;
+    kp.mode = kKeysCount;
+    kp.norms = norms;
+    kp.dlo = (uint64_t)blo << hist_shift;
+    kp.dhi = bhi >= kHistBins ? ~0ull : (uint64_t)bhi << hist_shift;
+    kp.cnt = kcnt;
+    hipError_t e = launch_keys_pass(d_points, eb, n, d, ib, mfma, kp, s);
+    if (e == hipSuccess) e = launch_fill_u32(kcnt + kcnt_len, 0u, 1, s);
+    if (e == hipSuccess)
+      e = launch_scan_u32(kcnt, kcnt_len + 1, static_cast<uint32_t*>(at(L.kcnt_tot)), s);
+    uint32_t total = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&total, kcnt + kcnt_len, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    *cnt = total;
+    return e;
+  };
   auto next_chunk = [&]() -> hipError_t {
     const int64_t target = std::max<int64_t>(L.E / 16, 8 * n) << std::min(chunks, 20);
     int b = bin_next;
     int64_t cnt = 0;
-    while (b < kHistBins && (cnt == 0 || cnt < target)) cnt += h[b++];
+    while (b < kHistBins && (cnt == 0 || cnt < target))
+      cnt += (int64_t)h[b++] * (keys_full ? 1 : sample);
     ++chunks;
+    if (!keys_full && sp.passes > 0) {
+      // Exact count; a sampled histogram can show keys where there are none.
+      while (true) {
+        const hipError_t e = count_range(bin_next, b, &cnt);
+        if (e != hipSuccess) return e;
+        if (cnt > 0 || b >= kHistBins) break;
+        while (b < kHistBins && h[b] == 0) ++b;
+        if (b < kHistBins) ++b;
+      }
+    }
     if (sp.passes == 0 || E_lim + 2 * cnt > L.E) {
       // The rest in one full sort; its prefix equals the chunks sorted so far.
       whole = true;
@@ -358,15 +422,29 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
       return full_sort();
     }
     KeyFilter f;
-    f.fshift = 2 * ib + hist_shift;
-    f.flo = (uint64_t)bin_next;
-    f.fhi = (uint64_t)b;
+    int64_t first_in = L.E;
+    if (keys_full) {  // the first pass picks the range out of all keys
+      f.fshift = 2 * ib + hist_shift;
+      f.flo = (uint64_t)bin_next;
+      f.fhi = (uint64_t)b;
+    } else {  // the range's keys, recomputed into keysA in colex order
+      KeyPass kp;
+      kp.mode = kKeysEmit;
+      kp.norms = norms;
+      kp.dlo = (uint64_t)bin_next << hist_shift;
+      kp.dhi = b >= kHistBins ? ~0ull : (uint64_t)b << hist_shift;
+      kp.cnt = kcnt;
+      kp.keys = keysA;
+      const hipError_t e = launch_keys_pass(d_points, eb, n, d, ib, mfma, kp, s);
+      if (e != hipSuccess) return e;
+      first_in = cnt;
+    }
     uint64_t* D = keysB + E_lim;        // the chunk's final place
     uint64_t* T = keysB + E_lim + cnt;  // scratch for the ping-pong
     const uint64_t* in = keysA;
     for (int p = 0; p < sp.passes; ++p) {
       uint64_t* o = ((sp.passes - 1 - p) % 2 == 0) ? D : T;
-      const hipError_t e = pass(in, o, p == 0 ? L.E : cnt, p, p == 0 ? f : KeyFilter(), cnt);
+      const hipError_t e = pass(in, o, p == 0 ? first_in : cnt, p, p == 0 ? f : KeyFilter(), cnt);
       if (e != hipSuccess) return e;
       in = o;
     }

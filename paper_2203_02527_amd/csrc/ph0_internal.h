@@ -68,11 +68,44 @@ hipError_t launch_coord_range(const void* pts, int elem_bytes, int64_t n, int32_
                               hipStream_t s);
 
 // Step 1: keys of all edges at colex positions, and the histogram of
-// delta >> hist_shift over kHistBins bins (added into `hist`).
+// delta >> hist_shift over kHistBins bins (added into `hist`).  `norms`
+// (n words) is scratch for the int8 Gram path.
 constexpr int kHistBins = 2048;
 hipError_t launch_keys(const void* pts, int elem_bytes, int64_t n, int32_t d, int ib,
                        uint64_t* keys, bool use_mfma, int hist_shift, uint32_t* hist,
-                       hipStream_t s);
+                       int32_t* norms, hipStream_t s);
+
+// One pass of the key kernels over all tiles of the distance matrix.
+//  * kKeysFull:  every key at its colex position, and the histogram;
+//  * kKeysHist:  the histogram only, over every `sample`-th tile;
+//  * kKeysCount: for the keys with dlo <= delta < dhi, their number per
+//                (64-row band J, row j in the band, tile I <= J), stored at
+//                key_count_index(J, j - 64 J, I);
+//  * kKeysEmit:  those keys again, each written at (the exclusive scan of
+//                the counts at its (J, row, I)) + (its rank among the kept
+//                keys of its row in the tile), i.e. in colex order.
+// The selected keys of a distance range are thus written without ever
+// storing the others: distances are recomputed, which costs a few MFMA
+// instructions per tile, instead of 8 bytes of HBM traffic per edge.
+enum : int { kKeysFull = 0, kKeysHist = 1, kKeysCount = 2, kKeysEmit = 3 };
+struct KeyPass {
+  int mode = kKeysFull;
+  uint64_t* keys = nullptr;
+  uint32_t* hist = nullptr;
+  int hist_shift = 0;
+  int64_t sample = 1;
+  uint64_t dlo = 0, dhi = 0;
+  uint32_t* cnt = nullptr;
+  int32_t* norms = nullptr;  // n words of scratch (int8 Gram path)
+};
+hipError_t launch_keys_pass(const void* pts, int elem_bytes, int64_t n, int32_t d, int ib,
+                            bool use_mfma, const KeyPass& kp, hipStream_t s);
+// Entries of the per-(band, row, tile) count array (64 per tile).
+int64_t key_count_len(int64_t n);
+// Exclusive prefix sum of v[0..len) in place; `totals` holds
+// scan_totals_len(len) words of scratch.
+int64_t scan_totals_len(int64_t len);
+hipError_t launch_scan_u32(uint32_t* v, int64_t len, uint32_t* totals, hipStream_t s);
 
 // Step 2: one stable LSD pass in -> out by digit (key >> shift) & ((1<<bits)-1).
 // `counts` holds radix_count_entries(count) words of scratch.

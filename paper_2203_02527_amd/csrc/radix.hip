@@ -258,4 +258,15 @@ hipError_t launch_radix_pass(const uint64_t* in, uint64_t* out, int64_t count, i
   return hipGetLastError();
 }
 
+int64_t scan_totals_len(int64_t len) { return (len + kScanBlock - 1) / kScanBlock + 1; }
+
+hipError_t launch_scan_u32(uint32_t* v, int64_t len, uint32_t* totals, hipStream_t s) {
+  if (len <= 0) return hipSuccess;
+  const int64_t nblocks = (len + kScanBlock - 1) / kScanBlock;
+  hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)nblocks), dim3(kThreads), 0, s, v, len, totals);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, s, totals, nblocks);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblocks), dim3(kThreads), 0, s, v, len, totals);
+  return hipGetLastError();
+}
+
 }  // namespace ph0

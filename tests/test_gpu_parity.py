@@ -208,6 +208,29 @@ def test_uniform_workload_n256(torch):
 def test_mixture_workload_n4096(torch):
     st = _check_full(torch, synth.workload("mixture_n4096_d16_i8", seed=0))
     assert st["keys_path"] == 1
+    assert st["sort_chunks"] >= 2  # several recomputed distance ranges
+
+
+# Above 2^22 edges the keys of each distance range are recomputed and emitted
+# in colex order instead of stored; these clouds exercise that path's edge
+# cases: an outlier that puts the last pivot at the very end (so the ranges
+# grow until the rest is sorted whole), massive ties (a few distinct
+# distances, whole ranges in one histogram bin), and the vector ALU path.
+def test_recomputed_ranges_outlier_forces_whole_sort(torch):
+    x = _cloud(41, 3000, 3, -100, 100, np.int16)
+    x[1234] = (16000, 16000, 16000)
+    st = _check_full(torch, x)
+    assert st["keys_path"] == 0 and st["E_eff"] > st["E"] // 2
+
+
+def test_recomputed_ranges_massive_ties(torch):
+    st = _check_full(torch, _cloud(42, 3100, 2, 0, 6, np.int8))
+    assert st["E"] >= 1 << 22
+
+
+def test_recomputed_ranges_mfma_ragged(torch):
+    st = _check_full(torch, _cloud(43, 2990, 64, -128, 127, np.int8))
+    assert st["keys_path"] == 1 and st["E"] >= 1 << 22
 
 
 def _sha(a, dt):
