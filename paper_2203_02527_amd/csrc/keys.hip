@@ -42,20 +42,52 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t count) {
     p[i] = v;
 }
 
+// Per-dimension coordinate ranges: lo[k] = min x_ik, hi[k] = max x_ik
+// (minmax = lo[0..d) then hi[0..d)).  A coalesced grid-stride pass over all
+// coordinates folds each into LDS per-dimension minima and maxima (d <= kRangeLds),
+// then one global atomic pair per dimension and workgroup.
+constexpr int kRangeLds = 1024;
+
 template <typename T>
-__global__ void k_coord_range(const T* __restrict__ x, int64_t n, int32_t d,
-                              int32_t* __restrict__ minmax) {
-  // One block per dimension chunk; grid-stride over points.
+__global__ __launch_bounds__(256) void k_coord_range(const T* __restrict__ x, int64_t n,
+                                                     int32_t d, int32_t* __restrict__ minmax) {
+  __shared__ int32_t lo[kRangeLds], hi[kRangeLds];
+  for (int k = threadIdx.x; k < d; k += blockDim.x) {
+    lo[k] = 0x7FFFFFFF;
+    hi[k] = (int32_t)0x80000000;
+  }
+  __syncthreads();
+  const int64_t total = n * d;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int k = (int)(e % d);
+  const int kstep = (int)(stride % d);
+  for (; e < total; e += stride) {
+    const int32_t v = x[e];
+    atomicMin(&lo[k], v);
+    atomicMax(&hi[k], v);
+    k += kstep;
+    if (k >= d) k -= d;
+  }
+  __syncthreads();
+  for (int kk = threadIdx.x; kk < d; kk += blockDim.x) {
+    if (lo[kk] != 0x7FFFFFFF) atomicMin(&minmax[kk], lo[kk]);
+    if (hi[kk] != (int32_t)0x80000000) atomicMax(&minmax[d + kk], hi[kk]);
+  }
+}
+
+// The same for d > kRangeLds: one dimension per workgroup row of the grid.
+template <typename T>
+__global__ void k_coord_range_wide(const T* __restrict__ x, int64_t n, int32_t d,
+                                   int32_t* __restrict__ minmax) {
   for (int k = blockIdx.y; k < d; k += gridDim.y) {
-    int lo = 1 << 30, hi = -(1 << 30);
+    int lo = 0x7FFFFFFF, hi = (int32_t)0x80000000;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-      int v = x[i * d + k];
+      const int v = x[i * d + k];
       lo = v < lo ? v : lo;
       hi = v > hi ? v : hi;
     }
-    // One atomic pair per wavefront: per-thread atomics on the same 2d
-    // addresses serialize.
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
       const int l2 = __shfl_xor(lo, o), h2 = __shfl_xor(hi, o);
@@ -63,8 +95,8 @@ __global__ void k_coord_range(const T* __restrict__ x, int64_t n, int32_t d,
       hi = h2 > hi ? h2 : hi;
     }
     if ((threadIdx.x & 63) == 0) {
-      atomicMin(&minmax[2 * k], lo);
-      atomicMax(&minmax[2 * k + 1], hi);
+      atomicMin(&minmax[k], lo);
+      atomicMax(&minmax[d + k], hi);
     }
   }
 }
@@ -328,13 +360,27 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s
 
 hipError_t launch_coord_range(const void* pts, int elem_bytes, int64_t n, int32_t d,
                               int32_t* minmax, hipStream_t s) {
-  dim3 grid(grid_for(n, 256, 64), d < 256 ? d : 256);
-  if (elem_bytes == 1)
-    hipLaunchKernelGGL(k_coord_range<int8_t>, grid, dim3(256), 0, s,
-                       static_cast<const int8_t*>(pts), n, d, minmax);
-  else
-    hipLaunchKernelGGL(k_coord_range<int16_t>, grid, dim3(256), 0, s,
-                       static_cast<const int16_t*>(pts), n, d, minmax);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t*>(minmax),
+                     0x7FFFFFFFu, (int64_t)d);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s,
+                     reinterpret_cast<uint32_t*>(minmax + d), 0x80000000u, (int64_t)d);
+  if (d <= kRangeLds) {
+    const int g = grid_for(n * d, 256 * 16, 1024);
+    if (elem_bytes == 1)
+      hipLaunchKernelGGL(k_coord_range<int8_t>, dim3(g), dim3(256), 0, s,
+                         static_cast<const int8_t*>(pts), n, d, minmax);
+    else
+      hipLaunchKernelGGL(k_coord_range<int16_t>, dim3(g), dim3(256), 0, s,
+                         static_cast<const int16_t*>(pts), n, d, minmax);
+  } else {
+    dim3 grid(grid_for(n, 256, 64), d < 256 ? d : 256);
+    if (elem_bytes == 1)
+      hipLaunchKernelGGL(k_coord_range_wide<int8_t>, grid, dim3(256), 0, s,
+                         static_cast<const int8_t*>(pts), n, d, minmax);
+    else
+      hipLaunchKernelGGL(k_coord_range_wide<int16_t>, grid, dim3(256), 0, s,
+                         static_cast<const int16_t*>(pts), n, d, minmax);
+  }
   return hipGetLastError();
 }
 

@@ -75,7 +75,7 @@ int64_t window_for(int64_t n, int64_t E) {
 struct Layout {
   int64_t n, E, LW, Wcap, tiles;
   size_t keysA, keysB, counts, hist, err, table, killer, lowc, touch, act0, act1, rtag, ra, rr, rrlo,
-      rst, ctl, blockcnt, dbv, minmax, kcnt, kcnt_tot, norms, total;
+      rst, ctl, dbv, minmax, kcnt, kcnt_tot, norms, total;
 };
 
 Layout make_layout(int64_t n, int32_t d) {
@@ -109,7 +109,6 @@ Layout make_layout(int64_t n, int32_t d) {
   L.rrlo = take(4 * (size_t)L.Wcap);
   L.rst = take(4 * (size_t)L.Wcap);
   L.ctl = take(sizeof(RedCtl));
-  L.blockcnt = take(4 * (size_t)(rank_blocks(keys) + 1));
   L.dbv = take(4 * (size_t)n);
   L.minmax = take(8 * (size_t)d);
   const int64_t kc = key_count_len(n) + 1;  // + 1: the scan leaves the total there
@@ -254,24 +253,16 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
 
   Timer tm(st != nullptr, s);
   tm.mark();  // 0
-  // Bound on the squared distance from the per-dimension coordinate ranges.
-  // The range kernel keeps (min, max) interleaved per dimension.
+  // Bound on the squared distance from the per-dimension coordinate ranges
+  // (lo[0..d) then hi[0..d)).
   int32_t* mm = static_cast<int32_t*>(at(L.minmax));
-  std::vector<int32_t> pairs(2 * (size_t)d);
-  {
-    std::vector<int32_t> init(2 * (size_t)d);
-    for (int32_t k = 0; k < d; ++k) {
-      init[2 * k] = 0x7FFFFFFF;
-      init[2 * k + 1] = (int32_t)0x80000000;
-    }
-    HIPCHK(hipMemcpyAsync(mm, init.data(), 8 * (size_t)d, hipMemcpyHostToDevice, s));
-    HIPCHK(launch_coord_range(d_points, eb, n, d, mm, s));
-    HIPCHK(hipMemcpyAsync(pairs.data(), mm, 8 * (size_t)d, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-  }
+  std::vector<int32_t> ranges(2 * (size_t)d);
+  HIPCHK(launch_coord_range(d_points, eb, n, d, mm, s));
+  HIPCHK(hipMemcpyAsync(ranges.data(), mm, 8 * (size_t)d, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
   unsigned __int128 bound = 0;
   for (int32_t k = 0; k < d; ++k) {
-    const int64_t w = (int64_t)pairs[2 * k + 1] - pairs[2 * k];
+    const int64_t w = (int64_t)ranges[d + k] - ranges[k];
     bound += (unsigned __int128)(w * w);
   }
   int dbits = 0;
@@ -525,38 +516,25 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   S.words_read = hc->words_read;
   S.rounds = hc->round;
 
-  // Grades over [0, E_eff) into the spare buffer, then per-vertex deaths.
-  uint32_t* rank = reinterpret_cast<uint32_t*>(spare);
-  HIPCHK(launch_rank(skeys, ra.ctl, 2 * ib, static_cast<uint32_t*>(at(L.blockcnt)), L.E, rank,
-                     s));
+  // Grades over [0, E_eff), per-vertex deaths and the barcode, in one
+  // ordered pass over the pivot positions (scratch: the spare key buffer).
   uint32_t* dbv = out.dbv ? out.dbv : static_cast<uint32_t*>(at(L.dbv));
-  HIPCHK(launch_vertex_deaths(ra.killer, rank, n, dbv, s));
-  uint32_t last_rank = 0;
-  HIPCHK(hipMemcpyAsync(&last_rank, rank + (hc->E_eff - 1), 4, hipMemcpyDeviceToHost, s));
+  uint32_t distinct = 0, npiv = 0;
+  if (grades_work_bytes(hc->E_eff) > 8 * (size_t)std::max<int64_t>(L.E, 2 * n + 64))
+    return fail(PH0_EDEVICE, "grade scratch does not fit the key buffer");
+  HIPCHK(launch_grades_and_bars(skeys, hc->E_eff, 2 * ib, ra.killer, n, spare, dbv,
+                                reinterpret_cast<uint32_t*>(out.bars), s, &distinct, &npiv));
   tm.mark();  // 5
-  if (out.bars) {
-    if (n <= kSmallSortMax) {
-      HIPCHK(launch_sort_bars_small(dbv, n, reinterpret_cast<uint32_t*>(out.bars), s));
-    } else {
-      // Larger barcodes: the same LSD passes over the 32 death bits.
-      uint64_t* ka = spare;
-      uint64_t* kb = spare + n;
-      HIPCHK(launch_u32_to_keys(dbv, n, ka, s));
-      for (int p = 0; p < 4; ++p) {
-        HIPCHK(launch_radix_pass(ka, kb, n, 8 * p, 8, counts, serr, s));
-        std::swap(ka, kb);
-      }
-      HIPCHK(launch_keys_to_bars(ka, n, reinterpret_cast<uint32_t*>(out.bars), s));
-    }
-  }
   if (out.killer_pos || out.killer_edge || out.killer_sqdist || out.partner)
     HIPCHK(launch_pairs_detail(ra.killer, skeys, ib, ra.table, L.LW, n, out.killer_pos,
                                out.killer_edge, out.killer_sqdist, out.partner, s));
   tm.mark();  // 6
   HIPCHK(hipMemcpyAsync(&herr, serr, 4, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (herr) return fail(PH0_EDEVICE, "barcode sort digit counts were inconsistent");
-  S.distinct_eff = last_rank;
+  if (herr) return fail(PH0_EDEVICE, "radix sort digit counts were inconsistent");
+  if (npiv != (uint32_t)(n - 1))
+    return fail(PH0_EDEVICE, "found %u pivot columns, expected %lld", npiv, (long long)(n - 1));
+  S.distinct_eff = 1 + distinct;
   if (st) {
     S.ms_keys = tm.ms(1, 2);
     S.ms_sort = tm.ms(2, 3);

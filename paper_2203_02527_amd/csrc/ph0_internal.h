@@ -44,6 +44,7 @@ struct RedCtl {
   int32_t done;
   int32_t err;  // bit 0: a reduced column had weight != 2; bit 1: ran out of columns
   int32_t need_more;  // every available column is final and pivots are missing
+  uint32_t ticket;    // commit workgroups finished this round (the last one advances)
 };
 
 // Per-column state of the reduction window, a ring indexed by p % Wcap.
@@ -64,7 +65,7 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s
 
 // Per-dimension coordinate range -> bound on the squared distance.
 hipError_t launch_coord_range(const void* pts, int elem_bytes, int64_t n, int32_t d,
-                              int32_t* minmax /* 2*d, zeroed to +-inf by caller */,
+                              int32_t* minmax /* 2*d: lo[0..d) then hi[0..d) */,
                               hipStream_t s);
 
 // Step 1: keys of all edges at colex positions, and the histogram of
@@ -143,25 +144,24 @@ hipError_t launch_reduce_extend(const RedArgs& a, int64_t E_lim, hipStream_t s);
 hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_walk);
 hipError_t launch_reduce_finish(const RedArgs& a, hipStream_t s);
 
-// Step 3 (dense grades) over the first E_eff sorted keys.
-int64_t rank_blocks(int64_t count);
-hipError_t launch_rank(const uint64_t* skeys, const RedCtl* ctl, int shift, uint32_t* blockcnt,
-                       int64_t max_count, uint32_t* rank_out, hipStream_t s);
-
-// Step 5: per-vertex deaths and the canonical barcode.
-hipError_t launch_vertex_deaths(const int64_t* killer, const uint32_t* rank, int64_t n,
-                                uint32_t* dbv, hipStream_t s);
-hipError_t launch_sort_bars_small(const uint32_t* dbv, int64_t n, uint32_t* out_bars,
-                                  hipStream_t s);
-hipError_t launch_u32_to_keys(const uint32_t* v, int64_t n, uint64_t* keys, hipStream_t s);
-hipError_t launch_keys_to_bars(const uint64_t* keys, int64_t n, uint32_t* out_bars,
-                               hipStream_t s);
+// Steps 3 and 5 together, over the first E_eff sorted keys: the grade of a
+// sorted position p is 1 + the number of distance changes in 1..p (dense
+// ranks of D); the pivot columns, in sorted order, are the deaths in
+// ascending order (grades only grow with p), so one ordered pass over the
+// positions writes both the canonical barcode and the per-vertex deaths,
+// with no sort.  `work` holds grades_work_bytes(E_eff) bytes; dbv may be the
+// caller's or scratch (n words); bars may be null.  *distinct receives the
+// number of distinct distances in the prefix, *pivots the pivot count.
+size_t grades_work_bytes(int64_t E_eff);
+hipError_t launch_grades_and_bars(const uint64_t* skeys, int64_t E_eff, int shift,
+                                  const int64_t* killer, int64_t n, void* work, uint32_t* dbv,
+                                  uint32_t* bars, hipStream_t s, uint32_t* distinct,
+                                  uint32_t* pivots);
 hipError_t launch_pairs_detail(const int64_t* killer, const uint64_t* skeys, int ib,
                                const uint64_t* table, int64_t LW, int64_t n,
                                int64_t* killer_pos, uint64_t* killer_edge,
                                int64_t* killer_sqdist, int32_t* partner, hipStream_t s);
 
-constexpr int kSmallSortMax = 16384;  // barcode sorts up to this size run in LDS
 
 // Many small clouds, one persistent launch (one workgroup per cloud).
 constexpr int kBatchMaxN = 512;     // largest cloud the fused kernel takes

@@ -6,166 +6,116 @@
 //
 // The grade of sorted position p is 1 + the number of positions q in 1..p
 // where the distance changes; only positions below E_eff are ever needed,
-// because no pivot lies beyond the last one.
+// because no pivot lies beyond the last one.  Grades never decrease with p,
+// so listing the pivot positions in order lists the deaths in ascending
+// order: the barcode needs a scan, not a sort.
 #include "ph0_internal.h"
 
 namespace ph0 {
 
 namespace {
 
-constexpr int kRankThreads = 256;
-constexpr int kRankPer = 16;
-constexpr int kRankBlock = kRankThreads * kRankPer;  // positions per block
+constexpr int kGroup = 256;  // positions per group (one workgroup pass)
 
-__device__ uint32_t block_sum_256(uint32_t v, uint32_t* tmp) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  if (lane == 0) tmp[wave] = v;
-  __syncthreads();
-  uint32_t s = tmp[0] + tmp[1] + tmp[2] + tmp[3];
-  __syncthreads();
-  return s;
-}
-
-__device__ uint32_t block_excl_256(uint32_t v, uint32_t* tmp) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) tmp[wave] = x;
-  __syncthreads();
-  uint32_t base = 0;
-  for (int w = 0; w < wave; ++w) base += tmp[w];
-  __syncthreads();
-  return base + x - v;
-}
-
-__device__ inline uint32_t change_flags(const uint64_t* __restrict__ k, int64_t p0, int64_t count,
-                                        int shift, uint32_t* bits) {
-  uint32_t m = 0, c = 0;
-  uint64_t prev = p0 > 0 && p0 - 1 < count ? k[p0 - 1] >> shift : ~0ull;
-#pragma unroll
-  for (int q = 0; q < kRankPer; ++q) {
-    const int64_t p = p0 + q;
-    if (p < count) {
-      const uint64_t v = k[p] >> shift;
-      if (p > 0 && v != prev) {
-        m |= 1u << q;
-        ++c;
-      }
-      prev = v;
-    }
-  }
-  *bits = m;
-  return c;
-}
-
-__global__ __launch_bounds__(kRankThreads) void k_rank_count(const uint64_t* __restrict__ k,
-                                                             const RedCtl* ctl, int shift,
-                                                             uint32_t* blockcnt) {
-  __shared__ uint32_t tmp[4];
-  const int64_t count = ctl->E_eff;
-  const int64_t nb = (count + kRankBlock - 1) / kRankBlock;
-  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-    uint32_t bits;
-    const uint32_t c = change_flags(k, b * kRankBlock + threadIdx.x * kRankPer, count, shift, &bits);
-    const uint32_t s = block_sum_256(c, tmp);
-    if (threadIdx.x == 0) blockcnt[b] = s;
-  }
-}
-
-__global__ __launch_bounds__(kRankThreads) void k_rank_scan(const RedCtl* ctl, uint32_t* blockcnt) {
-  __shared__ uint32_t tmp[4];
-  const int64_t count = ctl->E_eff;
-  const int64_t nb = (count + kRankBlock - 1) / kRankBlock;
-  uint32_t carry = 0;
-  for (int64_t b0 = 0; b0 < nb; b0 += kRankThreads) {
-    const int64_t b = b0 + threadIdx.x;
-    const uint32_t v = b < nb ? blockcnt[b] : 0;
-    const uint32_t ex = block_excl_256(v, tmp);
-    const uint32_t tot = block_sum_256(v, tmp);
-    if (b < nb) blockcnt[b] = carry + ex;
-    carry += tot;
-  }
-}
-
-__global__ __launch_bounds__(kRankThreads) void k_rank_write(const uint64_t* __restrict__ k,
-                                                             const RedCtl* ctl, int shift,
-                                                             const uint32_t* blockcnt,
-                                                             uint32_t* __restrict__ rank) {
-  __shared__ uint32_t tmp[4];
-  const int64_t count = ctl->E_eff;
-  const int64_t nb = (count + kRankBlock - 1) / kRankBlock;
-  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-    const int64_t p0 = b * kRankBlock + threadIdx.x * kRankPer;
-    uint32_t bits;
-    const uint32_t c = change_flags(k, p0, count, shift, &bits);
-    uint32_t run = 1 + blockcnt[b] + block_excl_256(c, tmp);
-#pragma unroll
-    for (int q = 0; q < kRankPer; ++q) {
-      run += (bits >> q) & 1u;
-      if (p0 + q < count) rank[p0 + q] = run;
-    }
-  }
-}
-
-__global__ void k_vertex_deaths(const int64_t* __restrict__ killer,
-                                const uint32_t* __restrict__ rank, int64_t n,
-                                uint32_t* __restrict__ dbv) {
+// Marks the pivot columns: bit p of the bitmap, and the pivot row of p.
+__global__ void k_pivot_marks(const int64_t* __restrict__ killer, int64_t n,
+                              uint32_t* __restrict__ bitmap, int32_t* __restrict__ prow,
+                              uint32_t* __restrict__ dbv) {
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
        r += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = killer[r];
-    dbv[r] = p >= 0 ? rank[p] : kInf;
-  }
-}
-
-// Bitonic sort of up to kSmallSortMax deaths in LDS; writes (0, death) bars.
-__global__ __launch_bounds__(1024) void k_sort_bars_small(const uint32_t* __restrict__ dbv,
-                                                          int64_t n,
-                                                          uint32_t* __restrict__ bars) {
-  __shared__ uint32_t s[kSmallSortMax];
-  int P = 1;
-  while (P < n) P <<= 1;
-  for (int i = threadIdx.x; i < P; i += blockDim.x) s[i] = i < n ? dbv[i] : kInf;
-  __syncthreads();
-  for (int size = 2; size <= P; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < P / 2; i += blockDim.x) {
-        const int lo = 2 * i - (i & (stride - 1));
-        const int hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const uint32_t x = s[lo], y = s[hi];
-        if ((x > y) == up) {
-          s[lo] = y;
-          s[hi] = x;
-        }
-      }
-      __syncthreads();
+    if (p >= 0) {
+      atomicOr(&bitmap[p >> 5], 1u << (p & 31));
+      prow[p] = (int32_t)r;
+    } else {
+      dbv[r] = kInf;  // the essential class
     }
   }
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    bars[2 * i] = 0;
-    bars[2 * i + 1] = s[i];
+}
+
+// Distance change at sorted position q (q >= 1) and pivot flag.
+__device__ inline void position_flags(const uint64_t* __restrict__ k, int64_t q, int64_t count,
+                                      int shift, const uint32_t* __restrict__ bitmap,
+                                      bool* change, bool* pivot) {
+  *change = false;
+  *pivot = false;
+  if (q < count) {
+    *change = q > 0 && (k[q] >> shift) != (k[q - 1] >> shift);
+    *pivot = (bitmap[q >> 5] >> (q & 31)) & 1u;
   }
 }
 
-__global__ void k_u32_to_keys(const uint32_t* __restrict__ v, int64_t n,
-                              uint64_t* __restrict__ keys) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    keys[i] = v[i];
+__device__ inline uint32_t wave_excl_count(bool f, uint64_t* m_out) {
+  const uint64_t m = __ballot(f);
+  *m_out = m;
+  return (uint32_t)__popcll(m & ((1ull << (threadIdx.x & 63)) - 1ull));
 }
 
-__global__ void k_keys_to_bars(const uint64_t* __restrict__ keys, int64_t n,
-                               uint32_t* __restrict__ bars) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    bars[2 * i] = 0;
-    bars[2 * i + 1] = (uint32_t)keys[i];
+// Per group of kGroup positions: the number of distance changes and pivots.
+__global__ __launch_bounds__(kGroup) void k_grade_count(const uint64_t* __restrict__ k,
+                                                        int64_t count, int shift,
+                                                        const uint32_t* __restrict__ bitmap,
+                                                        uint32_t* __restrict__ cc,
+                                                        uint32_t* __restrict__ cp) {
+  __shared__ uint32_t wc[2][kGroup / 64];
+  const int64_t ng = (count + kGroup - 1) / kGroup;
+  const int wave = threadIdx.x >> 6;
+  for (int64_t g = blockIdx.x; g < ng; g += gridDim.x) {
+    bool ch, pv;
+    position_flags(k, g * kGroup + threadIdx.x, count, shift, bitmap, &ch, &pv);
+    const uint64_t mc = __ballot(ch), mp = __ballot(pv);
+    if ((threadIdx.x & 63) == 0) {
+      wc[0][wave] = (uint32_t)__popcll(mc);
+      wc[1][wave] = (uint32_t)__popcll(mp);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      cc[g] = wc[0][0] + wc[0][1] + wc[0][2] + wc[0][3];
+      cp[g] = wc[1][0] + wc[1][1] + wc[1][2] + wc[1][3];
+    }
+    __syncthreads();
+  }
+}
+
+// With cc / cp scanned (exclusive): the grade of every pivot position, its
+// bar (in position order = death order) and its vertex's death.
+__global__ __launch_bounds__(kGroup) void k_grade_emit(const uint64_t* __restrict__ k,
+                                                       int64_t count, int shift,
+                                                       const uint32_t* __restrict__ bitmap,
+                                                       const int32_t* __restrict__ prow,
+                                                       const uint32_t* __restrict__ cc,
+                                                       const uint32_t* __restrict__ cp,
+                                                       uint32_t* __restrict__ dbv,
+                                                       uint32_t* __restrict__ bars) {
+  __shared__ uint32_t wc[2][kGroup / 64];
+  const int64_t ng = (count + kGroup - 1) / kGroup;
+  const int wave = threadIdx.x >> 6;
+  for (int64_t g = blockIdx.x; g < ng; g += gridDim.x) {
+    const int64_t q = g * kGroup + threadIdx.x;
+    bool ch, pv;
+    position_flags(k, q, count, shift, bitmap, &ch, &pv);
+    uint64_t mc, mp;
+    const uint32_t ec = wave_excl_count(ch, &mc), ep = wave_excl_count(pv, &mp);
+    if ((threadIdx.x & 63) == 0) {
+      wc[0][wave] = (uint32_t)__popcll(mc);
+      wc[1][wave] = (uint32_t)__popcll(mp);
+    }
+    __syncthreads();
+    uint32_t bc = 0, bp = 0;
+    for (int w = 0; w < wave; ++w) {
+      bc += wc[0][w];
+      bp += wc[1][w];
+    }
+    if (pv) {
+      const uint32_t grade = 1u + cc[g] + bc + ec + (ch ? 1u : 0u);
+      dbv[prow[q]] = grade;
+      if (bars) {
+        const uint32_t at = cp[g] + bp + ep;
+        bars[2 * at] = 0u;
+        bars[2 * at + 1] = grade;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -208,43 +158,44 @@ int grid_for(int64_t count, int per_block, int cap) {
 
 }  // namespace
 
-int64_t rank_blocks(int64_t count) { return (count + kRankBlock - 1) / kRankBlock; }
-
-hipError_t launch_rank(const uint64_t* skeys, const RedCtl* ctl, int shift, uint32_t* blockcnt,
-                       int64_t max_count, uint32_t* rank_out, hipStream_t s) {
-  const int g = grid_for(max_count, kRankBlock, 4096);
-  hipLaunchKernelGGL(k_rank_count, dim3(g), dim3(kRankThreads), 0, s, skeys, ctl, shift,
-                     blockcnt);
-  hipLaunchKernelGGL(k_rank_scan, dim3(1), dim3(kRankThreads), 0, s, ctl, blockcnt);
-  hipLaunchKernelGGL(k_rank_write, dim3(g), dim3(kRankThreads), 0, s, skeys, ctl, shift,
-                     blockcnt, rank_out);
-  return hipGetLastError();
+size_t grades_work_bytes(int64_t E_eff) {
+  const int64_t ng = (E_eff + kGroup - 1) / kGroup + 1;
+  const int64_t words = (E_eff + 31) / 32;
+  return 4 * (size_t)E_eff + 4 * (size_t)words + 2 * 4 * (size_t)ng +
+         2 * 4 * (size_t)scan_totals_len(ng) + 64;
 }
 
-hipError_t launch_vertex_deaths(const int64_t* killer, const uint32_t* rank, int64_t n,
-                                uint32_t* dbv, hipStream_t s) {
-  hipLaunchKernelGGL(k_vertex_deaths, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, killer, rank,
-                     n, dbv);
-  return hipGetLastError();
-}
-
-hipError_t launch_sort_bars_small(const uint32_t* dbv, int64_t n, uint32_t* out_bars,
-                                  hipStream_t s) {
-  if (n > kSmallSortMax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_sort_bars_small, dim3(1), dim3(1024), 0, s, dbv, n, out_bars);
-  return hipGetLastError();
-}
-
-hipError_t launch_u32_to_keys(const uint32_t* v, int64_t n, uint64_t* keys, hipStream_t s) {
-  hipLaunchKernelGGL(k_u32_to_keys, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, v, n, keys);
-  return hipGetLastError();
-}
-
-hipError_t launch_keys_to_bars(const uint64_t* keys, int64_t n, uint32_t* out_bars,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(k_keys_to_bars, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, keys, n,
-                     out_bars);
-  return hipGetLastError();
+hipError_t launch_grades_and_bars(const uint64_t* skeys, int64_t E_eff, int shift,
+                                  const int64_t* killer, int64_t n, void* work, uint32_t* dbv,
+                                  uint32_t* bars, hipStream_t s, uint32_t* distinct,
+                                  uint32_t* pivots) {
+  const int64_t ng = (E_eff + kGroup - 1) / kGroup;
+  const int64_t words = (E_eff + 31) / 32;
+  int32_t* prow = static_cast<int32_t*>(work);
+  uint32_t* bitmap = reinterpret_cast<uint32_t*>(prow + E_eff);
+  uint32_t* cc = bitmap + words;
+  uint32_t* cp = cc + ng + 1;
+  uint32_t* tot_c = cp + ng + 1;
+  uint32_t* tot_p = tot_c + scan_totals_len(ng + 1);
+  hipError_t e = launch_fill_u32(bitmap, 0u, words, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pivot_marks, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, killer, n,
+                     bitmap, prow, dbv);
+  const int g = grid_for(E_eff, kGroup, 4096);
+  hipLaunchKernelGGL(k_grade_count, dim3(g), dim3(kGroup), 0, s, skeys, E_eff, shift, bitmap, cc,
+                     cp);
+  if ((e = launch_fill_u32(cc + ng, 0u, 1, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32(cp + ng, 0u, 1, s)) != hipSuccess) return e;
+  if ((e = launch_scan_u32(cc, ng + 1, tot_c, s)) != hipSuccess) return e;
+  if ((e = launch_scan_u32(cp, ng + 1, tot_p, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_grade_emit, dim3(g), dim3(kGroup), 0, s, skeys, E_eff, shift, bitmap,
+                     prow, cc, cp, dbv, bars);
+  if (bars) {  // the essential bar, last
+    if ((e = launch_fill_u32(bars + 2 * (n - 1), 0u, 1, s)) != hipSuccess) return e;
+    if ((e = launch_fill_u32(bars + 2 * (n - 1) + 1, kInf, 1, s)) != hipSuccess) return e;
+  }
+  if ((e = hipMemcpyAsync(distinct, cc + ng, 4, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+  return hipMemcpyAsync(pivots, cp + ng, 4, hipMemcpyDeviceToHost, s);
 }
 
 hipError_t launch_pairs_detail(const int64_t* killer, const uint64_t* skeys, int ib,

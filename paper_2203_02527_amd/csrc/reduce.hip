@@ -784,6 +784,43 @@ __global__ __launch_bounds__(256) void k_decide(Ring ring, int64_t Wcap, const i
     atomicMin((unsigned long long*)&ctl->firstdup[round & 1], (unsigned long long)best);
 }
 
+// End of a round: the next window start F (first column left active), the
+// next window, and the hand-over of the active list.  Run by the last commit
+// workgroup to finish; every value it reads was written by other workgroups'
+// atomics, so the reads are volatile (no stale L1 lines).
+__device__ void advance_round(RedCtl* ctl_, int64_t n, int64_t E, int64_t Wcap) {
+  volatile RedCtl* ctl = ctl_;
+  const int64_t round = ctl->round;
+  const uint64_t nf = ctl->newF[round & 1];
+  const int64_t F = nf == kNoValue ? ctl->Wend : (int64_t)nf;
+  int64_t Wend = ctl->Wend;
+  if (ctl->pivots >= n - 1) {
+    // Every later column reduces to zero; only columns before the last
+    // pivot still need finishing (for the exact addition count).
+    if (F >= ctl->E_eff) ctl->done = 1;
+  } else {
+    const int64_t lim = ctl->E_lim;
+    Wend = F + Wcap < lim ? F + Wcap : lim;
+    if (F >= lim) {
+      if (lim < E) {
+        ctl->need_more = 1;  // the host sorts the next distance range
+      } else {
+        ctl->done = 1;
+        ctl->err |= 2;
+      }
+    }
+  }
+  ctl->fresh_lo = ctl->Wend;
+  ctl->fresh_hi = Wend;
+  ctl->nA = ctl->nA_next;
+  ctl->nA_next = 0;
+  ctl->cur ^= 1;
+  ctl->F = F;
+  ctl->Wend = Wend;
+  if (Wend > ctl->maxWend) ctl->maxWend = Wend;
+  ctl->round = round + 1;
+}
+
 // Commit the survivors the rule allows; append the rest to the next active
 // list.  Two phases per block so that the list needs one atomic per block:
 // commit and count, then (after one block-wide scan) write the stayers.
@@ -791,7 +828,7 @@ __global__ __launch_bounds__(256) void k_commit(Ring ring, int64_t Wcap, int64_t
                                                 int64_t* act1, const uint64_t* lowc,
                                                 const uint64_t* touch,
                                                 uint64_t* table, int64_t LW, int64_t* killer,
-                                                RedCtl* ctl) {
+                                                RedCtl* ctl, int64_t n, int64_t E) {
   __shared__ int64_t itmp[4];
   __shared__ uint64_t utmp[4];
   __shared__ int64_t s_base;
@@ -856,40 +893,13 @@ __global__ __launch_bounds__(256) void k_commit(Ring ring, int64_t Wcap, int64_t
       ctl->firstdup[(round + 1) & 1] = kNoValue;
       ctl->newF[(round + 1) & 1] = kNoValue;
     }
-  }
-}
-
-__global__ void k_advance(RedCtl* ctl, int64_t n, int64_t E, int64_t Wcap) {
-  if (ctl->done) return;
-  const int64_t round = ctl->round;
-  const uint64_t nf = ctl->newF[round & 1];
-  const int64_t F = nf == kNoValue ? ctl->Wend : (int64_t)nf;
-  int64_t Wend = ctl->Wend;
-  if (ctl->pivots >= n - 1) {
-    // Every later column reduces to zero; only columns before the last
-    // pivot still need finishing (for the exact addition count).
-    if (F >= ctl->E_eff) ctl->done = 1;
-  } else {
-    const int64_t lim = ctl->E_lim;
-    Wend = F + Wcap < lim ? F + Wcap : lim;
-    if (F >= lim) {
-      if (lim < E) {
-        ctl->need_more = 1;  // the host sorts the next distance range
-      } else {
-        ctl->done = 1;
-        ctl->err |= 2;
-      }
+    __threadfence();
+    if (atomicAdd(&ctl->ticket, 1u) == gridDim.x - 1) {  // the last workgroup
+      __threadfence();
+      ctl->ticket = 0;
+      advance_round(ctl, n, E, Wcap);
     }
   }
-  ctl->fresh_lo = ctl->Wend;
-  ctl->fresh_hi = Wend;
-  ctl->nA = ctl->nA_next;
-  ctl->nA_next = 0;
-  ctl->cur ^= 1;
-  ctl->F = F;
-  ctl->Wend = Wend;
-  if (Wend > ctl->maxWend) ctl->maxWend = Wend;
-  ctl->round = round + 1;
 }
 
 __global__ void k_reduce_extend(RedCtl* ctl, int64_t E_lim, int64_t Wcap) {
@@ -1029,8 +1039,7 @@ hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_w
   hipLaunchKernelGGL(k_decide, dim3(sb), dim3(256), 0, s, a.ring, a.Wcap, a.act[0], a.act[1],
                      a.lowc, a.ctl);
   hipLaunchKernelGGL(k_commit, dim3(sb), dim3(256), 0, s, a.ring, a.Wcap, a.act[0], a.act[1],
-                     a.lowc, a.touch, a.table, a.LW, a.killer, a.ctl);
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, a.ctl, a.n, a.E, a.Wcap);
+                     a.lowc, a.touch, a.table, a.LW, a.killer, a.ctl, a.n, a.E);
   return hipGetLastError();
 }
 
