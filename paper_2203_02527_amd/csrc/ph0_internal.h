@@ -44,7 +44,6 @@ struct RedCtl {
   int32_t done;
   int32_t err;  // bit 0: a reduced column had weight != 2; bit 1: ran out of columns
   int32_t need_more;  // every available column is final and pivots are missing
-  uint32_t ticket;    // commit workgroups finished this round (the last one advances)
 };
 
 // Per-column state of the reduction window, a ring indexed by p % Wcap.

@@ -785,9 +785,9 @@ __global__ __launch_bounds__(256) void k_decide(Ring ring, int64_t Wcap, const i
 }
 
 // End of a round: the next window start F (first column left active), the
-// next window, and the hand-over of the active list.  Run by the last commit
-// workgroup to finish; every value it reads was written by other workgroups'
-// atomics, so the reads are volatile (no stale L1 lines).
+// next window, and the hand-over of the active list (one thread; a separate
+// launch costs less than electing the last commit workgroup with a ticket,
+// whose same-address atomics serialize across the grid).
 __device__ void advance_round(RedCtl* ctl_, int64_t n, int64_t E, int64_t Wcap) {
   volatile RedCtl* ctl = ctl_;
   const int64_t round = ctl->round;
@@ -828,7 +828,7 @@ __global__ __launch_bounds__(256) void k_commit(Ring ring, int64_t Wcap, int64_t
                                                 int64_t* act1, const uint64_t* lowc,
                                                 const uint64_t* touch,
                                                 uint64_t* table, int64_t LW, int64_t* killer,
-                                                RedCtl* ctl, int64_t n, int64_t E) {
+                                                RedCtl* ctl) {
   __shared__ int64_t itmp[4];
   __shared__ uint64_t utmp[4];
   __shared__ int64_t s_base;
@@ -893,13 +893,12 @@ __global__ __launch_bounds__(256) void k_commit(Ring ring, int64_t Wcap, int64_t
       ctl->firstdup[(round + 1) & 1] = kNoValue;
       ctl->newF[(round + 1) & 1] = kNoValue;
     }
-    __threadfence();
-    if (atomicAdd(&ctl->ticket, 1u) == gridDim.x - 1) {  // the last workgroup
-      __threadfence();
-      ctl->ticket = 0;
-      advance_round(ctl, n, E, Wcap);
-    }
   }
+}
+
+__global__ void k_advance(RedCtl* ctl, int64_t n, int64_t E, int64_t Wcap) {
+  if (ctl->done) return;
+  advance_round(ctl, n, E, Wcap);
 }
 
 __global__ void k_reduce_extend(RedCtl* ctl, int64_t E_lim, int64_t Wcap) {
@@ -1039,7 +1038,8 @@ hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_w
   hipLaunchKernelGGL(k_decide, dim3(sb), dim3(256), 0, s, a.ring, a.Wcap, a.act[0], a.act[1],
                      a.lowc, a.ctl);
   hipLaunchKernelGGL(k_commit, dim3(sb), dim3(256), 0, s, a.ring, a.Wcap, a.act[0], a.act[1],
-                     a.lowc, a.touch, a.table, a.LW, a.killer, a.ctl, a.n, a.E);
+                     a.lowc, a.touch, a.table, a.LW, a.killer, a.ctl);
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, a.ctl, a.n, a.E, a.Wcap);
   return hipGetLastError();
 }
 
