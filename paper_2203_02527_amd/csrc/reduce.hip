@@ -35,6 +35,8 @@
 // -- equals the sequential left-to-right reduction.  Once N-1 pivots exist
 // the remaining columns must reduce to zero (the complete graph is
 // connected), so the reduction stops there.
+#include <climits>
+
 #include "ph0_internal.h"
 
 namespace ph0 {
@@ -315,58 +317,23 @@ __global__ __launch_bounds__(256) void k_walk(const uint64_t* __restrict__ skeys
 
 // ---- full-wave walk (N > 2048: a pivot row needs all 64 lanes) ----
 //
-// The walk is bound by instruction issue and load latency, not by HBM
-// bandwidth, so this version keeps every per-step quantity scalar: the
-// current low r is wave-uniform, the row's address and length go into a
-// buffer resource (words past the row's top word come back as zero from the
-// hardware range check), and the loop runs in stages by the number S of
-// 64-word slots the row prefix spans (S = r / 4096 + 1, which only falls as
-// r falls), so each stage loads, XORs and searches exactly S slots with no
-// per-slot tests.  Word w of a column lives in lane w % 64, slot w / 64.
+// A reduced column is 2-sparse: its nonzero rows are {a, r}, a < r, and the
+// stored column of row r is {x, r}, x < r.  Adding one to the other over F2
+// cancels row r and leaves {a, x} (or nothing when x = a).  The full-wave
+// walk therefore carries the column as its two rows (wave-uniform scalars)
+// and performs each addition on that support, while the stored column is
+// read from the dense bit-packed table: the 64 lanes load its words 0..r/64
+// (word w in lane w % 64, slot w / 64), bit r is cleared, and x is the
+// highest remaining set bit, found with one ballot per slot and a lane read.
+// An empty row (no bit below r) means slot r is free.  Each addition is
+// exactly the one the sequential dense reduction makes.
+//
+// The row's address and length (r / 64 + 1 words) go into a buffer resource,
+// so the hardware range check returns zeros past the row's top word, and the
+// loop runs in stages by the number S of 64-word slots the row prefix spans
+// (S = r / 4096 + 1, which only falls as r falls), so each stage loads and
+// searches exactly S slots with no per-slot tests.
 
-__device__ inline __amdgpu_buffer_rsrc_t row_rsrc(const uint64_t* table, int64_t LW, int r) {
-  const int top = r >> 6;
-  return __builtin_amdgcn_make_buffer_rsrc((void*)(table + (int64_t)r * LW), 0, (top + 1) * 8,
-                                           0x00020000);
-}
-
-template <int WPL>
-__device__ inline void wide_load(uint64_t (&v)[WPL], __amdgpu_buffer_rsrc_t rs, int qmax,
-                                 int lane) {
-#pragma unroll
-  for (int q = 0; q < WPL; ++q) {
-    if (q <= qmax) {
-      const auto x = __builtin_amdgcn_raw_buffer_load_b64(rs, lane * 8, q * 512, 0);
-      v[q] = ((uint64_t)x[1] << 32) | x[0];
-    } else {
-      v[q] = 0;
-    }
-  }
-}
-
-// Highest set bit among slots 0..qmax, or -1.
-template <int WPL>
-__device__ inline int wide_top(const uint64_t (&w)[WPL], int qmax) {
-#pragma unroll
-  for (int q = WPL - 1; q >= 0; --q) {
-    if (q > qmax) continue;
-    const uint64_t m = __ballot(w[q] != 0);
-    if (m) {
-      const int L = 63 - __clzll(m);
-      const uint64_t word = readlane64(w[q], L);
-      return (q * 64 + L) * 64 + 63 - __clzll(word);
-    }
-  }
-  return -1;
-}
-
-// One walk step against row r, whose prefix spans S slots: XOR the row's
-// words 0..r/64 into the column and return the column's new top bit (-1 if
-// the column became zero).  Slots >= S of the column are zero already (its
-// bits are <= r), so only S slots are loaded and searched.  The search takes
-// one ballot per slot and picks the highest non-empty slot with scalar
-// selects; the row's byte offset r * rowb is 32-bit (the table stays below
-// 4 GiB for every supported N).
 __device__ inline __amdgpu_buffer_rsrc_t wide_rsrc(const char* tbase, uint32_t rowb, int r) {
   const uint32_t nrec = (((uint32_t)r | 63u) >> 3) + 1u;  // (r / 64 + 1) words
   return __builtin_amdgcn_make_buffer_rsrc((void*)(tbase + (uint32_t)r * rowb), 0, (int)nrec,
@@ -410,22 +377,6 @@ __device__ inline int slots_top(const uint64_t (&w)[N]) {
   return (qs * 64 + L) * 64 + 63 - __clzll(word);
 }
 
-// slots_top with the slot count S = s chosen at run time (1 <= s <= WPL).
-template <int WPL, int S = WPL>
-__device__ inline int slots_top_n(int s, const uint64_t (&w)[WPL]) {
-  if constexpr (S > 1) {
-    if (s < S) return slots_top_n<WPL, S - 1>(s, w);
-  }
-  return slots_top<S>(w);
-}
-
-template <int WPL, int S>
-__device__ inline int wide_xor_top(uint64_t (&col)[WPL], const uint64_t (&v)[S]) {
-#pragma unroll
-  for (int q = 0; q < S; ++q) col[q] ^= v[q];
-  return slots_top<S>(col);
-}
-
 // Highest set bit of stored row v below v itself (-1 if the row holds only
 // its slot flag or is empty): the row's prefix spans S = v / 4096 + 1 slots,
 // and bit v sits in slot S - 1.
@@ -445,60 +396,47 @@ __device__ inline int row_below_n(const char* tbase, uint32_t rowb, int v, int l
   return row_below<S>(tbase, rowb, v, lane);
 }
 
-// One walk step against row r, whose prefix spans S slots: XOR the row's
-// words 0..r/64 into the column and return the column's new top bit.  The
-// row's byte offset r * rowb is 32-bit (the table stays below 4 GiB for every
-// supported N); the buffer's length ends the row at word r/64.
-template <int WPL, int S>
-__device__ inline int wide_step(uint64_t (&col)[WPL], const char* tbase, uint32_t rowb, int r,
-                                int lane) {
-  uint64_t v[S];
-  wide_issue<S>(v, wide_rsrc(tbase, rowb, r), lane);
-  return wide_xor_top<WPL, S>(col, v);
-}
-
 struct WalkState {
-  int r;      // current low (wave-uniform)
+  int r;      // the column's low (wave-uniform)
+  int a;      // its other row (wave-uniform)
   int moved;  // additions made
   int words;  // table words loaded
   bool stop, zero, bad;
 };
 
-// Apply a step's result nr (the column's new top bit) to the walk state.
-__device__ inline void wide_advance(WalkState& w, int nr) {
-  const int r = w.r;
-  w.words += (r >> 6) + 1;
-  if ((unsigned)nr >= (unsigned)r) {  // rare: row empty, zero column, or corrupt
-    w.stop = true;
-    if (nr == r) return;  // row r is empty: slot r is free
-    ++w.moved;
-    w.zero = true;
-    if (nr > r) w.bad = true;  // lows must decrease; a corrupt table ends the walk
-    return;
-  }
-  ++w.moved;
-  w.r = nr;
-}
-
 // Steps on rows whose prefix spans S slots -- r >= (S - 1) * 4096; r < S *
 // 4096 holds already since r only decreases -- then the stages below.
+// Returns the last row read's other bit x when the walk stopped (x < 0: slot
+// r is free; x == a: the column became zero), or INT_MIN if it did not stop.
 template <int WPL, int S>
-__device__ inline void wide_stages(uint64_t (&col)[WPL], const char* tbase, uint32_t rowb,
-                                   int lane, WalkState& w) {
-  while (!w.stop && w.r >= (S - 1) * 4096)
-    wide_advance(w, __builtin_amdgcn_readfirstlane(wide_step<WPL, S>(col, tbase, rowb, w.r, lane)));
-  if constexpr (S > 1) wide_stages<WPL, S - 1>(col, tbase, rowb, lane, w);
+__device__ inline int wide_stages(const char* tbase, uint32_t rowb, int lane, int& r, int& a,
+                                  int& moved, int& words) {
+  while (r >= (S - 1) * 4096) {
+    const int x = __builtin_amdgcn_readfirstlane(row_below<S>(tbase, rowb, r, lane));
+    words += r >> 6;
+    if (x < 0 || x == a) return x;
+    ++moved;
+    // {a, r} + {x, r} = {a, x}
+    const int lo = x < a ? x : a;
+    r = x < a ? a : x;
+    a = lo;
+  }
+  if constexpr (S > 1) return wide_stages<WPL, S - 1>(tbase, rowb, lane, r, a, moved, words);
+  return INT_MIN;  // unreachable: r >= 0 always stops in the last stage
 }
 
-// Every slot is XORed with a masked value (zero except in the bit's slot):
-// a conditional update of one slot would let the compiler turn the array
-// access into a dynamic index and move the column out of registers.
+// Walk a column to its stop: a free slot r (survivor) or zero.
 template <int WPL>
-__device__ inline void wide_flip(uint64_t (&w)[WPL], int lane, int bit) {
-  const int word = bit >> 6;
-  const uint64_t b = (lane == (word & 63)) ? (1ull << (bit & 63)) : 0ull;
-#pragma unroll
-  for (int q = 0; q < WPL; ++q) w[q] ^= b & (0ull - (uint64_t)(q == (word >> 6)));
+__device__ inline void wide_walk(const char* tbase, uint32_t rowb, int lane, WalkState& w) {
+  int r = w.r, a = w.a, moved = 0, words = 0;
+  const int x = wide_stages<WPL, WPL>(tbase, rowb, lane, r, a, moved, words);
+  const bool zero = x >= 0;  // x == a: the addition cancelled the column
+  w.r = r;
+  w.a = a;
+  w.moved = moved + (zero ? 1 : 0);
+  w.words = words + moved + 1;  // one row load per step: (r / 64 + 1) words
+  w.zero = zero;
+  w.stop = true;
 }
 
 // Per-launch context of the full-wave walk kernels.
@@ -558,10 +496,8 @@ __device__ inline void next_fetch2(const WideCtx& x, WideNext& nx) {
 }
 
 // Start the prefetched item: an active column resumed from its ring entry,
-// or a fresh column from its key.  Sets the column's two bits.
-template <int WPL>
-__device__ inline void wide_begin(const WideCtx& x, const WideNext& nx, WideCol& c,
-                                  uint64_t (&col)[WPL]) {
+// or a fresh column {i, j} from its key.
+__device__ inline void wide_begin(const WideCtx& x, const WideNext& nx, WideCol& c) {
   int a, r, rlo;
   if (nx.t < x.nA) {
     c.p = (int64_t)nx.raw;
@@ -578,68 +514,51 @@ __device__ inline void wide_begin(const WideCtx& x, const WideNext& nx, WideCol&
   }
   c.a = __builtin_amdgcn_readfirstlane(a);
   c.rlo = __builtin_amdgcn_readfirstlane(rlo);
-  c.w = WalkState{__builtin_amdgcn_readfirstlane(r), 0, 0, false, false, false};
-#pragma unroll
-  for (int q = 0; q < WPL; ++q) col[q] = 0;
-  wide_flip<WPL>(col, x.lane, c.a);
-  wide_flip<WPL>(col, x.lane, c.w.r);
+  c.w = WalkState{__builtin_amdgcn_readfirstlane(r), c.a, 0, 0, false, false, false};
 }
 
-// A column whose walk stopped: a zero column, or a survivor on free slot r.
-// A survivor's other row a is read off the column (which must hold exactly
-// the two bits {a, r}), the root of a in the current forest is found by
+// A column whose walk stopped: a zero column, or a survivor {a, r} on free
+// slot r.  For a survivor the root of a in the current forest is found by
 // following stored columns down, and the round-tagged minima for slot r and
 // that root are lowered (both current values are read before either atomic,
-// so the wave waits once).  The column's state goes back to the ring.
+// so the wave waits once).  The column's state goes back to the ring (a zero
+// column needs only its status and owner).
 template <int WPL>
-__device__ inline void wide_finish(WideCtx& x, WideCol& c, uint64_t (&col)[WPL]) {
+__device__ inline void wide_finish(WideCtx& x, WideCol& c) {
   const int lane = x.lane;
-  const int r = c.w.r;
-  int a = c.a, rlo = c.rlo;
+  const int r = c.w.r, a = c.w.a;
+  int rlo = c.rlo;
   x.adds += c.w.moved;
   x.words += c.w.words;
   if (c.w.bad) x.bad = 1;
-  int32_t status = kActive;
+  const int64_t q = c.p & (x.Wcap - 1);
   if (c.w.zero) {
-    status = kZero;
-  } else {
-    const int s = (r >> 12) + 1;
-    wide_flip<WPL>(col, lane, r);
-    const int na = __builtin_amdgcn_readfirstlane(slots_top_n<WPL>(s, col));
-    if (na >= 0) wide_flip<WPL>(col, lane, na);
-    bool rest = false;
-#pragma unroll
-    for (int q = 0; q < WPL; ++q) rest |= col[q] != 0;
-    if (na < 0 || __ballot(rest) != 0) x.bad = 1;
-    a = na < 0 ? 0 : na;
-    // Root of row a in the current forest: follow stored columns down.
-    int v = c.w.moved ? a : rlo;
-    while (true) {
-      x.words += (v >> 6) + 1;
-      const int cb = __builtin_amdgcn_readfirstlane(row_below_n<WPL>(x.tbase, x.rowb, v, lane));
-      if (cb < 0) break;  // empty row: v is a root
-      ++x.finds;
-      if (cb >= v) {
-        x.bad = 1;
-        break;
-      }
-      v = cb;
-    }
-    rlo = v;
     if (lane == 0) {
-      const uint64_t e = enc(x.round, c.p);
-      const uint64_t cur_l = *(volatile uint64_t*)&x.lowc[r];
-      const uint64_t cur_t = *(volatile uint64_t*)&x.touch[rlo];
-      if (cur_l > e) atomicMin((unsigned long long*)&x.lowc[r], (unsigned long long)e);
-      if (cur_t > e) atomicMin((unsigned long long*)&x.touch[rlo], (unsigned long long)e);
+      x.ring.st[q] = kZero | ((c.prev + c.w.moved) << 2);
+      x.ring.tag[q] = c.p;
     }
+    return;
   }
+  // Root of row a in the current forest: follow stored columns down.
+  int v = c.w.moved ? a : rlo;
+  while (true) {
+    x.words += (v >> 6) + 1;
+    const int cb = __builtin_amdgcn_readfirstlane(row_below_n<WPL>(x.tbase, x.rowb, v, lane));
+    if (cb < 0) break;  // empty row: v is a root
+    ++x.finds;
+    v = cb;
+  }
+  rlo = v;
   if (lane == 0) {
-    const int64_t q = c.p & (x.Wcap - 1);
+    const uint64_t e = enc(x.round, c.p);
+    const uint64_t cur_l = *(volatile uint64_t*)&x.lowc[r];
+    const uint64_t cur_t = *(volatile uint64_t*)&x.touch[rlo];
+    if (cur_l > e) atomicMin((unsigned long long*)&x.lowc[r], (unsigned long long)e);
+    if (cur_t > e) atomicMin((unsigned long long*)&x.touch[rlo], (unsigned long long)e);
     x.ring.a[q] = a;
     x.ring.r[q] = r;
     x.ring.rlo[q] = rlo;
-    x.ring.st[q] = status | ((c.prev + c.w.moved) << 2);
+    x.ring.st[q] = kActive | ((c.prev + c.w.moved) << 2);
     x.ring.tag[q] = c.p;
   }
 }
@@ -712,13 +631,12 @@ __global__ __launch_bounds__(256) void k_walk_wide(const uint64_t* __restrict__ 
   next_fetch2(x, nx);
   while (nx.t < items) {
     WideCol c;
-    uint64_t col[WPL];
-    wide_begin<WPL>(x, nx, c, col);
+    wide_begin(x, nx, c);
     nx.t += wtotal;
     next_fetch1(x, nx, items);
-    wide_stages<WPL, WPL>(col, x.tbase, x.rowb, x.lane, c.w);
+    wide_walk<WPL>(x.tbase, x.rowb, x.lane, c.w);
     next_fetch2(x, nx);
-    wide_finish<WPL>(x, c, col);
+    wide_finish<WPL>(x, c);
   }
   wide_flush(x, ctl);
 }
