@@ -136,10 +136,9 @@ __global__ void k_pairs_detail(const int64_t* __restrict__ killer,
       pos = p;
       sq = (int64_t)(key >> (2 * ib));
       edge = (((key >> ib) & imask) << 32) | (key & imask);
-      const uint64_t* row = table + r * LW;
+      const uint64_t* row = table + r * LW;  // holds the stored column's other bit
       for (int64_t w = r >> 6; w >= 0 && other < 0; --w) {
-        uint64_t x = row[w];
-        if (w == (r >> 6)) x &= ~(1ull << (r & 63));
+        const uint64_t x = row[w];
         if (x) other = (int32_t)(w * 64 + 63 - __clzll(x));
       }
     }

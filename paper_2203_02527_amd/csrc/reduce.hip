@@ -4,20 +4,21 @@
 //
 // Data layout.  The pivot table is dense and bit-packed: row r (the stored
 // column whose low is r) holds N bits in LW = ceil(N/64) 64-bit words at
-// table[r * LW].  A stored column has bits only at rows <= r, so a lookup
-// reads words 0 .. r/64 only.  Bit r of row r doubles as the "slot r is
-// taken" flag (the table starts zeroed).
+// table[r * LW].  The pivot bit r itself is implicit (a stored column's low
+// is its row index), so row r holds exactly the column's other bit, below r:
+// a lookup reads words 0 .. r/64 only, and a row is taken iff it is nonzero
+// (the table starts zeroed).
 //
-// One column, one lane group.  A group of G lanes holds the current column
-// as a dense register bitset, WPL words per lane (G * WPL >= LW); a wave
-// reduces 64/G columns side by side.  Each step XORs the stored column of the
-// current low into the register column and finds the new low: per-lane
-// highest set bit, a ballot over the group, and a lane read from the highest
-// nonzero lane.  The step is speculative: an untaken slot's row is all zero,
-// so "the low did not move" is how a free slot is recognised, and no separate
-// presence check sits on the dependent chain.  Over F2 every column met on
-// the way has exactly two nonzero rows, which the kernel checks.
-//
+// Columns are 2-sparse.  A reduced column has nonzero rows {a, r}, a < r,
+// and the stored column of row r is {x, r}; adding one to the other over F2
+// cancels row r and leaves {a, x} (nothing when x = a).  So the walk carries
+// the column as its two rows and performs each addition on that support,
+// while each stored column is read from the dense table by a lane group
+// (word w in lane w % G, slot w / G) and its bit x found with a per-lane
+// highest-set-bit, a ballot over the group and a lane read.  An all-zero row
+// means slot r is free.  Every addition is exactly the one the sequential
+// dense reduction makes.
+
 // Rounds.  A window of consecutive sorted columns [F, Wend) is reduced side
 // by side against the table as committed so far (every slot there belongs to
 // an earlier column, so each step is one the sequential reduction also
@@ -98,40 +99,13 @@ __device__ inline int group_top_bit(const uint64_t (&w)[WPL], int gbase, int qma
   return -1;
 }
 
-template <int G>
-__device__ inline bool group_any(bool v, int gbase) {
-  uint64_t m = __ballot(v);
-  if constexpr (G < 64) m = (m >> gbase) & ((1ull << G) - 1ull);
-  return m != 0;
-}
-
+// Words 0..(r >> 6) of stored row r into w (the rest are zero).  Every lane
+// issues all WPL loads unconditionally (addresses past the top word are
+// clamped to it and the value masked), so the loads of one step are in
+// flight together and wait once.
 template <int G, int WPL>
-__device__ inline void flip_bit(uint64_t (&w)[WPL], int gl, int bit) {
-  const int word = bit >> 6;
-  if (gl == word % G) {
-#pragma unroll
-    for (int q = 0; q < WPL; ++q)
-      if (q == word / G) w[q] ^= 1ull << (bit & 63);
-  }
-}
-
-template <int G, int WPL>
-__device__ inline void clear_bit(uint64_t (&w)[WPL], int gl, int bit) {
-  const int word = bit >> 6;
-  if (gl == word % G) {
-#pragma unroll
-    for (int q = 0; q < WPL; ++q)
-      if (q == word / G) w[q] &= ~(1ull << (bit & 63));
-  }
-}
-
-// XOR words 0..(r >> 6) of stored column r into w (the rest are zero).
-// Every lane issues all WPL loads unconditionally (addresses past the top
-// word are clamped to it and the value masked), so the loads of one step are
-// in flight together and wait once.
-template <int G, int WPL>
-__device__ inline void xor_row(uint64_t (&w)[WPL], const uint64_t* __restrict__ table,
-                               int64_t LW, int r, int gl) {
+__device__ inline void load_row(uint64_t (&w)[WPL], const uint64_t* __restrict__ table,
+                                int64_t LW, int r, int gl) {
   const int top = r >> 6;
   const uint64_t* rp = table + (int64_t)r * LW;
   uint64_t v[WPL];
@@ -143,8 +117,18 @@ __device__ inline void xor_row(uint64_t (&w)[WPL], const uint64_t* __restrict__ 
 #pragma unroll
   for (int q = 0; q < WPL; ++q) {
     const int widx = q * G + gl;
-    w[q] ^= widx <= top ? v[q] : 0ull;
+    w[q] = widx <= top ? v[q] : 0ull;
   }
+}
+
+// The bit stored in row r (the stored column's other row), or -1 if the row
+// is empty (slot r free).
+template <int G, int WPL>
+__device__ inline int row_bit(const uint64_t* __restrict__ table, int64_t LW, int r, int gl,
+                              int gbase) {
+  uint64_t w[WPL];
+  load_row<G, WPL>(w, table, LW, r, gl);
+  return group_top_bit<G, WPL>(w, gbase, (r >> 6) / G);
 }
 
 // A value the whole group agrees on; for a full-wave group it is moved to a
@@ -222,57 +206,42 @@ __global__ __launch_bounds__(256) void k_walk(const uint64_t* __restrict__ skeys
       rlo = a;
       prev_steps = 0;
     }
-    uint64_t col[WPL];
-#pragma unroll
-    for (int q = 0; q < WPL; ++q) col[q] = 0;
-    flip_bit<G, WPL>(col, gl, a);
-    flip_bit<G, WPL>(col, gl, r);
     int moved = 0;
     bool zero = false;
     r = group_uniform<G>(r);
+    a = group_uniform<G>(a);
     while (true) {
-      xor_row<G, WPL>(col, table, LW, r, gl);
+      const int x = group_uniform<G>(row_bit<G, WPL>(table, LW, r, gl, gbase));
       words += (r >> 6) + 1;
-      const int nr = group_uniform<G>(group_top_bit<G, WPL>(col, gbase, (r >> 6) / G));
-      if (nr == r) break;  // row r is empty: slot r is free
+      if (x < 0) break;  // row r is empty: slot r is free
       ++moved;
-      if (nr < 0) {
+      if (x == a) {  // {a, r} + {a, r} = 0
         zero = true;
         break;
       }
-      if (nr > r) {  // lows must decrease; a corrupt table ends the walk
+      if (x >= r) {  // a stored bit must lie below its row; a corrupt table ends the walk
         bad = 1;
         zero = true;
         break;
       }
-      r = nr;
+      // {a, r} + {x, r} = {a, x}
+      const int lo = x < a ? x : a;
+      r = x < a ? a : x;
+      a = lo;
     }
     adds += moved;
     int32_t status = kActive;
     if (zero) {
       status = kZero;
     } else {
-      flip_bit<G, WPL>(col, gl, r);
-      const int na = group_top_bit<G, WPL>(col, gbase, (r >> 6) / G);
-      if (na >= 0) flip_bit<G, WPL>(col, gl, na);
-      bool rest = false;
-#pragma unroll
-      for (int q = 0; q < WPL; ++q) rest |= col[q] != 0;
-      if (na < 0 || group_any<G>(rest, gbase)) bad = 1;
-      a = na < 0 ? 0 : na;
-      // Root of row a in the current forest: follow stored columns down
-      // (col is all zero here and serves as the row buffer).
+      // Root of row a in the current forest: follow stored columns down.
       int v = group_uniform<G>(moved ? a : rlo);
       while (true) {
-#pragma unroll
-        for (int q = 0; q < WPL; ++q) col[q] = 0;
-        xor_row<G, WPL>(col, table, LW, v, gl);
+        const int c = group_uniform<G>(row_bit<G, WPL>(table, LW, v, gl, gbase));
         words += (v >> 6) + 1;
-        clear_bit<G, WPL>(col, gl, v);
-        const int c = group_uniform<G>(group_top_bit<G, WPL>(col, gbase, (v >> 6) / G));
         if (c < 0) break;  // empty row: v is a root
         ++finds;
-        if (c >= v) {  // a stored column needs a second, smaller row
+        if (c >= v) {  // a stored bit must lie below its row
           bad = 1;
           break;
         }
@@ -377,23 +346,21 @@ __device__ inline int slots_top(const uint64_t (&w)[N]) {
   return (qs * 64 + L) * 64 + 63 - __clzll(word);
 }
 
-// Highest set bit of stored row v below v itself (-1 if the row holds only
-// its slot flag or is empty): the row's prefix spans S = v / 4096 + 1 slots,
-// and bit v sits in slot S - 1.
+// The bit stored in row v (-1 if the row is empty): the row's prefix spans
+// S = v / 4096 + 1 slots.
 template <int S>
-__device__ inline int row_below(const char* tbase, uint32_t rowb, int v, int lane) {
+__device__ inline int row_top(const char* tbase, uint32_t rowb, int v, int lane) {
   uint64_t row[S];
   wide_issue<S>(row, wide_rsrc(tbase, rowb, v), lane);
-  row[S - 1] &= ~((lane == ((v >> 6) & 63)) ? (1ull << (v & 63)) : 0ull);
   return slots_top<S>(row);
 }
 
 template <int WPL, int S = WPL>
-__device__ inline int row_below_n(const char* tbase, uint32_t rowb, int v, int lane) {
+__device__ inline int row_top_n(const char* tbase, uint32_t rowb, int v, int lane) {
   if constexpr (S > 1) {
-    if (v < (S - 1) * 4096) return row_below_n<WPL, S - 1>(tbase, rowb, v, lane);
+    if (v < (S - 1) * 4096) return row_top_n<WPL, S - 1>(tbase, rowb, v, lane);
   }
-  return row_below<S>(tbase, rowb, v, lane);
+  return row_top<S>(tbase, rowb, v, lane);
 }
 
 struct WalkState {
@@ -412,7 +379,7 @@ template <int WPL, int S>
 __device__ inline int wide_stages(const char* tbase, uint32_t rowb, int lane, int& r, int& a,
                                   int& moved, int& words) {
   while (r >= (S - 1) * 4096) {
-    const int x = __builtin_amdgcn_readfirstlane(row_below<S>(tbase, rowb, r, lane));
+    const int x = __builtin_amdgcn_readfirstlane(row_top<S>(tbase, rowb, r, lane));
     words += r >> 6;
     if (x < 0 || x == a) return x;
     ++moved;
@@ -543,7 +510,7 @@ __device__ inline void wide_finish(WideCtx& x, WideCol& c) {
   int v = c.w.moved ? a : rlo;
   while (true) {
     x.words += (v >> 6) + 1;
-    const int cb = __builtin_amdgcn_readfirstlane(row_below_n<WPL>(x.tbase, x.rowb, v, lane));
+    const int cb = __builtin_amdgcn_readfirstlane(row_top_n<WPL>(x.tbase, x.rowb, v, lane));
     if (cb < 0) break;  // empty row: v is a root
     ++x.finds;
     v = cb;
@@ -769,13 +736,7 @@ __global__ __launch_bounds__(256) void k_commit(Ring ring, int64_t Wcap, int64_t
     const uint64_t e = enc(round, p);
     if ((uint64_t)p < fd || (lowc[r] == e && touch[r] > e)) {
       const int32_t a = ring.a[k];
-      uint64_t* row = table + (int64_t)r * LW;
-      if ((a >> 6) == (r >> 6)) {
-        row[r >> 6] = (1ull << (r & 63)) | (1ull << (a & 63));
-      } else {
-        row[a >> 6] = 1ull << (a & 63);
-        row[r >> 6] = 1ull << (r & 63);
-      }
+      table[(int64_t)r * LW + (a >> 6)] = 1ull << (a & 63);  // pivot bit r is implicit
       killer[r] = p;
       ring.st[k] = (st & ~3) | kCommitted;
       ++npiv;
