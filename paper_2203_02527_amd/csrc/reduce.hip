@@ -379,9 +379,28 @@ template <int WPL, int S>
 __device__ inline int wide_stages(const char* tbase, uint32_t rowb, int lane, int& r, int& a,
                                   int& moved, int& words) {
   while (r >= (S - 1) * 4096) {
-    const int x = __builtin_amdgcn_readfirstlane(row_top<S>(tbase, rowb, r, lane));
+    uint64_t w[S];
+    wide_issue<S>(w, wide_rsrc(tbase, rowb, r), lane);
     words += r >> 6;
-    if (x < 0 || x == a) return x;
+    // The stored bit x: highest non-empty slot, highest lane, highest bit.
+    uint64_t m = __ballot(w[0] != 0);
+    int qs = 0;
+#pragma unroll
+    for (int q = 1; q < S; ++q) {
+      const uint64_t mq = __ballot(w[q] != 0);
+      qs = mq ? q : qs;
+      m = mq ? mq : m;
+    }
+    if (m == 0) return -1;  // row r is empty: slot r is free
+    const int L = 63 - __builtin_clzll(m);
+    uint64_t word = readlane64(w[0], L);
+#pragma unroll
+    for (int q = 1; q < S; ++q) {
+      const uint64_t wq = readlane64(w[q], L);
+      word = qs == q ? wq : word;
+    }
+    const int x = (qs * 64 + L) * 64 + 63 - __builtin_clzll(word);
+    if (x == a) return x;  // {a, r} + {a, r} = 0
     ++moved;
     // {a, r} + {x, r} = {a, x}
     const int lo = x < a ? x : a;
