@@ -198,11 +198,24 @@ struct KernelClock {
   }
 };
 
-RedCtl* pinned_ctl() {
-  thread_local RedCtl* p = nullptr;
-  if (!p && hipHostMalloc((void**)&p, sizeof(RedCtl), hipHostMallocDefault) != hipSuccess)
-    p = nullptr;
-  return p;
+// Two pinned control-block copies and their events per host thread: the
+// reduction loop inspects one burst's copy while the next burst runs.
+struct CtlReadback {
+  RedCtl* hc = nullptr;  // [2]
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool ok = false;
+};
+
+CtlReadback* pinned_ctl() {
+  thread_local CtlReadback rb;
+  if (!rb.ok) {
+    if (hipHostMalloc((void**)&rb.hc, 2 * sizeof(RedCtl), hipHostMallocDefault) != hipSuccess)
+      return nullptr;
+    for (int k = 0; k < 2; ++k)
+      if (hipEventCreateWithFlags(&rb.ev[k], hipEventDisableTiming) != hipSuccess) return nullptr;
+    rb.ok = true;
+  }
+  return &rb;
 }
 
 enum Stop { kStopKeys = 1, kStopSorted = 2, kStopAll = 3 };
@@ -469,32 +482,52 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   ra.ring.rlo = static_cast<int32_t*>(at(L.rrlo));
   ra.ring.st = static_cast<int32_t*>(at(L.rst));
   ra.ctl = static_cast<RedCtl*>(at(L.ctl));
-  RedCtl* hc = pinned_ctl();
-  if (!hc) return fail(PH0_ENOMEM, "pinned host allocation failed");
+  CtlReadback* rb = pinned_ctl();
+  if (!rb) return fail(PH0_ENOMEM, "pinned host allocation failed");
+  RedCtl* hc = rb->hc;
   HIPCHK(launch_reduce_init(ra, E_lim, s));
+  // Rounds go out in bursts, each followed by an asynchronous copy of the
+  // control block and an event.  The host inspects a burst's copy while the
+  // next burst already runs, so the GPU never waits for the host; rounds
+  // issued after the end find `done` (or an empty range) and return at once.
   // Every round finalizes at least the first unfinished column (it either
   // reduces to zero or commits), so the window start must advance.
-  int64_t prevF = -1;
   const int burst = 8;
+  auto issue = [&](int slot) -> hipError_t {
+    for (int t = 0; t < burst; ++t) {
+      const hipError_t e = launch_reduce_round(ra, s, walk_clock.pair());
+      if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMemcpyAsync(&hc[slot], ra.ctl, sizeof(RedCtl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(rb->ev[slot], s);
+    return e;
+  };
+  int64_t prevF = -1;
+  int cur = 0;
+  HIPCHK(issue(cur));
   while (true) {
-    for (int t = 0; t < burst; ++t) HIPCHK(launch_reduce_round(ra, s, walk_clock.pair()));
-    HIPCHK(hipMemcpyAsync(hc, ra.ctl, sizeof(RedCtl), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (hc->done) break;
-    if (hc->need_more && !hc->err) {
+    HIPCHK(issue(cur ^ 1));
+    HIPCHK(hipEventSynchronize(rb->ev[cur]));
+    const RedCtl& h = hc[cur];
+    if (h.done) break;
+    if (h.need_more && !h.err) {
       if (whole) return fail(PH0_EDEVICE, "reduction asked for columns past the last one");
+      HIPCHK(hipStreamSynchronize(s));  // the queued burst found nothing to do
       HIPCHK(next_chunk());
       ra.skeys = skeys;
       HIPCHK(launch_reduce_extend(ra, E_lim, s));
       prevF = -1;
+      cur = 0;
+      HIPCHK(issue(cur));
       continue;
     }
-    if (hc->F <= prevF || hc->err) {
+    if (h.F <= prevF || h.err) {
       HIPCHK(hipStreamSynchronize(s));
-      return fail(PH0_EDEVICE, "reduction stalled at column %lld (err %d)", (long long)hc->F,
-                  hc->err);
+      return fail(PH0_EDEVICE, "reduction stalled at column %lld (err %d)", (long long)h.F,
+                  h.err);
     }
-    prevF = hc->F;
+    prevF = h.F;
+    cur ^= 1;
   }
   S.sort_chunks = chunks;
   S.sorted_keys = E_lim;
