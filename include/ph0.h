@@ -204,7 +204,7 @@ int64_t ph0_server_in_flight(ph0_server* srv);
 void ph0_server_destroy(ph0_server* srv);
 
 /* Reduction window (columns reduced side by side per round, rounded up to a
- * power of two); 0 restores the built-in choice, max(65536, 8 n) capped at
+ * power of two); 0 restores the built-in choice, max(65536, 16 n) capped at
  * E.  Affects speed only, never results.  Process-wide. */
 int ph0_set_window(int64_t columns);
 

@@ -65,7 +65,7 @@ int index_bits(int64_t n) { return n <= 1 ? 0 : 64 - __builtin_clzll((uint64_t)(
 // state is a ring indexed by column & (window - 1)).
 int64_t window_for(int64_t n, int64_t E) {
   int64_t w = g_window.load();
-  if (w <= 0) w = std::max<int64_t>(65536, 8 * n);
+  if (w <= 0) w = std::max<int64_t>(65536, 16 * n);
   w = std::min<int64_t>(w, std::max<int64_t>(E, 1));
   int64_t p = 1;
   while (p < w) p <<= 1;
@@ -492,7 +492,9 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   // issued after the end find `done` (or an empty range) and return at once.
   // Every round finalizes at least the first unfinished column (it either
   // reduces to zero or commits), so the window start must advance.
-  const int burst = 8;
+  // The first burst is short and inspected before anything else is queued,
+  // so that small problems (a round or two) do not queue idle rounds.
+  int burst = 2;  // grows to 8
   auto issue = [&](int slot) -> hipError_t {
     for (int t = 0; t < burst; ++t) {
       const hipError_t e = launch_reduce_round(ra, s, walk_clock.pair());
@@ -502,23 +504,37 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     if (e == hipSuccess) e = hipEventRecord(rb->ev[slot], s);
     return e;
   };
+  // Up to two bursts in flight (slots alternate; a slot is reused only after
+  // it was inspected); the first burst is inspected alone.
   int64_t prevF = -1;
-  int cur = 0;
-  HIPCHK(issue(cur));
+  int next_slot = 0, q_head = 0, q_len = 0;
+  int queue[2];
+  auto issue_next = [&]() -> hipError_t {
+    const hipError_t e = issue(next_slot);
+    queue[(q_head + q_len) & 1] = next_slot;
+    ++q_len;
+    next_slot ^= 1;
+    return e;
+  };
+  bool pipelined = false;
+  HIPCHK(issue_next());
   while (true) {
-    HIPCHK(issue(cur ^ 1));
-    HIPCHK(hipEventSynchronize(rb->ev[cur]));
-    const RedCtl& h = hc[cur];
+    if (pipelined && q_len < 2) HIPCHK(issue_next());
+    const int k = queue[q_head];
+    q_head ^= 1;
+    --q_len;
+    HIPCHK(hipEventSynchronize(rb->ev[k]));
+    const RedCtl& h = hc[k];
     if (h.done) break;
     if (h.need_more && !h.err) {
       if (whole) return fail(PH0_EDEVICE, "reduction asked for columns past the last one");
-      HIPCHK(hipStreamSynchronize(s));  // the queued burst found nothing to do
+      HIPCHK(hipStreamSynchronize(s));  // any queued burst found nothing to do
+      q_len = 0;
       HIPCHK(next_chunk());
       ra.skeys = skeys;
       HIPCHK(launch_reduce_extend(ra, E_lim, s));
       prevF = -1;
-      cur = 0;
-      HIPCHK(issue(cur));
+      HIPCHK(issue_next());
       continue;
     }
     if (h.F <= prevF || h.err) {
@@ -527,7 +543,11 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
                   h.err);
     }
     prevF = h.F;
-    cur ^= 1;
+    // Bursts grow 2, 4, 8 (then stay): rounds queued past the end cost a few
+    // launches each, so small problems queue few.
+    pipelined = true;
+    if (burst < 8) burst *= 2;
+    if (q_len == 0) HIPCHK(issue_next());
   }
   S.sort_chunks = chunks;
   S.sorted_keys = E_lim;

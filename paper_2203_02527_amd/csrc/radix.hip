@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(uint32_t* __restrict__ 
     x[q] = p0 + q < len ? v[p0 + q] : 0;
     s += x[q];
   }
-  uint32_t run = totals[blockIdx.x] + block_exclusive_scan(s, tmp);
+  uint32_t run = (totals ? totals[blockIdx.x] : 0u) + block_exclusive_scan(s, tmp);
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
     if (p0 + q < len) v[p0 + q] = run;
@@ -263,6 +263,11 @@ int64_t scan_totals_len(int64_t len) { return (len + kScanBlock - 1) / kScanBloc
 hipError_t launch_scan_u32(uint32_t* v, int64_t len, uint32_t* totals, hipStream_t s) {
   if (len <= 0) return hipSuccess;
   const int64_t nblocks = (len + kScanBlock - 1) / kScanBlock;
+  if (nblocks == 1) {  // one block: its base is 0, no totals pass needed
+    hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kThreads), 0, s, v, len,
+                       (const uint32_t*)nullptr);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)nblocks), dim3(kThreads), 0, s, v, len, totals);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, s, totals, nblocks);
   hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblocks), dim3(kThreads), 0, s, v, len, totals);

@@ -60,6 +60,7 @@ __global__ __launch_bounds__(kGroup) void k_grade_count(const uint64_t* __restri
   __shared__ uint32_t wc[2][kGroup / 64];
   const int64_t ng = (count + kGroup - 1) / kGroup;
   const int wave = threadIdx.x >> 6;
+  if (blockIdx.x == 0 && threadIdx.x == 0) cc[ng] = cp[ng] = 0;  // the scans' totals land here
   for (int64_t g = blockIdx.x; g < ng; g += gridDim.x) {
     bool ch, pv;
     position_flags(k, g * kGroup + threadIdx.x, count, shift, bitmap, &ch, &pv);
@@ -86,10 +87,14 @@ __global__ __launch_bounds__(kGroup) void k_grade_emit(const uint64_t* __restric
                                                        const uint32_t* __restrict__ cc,
                                                        const uint32_t* __restrict__ cp,
                                                        uint32_t* __restrict__ dbv,
-                                                       uint32_t* __restrict__ bars) {
+                                                       uint32_t* __restrict__ bars, int64_t n) {
   __shared__ uint32_t wc[2][kGroup / 64];
   const int64_t ng = (count + kGroup - 1) / kGroup;
   const int wave = threadIdx.x >> 6;
+  if (bars && blockIdx.x == 0 && threadIdx.x == 0) {  // the essential bar, last
+    bars[2 * (n - 1)] = 0u;
+    bars[2 * (n - 1) + 1] = kInf;
+  }
   for (int64_t g = blockIdx.x; g < ng; g += gridDim.x) {
     const int64_t q = g * kGroup + threadIdx.x;
     bool ch, pv;
@@ -183,16 +188,10 @@ hipError_t launch_grades_and_bars(const uint64_t* skeys, int64_t E_eff, int shif
   const int g = grid_for(E_eff, kGroup, 4096);
   hipLaunchKernelGGL(k_grade_count, dim3(g), dim3(kGroup), 0, s, skeys, E_eff, shift, bitmap, cc,
                      cp);
-  if ((e = launch_fill_u32(cc + ng, 0u, 1, s)) != hipSuccess) return e;
-  if ((e = launch_fill_u32(cp + ng, 0u, 1, s)) != hipSuccess) return e;
   if ((e = launch_scan_u32(cc, ng + 1, tot_c, s)) != hipSuccess) return e;
   if ((e = launch_scan_u32(cp, ng + 1, tot_p, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_grade_emit, dim3(g), dim3(kGroup), 0, s, skeys, E_eff, shift, bitmap,
-                     prow, cc, cp, dbv, bars);
-  if (bars) {  // the essential bar, last
-    if ((e = launch_fill_u32(bars + 2 * (n - 1), 0u, 1, s)) != hipSuccess) return e;
-    if ((e = launch_fill_u32(bars + 2 * (n - 1) + 1, kInf, 1, s)) != hipSuccess) return e;
-  }
+                     prow, cc, cp, dbv, bars, n);
   if ((e = hipMemcpyAsync(distinct, cc + ng, 4, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
   return hipMemcpyAsync(pivots, cp + ng, 4, hipMemcpyDeviceToHost, s);
 }
