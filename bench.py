@@ -44,10 +44,75 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--paper-scaling", action="store_true",
+                    help="only run the paper's experiment: N uniform points in [0,1]^2 (on a "
+                         "fixed-point grid), N = 50..700 and beyond, GPU and CPU-oracle time "
+                         "per barcode with fitted run-time exponents, and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 5 times (a reference kernel of "
                          "known traffic for hardware byte counters) and exit")
     return ap.parse_args()
+
+
+SCALING_N = (50, 100, 150, 200, 300, 400, 500, 600, 700, 1000, 2000, 4096, 8192, 16384)
+
+
+def paper_scaling(reps=10, seed=0):
+    """The paper's run-time experiment on this GPU: N uniform random points in
+    [0,1]^2, the mean of `reps` whole barcodes per N (points resident in HBM),
+    beside the single-threaded CPU oracle for N <= 2000, and the slopes of
+    log(time) against log(N) over the ranges the paper fits."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2203_02527_amd import ph0, synth
+
+    rows = []
+    for n in SCALING_N:
+        x = synth.unit_square_cloud(n, seed=seed + n)
+        xd = torch.from_numpy(x).to("cuda:0")
+        ws = ph0.alloc_workspace(n, 2, x.dtype, "cuda:0")
+        out = torch.empty((n, 2), dtype=torch.int32, device="cuda:0")
+        for _ in range(2):
+            ph0.ph0_barcodes_device(xd, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ph0.ph0_barcodes_device(xd, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        gpu_ms = 1000.0 * (time.perf_counter() - t0) / reps
+        got = out.cpu().numpy().view(np.uint32)[:, 1]
+        row = {"n": n, "gpu_ms": round(gpu_ms, 4)}
+        if n <= 2000:
+            creps = 3 if n > 700 else reps
+            t0 = time.perf_counter()
+            for _ in range(creps):
+                ref = oracle.barcode(x)
+            row["cpu_oracle_ms"] = round(1000.0 * (time.perf_counter() - t0) / creps, 3)
+            row["matches_oracle"] = bool(np.array_equal(got, ref.canonical))
+        rows.append(row)
+        note("scaling N=%d: %s" % (n, row))
+
+    def slope(key, lo, hi):
+        pts = [(r["n"], r[key]) for r in rows if lo <= r["n"] <= hi and key in r]
+        if len(pts) < 2:
+            return None
+        lx = np.log([p[0] for p in pts])
+        ly = np.log([p[1] for p in pts])
+        return round(float(np.polyfit(lx, ly, 1)[0]), 3)
+
+    exps = {}
+    for key in ("gpu_ms", "cpu_oracle_ms"):
+        for lo, hi in ((50, 150), (200, 700), (1000, 16384)):
+            v = slope(key, lo, hi)
+            if v is not None:
+                exps["%s_N%d_%d" % (key.replace("_ms", ""), lo, hi)] = v
+    return {"mode": "paper_scaling",
+            "workload": "N uniform points in [0,1]^2 on the grid rint(u * %d) (int16), seed "
+                        "%d + N; mean of %d barcodes per N from HBM-resident points"
+                        % (synth.UNIT_SCALE, seed, reps),
+            "points": rows, "exponents": exps}
 
 
 def calibrate_copy(mib):
@@ -208,6 +273,9 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
+        return
+    if args.paper_scaling:
+        print(json.dumps(paper_scaling()), flush=True)
         return
     import numpy as np
     import torch

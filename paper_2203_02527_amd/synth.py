@@ -29,6 +29,7 @@ import numpy as np
 
 __all__ = [
     "uniform_cloud",
+    "unit_square_cloud",
     "mixture_cloud",
     "batch_clouds",
     "circle_cloud",
@@ -48,6 +49,18 @@ def uniform_cloud(n: int = 256, d: int = 3, lo: int = -100, hi: int = 100,
     """n x d integer points uniform in [lo, hi] (inclusive)."""
     rng = _rng(seed)
     return rng.integers(lo, hi + 1, size=(n, d)).astype(dtype)
+
+
+UNIT_SCALE = 32767  # fixed-point grid of the unit-square workload
+
+
+def unit_square_cloud(n: int, seed: int = 0, scale: int = UNIT_SCALE) -> np.ndarray:
+    """n points uniform in [0, 1]^2 (the paper's experiments), on a
+    fixed-point grid: each coordinate is rint(u * scale) as int16, so that
+    squared distances, their order and their ties are exact integers."""
+    rng = _rng(seed)
+    u = rng.random((n, 2))
+    return np.rint(u * scale).astype(np.int16)
 
 
 def _mixture(rng: np.random.Generator, n: int, d: int, k: int, std: float,

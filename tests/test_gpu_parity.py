@@ -253,3 +253,9 @@ def test_mixture_workload_n16384_against_stored_oracle(torch):
     assert _sha(pr.partner.cpu().numpy(), "<i4") == rec["partner_sha256"]
     assert st["E_eff"] == rec["E_eff"] and st["additions"] == rec["additions"]
     assert st["E"] == rec["E"]
+
+
+@pytest.mark.parametrize("n", [50, 150, 700, 3000])
+def test_unit_square_workload(torch, n):
+    # The paper's experiment: uniform points in [0,1]^2 on a fixed-point grid.
+    _check_full(torch, synth.unit_square_cloud(n, seed=n))

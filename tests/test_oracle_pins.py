@@ -174,3 +174,15 @@ def test_bad_arguments_rejected():
         oracle.barcode(np.zeros((3, 2), np.int32))
     with pytest.raises(ValueError):
         oracle.barcode(np.zeros((0, 2), np.int8))
+
+
+def test_unit_square_generator_is_a_fixed_point_grid():
+    from paper_2203_02527_amd import synth
+
+    x = synth.unit_square_cloud(500, seed=9)
+    assert x.dtype == np.int16 and x.shape == (500, 2)
+    assert x.min() >= 0 and x.max() <= synth.UNIT_SCALE
+    np.testing.assert_array_equal(x, synth.unit_square_cloud(500, seed=9))
+    # the grid is rint(u * scale) of the seeded uniform draws
+    u = np.random.default_rng(9).random((500, 2))
+    np.testing.assert_array_equal(x, np.rint(u * synth.UNIT_SCALE).astype(np.int16))
