@@ -394,8 +394,9 @@ void keys_launch(const void* pts, int elem_bytes, int64_t n, int32_t d, int ib, 
                  int64_t ntiles, int grid, const KeyPass& kp, hipStream_t s) {
   if (use_mfma && elem_bytes == 1) {
     const bool vec16 = (d % 16) == 0 && (reinterpret_cast<uintptr_t>(pts) % 16) == 0;
-    hipLaunchKernelGGL(k_norms_i8, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s,
-                       static_cast<const int8_t*>(pts), n, d, kp.norms);
+    if (!kp.norms_ready)
+      hipLaunchKernelGGL(k_norms_i8, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s,
+                         static_cast<const int8_t*>(pts), n, d, kp.norms);
     if (d <= 64)
       hipLaunchKernelGGL((k_keys_mfma<MODE, 64>), dim3(grid), dim3(256), 0, s,
                          static_cast<const int8_t*>(pts), n, d, ib, ntiles,

@@ -389,6 +389,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     KeyPass kp;
     kp.mode = kKeysCount;
     kp.norms = norms;
+    kp.norms_ready = true;  // the histogram pass computed them
     kp.dlo = (uint64_t)blo << hist_shift;
     kp.dhi = bhi >= kHistBins ? ~0ull : (uint64_t)bhi << hist_shift;
     kp.cnt = kcnt;
@@ -435,6 +436,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
       KeyPass kp;
       kp.mode = kKeysEmit;
       kp.norms = norms;
+      kp.norms_ready = true;
       kp.dlo = (uint64_t)bin_next << hist_shift;
       kp.dhi = b >= kHistBins ? ~0ull : (uint64_t)b << hist_shift;
       kp.cnt = kcnt;

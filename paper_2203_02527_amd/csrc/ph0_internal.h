@@ -97,6 +97,7 @@ struct KeyPass {
   uint64_t dlo = 0, dhi = 0;
   uint32_t* cnt = nullptr;
   int32_t* norms = nullptr;  // n words of scratch (int8 Gram path)
+  bool norms_ready = false;  // norms already hold this cloud's |x_i|^2
 };
 hipError_t launch_keys_pass(const void* pts, int elem_bytes, int64_t n, int32_t d, int ib,
                             bool use_mfma, const KeyPass& kp, hipStream_t s);
