@@ -4,7 +4,8 @@
 // host orders clouds largest first) and runs the whole barcode algorithm of
 // Section 2 for it, the five GPU steps of Section 4 fused in one workgroup:
 //   * points and the dense bit-packed pivot table live in LDS (N <= 512:
-//     at most 512 rows x 8 words);
+//     at most 512 rows x 8 words; row r holds its stored column's other bit,
+//     the pivot bit r being implicit);
 //   * distances are recomputed from LDS as needed: a histogram of the
 //     squared distances picks chunks of whole histogram bins, lowest first;
 //     a chunk's edges are compacted in colex order into per-workgroup scratch
@@ -198,42 +199,38 @@ __device__ void reduce_chunk(Shared& S, const uint64_t* keys, const uint32_t* gr
     __syncthreads();
     if (nwin == 0) break;
 
-    // Walk every window column against the table.
+    // Walk every window column against the table.  A column is 2-sparse,
+    // {a, r}; adding the stored column {x, r} leaves {a, x}.  Row r of the
+    // table holds the stored column's other bit x (its pivot bit r is
+    // implicit), so one group search over the row's words 0..r/64 gives x,
+    // and an empty row means slot r is free.
     for (int s = gid; s < nwin; s += kGroups) {
       int a = S.wa[s], r = S.wr[s], rlo = S.wrlo[s];
-      uint64_t col = 0;
-      if (gl == (a >> 6)) col ^= 1ull << (a & 63);
-      if (gl == (r >> 6)) col ^= 1ull << (r & 63);
       int moved = 0;
       bool zero = false;
       while (true) {
-        if (gl <= (r >> 6) && gl < LW) col ^= S.table[r * kMaxLW + gl];
-        const int nr = grp_top<G>(col, gbase);
-        if (nr == r) break;
+        const uint64_t w = (gl <= (r >> 6) && gl < LW) ? S.table[r * kMaxLW + gl] : 0ull;
+        const int x = grp_top<G>(w, gbase);
+        if (x < 0) break;  // slot r is free
         ++moved;
-        if (nr < 0 || nr > r) {
-          if (nr > r) *err = 1;
+        if (x == a || x >= r) {  // zero column (or a corrupt table)
+          if (x >= r) *err = 1;
           zero = true;
           break;
         }
-        r = nr;
+        const int lo = x < a ? x : a;
+        r = x < a ? a : x;
+        a = lo;
       }
       if (zero) {
         if (gl == 0) S.wst[s] = kFinal;
         continue;
       }
-      if (gl == (r >> 6)) col &= ~(1ull << (r & 63));
-      const int na = grp_top<G>(col, gbase);
-      if (na < 0) {
-        if (gl == 0) *err = 1;
-        continue;
-      }
-      a = na;
+      // Root of row a in the current forest: follow stored columns down.
       int v = moved ? a : rlo;
       while (true) {
-        uint64_t row = (gl <= (v >> 6) && gl < LW) ? S.table[v * kMaxLW + gl] : 0ull;
-        if (gl == (v >> 6)) row &= ~(1ull << (v & 63));
-        const int c = grp_top<G>(row, gbase);
+        const uint64_t w = (gl <= (v >> 6) && gl < LW) ? S.table[v * kMaxLW + gl] : 0ull;
+        const int c = grp_top<G>(w, gbase);
         if (c < 0) break;
         if (c >= v) {
           *err = 1;
@@ -271,12 +268,7 @@ __device__ void reduce_chunk(Shared& S, const uint64_t* keys, const uint32_t* gr
       const int r = S.wr[s], a = S.wa[s];
       const uint32_t e = benc(round, S.wpos[s]);
       if ((uint32_t)S.wpos[s] < fd || (S.lowc[r] == e && S.touch[r] > e)) {
-        if ((a >> 6) == (r >> 6)) {
-          S.table[r * kMaxLW + (r >> 6)] = (1ull << (r & 63)) | (1ull << (a & 63));
-        } else {
-          S.table[r * kMaxLW + (a >> 6)] = 1ull << (a & 63);
-          S.table[r * kMaxLW + (r >> 6)] = 1ull << (r & 63);
-        }
+        S.table[r * kMaxLW + (a >> 6)] = 1ull << (a & 63);  // pivot bit r is implicit
         S.death[r] = gr[S.wpos[s]];
         S.wst[s] = kFinal;
         atomicAdd(&S.s_pivots, 1u);
