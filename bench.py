@@ -47,7 +47,11 @@ def parse():
     ap.add_argument("--paper-scaling", action="store_true",
                     help="only run the paper's experiment: N uniform points in [0,1]^2 (on a "
                          "fixed-point grid), N = 50..700 and beyond, GPU and CPU-oracle time "
-                         "per barcode with fitted run-time exponents, and exit")
+                         "per barcode with fitted run-time exponents, and the paper's OpenMP "
+                         "CPU scheme at 1..all host threads, and exit")
+    ap.add_argument("--cpu-openmp", action="store_true",
+                    help="only run the paper's OpenMP CPU scheme on the unit-square clouds at "
+                         "1..all host threads (no GPU needed), and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 5 times (a reference kernel of "
                          "known traffic for hardware byte counters) and exit")
@@ -55,6 +59,8 @@ def parse():
 
 
 SCALING_N = (50, 100, 150, 200, 300, 400, 500, 600, 700, 1000, 2000, 4096, 8192, 16384)
+OMP_N = (50, 100, 150, 200, 300, 400, 500, 600, 700, 1000, 2000)
+OMP_REPS = 5
 
 
 def paper_scaling(reps=10, seed=0):
@@ -102,6 +108,13 @@ def paper_scaling(reps=10, seed=0):
         ly = np.log([p[1] for p in pts])
         return round(float(np.polyfit(lx, ly, 1)[0]), 3)
 
+    omp = omp_sweep(seed)
+    omp_rows = omp["points"]
+    for r in rows:
+        for o in omp_rows:
+            if o["n"] == r["n"]:
+                r["cpu_omp_best_ms"] = min(v for k, v in o.items() if k.endswith("_ms"))
+
     exps = {}
     for key in ("gpu_ms", "cpu_oracle_ms"):
         for lo, hi in ((50, 150), (200, 700), (1000, 16384)):
@@ -112,7 +125,42 @@ def paper_scaling(reps=10, seed=0):
             "workload": "N uniform points in [0,1]^2 on the grid rint(u * %d) (int16), seed "
                         "%d + N; mean of %d barcodes per N from HBM-resident points"
                         % (synth.UNIT_SCALE, seed, reps),
-            "points": rows, "exponents": exps}
+            "points": rows, "exponents": exps,
+            "cpu_openmp": omp}
+
+
+def omp_sweep(seed=0):
+    """The paper's multi-core CPU scheme (Section 3) on the same unit-square
+    clouds, at the thread counts of its two CPU figures (1, 2; 3, 4, 6) and
+    at all host cores; each run's barcode is checked against the oracle."""
+    import numpy as np
+
+    import oracle
+    from paper_2203_02527_amd import synth
+
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = sorted({t for t in (1, 2, 3, 4, 6, cores) if t <= max(cores, 1)})
+    omp_rows = []
+    for n in OMP_N:
+        x = synth.unit_square_cloud(n, seed=seed + n)
+        ref = oracle.barcode(x)
+        row = {"n": n}
+        for t in threads:
+            oracle.omp_barcode(x, t)
+            t0 = time.perf_counter()
+            for _ in range(OMP_REPS):
+                got = oracle.omp_barcode(x, t)
+            row["t%d_ms" % t] = round(1000.0 * (time.perf_counter() - t0) / OMP_REPS, 3)
+            if not np.array_equal(got.canonical, ref.canonical):
+                raise RuntimeError("OpenMP baseline differs from the oracle at N=%d" % n)
+        if "t2_ms" in row:
+            row["speedup_2_vs_1"] = round(row["t1_ms"] / row["t2_ms"], 3)
+        omp_rows.append(row)
+        note("openmp N=%d: %s" % (n, row))
+    return {"scheme": "Section 3: OpenMP loops inside the sequential column loop (parallel "
+                      "distances; each column addition with its low search is one parallel "
+                      "region); stop at the (N-1)-th pivot",
+            "host_cores": cores, "threads": threads, "reps": OMP_REPS, "points": omp_rows}
 
 
 def calibrate_copy(mib):
@@ -273,6 +321,9 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
+        return
+    if args.cpu_openmp:
+        print(json.dumps({"mode": "cpu_openmp", **omp_sweep(args.seed)}), flush=True)
         return
     if args.paper_scaling:
         print(json.dumps(paper_scaling()), flush=True)

@@ -8,6 +8,11 @@ or executes anything here; the two share no code.
 barcode algorithm of Section 2 of the paper (distances, sort, dedupe to
 grades, dense F2 column reduction, read-off).  This wrapper builds it with
 g++ on first use and exposes it on numpy arrays.
+
+``ph0_omp.cpp`` is the paper's multi-core CPU scheme (Section 3: OpenMP
+work-sharing loops inside the sequential column loop), a CPU timing baseline
+beside the GPU; ``omp_barcode`` runs it.  It is written apart from the oracle
+and checked against it in the tests.
 """
 from __future__ import annotations
 
@@ -21,6 +26,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ph0_oracle.cpp")
 _LIB = os.path.join(_HERE, "libph0_oracle.so")
+_OMP_SRC = os.path.join(_HERE, "ph0_omp.cpp")
+_OMP_LIB = os.path.join(_HERE, "libph0_omp.so")
 
 INF = 0xFFFFFFFF
 
@@ -43,16 +50,20 @@ class _Stats(ctypes.Structure):
     ]
 
 
+def _compile(src: str, lib: str, flags: list, force: bool) -> str:
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+        tmp = lib + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++", "-O3", "-std=c++17", "-fPIC", "-shared", *flags,
+                               "-o", tmp, src])
+        os.replace(tmp, lib)
+    return lib
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle shared library with g++ (single-threaded, -O3)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call([
-            "g++", "-O3", "-std=c++17", "-fPIC", "-shared",
-            "-o", tmp, _SRC,
-        ])
-        os.replace(tmp, _LIB)
-    return _LIB
+    """Compile the oracle shared library (single-threaded, -O3) and the
+    OpenMP baseline with g++; returns the oracle library's path."""
+    _compile(_OMP_SRC, _OMP_LIB, ["-fopenmp"], force)
+    return _compile(_SRC, _LIB, [], force)
 
 
 _lib = None
@@ -164,3 +175,72 @@ def sorted_edges(points: np.ndarray) -> SortedEdges:
     if rc != 0:
         raise RuntimeError("oracle rejected its arguments")
     return SortedEdges(cd, de, jj, ii, gg, int(nd.value))
+
+
+class _OmpStats(ctypes.Structure):
+    _fields_ = [
+        ("E", ctypes.c_int64),
+        ("E_eff", ctypes.c_int64),
+        ("distinct", ctypes.c_int64),
+        ("additions", ctypes.c_int64),
+        ("pivots", ctypes.c_int64),
+        ("threads", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("s_dist", ctypes.c_double),
+        ("s_sort", ctypes.c_double),
+        ("s_rank", ctypes.c_double),
+        ("s_reduce", ctypes.c_double),
+        ("s_emit", ctypes.c_double),
+    ]
+
+
+_omp = None
+
+
+def _load_omp():
+    global _omp
+    if _omp is None:
+        build()
+        lib = ctypes.CDLL(_OMP_LIB)
+        P = ctypes.c_void_p
+        lib.ph0p_barcode.argtypes = [P, ctypes.c_int, ctypes.c_int64, ctypes.c_int32, ctypes.c_int,
+                                     ctypes.c_int, P, P, ctypes.POINTER(_OmpStats)]
+        lib.ph0p_barcode.restype = ctypes.c_int
+        _omp = lib
+    return _omp
+
+
+@dataclass
+class OmpResult:
+    canonical: np.ndarray        # n uint32 deaths ascending, INF last
+    death_by_vertex: np.ndarray  # n uint32
+    E: int
+    E_eff: int
+    distinct: int
+    additions: int
+    pivots: int
+    threads: int
+    seconds: dict
+
+
+def omp_barcode(points: np.ndarray, threads: int, early_exit: bool = True) -> OmpResult:
+    """The paper's multi-core CPU scheme (Section 3) with `threads` OpenMP
+    threads: a timing baseline, not the oracle."""
+    x, eb = _points(points)
+    n, d = x.shape
+    if n < 1 or d < 1 or threads < 1:
+        raise ValueError("need N >= 1, d >= 1, threads >= 1")
+    lib = _load_omp()
+    dv = np.empty(n, np.uint32)
+    can = np.empty(n, np.uint32)
+    st = _OmpStats()
+    rc = lib.ph0p_barcode(_ptr(x), eb, n, d, int(threads), 1 if early_exit else 0, _ptr(dv),
+                          _ptr(can), ctypes.byref(st))
+    if rc != 0:
+        raise RuntimeError("OpenMP baseline rejected its arguments")
+    return OmpResult(
+        canonical=can, death_by_vertex=dv, E=st.E, E_eff=st.E_eff, distinct=st.distinct,
+        additions=st.additions, pivots=st.pivots, threads=st.threads,
+        seconds=dict(dist=st.s_dist, sort=st.s_sort, rank=st.s_rank,
+                     reduce=st.s_reduce, emit=st.s_emit),
+    )
