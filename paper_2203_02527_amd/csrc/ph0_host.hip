@@ -142,14 +142,44 @@ SortPlan plan_sort(int ib, int dbits) {
   return sp;
 }
 
+// Timing events are taken from a per-thread pool that grows on demand, so a
+// call with statistics creates no events once the pool covers it.  The
+// events are never destroyed: a thread-exit destructor could run after the
+// HIP runtime has shut down at process exit.
+struct EventPool {
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used == ev.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ev.push_back(e);
+    }
+    return ev[used++];
+  }
+};
+
+EventPool& event_pool() {
+  thread_local EventPool pool;
+  return pool;
+}
+
+// Returns the pool's events to it when a call ends (calls on one thread do
+// not overlap, and each call reads its times before it returns).
+struct PoolScope {
+  size_t mark;
+  PoolScope() : mark(event_pool().used) {}
+  ~PoolScope() { event_pool().used = mark; }
+};
+
 struct Timer {
   bool on;
   hipStream_t s;
-  hipEvent_t ev[8];
+  hipEvent_t ev[8] = {};
   int k = 0;
   explicit Timer(bool enabled, hipStream_t st) : on(enabled), s(st) {
     if (on)
-      for (auto& e : ev) on = on && hipEventCreate(&e) == hipSuccess;
+      for (auto& e : ev) on = on && (e = event_pool().get()) != nullptr;
   }
   void mark() {
     if (on && k < 8) (void)hipEventRecord(ev[k++], s);
@@ -159,43 +189,30 @@ struct Timer {
     if (on && b < k) (void)hipEventElapsedTime(&v, ev[a], ev[b]);
     return v;
   }
-  ~Timer() {
-    if (on)
-      for (auto& e : ev) (void)hipEventDestroy(e);
-  }
 };
 
 // Event pairs around individual kernel launches (stats only).
 struct KernelClock {
   bool on;
   std::vector<hipEvent_t> ev;
-  size_t used = 0;
   explicit KernelClock(bool enabled) : on(enabled) {}
   hipEvent_t* pair() {
     if (!on) return nullptr;
-    if (used + 2 > ev.size()) {
-      for (int k = 0; k < 2; ++k) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        ev.push_back(e);
-      }
-    }
-    hipEvent_t* p = &ev[used];
-    used += 2;
-    return p;
+    const hipEvent_t a = event_pool().get(), b = event_pool().get();
+    if (!a || !b) return nullptr;
+    ev.push_back(a);
+    ev.push_back(b);
+    return &ev[ev.size() - 2];
   }
   float total_ms() const {
     float t = 0;
-    for (size_t k = 0; k + 1 < used; k += 2) {
+    for (size_t k = 0; k + 1 < ev.size(); k += 2) {
       float v = 0;
       if (hipEventElapsedTime(&v, ev[k], ev[k + 1]) == hipSuccess) t += v;
     }
     return t;
   }
-  int launches() const { return (int)(used / 2); }
-  ~KernelClock() {
-    for (auto e : ev) (void)hipEventDestroy(e);
-  }
+  int launches() const { return (int)(ev.size() / 2); }
 };
 
 // Two pinned control-block copies and their events per host thread: the
@@ -264,6 +281,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     return PH0_OK;
   }
 
+  PoolScope pool_scope;
   Timer tm(st != nullptr, s);
   tm.mark();  // 0
   // Bound on the squared distance from the per-dimension coordinate ranges
@@ -795,6 +813,7 @@ int ph0_barcodes_batched_device(const void* d_points, ph0_dtype dt, const int64_
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   char* ws = static_cast<char*>(d_ws);
   const int eb = dt == PH0_I8 ? 1 : 2;
+  PoolScope pool_scope;
   Timer tm(st != nullptr, s);
   tm.mark();
   HIPCHK(hipMemcpyAsync(ws + P.offs, offsets, 8 * (size_t)(nclouds + 1), hipMemcpyHostToDevice, s));
