@@ -66,6 +66,11 @@ def build(force: bool = False) -> str:
     return _compile(_SRC, _LIB, [], force)
 
 
+class _H1Stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in
+                ("E", "T", "T_eff", "additions", "pivots", "zero_length", "columns")]
+
+
 _lib = None
 
 
@@ -80,6 +85,10 @@ def _load():
         lib.ph0o_sorted_edges.argtypes = [P, ctypes.c_int, ctypes.c_int64, ctypes.c_int32,
                                           P, P, P, P, P, ctypes.POINTER(ctypes.c_int64)]
         lib.ph0o_sorted_edges.restype = ctypes.c_int
+        lib.ph0o_h1.argtypes = [P, ctypes.c_int, ctypes.c_int64, ctypes.c_int32, ctypes.c_int,
+                                P, P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(_H1Stats)]
+        lib.ph0o_h1.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -146,6 +155,45 @@ def barcode(points: np.ndarray, early_exit: bool = True) -> OracleResult:
         seconds=dict(dist=st.s_dist, sort=st.s_sort, rank=st.s_rank,
                      reduce=st.s_reduce, emit=st.s_emit),
     )
+
+
+@dataclass
+class H1Result:
+    bars: np.ndarray         # m x 2 uint32 (birth, death) grades, birth < death, sorted
+    tri_of_edge: np.ndarray  # E int64: triangle (in triangle order) paired with the edge at
+                             # each sorted position, -1 if none
+    E: int
+    T: int
+    T_eff: int
+    additions: int
+    pivots: int
+    zero_length: int
+    columns: int
+
+
+def h1_barcode(points: np.ndarray, early_exit: bool = True) -> H1Result:
+    """H1 of the same filtration: dense F2 reduction of the edge-by-triangle
+    boundary matrix (readings in ph0_oracle.cpp)."""
+    x, eb = _points(points)
+    n, d = x.shape
+    if n < 1 or d < 1:
+        raise ValueError("need N >= 1 and d >= 1")
+    E = n * (n - 1) // 2
+    cap = max(E - n + 1, 0)
+    lib = _load()
+    toe = np.empty(E, np.int64)
+    b = np.empty(max(cap, 1), np.uint32)
+    dd = np.empty(max(cap, 1), np.uint32)
+    nb = ctypes.c_int64(0)
+    st = _H1Stats()
+    rc = lib.ph0o_h1(_ptr(x), eb, n, d, 1 if early_exit else 0, _ptr(toe), _ptr(b), _ptr(dd),
+                     cap, ctypes.byref(nb), ctypes.byref(st))
+    if rc != 0:
+        raise RuntimeError("oracle rejected its arguments (%d)" % rc)
+    m = int(nb.value)
+    return H1Result(bars=np.stack([b[:m], dd[:m]], axis=1), tri_of_edge=toe, E=st.E, T=st.T,
+                    T_eff=st.T_eff, additions=st.additions, pivots=st.pivots,
+                    zero_length=st.zero_length, columns=st.columns)
 
 
 @dataclass

@@ -233,4 +233,113 @@ int ph0o_barcode(const void* points, int elem_bytes, int64_t n, int32_t d, int e
   return 0;
 }
 
+// ---- H1: the edge-by-triangle boundary matrix ----
+//
+// The 1st persistent homology of the same filtration, the higher-dimension
+// repetition Section 3 anticipates and the conclusion leaves to future work.
+// Readings (the paper gives no H1 details):
+//   * the 2-skeleton of the Vietoris-Rips complex: a triangle {a, b, c}
+//     enters with its latest edge, the one of its three edges that comes last
+//     in the H0 edge order (delta, j, i); its grade is that edge's grade;
+//   * triangles are ordered by (position of the latest edge, third vertex),
+//     which lists every face before its cofaces;
+//   * the boundary matrix has one row per edge (in edge order) and one
+//     column per triangle (in triangle order), the triangle's three edges;
+//     columns are reduced left to right over F2, low = largest edge position;
+//   * a reduced column with low e pairs edge e with the triangle: the H1
+//     interval [grade(e), grade(triangle)); intervals of length 0 are not
+//     bars.  The complete 2-skeleton has no H1, so exactly E - N + 1 pairs
+//     exist and no interval is infinite; early_exit stops at the last one.
+// Columns are dense bitsets of E bits.  Outputs (NULL allowed):
+//   tri_of_edge[E]   for the edge at sorted position q, the index (in
+//                    triangle order) of the triangle it pairs with, -1 if none
+//   birth[cap], death[cap]  the bars (birth < death), sorted by (birth, death);
+//                    *nbars receives their number (at most E - N + 1)
+// Returns 0, -1 on bad arguments, -2 when cap is too small.
+typedef struct {
+  int64_t E, T, T_eff, additions, pivots, zero_length, columns;
+} ph0o_h1_stats;
+
+int ph0o_h1(const void* points, int elem_bytes, int64_t n, int32_t d, int early_exit,
+            int64_t* tri_of_edge, uint32_t* birth, uint32_t* death, int64_t cap,
+            int64_t* nbars, ph0o_h1_stats* st) {
+  if (!points || (elem_bytes != 1 && elem_bytes != 2) || n < 1 || d < 1 || cap < 0) return -1;
+  ph0o_h1_stats s;
+  std::memset(&s, 0, sizeof(s));
+  std::vector<Edge> edges = all_pairs(points, elem_bytes, n, d);
+  std::sort(edges.begin(), edges.end(), edge_less);
+  int64_t distinct = 0;
+  std::vector<uint32_t> g = grades(edges, &distinct);
+  const int64_t E = static_cast<int64_t>(edges.size());
+  s.E = E;
+  // Sorted position of edge {i, j}, i < j.
+  std::vector<int64_t> pos(static_cast<size_t>(n * n), -1);
+  for (int64_t q = 0; q < E; ++q) {
+    pos[static_cast<size_t>(edges[q].i * n + edges[q].j)] = q;
+    pos[static_cast<size_t>(edges[q].j * n + edges[q].i)] = q;
+  }
+  // Triangles with their three edge positions, in (latest edge, third vertex) order.
+  struct Tri {
+    int64_t e0, e1, e2;  // e2 = latest edge; e0 < e1 < e2
+    int32_t k;           // vertex not on the latest edge
+  };
+  std::vector<Tri> tris;
+  tris.reserve(static_cast<size_t>(n * (n - 1) * (n - 2) / 6));
+  for (int64_t a = 0; a < n; ++a)
+    for (int64_t b = a + 1; b < n; ++b)
+      for (int64_t c = b + 1; c < n; ++c) {
+        int64_t e[3] = {pos[a * n + b], pos[a * n + c], pos[b * n + c]};
+        std::sort(e, e + 3);
+        const int64_t third = e[2] == pos[a * n + b] ? c : e[2] == pos[a * n + c] ? b : a;
+        tris.push_back(Tri{e[0], e[1], e[2], static_cast<int32_t>(third)});
+      }
+  std::sort(tris.begin(), tris.end(), [](const Tri& x, const Tri& y) {
+    return x.e2 != y.e2 ? x.e2 < y.e2 : x.k < y.k;
+  });
+  s.T = static_cast<int64_t>(tris.size());
+
+  const int64_t words = (E + 63) / 64;
+  std::vector<std::vector<uint64_t>> slot(static_cast<size_t>(E));
+  std::vector<int64_t> paired(static_cast<size_t>(E), -1);
+  std::vector<uint64_t> col(static_cast<size_t>(words));
+  const int64_t want = E - (n - 1);
+  for (int64_t t = 0; t < s.T; ++t) {
+    if (early_exit && s.pivots == want) break;
+    ++s.columns;
+    std::fill(col.begin(), col.end(), 0);
+    for (int64_t e : {tris[t].e0, tris[t].e1, tris[t].e2}) col[e / 64] ^= 1ull << (e % 64);
+    int64_t low = low_of(col);
+    while (low >= 0 && !slot[low].empty()) {
+      for (int64_t w = 0; w < words; ++w) col[w] ^= slot[low][w];
+      ++s.additions;
+      low = low_of(col);
+    }
+    if (low >= 0) {
+      slot[low] = col;
+      paired[low] = t;
+      ++s.pivots;
+      s.T_eff = t + 1;
+    }
+  }
+  std::vector<std::pair<uint32_t, uint32_t>> bars;
+  for (int64_t q = 0; q < E; ++q) {
+    if (tri_of_edge) tri_of_edge[q] = paired[q];
+    if (paired[q] < 0) continue;
+    const uint32_t b = g[q], dd = g[tris[paired[q]].e2];
+    if (b == dd)
+      ++s.zero_length;
+    else
+      bars.push_back({b, dd});
+  }
+  std::sort(bars.begin(), bars.end());
+  if (nbars) *nbars = static_cast<int64_t>(bars.size());
+  if (st) *st = s;
+  if (static_cast<int64_t>(bars.size()) > cap && (birth || death)) return -2;
+  for (size_t k = 0; k < bars.size(); ++k) {
+    if (birth) birth[k] = bars[k].first;
+    if (death) death[k] = bars[k].second;
+  }
+  return 0;
+}
+
 }  // extern "C"
