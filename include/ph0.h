@@ -203,6 +203,49 @@ int64_t ph0_server_in_flight(ph0_server* srv);
 /* Waits for running requests, then frees the server. */
 void ph0_server_destroy(ph0_server* srv);
 
+/* ---- H1: 1st persistent homology of the same filtration ----------------
+ *
+ * The higher-dimension repetition of the algorithm that Section 3 anticipates
+ * (and the conclusion leaves to future work), on the 2-skeleton of the same
+ * Vietoris-Rips filtration:
+ *   - edges in the order and with the grades of the H0 computation;
+ *   - a triangle enters with its latest edge (the last of its three edges in
+ *     that order) and carries that edge's grade; triangles are ordered by
+ *     (latest edge, third vertex);
+ *   - the edge-by-triangle boundary matrix is column-reduced over F2 left to
+ *     right (low = largest edge position); a reduced column with low e pairs
+ *     edge e with the triangle, the interval [grade(e), grade(triangle)).
+ * The complete 2-skeleton has no H1, so exactly E - n + 1 pairs exist and no
+ * interval is infinite; pairs of length 0 are not bars.  n <= 512 (stored
+ * columns are dense bitsets of E = n(n-1)/2 bits); larger n gives ERANGE. */
+typedef struct {
+  int64_t E;            /* edges n(n-1)/2 */
+  int64_t T;            /* triangles n(n-1)(n-2)/6 */
+  int64_t pivots;       /* pairs found: E - n + 1 */
+  int64_t emergent;     /* pairs of a triangle with its own latest edge, stored unreduced */
+  int64_t bars;         /* pairs of positive length */
+  int64_t zero_length;  /* pairs of length 0 */
+  int64_t additions;    /* column additions of the reduction (every column reduced) */
+  int64_t rounds;       /* reduction rounds */
+  int64_t walks;        /* column walks, counting repeats (each round's, and commits') */
+  float ms_setup, ms_reduce, ms_total;  /* GPU event times when measured, else 0 */
+  int32_t reserved;
+} ph0_h1_stats;
+
+/* Device workspace for ph0_h1_device (dominated by E x ceil(E/64) words of
+ * stored columns and 20 bytes per triangle). */
+int ph0_h1_workspace_bytes(int64_t n, int32_t d, ph0_dtype dt, size_t* bytes);
+
+/* H1 barcode on device memory.  d_bars receives the bars (birth < death, in
+ * grade units) sorted by (birth, death) and must hold E - n + 1 entries (the
+ * most there can be); *n_bars (host) receives their number.  d_tri_of_edge
+ * (E entries, may be NULL) receives, for the edge at each sorted position,
+ * the index in triangle order of the triangle it pairs with, or -1.  `st` may
+ * be NULL.  Blocks until done. */
+int ph0_h1_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, ph0_bar* d_bars,
+                  int64_t* d_tri_of_edge, int64_t* n_bars, void* d_workspace, size_t ws_bytes,
+                  void* hip_stream, ph0_h1_stats* st);
+
 /* Reduction window (columns reduced side by side per round, rounded up to a
  * power of two); 0 restores the built-in choice, max(65536, 16 n) capped at
  * E.  Affects speed only, never results.  Process-wide. */

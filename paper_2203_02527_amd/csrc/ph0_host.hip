@@ -695,6 +695,59 @@ int plan_batch(const int64_t* offsets, int64_t nclouds, int32_t d, ph0_dtype dt,
   return PH0_OK;
 }
 
+// ---- H1 path ----
+
+struct H1Layout {
+  int64_t E = 0, T = 0, LWE = 0;
+  size_t h0 = 0, h0_bytes = 0, keys = 0, inv = 0, grade = 0, cnt = 0, start = 0, scan = 0,
+         tri = 0, owner = 0, lowc = 0, table = 0, surv = 0, clist = 0, wlist = 0, packed = 0,
+         sorted = 0, rcounts = 0, rerr = 0, ctl = 0, total = 0;
+};
+
+int plan_h1(int64_t n, int32_t d, ph0_dtype dt, H1Layout* L) {
+  L->E = n * (n - 1) / 2;
+  L->T = n * (n - 1) * (n - 2) / 6;
+  L->LWE = (L->E + 63) / 64;
+  if (ph0_workspace_bytes(n, d, dt, &L->h0_bytes) != PH0_OK) return PH0_EINVAL;
+  const int64_t E1 = std::max<int64_t>(L->E, 1), T1 = std::max<int64_t>(L->T, 1);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L->h0 = take(L->h0_bytes);
+  L->keys = take(8 * (size_t)E1);
+  L->inv = take(4 * (size_t)E1);
+  L->grade = take(4 * (size_t)E1);
+  L->cnt = take(4 * (size_t)E1);
+  L->start = take(4 * (size_t)(E1 + 1));
+  L->scan = take(4 * (size_t)scan_totals_len(E1 + 1));
+  L->tri = take(8 * (size_t)T1);
+  L->owner = take(4 * (size_t)E1);
+  L->lowc = take(8 * (size_t)E1);
+  L->table = take(8 * (size_t)E1 * (size_t)std::max<int64_t>(L->LWE, 1));
+  L->surv = take(8 * (size_t)T1);
+  L->clist = take(8 * (size_t)E1);
+  L->wlist = take(4 * (size_t)T1);
+  L->packed = take(8 * (size_t)E1);
+  L->sorted = take(8 * (size_t)E1);
+  L->rcounts = take(4 * (size_t)radix_count_entries(E1));
+  L->rerr = take(4);
+  L->ctl = take(sizeof(H1Ctl));
+  L->total = o;
+  return PH0_OK;
+}
+
+int check_h1_args(const void* p, ph0_dtype dt, int64_t n, int32_t d) {
+  int rc = check_args(p, dt, n, d);
+  if (rc) return rc;
+  if (n > kH1MaxN)
+    return fail(PH0_ERANGE, "H1 supports n <= %lld (dense stored columns of n(n-1)/2 bits); "
+                "got %lld", (long long)kH1MaxN, (long long)n);
+  return PH0_OK;
+}
+
 struct DeviceBuffer {
   void* p = nullptr;
   ~DeviceBuffer() {
@@ -863,6 +916,141 @@ int ph0_barcodes_batched_device(const void* d_points, ph0_dtype dt, const int64_
     S.ms_reduce = tm.ms(0, 1);
     S.ms_emit = tm.ms(1, 2);
     S.ms_total = tm.ms(0, 2);
+    *st = S;
+  }
+  return PH0_OK;
+}
+
+int ph0_h1_workspace_bytes(int64_t n, int32_t d, ph0_dtype dt, size_t* bytes) {
+  static const char probe = 0;
+  int rc = check_h1_args(&probe, dt, n, d);
+  if (rc) return rc;
+  if (!bytes) return fail(PH0_EINVAL, "bytes pointer is NULL");
+  H1Layout L;
+  if ((rc = plan_h1(n, d, dt, &L))) return rc;
+  *bytes = L.total;
+  return PH0_OK;
+}
+
+int ph0_h1_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, ph0_bar* d_bars,
+                  int64_t* d_tri_of_edge, int64_t* n_bars, void* d_ws, size_t ws_bytes,
+                  void* hip_stream, ph0_h1_stats* st) {
+  int rc = check_h1_args(d_points, dt, n, d);
+  if (rc) return rc;
+  if (!n_bars) return fail(PH0_EINVAL, "n_bars pointer is NULL");
+  if (!d_ws) return fail(PH0_EINVAL, "workspace pointer is NULL");
+  H1Layout L;
+  if ((rc = plan_h1(n, d, dt, &L))) return rc;
+  if (ws_bytes < L.total)
+    return fail(PH0_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+  if (!d_bars && L.E - n + 1 > 0) return fail(PH0_EINVAL, "bars pointer is NULL");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  char* ws = static_cast<char*>(d_ws);
+  auto at = [&](size_t off) { return static_cast<void*>(ws + off); };
+  ph0_h1_stats S = {};
+  S.E = L.E;
+  S.T = L.T;
+  *n_bars = 0;
+  PoolScope pool_scope;
+  Timer tm(st != nullptr, s);
+  tm.mark();
+  if (n < 3) {  // no triangle, no cycle
+    if (d_tri_of_edge && L.E > 0) HIPCHK(launch_fill_u64((uint64_t*)d_tri_of_edge, ~0ull, L.E, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st) *st = S;
+    return PH0_OK;
+  }
+  uint64_t* keys = static_cast<uint64_t*>(at(L.keys));
+  if ((rc = ph0_sorted_keys_device(d_points, dt, n, d, keys, at(L.h0), L.h0_bytes, s)))
+    return rc;
+  H1Args A;
+  A.keys = keys;
+  A.ib = index_bits(n);
+  A.n = n;
+  A.E = L.E;
+  A.T = L.T;
+  A.LWE = L.LWE;
+  A.inv = static_cast<int32_t*>(at(L.inv));
+  A.grade = static_cast<uint32_t*>(at(L.grade));
+  A.cnt = static_cast<uint32_t*>(at(L.cnt));
+  A.start = static_cast<uint32_t*>(at(L.start));
+  A.scan_tmp = static_cast<uint32_t*>(at(L.scan));
+  A.tri = static_cast<uint64_t*>(at(L.tri));
+  A.owner = static_cast<int32_t*>(at(L.owner));
+  A.lowc = static_cast<uint64_t*>(at(L.lowc));
+  A.table = static_cast<uint64_t*>(at(L.table));
+  A.surv = static_cast<uint64_t*>(at(L.surv));
+  A.clist = static_cast<uint64_t*>(at(L.clist));
+  A.wlist = static_cast<uint32_t*>(at(L.wlist));
+  A.nsurv_host = 0;
+  A.cus = device_cu_count();
+  A.ctl = static_cast<H1Ctl*>(at(L.ctl));
+  H1Ctl c0 = {};
+  c0.T = L.T;
+  c0.firstdup = ~0ull;
+  HIPCHK(hipMemcpyAsync(A.ctl, &c0, sizeof(c0), hipMemcpyHostToDevice, s));
+  HIPCHK(launch_h1_setup(A, s));
+  tm.mark();
+  // Rounds until every column is final.  Every round after the first
+  // commits at least its smallest live survivor, so there are at most
+  // E - n + 2 of them.
+  H1Ctl hc = {};
+  uint32_t tcount = 0;
+  HIPCHK(hipMemcpyAsync(&tcount, A.start + L.E, 4, hipMemcpyDeviceToHost, s));
+  int64_t rounds = 0;
+  for (bool first = true;; first = false) {
+    HIPCHK(launch_h1_round(A, first, s));
+    ++rounds;
+    HIPCHK(hipMemcpyAsync(&hc, A.ctl, sizeof(hc), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hc.err)
+      return fail(PH0_EDEVICE, "H1 reduction: %s (round %lld)",
+                  (hc.err & 2) ? "a stored column's top bit is not its row" :
+                                 "a repeated walk diverged", (long long)rounds);
+    if (hc.live == 0) break;
+    if (rounds > L.E - n + 2)
+      return fail(PH0_EDEVICE, "H1 reduction made no progress after %lld rounds",
+                  (long long)rounds);
+    A.nsurv_host = hc.nsurv;
+  }
+  if ((int64_t)tcount != L.T)
+    return fail(PH0_EDEVICE, "H1 triangle count %u != %lld", tcount, (long long)L.T);
+  tm.mark();
+  uint64_t* packed = static_cast<uint64_t*>(at(L.packed));
+  HIPCHK(launch_h1_bars(A, packed, s));
+  HIPCHK(hipMemcpyAsync(&hc, A.ctl, sizeof(hc), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hc.stored != L.E - n + 1)
+    return fail(PH0_EDEVICE, "H1 reduction stored %lld pivots, expected E - n + 1 = %lld",
+                (long long)hc.stored, (long long)(L.E - n + 1));
+  const int64_t m = hc.nbars;
+  // Canonical order: (birth, death) ascending, by LSD passes over the
+  // packed birth << 20 | death (grades are below 2^20 for n <= 512).
+  uint64_t* src = packed;
+  uint64_t* dst = static_cast<uint64_t*>(at(L.sorted));
+  if (m > 1) {
+    for (int sh = 0; sh < 40; sh += 8) {
+      HIPCHK(launch_radix_pass(src, dst, m, sh, 8, static_cast<uint32_t*>(at(L.rcounts)),
+                               static_cast<int32_t*>(at(L.rerr)), s));
+      std::swap(src, dst);
+    }
+  }
+  HIPCHK(launch_h1_bars_out(src, m, reinterpret_cast<uint32_t*>(d_bars), s));
+  if (d_tri_of_edge) HIPCHK(launch_h1_owner_out(A.owner, L.E, d_tri_of_edge, s));
+  tm.mark();
+  HIPCHK(hipStreamSynchronize(s));
+  *n_bars = m;
+  if (st) {
+    S.rounds = rounds;
+    S.pivots = hc.stored;
+    S.emergent = hc.stored - hc.pivots;
+    S.bars = m;
+    S.zero_length = hc.stored - m;
+    S.additions = hc.additions;
+    S.walks = hc.walks;
+    S.ms_setup = tm.ms(0, 1);
+    S.ms_reduce = tm.ms(1, 2);
+    S.ms_total = tm.ms(0, 3);
     *st = S;
   }
   return PH0_OK;

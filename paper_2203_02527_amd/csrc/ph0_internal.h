@@ -185,4 +185,50 @@ struct BatchArgs {
 size_t batched_shared_bytes();
 hipError_t launch_batched(const BatchArgs& a, int blocks, hipStream_t s);
 
+// H1: reduction of the edge-by-triangle boundary matrix (h1.hip).
+constexpr int64_t kH1MaxN = 512;  // dense stored columns: E x ceil(E/64) words
+struct H1Ctl {
+  int64_t round;        // rounds completed
+  int64_t T;            // triangles, n(n-1)(n-2)/6
+  int64_t nsurv;        // entries of the survivor array (set by the first round)
+  int64_t live;         // survivors whose column is not final yet
+  int64_t ncommit;      // survivors picked to commit this round
+  int64_t nwalk;        // survivors that walk again this round
+  int64_t pivots;       // columns committed by the rounds (emergent pairs excluded)
+  int64_t additions;    // column additions of final walks
+  int64_t walks;        // column walks, counting repeats
+  int64_t stored;       // rows taken at the end (all pivots)
+  int64_t nbars;        // pairs of positive length
+  uint64_t firstdup;    // first live survivor that is not the smallest on its row
+  int32_t err;          // bit 0: a repeated walk ended elsewhere; bit 1: corrupt table
+  int32_t pad;
+};
+struct H1Args {
+  const uint64_t* keys;  // E sorted H0 keys
+  int ib;
+  int64_t n, E, T, LWE;
+  int32_t* inv;          // E: colex edge id -> sorted position
+  uint32_t* grade;       // E: grade of each sorted position
+  uint32_t* cnt;         // E: triangles whose latest edge is q
+  uint32_t* start;       // E + 1: exclusive scan of cnt
+  uint32_t* scan_tmp;    // scan_totals_len(E + 1) words
+  uint64_t* tri;         // T: (latest edge q << 32) | third vertex, in triangle order
+  int32_t* owner;        // E: triangle stored in row q, -1 = free
+  uint64_t* lowc;        // E: smallest live survivor per row
+  uint64_t* table;       // E x LWE words
+  uint64_t* surv;        // T: survivor array, (t << 32) | low, low = ~0 once final
+  uint64_t* clist;       // E: survivors committing this round
+  uint32_t* wlist;       // T: survivors walking again this round (indices into surv)
+  int64_t nsurv_host;    // entries of surv (for the grid sizes)
+  int cus;
+  H1Ctl* ctl;
+};
+int h1_words_per_lane(int64_t LWE);
+hipError_t launch_h1_setup(const H1Args& a, hipStream_t s);
+// The first round walks every triangle; later rounds commit and walk again.
+hipError_t launch_h1_round(const H1Args& a, bool first, hipStream_t s);
+hipError_t launch_h1_bars(const H1Args& a, uint64_t* packed, hipStream_t s);
+hipError_t launch_h1_bars_out(const uint64_t* sorted, int64_t m, uint32_t* bars, hipStream_t s);
+hipError_t launch_h1_owner_out(const int32_t* owner, int64_t E, int64_t* out, hipStream_t s);
+
 }  // namespace ph0

@@ -66,6 +66,27 @@ class ph0_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ph0_h1_stats(ctypes.Structure):
+    _fields_ = [
+        ("E", ctypes.c_int64),
+        ("T", ctypes.c_int64),
+        ("pivots", ctypes.c_int64),
+        ("emergent", ctypes.c_int64),
+        ("bars", ctypes.c_int64),
+        ("zero_length", ctypes.c_int64),
+        ("additions", ctypes.c_int64),
+        ("rounds", ctypes.c_int64),
+        ("walks", ctypes.c_int64),
+        ("ms_setup", ctypes.c_float),
+        ("ms_reduce", ctypes.c_float),
+        ("ms_total", ctypes.c_float),
+        ("reserved", ctypes.c_int32),
+    ]
+
+    def to_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -95,6 +116,9 @@ _SIGS = {
     "ph0_server_destroy": ([_P], None),
     "ph0_keys_device": ([_P, ctypes.c_int, _I64, _I32, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "ph0_sorted_keys_device": ([_P, ctypes.c_int, _I64, _I32, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "ph0_h1_workspace_bytes": ([_I64, _I32, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "ph0_h1_device": ([_P, ctypes.c_int, _I64, _I32, _P, _P, ctypes.POINTER(_I64), _P, ctypes.c_size_t,
+                       _P, ctypes.POINTER(ph0_h1_stats)], ctypes.c_int),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -219,6 +243,36 @@ def ph0_barcodes_device(points, out=None, workspace=None, stream=None, with_stat
                                      _ptr(workspace), workspace.numel(), _stream_ptr(stream),
                                      ctypes.byref(st)))
     return (out, st.to_dict()) if with_stats else out
+
+
+def ph0_h1_workspace_bytes(n: int, d: int, dtype) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().ph0_h1_workspace_bytes(n, d, _dtype_code(dtype), ctypes.byref(b)))
+    return b.value
+
+
+def ph0_h1_device(points, workspace=None, stream=None, with_stats=False):
+    """H1 barcode (see include/ph0.h).  Returns (bars, tri_of_edge): an
+    m x 2 int32 tensor of (birth, death) grades sorted by (birth, death), and
+    an int64 tensor of E entries (the triangle paired with each sorted edge
+    position, -1 if none); with_stats adds the statistics dict."""
+    torch = _torch()
+    x = _points_dev(points)
+    n, d = x.shape
+    E = n * (n - 1) // 2
+    cap = max(E - n + 1, 1)
+    bars = torch.empty((cap, 2), dtype=torch.int32, device=x.device)
+    toe = torch.empty(max(E, 1), dtype=torch.int64, device=x.device)
+    if workspace is None:
+        workspace = torch.empty(ph0_h1_workspace_bytes(n, d, x.dtype), dtype=torch.uint8,
+                                device=x.device)
+    m = _I64(0)
+    st = ph0_h1_stats()
+    _check(lib().ph0_h1_device(_ptr(x), _dtype_code(x.dtype), n, d, _ptr(bars), _ptr(toe),
+                               ctypes.byref(m), _ptr(workspace), workspace.numel(),
+                               _stream_ptr(stream), ctypes.byref(st)))
+    out = (bars[: m.value], toe[:E])
+    return (*out, st.to_dict()) if with_stats else out
 
 
 @dataclass

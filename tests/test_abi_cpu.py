@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     txt = open(os.path.join(ROOT, "include", "ph0.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(ph0_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(ph0_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -77,3 +77,17 @@ def test_tuning_table_loader(tmp_path):
             autotune.load(str(p))
     if os.path.exists(autotune.TABLE):  # the committed table must load
         assert autotune.load() is not None
+
+
+def test_h1_workspace_bytes_and_size_limit():
+    n = 256
+    E, T = n * (n - 1) // 2, n * (n - 1) * (n - 2) // 6
+    ws = ph0.ph0_h1_workspace_bytes(n, 3, np.int16)
+    assert ws >= 8 * E * ((E + 63) // 64) + 20 * T  # dense stored columns + triangle lists
+    assert ph0.ph0_h1_workspace_bytes(3, 2, np.int8) > 0
+    with pytest.raises(ph0.Ph0Error) as ei:
+        ph0.ph0_h1_workspace_bytes(513, 3, np.int16)
+    assert ei.value.code == -2
+    with pytest.raises(ph0.Ph0Error) as ei:
+        ph0.ph0_h1_workspace_bytes(0, 3, np.int16)
+    assert ei.value.code == -1

@@ -1,0 +1,109 @@
+"""GPU parity of the H1 path (edge-by-triangle boundary matrix) against the
+CPU oracle, through the C ABI: the bars, the edge-to-triangle pairing and the
+number of column additions must be identical (all integer, tolerance 0).
+The GPU reduces every column, so additions are compared with the oracle's
+literal mode (no stop at the last pair)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_02527_amd import ph0, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    assert t.cuda.is_available(), "GPU tests need a HIP device"
+    ph0.lib()
+    return t
+
+
+def _run(torch, x):
+    print("h1 case n=%d d=%d %s" % (x.shape[0], x.shape[1], x.dtype), flush=True)
+    xd = torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+    bars, toe, st = ph0.ph0_h1_device(xd, with_stats=True)
+    torch.cuda.synchronize()
+    return bars.cpu().numpy().view(np.uint32).reshape(-1, 2), toe.cpu().numpy(), st
+
+
+def _check(torch, x):
+    got, toe, st = _run(torch, x)
+    ref = oracle.h1_barcode(x, early_exit=False)
+    np.testing.assert_array_equal(got, ref.bars)
+    np.testing.assert_array_equal(toe, ref.tri_of_edge)
+    n = x.shape[0]
+    assert st["pivots"] == n * (n - 1) // 2 - n + 1 == ref.pivots
+    assert st["bars"] == ref.bars.shape[0] and st["zero_length"] == ref.zero_length
+    assert st["additions"] == ref.additions
+    return st
+
+
+def _rand(seed, n, d, lo, hi, dtype):
+    return np.random.default_rng(seed).integers(lo, hi + 1, size=(n, d)).astype(dtype)
+
+
+@pytest.mark.parametrize("n,d,lo,hi,dtype", [
+    (3, 2, -100, 100, np.int16),
+    (7, 1, -3, 3, np.int8),      # collinear with ties
+    (20, 2, 0, 2, np.int8),      # heavy ties
+    (33, 3, -100, 100, np.int16),
+    (64, 3, -100, 100, np.int16),
+    (65, 4, -10, 10, np.int8),   # a ragged word of the dense columns
+    (100, 16, -127, 127, np.int8),
+])
+def test_h1_random_clouds(torch, n, d, lo, hi, dtype):
+    _check(torch, _rand(n, n, d, lo, hi, dtype))
+
+
+def test_h1_square_and_trivial_sizes(torch):
+    sq = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], np.int8)
+    got, toe, st = _run(torch, sq)
+    np.testing.assert_array_equal(got, [[1, 2]])
+    for n in (1, 2):
+        got, toe, st = _run(torch, np.zeros((n, 3), np.int16))
+        assert got.shape == (0, 2) and (toe == -1).all()
+
+
+def test_h1_workload_shapes(torch):
+    # Circle and mixture clouds of the batch and serving workloads, and the
+    # paper's unit square, at sizes the oracle finishes in seconds; more than
+    # 64 words per dense column (two and four slots per lane).
+    rng = np.random.default_rng(5)
+    st = _check(torch, synth.circle_cloud(rng, 120))
+    assert st["bars"] >= 1  # the circle's long cycle
+    _check(torch, synth.mixture_cloud(128, 16, 3, 10.0, seed=9))
+    _check(torch, synth.unit_square_cloud(150, seed=3))
+
+
+def test_h1_repeated_calls_are_identical(torch):
+    x = synth.uniform_cloud(90, 3, seed=12)
+    a = _run(torch, x)
+    b = _run(torch, x)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_h1_statistics_count_emergent_and_committed_pairs(torch):
+    # Every pair is either emergent (the first triangle of an edge, whose
+    # latest edge that is, stored unreduced) or committed by a round.  The
+    # emergent ones are exactly the edges that are the latest edge of some
+    # triangle, counted here from the sorted edge list.
+    n = 80
+    x = synth.uniform_cloud(n, 3, seed=4)
+    got, toe, st = _run(torch, x)
+    se = oracle.sorted_edges(x)
+    pos = np.full((n, n), -1, np.int64)
+    pos[se.i, se.j] = pos[se.j, se.i] = np.arange(se.delta.size)
+    emergent = 0
+    for q in range(se.delta.size):
+        i, j = se.i[q], se.j[q]
+        others = np.array([k for k in range(n) if k != i and k != j])
+        emergent += bool(((pos[i, others] < q) & (pos[j, others] < q)).any())
+    E = n * (n - 1) // 2
+    assert st["pivots"] == E - n + 1
+    assert st["emergent"] == emergent
+    assert st["bars"] + st["zero_length"] == st["pivots"]
+    assert st["walks"] >= st["T"] - st["emergent"]
