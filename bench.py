@@ -10,7 +10,13 @@ canonical barcode in HBM, through ph0_barcodes_device.
 value = E_eff / step time: sorted edge columns up to the last pivot, i.e. the
 columns the reduction actually processes (the remaining E - E_eff columns are
 zero by the early-exit argument and cost nothing), per second of the whole
-step.  One JSON line is printed.
+step.  One JSON line is printed; beside the headline figures it carries the
+batched launch over 10,000 small clouds, the serving stream, the H1 barcode
+of a 256-point cloud, and the single-threaded CPU oracle.
+
+Other modes: --paper-scaling (the paper's unit-square run-time experiment),
+--cpu-openmp (the paper's multi-core CPU scheme), --calibrate-copy (a copy
+of known size for the hardware byte counters).
 """
 from __future__ import annotations
 
@@ -43,6 +49,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-h1", action="store_true")
+    ap.add_argument("--h1-only", action="store_true",
+                    help="only run the H1 leg (no CPU oracle) and print its JSON")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--paper-scaling", action="store_true",
                     help="only run the paper's experiment: N uniform points in [0,1]^2 (on a "
@@ -243,6 +252,63 @@ def bench_batched(torch, ph0, synth, reps=3):
     }
 
 
+H1_N = 256
+H1_CPU_N = 128
+
+
+def bench_h1(torch, ph0, synth, with_cpu, reps=5):
+    """H1 (edge-by-triangle boundary matrix) of the uniform N=256, d=3 int16
+    cloud: whole calls from HBM-resident points, the oracle beside it on a
+    128-point cloud of the same recipe, and the dense-column rate: each
+    column addition of the dense method moves one E-bit column (the kernel
+    reads only the part of it at or below the stored column's low)."""
+    x = synth.uniform_cloud(H1_N, 3, seed=0)
+    xd = torch.from_numpy(x).to("cuda:0")
+    ws = torch.empty(ph0.ph0_h1_workspace_bytes(H1_N, 3, x.dtype), dtype=torch.uint8,
+                     device="cuda:0")
+    ph0.ph0_h1_device(xd, workspace=ws)
+    torch.cuda.synchronize()
+    sts = []
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, _, st = ph0.ph0_h1_device(xd, workspace=ws, with_stats=True)
+        sts.append(st)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    st = sts[-1]
+    E = H1_N * (H1_N - 1) // 2
+    dense_bytes = 8.0 * ((E + 63) // 64) * st["additions"]
+    rec = {
+        "workload": "uniform_n256_d3_i16 (integers in [-100, 100]^3, seed 0)",
+        "ms_per_call": round(1000 * t, 3),
+        "triangles": st["T"],
+        "triangles_per_s": st["T"] / t,
+        "additions_per_s": st["additions"] / t,
+        "pairs": st["pivots"], "emergent": st["emergent"], "bars": st["bars"],
+        "rounds": st["rounds"], "walks": st["walks"],
+        "dense_column_gbs": round(dense_bytes / t / 1e9, 1),
+        "dense_column_frac_of_hbm": round(dense_bytes / t / 1e9 / HBM_PEAK_GBS, 4),
+    }
+    if with_cpu:
+        import oracle
+
+        xs = synth.uniform_cloud(H1_CPU_N, 3, seed=0)
+        t0 = time.perf_counter()
+        ref = oracle.h1_barcode(xs)
+        tc = time.perf_counter() - t0
+        got, _ = ph0.ph0_h1_device(torch.from_numpy(xs).to("cuda:0"))
+        torch.cuda.synchronize()
+        import numpy as np
+
+        rec["cpu_oracle"] = {
+            "sample": "uniform N=%d, d=3 int16, seed 0: %d triangles" % (H1_CPU_N, ref.T),
+            "seconds": round(tc, 3), "cores": 1,
+            "triangles_per_s": ref.T / tc,
+            "gpu_matches": bool(np.array_equal(got.cpu().numpy().view(np.uint32), ref.bars)),
+        }
+    return rec
+
+
 def bench_serving(ph0, synth, count):
     """Mixed request stream: closed-loop saturation, then Poisson at 0.8x."""
     from paper_2203_02527_amd import serve
@@ -341,6 +407,10 @@ def main():
         ph0.ph0_set_window(args.window)
     if args.lanes:
         ph0.ph0_set_walk_lanes(args.lanes)
+    if args.h1_only:
+        print(json.dumps({"mode": "h1", **bench_h1(torch, ph0, synth, False,
+                                                  reps=max(args.steps, 1))}), flush=True)
+        return
     pts = synth.workload(args.workload, seed=args.seed)
     n, d = pts.shape
     dev = torch.device("cuda:0")
@@ -462,6 +532,9 @@ def main():
     if not args.no_serving:
         rec["serving"] = bench_serving(ph0, synth, args.serve_requests)
         note("serving done")
+    if not args.no_h1:
+        rec["h1"] = bench_h1(torch, ph0, synth, not args.no_cpu_baseline)
+        note("h1 done")
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(pts, n)
         note("cpu baseline done")
