@@ -45,7 +45,6 @@ def parse():
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--window", type=int, default=0, help="reduction window (0 = built-in)")
-    ap.add_argument("--lanes", type=int, default=0, help="walk lanes per column (0 = built-in)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -405,8 +404,6 @@ def main():
         __graft_entry__.build()
     if args.window:
         ph0.ph0_set_window(args.window)
-    if args.lanes:
-        ph0.ph0_set_walk_lanes(args.lanes)
     if args.h1_only:
         print(json.dumps({"mode": "h1", **bench_h1(torch, ph0, synth, False,
                                                   reps=max(args.steps, 1))}), flush=True)
@@ -448,14 +445,14 @@ def main():
     # Walk: the algorithmic bytes are those of the dense method -- one N-bit
     # pivot column (LW 64-bit words) per column addition of the sequential
     # reduction, plus the 8-byte key of each column up to the last pivot.
-    # The kernel itself loads only the words of a stored column at or below
-    # its low (a stored column has no bits above it), which it reports as
-    # words_read; both rates are given.
+    # The kernel holds each stored column as its other row (a 2-sparse
+    # column is fixed by it) and loads one 4-byte entry per step, which it
+    # reports as words_read; both rates are given.
     LW = (n + 63) // 64
     walk_ms = mean("ms_walk_kernel")
     walk_launches = mean("walk_launches")
     walk_bytes = 8.0 * LW * mean("additions") + 8.0 * mean("E_eff")
-    walk_loaded = 8.0 * mean("words_read")
+    walk_loaded = 4.0 * mean("words_read")
     radix_ms = mean("ms_radix_kernel")
     radix_launches = mean("radix_launches")
     radix_bytes = mean("radix_bytes")

@@ -69,7 +69,7 @@ typedef struct {
   int64_t additions;     /* column additions of columns < E_eff (the sequential count) */
   int64_t additions_all; /* column additions performed, incl. columns >= E_eff */
   int64_t find_steps;    /* root look-ups made by the parallel commit rule */
-  int64_t words_read;    /* 64-bit pivot-table words loaded by the reduction */
+  int64_t words_read;    /* pivot-table entries (4 bytes each) loaded by the reduction */
   int64_t rounds;        /* reduction rounds (walk, decide, commit) */
   int64_t window;        /* columns reduced side by side in one round */
   int32_t sort_passes;   /* LSD radix passes over the distance bits */
@@ -251,11 +251,6 @@ int ph0_h1_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, ph0_
  * E.  Affects speed only, never results.  Process-wide. */
 int ph0_set_window(int64_t columns);
 
-/* Lanes of a wavefront that reduce one column together (a power of two up to
- * 64; 0 restores the built-in choice, the fewest lanes that cover a pivot
- * row, at most 64).  Fewer lanes put more columns in flight per wavefront.
- * Affects speed only, never results.  Process-wide. */
-int ph0_set_walk_lanes(int32_t lanes);
 
 #ifdef __cplusplus
 }

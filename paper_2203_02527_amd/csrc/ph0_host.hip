@@ -28,7 +28,6 @@ namespace {
 
 thread_local char g_err[512] = "";
 std::atomic<int64_t> g_window{0};
-std::atomic<int32_t> g_walk_lanes{0};
 
 int fail(int code, const char* fmt, ...) {
   va_list ap;
@@ -73,8 +72,8 @@ int64_t window_for(int64_t n, int64_t E) {
 }
 
 struct Layout {
-  int64_t n, E, LW, Wcap, tiles;
-  size_t keysA, keysB, counts, hist, err, table, killer, lowc, touch, act0, act1, rtag, ra, rr, rrlo,
+  int64_t n, E, Wcap, tiles;
+  size_t keysA, keysB, counts, hist, err, part, killer, lowc, touch, act0, act1, rtag, ra, rr, rrlo,
       rst, ctl, dbv, minmax, kcnt, kcnt_tot, norms, total;
 };
 
@@ -82,7 +81,6 @@ Layout make_layout(int64_t n, int32_t d) {
   Layout L;
   L.n = n;
   L.E = n * (n - 1) / 2;
-  L.LW = (n + 63) / 64;
   L.Wcap = window_for(n, L.E);
   const int64_t keys = std::max<int64_t>(L.E, 2 * n + 64);  // room for the bar sort too
   L.tiles = radix_tiles(keys);
@@ -97,7 +95,7 @@ Layout make_layout(int64_t n, int32_t d) {
   L.counts = take(4 * (size_t)radix_count_entries(keys));
   L.hist = take(4 * (size_t)kHistBins);
   L.err = take(4);
-  L.table = take(8 * (size_t)(n * L.LW));
+  L.part = take(4 * (size_t)n);
   L.killer = take(8 * (size_t)n);
   L.lowc = take(8 * (size_t)n);
   L.touch = take(8 * (size_t)n);
@@ -487,12 +485,10 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   ra.ib = ib;
   ra.n = n;
   ra.E = L.E;
-  ra.LW = L.LW;
   ra.Wcap = L.Wcap;
-  ra.lanes = g_walk_lanes.load();
   ra.act[0] = static_cast<int64_t*>(at(L.act0));
   ra.act[1] = static_cast<int64_t*>(at(L.act1));
-  ra.table = static_cast<uint64_t*>(at(L.table));
+  ra.part = static_cast<int32_t*>(at(L.part));
   ra.killer = static_cast<int64_t*>(at(L.killer));
   ra.lowc = static_cast<uint64_t*>(at(L.lowc));
   ra.touch = static_cast<uint64_t*>(at(L.touch));
@@ -599,7 +595,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
                                 reinterpret_cast<uint32_t*>(out.bars), s, &distinct, &npiv));
   tm.mark();  // 5
   if (out.killer_pos || out.killer_edge || out.killer_sqdist || out.partner)
-    HIPCHK(launch_pairs_detail(ra.killer, skeys, ib, ra.table, L.LW, n, out.killer_pos,
+    HIPCHK(launch_pairs_detail(ra.killer, skeys, ib, ra.part, n, out.killer_pos,
                                out.killer_edge, out.killer_sqdist, out.partner, s));
   tm.mark();  // 6
   HIPCHK(hipMemcpyAsync(&herr, serr, 4, hipMemcpyDeviceToHost, s));
@@ -789,13 +785,6 @@ int ph0_key_layout(int64_t n, int32_t d, ph0_dtype dt, int32_t* ibits, int32_t* 
 int ph0_set_window(int64_t columns) {
   if (columns < 0) return fail(PH0_EINVAL, "window must be >= 0");
   g_window.store(columns);
-  return PH0_OK;
-}
-
-int ph0_set_walk_lanes(int32_t lanes) {
-  if (lanes < 0 || lanes > 64 || (lanes & (lanes - 1)))
-    return fail(PH0_EINVAL, "lanes must be 0 or a power of two <= 64");
-  g_walk_lanes.store(lanes);
   return PH0_OK;
 }
 

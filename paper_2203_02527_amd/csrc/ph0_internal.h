@@ -126,9 +126,8 @@ hipError_t launch_radix_pass(const uint64_t* in, uint64_t* out, int64_t count, i
 struct RedArgs {
   const uint64_t* skeys;
   int ib;
-  int64_t n, E, LW, Wcap;
-  int lanes;     // lanes per column in the walk (0 = built-in choice)
-  uint64_t* table;
+  int64_t n, E, Wcap;
+  int32_t* part;  // n: other row of the column stored with low r, -1 = free
   int64_t* killer;
   uint64_t* lowc;
   uint64_t* touch;
@@ -158,7 +157,7 @@ hipError_t launch_grades_and_bars(const uint64_t* skeys, int64_t E_eff, int shif
                                   uint32_t* bars, hipStream_t s, uint32_t* distinct,
                                   uint32_t* pivots);
 hipError_t launch_pairs_detail(const int64_t* killer, const uint64_t* skeys, int ib,
-                               const uint64_t* table, int64_t LW, int64_t n,
+                               const int32_t* part, int64_t n,
                                int64_t* killer_pos, uint64_t* killer_edge,
                                int64_t* killer_sqdist, int32_t* partner, hipStream_t s);
 

@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kGroup) void k_grade_emit(const uint64_t* __restric
 
 __global__ void k_pairs_detail(const int64_t* __restrict__ killer,
                                const uint64_t* __restrict__ skeys, int ib,
-                               const uint64_t* __restrict__ table, int64_t LW, int64_t n,
+                               const int32_t* __restrict__ part, int64_t n,
                                int64_t* killer_pos, uint64_t* killer_edge,
                                int64_t* killer_sqdist, int32_t* partner) {
   const uint64_t imask = (1ull << ib) - 1ull;
@@ -141,11 +141,7 @@ __global__ void k_pairs_detail(const int64_t* __restrict__ killer,
       pos = p;
       sq = (int64_t)(key >> (2 * ib));
       edge = (((key >> ib) & imask) << 32) | (key & imask);
-      const uint64_t* row = table + r * LW;  // holds the stored column's other bit
-      for (int64_t w = r >> 6; w >= 0 && other < 0; --w) {
-        const uint64_t x = row[w];
-        if (x) other = (int32_t)(w * 64 + 63 - __clzll(x));
-      }
+      other = part[r];  // the stored column's other row
     }
     if (killer_pos) killer_pos[r] = pos;
     if (killer_edge) killer_edge[r] = edge;
@@ -197,11 +193,11 @@ hipError_t launch_grades_and_bars(const uint64_t* skeys, int64_t E_eff, int shif
 }
 
 hipError_t launch_pairs_detail(const int64_t* killer, const uint64_t* skeys, int ib,
-                               const uint64_t* table, int64_t LW, int64_t n,
+                               const int32_t* part, int64_t n,
                                int64_t* killer_pos, uint64_t* killer_edge,
                                int64_t* killer_sqdist, int32_t* partner, hipStream_t s) {
   hipLaunchKernelGGL(k_pairs_detail, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, killer,
-                     skeys, ib, table, LW, n, killer_pos, killer_edge, killer_sqdist, partner);
+                     skeys, ib, part, n, killer_pos, killer_edge, killer_sqdist, partner);
   return hipGetLastError();
 }
 

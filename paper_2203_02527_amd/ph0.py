@@ -97,7 +97,6 @@ _SIGS = {
     "ph0_workspace_bytes": ([_I64, _I32, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "ph0_key_layout": ([_I64, _I32, ctypes.c_int, ctypes.POINTER(_I32), ctypes.POINTER(_I32)], ctypes.c_int),
     "ph0_set_window": ([_I64], ctypes.c_int),
-    "ph0_set_walk_lanes": ([_I32], ctypes.c_int),
     "ph0_barcodes": ([_P, ctypes.c_int, _I64, _I32, _P, ctypes.POINTER(ph0_stats)], ctypes.c_int),
     "ph0_barcodes_device": ([_P, ctypes.c_int, _I64, _I32, _P, _P, ctypes.c_size_t, _P,
                              ctypes.POINTER(ph0_stats)], ctypes.c_int),
@@ -174,10 +173,6 @@ def ph0_key_layout(n: int, d: int, dtype) -> tuple[int, int, int]:
 
 def ph0_set_window(columns: int) -> None:
     _check(lib().ph0_set_window(columns))
-
-
-def ph0_set_walk_lanes(lanes: int) -> None:
-    _check(lib().ph0_set_walk_lanes(lanes))
 
 
 def ph0_barcodes(points: np.ndarray, with_stats: bool = False):

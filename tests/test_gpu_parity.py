@@ -160,17 +160,16 @@ def test_windows_give_identical_results(torch):
         ph0.ph0_set_window(0)
 
 
-def test_walk_lane_shapes_give_identical_results(torch):
+def test_pairs_detail_at_n3000_int8_gram(torch):
+    # Partners (the stored columns), per-vertex deaths and the addition count
+    # on the int8 Gram path, several windows' worth of rounds.
     x = synth.mixture_cloud(3000, 16, 8, 10.0, seed=6)
     ref = oracle.barcode(x)
-    try:
-        for lanes in (0, 64, 32, 16, 8):
-            ph0.ph0_set_walk_lanes(lanes)
-            pr = ph0.ph0_pairs_device(_dev(torch, x))
-            np.testing.assert_array_equal(pr.partner.cpu().numpy(), ref.partner)
-            assert pr.stats["additions"] == ref.additions
-    finally:
-        ph0.ph0_set_walk_lanes(0)
+    pr = ph0.ph0_pairs_device(_dev(torch, x))
+    np.testing.assert_array_equal(pr.partner.cpu().numpy(), ref.partner)
+    np.testing.assert_array_equal(pr.death_by_vertex.cpu().numpy().view(np.uint32),
+                                  ref.death_by_vertex)
+    assert pr.stats["additions"] == ref.additions
 
 
 def test_repeat_runs_are_bit_identical(torch):
