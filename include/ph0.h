@@ -246,9 +246,12 @@ int ph0_h1_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, ph0_
                   int64_t* d_tri_of_edge, int64_t* n_bars, void* d_workspace, size_t ws_bytes,
                   void* hip_stream, ph0_h1_stats* st);
 
-/* Reduction window (columns reduced side by side per round, rounded up to a
- * power of two); 0 restores the built-in choice, max(65536, 16 n) capped at
- * E.  Affects speed only, never results.  Process-wide. */
+/* Base reduction window (columns reduced side by side per round, rounded up
+ * to a power of two); 0 restores the built-in choice, max(65536, 16 n) capped
+ * at E.  A round widens the window up to 4 times the base while almost every
+ * column of the previous round became final, and narrows it back when many
+ * stay.  Affects speed and workspace size only, never results.
+ * Process-wide. */
 int ph0_set_window(int64_t columns);
 
 

@@ -60,8 +60,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 int index_bits(int64_t n) { return n <= 1 ? 0 : 64 - __builtin_clzll((uint64_t)(n - 1)); }
 
-// Columns in flight per reduction round; a power of two (the per-column
-// state is a ring indexed by column & (window - 1)).
+// Base number of columns in flight per reduction round; a power of two.
 int64_t window_for(int64_t n, int64_t E) {
   int64_t w = g_window.load();
   if (w <= 0) w = std::max<int64_t>(65536, 16 * n);
@@ -71,8 +70,21 @@ int64_t window_for(int64_t n, int64_t E) {
   return p;
 }
 
+// The window grows up to this many times its base width while rounds leave
+// almost nothing active.
+constexpr int64_t kWindowGrowth = 4;
+
+// Capacity of the per-column ring (indexed by column & (capacity - 1)): the
+// largest window, a power of two.
+int64_t ring_for(int64_t n, int64_t E) {
+  const int64_t w = window_for(n, E);
+  int64_t p = 1;
+  while (p < std::max<int64_t>(E, 1)) p <<= 1;
+  return std::min<int64_t>(kWindowGrowth * w, std::max<int64_t>(p, w));
+}
+
 struct Layout {
-  int64_t n, E, Wcap, tiles;
+  int64_t n, E, Wcap, width, tiles;
   size_t keysA, keysB, counts, hist, err, part, killer, lowc, touch, act0, act1, rtag, ra, rr, rrlo,
       rst, ctl, dbv, minmax, kcnt, kcnt_tot, norms, total;
 };
@@ -81,7 +93,8 @@ Layout make_layout(int64_t n, int32_t d) {
   Layout L;
   L.n = n;
   L.E = n * (n - 1) / 2;
-  L.Wcap = window_for(n, L.E);
+  L.width = window_for(n, L.E);
+  L.Wcap = ring_for(n, L.E);
   const int64_t keys = std::max<int64_t>(L.E, 2 * n + 64);  // room for the bar sort too
   L.tiles = radix_tiles(keys);
   size_t o = 0;
@@ -261,7 +274,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   S.n = n;
   S.E = L.E;
   S.index_bits = ib;
-  S.window = L.Wcap;
+  S.window = L.width;
 
   if (n == 1) {
     if (stop != kStopAll) return PH0_OK;
@@ -486,6 +499,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   ra.n = n;
   ra.E = L.E;
   ra.Wcap = L.Wcap;
+  ra.width = L.width;
   ra.act[0] = static_cast<int64_t*>(at(L.act0));
   ra.act[1] = static_cast<int64_t*>(at(L.act1));
   ra.part = static_cast<int32_t*>(at(L.part));

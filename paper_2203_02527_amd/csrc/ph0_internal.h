@@ -25,6 +25,8 @@ struct SortPlan {
 struct RedCtl {
   int64_t F;         // first column that is not final
   int64_t Wend;      // end of the window [F, Wend); Wend - F <= Wcap
+  int64_t width;     // current window width (width_min .. Wcap)
+  int64_t width_min; // base width
   int64_t maxWend;   // largest Wend ever used
   int64_t fresh_lo;  // columns entering this round
   int64_t fresh_hi;
@@ -126,7 +128,8 @@ hipError_t launch_radix_pass(const uint64_t* in, uint64_t* out, int64_t count, i
 struct RedArgs {
   const uint64_t* skeys;
   int ib;
-  int64_t n, E, Wcap;
+  int64_t n, E, Wcap;  // Wcap: ring capacity, a power of two
+  int64_t width;       // base window width (<= Wcap)
   int32_t* part;  // n: other row of the column stored with low r, -1 = free
   int64_t* killer;
   uint64_t* lowc;

@@ -282,7 +282,19 @@ __device__ void advance_round(RedCtl* ctl_, int64_t n, int64_t E, int64_t Wcap) 
     if (F >= ctl->E_eff) ctl->done = 1;
   } else {
     const int64_t lim = ctl->E_lim;
-    Wend = F + Wcap < lim ? F + Wcap : lim;
+    // Window width: doubles (up to the ring's capacity) while almost every
+    // column of a round becomes final, halves (down to the base width) when
+    // many stay.  The end never moves back: columns already in the window
+    // stay there.
+    int64_t width = ctl->width;
+    const int64_t stay = ctl->nA_next;
+    if (stay < width / 256)
+      width = 2 * width < Wcap ? 2 * width : Wcap;
+    else if (stay > width / 16)
+      width = width / 2 > ctl->width_min ? width / 2 : ctl->width_min;
+    ctl->width = width;
+    const int64_t want = F + width < lim ? F + width : lim;
+    Wend = want > Wend ? want : Wend;
     if (F >= lim) {
       if (lim < E) {
         ctl->need_more = 1;  // the host sorts the next distance range
@@ -376,23 +388,26 @@ __global__ void k_advance(RedCtl* ctl, int64_t n, int64_t E, int64_t Wcap) {
   advance_round(ctl, n, E, Wcap);
 }
 
-__global__ void k_reduce_extend(RedCtl* ctl, int64_t E_lim, int64_t Wcap) {
+__global__ void k_reduce_extend(RedCtl* ctl, int64_t E_lim) {
   // All columns before the old limit are final here (F == old limit).
   ctl->E_lim = E_lim;
   ctl->need_more = 0;
   const int64_t F = ctl->F;
-  const int64_t Wend = F + Wcap < E_lim ? F + Wcap : E_lim;
+  const int64_t width = ctl->width;
+  const int64_t Wend = F + width < E_lim ? F + width : E_lim;
   ctl->fresh_lo = ctl->Wend;
   ctl->fresh_hi = Wend;
   ctl->Wend = Wend;
   if (Wend > ctl->maxWend) ctl->maxWend = Wend;
 }
 
-__global__ void k_reduce_init(RedCtl* ctl, int64_t E_lim, int64_t Wcap, int64_t n) {
+__global__ void k_reduce_init(RedCtl* ctl, int64_t E_lim, int64_t width, int64_t n) {
   RedCtl c = {};
   c.F = 0;
   c.E_lim = E_lim;
-  c.Wend = Wcap < E_lim ? Wcap : E_lim;
+  c.width = width;
+  c.width_min = width;
+  c.Wend = width < E_lim ? width : E_lim;
   c.maxWend = c.Wend;
   c.fresh_lo = 0;
   c.fresh_hi = c.Wend;
@@ -451,7 +466,7 @@ int walk_blocks(int64_t Wcap) {
 }  // namespace
 
 hipError_t launch_reduce_extend(const RedArgs& a, int64_t E_lim, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_extend, dim3(1), dim3(1), 0, s, a.ctl, E_lim, a.Wcap);
+  hipLaunchKernelGGL(k_reduce_extend, dim3(1), dim3(1), 0, s, a.ctl, E_lim);
   return hipGetLastError();
 }
 
@@ -467,7 +482,7 @@ hipError_t launch_reduce_init(const RedArgs& a, int64_t E_lim, hipStream_t s) {
   if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(a.ring.tag), ~0ull, a.Wcap, s)) !=
       hipSuccess)
     return e;
-  hipLaunchKernelGGL(k_reduce_init, dim3(1), dim3(1), 0, s, a.ctl, E_lim, a.Wcap, a.n);
+  hipLaunchKernelGGL(k_reduce_init, dim3(1), dim3(1), 0, s, a.ctl, E_lim, a.width, a.n);
   return hipGetLastError();
 }
 
