@@ -141,8 +141,8 @@ int ph0_key_layout(int64_t n, int32_t d, ph0_dtype dt, int32_t* index_bits,
 /* ---- Many clouds in one launch ---------------------------------------- */
 
 /* Speed-only tuning of the batched path (never changes results).  A zero
- * field takes the built-in value; the built-in values (chunk_mult 6, 6, 6,
- * 48; one workgroup per CU) are those the package's autotuner
+ * field takes the built-in value; the built-in values (chunk_mult 6, 6, 8,
+ * 48; two workgroups per CU) are those the package's autotuner
  * (paper_2203_02527_amd/autotune.py) measured best on MI355X, which writes
  * them to a table the Python binding passes by default. */
 typedef struct {

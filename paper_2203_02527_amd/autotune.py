@@ -11,8 +11,7 @@ that change speed but never results:
   out need extra chunks (another histogram-guided pass over all edges); too
   large and edges past the last pivot are written and sorted for nothing.
 * blocks_per_cu -- workgroups launched per compute unit (1 or 2; a workgroup
-  holds about 93 KB of LDS, so two fit a 160 KB CU only if the kernel's LDS
-  footprint allows it).
+  holds about 60 KB of LDS, so two fit the 160 KB of a CU).
 
 The search is coordinate-wise: for each bucket, one launch per candidate
 multiplier over a seeded sample of that bucket's clouds (the batch

@@ -3,9 +3,9 @@
 // Each 512-thread workgroup takes the next cloud from an atomic queue (the
 // host orders clouds largest first) and runs the whole barcode algorithm of
 // Section 2 for it, the five GPU steps of Section 4 fused in one workgroup:
-//   * points and the dense bit-packed pivot table live in LDS (N <= 512:
-//     at most 512 rows x 8 words; row r holds its stored column's other bit,
-//     the pivot bit r being implicit);
+//   * points and the pivot table live in LDS: every stored column is
+//     2-sparse, {x, r}, so row r keeps only x (part[r], -1 while free; at
+//     most 512 entries);
 //   * distances are recomputed from LDS as needed: a histogram of the
 //     squared distances picks chunks of whole histogram bins, lowest first;
 //     a chunk's edges are compacted in colex order into per-workgroup scratch
@@ -28,7 +28,6 @@ namespace {
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
 constexpr int kMaxN = kBatchMaxN;
-constexpr int kMaxLW = kMaxN / 64;
 constexpr int kMaxPts = kBatchMaxPts;
 constexpr int kBins = 1024;
 constexpr int kWindow = 2048;
@@ -37,7 +36,7 @@ constexpr int kActiveB = 0, kFinal = 1;
 
 struct Shared {
   int16_t pts[kMaxPts];
-  uint64_t table[kMaxN * kMaxLW];
+  int16_t part[kMaxN];
   uint32_t hist[kBins];
   uint32_t wcnt[kWaves][256];
   uint32_t digit_base[256];
@@ -144,18 +143,6 @@ __device__ void block_radix_pass(Shared& S, const uint64_t* src, uint64_t* dst, 
   }
 }
 
-template <int G>
-__device__ inline int grp_top(uint64_t w, int gbase) {
-  uint64_t m = __ballot(w != 0);
-  if constexpr (G < 64) m = (m >> gbase) & ((1ull << G) - 1ull);
-  if (m == 0) return -1;
-  const int top = 63 - __clzll(m);
-  const uint32_t lo = __shfl((uint32_t)w, gbase + top, 64);
-  const uint32_t hi = __shfl((uint32_t)(w >> 32), gbase + top, 64);
-  const uint64_t word = ((uint64_t)hi << 32) | lo;
-  return top * 64 + 63 - __clzll(word);
-}
-
 __device__ inline uint32_t benc(int round, int pos) {
   return ((uint32_t)(0x7FFF - (round & 0x7FFF)) << 17) | (uint32_t)pos;
 }
@@ -163,14 +150,9 @@ __device__ inline uint32_t benc(int round, int pos) {
 // Reduce the sorted chunk keys[0..cnt) (grades in gr) against the LDS table.
 // `round` runs on across the chunks of one cloud: the per-row minima are
 // tagged with it, so a value left by an earlier round never matches.
-template <int G>
 __device__ void reduce_chunk(Shared& S, const uint64_t* keys, const uint32_t* gr, int64_t cnt,
                              int n, int ib, int* err, int& round) {
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int gl = lane & (G - 1), gbase = lane & ~(G - 1);
-  const int gid = tid / G;
-  constexpr int kGroups = kThreads / G;
-  const int LW = (n + 63) >> 6;
+  const int tid = threadIdx.x;
   const uint64_t imask = (1ull << ib) - 1ull;
   int64_t next = 0;
   int nwin = 0;
@@ -199,19 +181,16 @@ __device__ void reduce_chunk(Shared& S, const uint64_t* keys, const uint32_t* gr
     __syncthreads();
     if (nwin == 0) break;
 
-    // Walk every window column against the table.  A column is 2-sparse,
-    // {a, r}; adding the stored column {x, r} leaves {a, x}.  Row r of the
-    // table holds the stored column's other bit x (its pivot bit r is
-    // implicit), so one group search over the row's words 0..r/64 gives x,
-    // and an empty row means slot r is free.
-    for (int s = gid; s < nwin; s += kGroups) {
+    // Walk every window column against the table, one thread per column.  A
+    // column is 2-sparse, {a, r}; adding the stored column {x, r} of row r
+    // (x = part[r]) leaves {a, x}, and a free row (part[r] < 0) stops it.
+    for (int s = tid; s < nwin; s += kThreads) {
       int a = S.wa[s], r = S.wr[s], rlo = S.wrlo[s];
       int moved = 0;
       bool zero = false;
       while (true) {
-        const uint64_t w = (gl <= (r >> 6) && gl < LW) ? S.table[r * kMaxLW + gl] : 0ull;
-        const int x = grp_top<G>(w, gbase);
-        if (x < 0) break;  // slot r is free
+        const int x = S.part[r];
+        if (x < 0) break;  // row r is free
         ++moved;
         if (x == a || x >= r) {  // zero column (or a corrupt table)
           if (x >= r) *err = 1;
@@ -223,14 +202,13 @@ __device__ void reduce_chunk(Shared& S, const uint64_t* keys, const uint32_t* gr
         a = lo;
       }
       if (zero) {
-        if (gl == 0) S.wst[s] = kFinal;
+        S.wst[s] = kFinal;
         continue;
       }
       // Root of row a in the current forest: follow stored columns down.
       int v = moved ? a : rlo;
       while (true) {
-        const uint64_t w = (gl <= (v >> 6) && gl < LW) ? S.table[v * kMaxLW + gl] : 0ull;
-        const int c = grp_top<G>(w, gbase);
+        const int c = S.part[v];
         if (c < 0) break;
         if (c >= v) {
           *err = 1;
@@ -239,14 +217,12 @@ __device__ void reduce_chunk(Shared& S, const uint64_t* keys, const uint32_t* gr
         v = c;
       }
       rlo = v;
-      if (gl == 0) {
-        S.wa[s] = (int16_t)a;
-        S.wr[s] = (int16_t)r;
-        S.wrlo[s] = (int16_t)rlo;
-        const uint32_t e = benc(round, S.wpos[s]);
-        atomicMin(&S.lowc[r], e);
-        atomicMin(&S.touch[rlo], e);
-      }
+      S.wa[s] = (int16_t)a;
+      S.wr[s] = (int16_t)r;
+      S.wrlo[s] = (int16_t)rlo;
+      const uint32_t e = benc(round, S.wpos[s]);
+      atomicMin(&S.lowc[r], e);
+      atomicMin(&S.touch[rlo], e);
     }
     __syncthreads();
     // First survivor whose low repeats an earlier survivor's low.
@@ -268,7 +244,7 @@ __device__ void reduce_chunk(Shared& S, const uint64_t* keys, const uint32_t* gr
       const int r = S.wr[s], a = S.wa[s];
       const uint32_t e = benc(round, S.wpos[s]);
       if ((uint32_t)S.wpos[s] < fd || (S.lowc[r] == e && S.touch[r] > e)) {
-        S.table[r * kMaxLW + (a >> 6)] = 1ull << (a & 63);  // pivot bit r is implicit
+        S.part[r] = (int16_t)a;  // the stored column {a, r}
         S.death[r] = gr[S.wpos[s]];
         S.wst[s] = kFinal;
         atomicAdd(&S.s_pivots, 1u);
@@ -381,8 +357,7 @@ __global__ __launch_bounds__(kThreads) void k_batched(BatchArgs A) {
       S.s_pivots = 0;
     }
     const int ib = 64 - __clzll((uint64_t)(n - 1));
-    const int LW = (n + 63) >> 6;
-    for (int k = tid; k < n * kMaxLW; k += kThreads) S.table[k] = 0;
+    for (int k = tid; k < n; k += kThreads) S.part[k] = -1;
     for (int k = tid; k < n; k += kThreads) {
       S.death[k] = kInf;
       S.lowc[k] = kNone;
@@ -462,14 +437,7 @@ __global__ __launch_bounds__(kThreads) void k_batched(BatchArgs A) {
       }
       distinct = run;
       __syncthreads();
-      if (LW <= 1)
-        reduce_chunk<1>(S, src, gr, cnt, n, ib, &err, round);
-      else if (LW <= 2)
-        reduce_chunk<2>(S, src, gr, cnt, n, ib, &err, round);
-      else if (LW <= 4)
-        reduce_chunk<4>(S, src, gr, cnt, n, ib, &err, round);
-      else
-        reduce_chunk<8>(S, src, gr, cnt, n, ib, &err, round);
+      reduce_chunk(S, src, gr, cnt, n, ib, &err, round);
       bin_lo = bin_hi;
     }
     if (err) A.errs[c] = err;

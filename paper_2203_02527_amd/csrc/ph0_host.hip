@@ -49,7 +49,10 @@ constexpr int64_t kMaxN = 65536;
 // (n <= 64, <= 128, <= 256, <= 512), used when no tuning is passed: the
 // values the autotuner (paper_2203_02527_amd/autotune.py) chose on MI355X
 // for the batch workload's clouds.
-constexpr int32_t kChunkMult[4] = {6, 6, 6, 48};
+constexpr int32_t kChunkMult[4] = {6, 6, 8, 48};
+// Built-in workgroups per compute unit of the batched kernel (two fit the
+// 160 KB of LDS of a CU).
+constexpr int32_t kBlocksPerCu = 2;
 // Edge count from which the single-cloud path recomputes keys per distance
 // range instead of storing all of them (below it, the extra passes and host
 // round trips cost more than the stored keys).
@@ -682,7 +685,7 @@ int plan_batch(const int64_t* offsets, int64_t nclouds, int32_t d, ph0_dtype dt,
                      return x.first > y.first;
                    });
   for (auto& e : bysize) P->order.push_back(e.second);
-  const int bpc = tune && tune->blocks_per_cu > 0 ? std::min(tune->blocks_per_cu, 2) : 1;
+  const int bpc = tune && tune->blocks_per_cu > 0 ? std::min(tune->blocks_per_cu, 2) : kBlocksPerCu;
   P->blocks = std::min<int64_t>((int64_t)device_cu_count() * bpc,
                                 std::max<int64_t>((int64_t)P->order.size(), 1));
   if (P->big_n > 0) {
