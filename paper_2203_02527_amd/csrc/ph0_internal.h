@@ -136,8 +136,14 @@ struct RedArgs {
   uint64_t* touch;
   int64_t* act[2];  // active lists, Wcap entries each
   Ring ring;
+  int64_t* surv;    // walk_blocks(Wcap) x walk_segment(Wcap): each block's survivors
+  uint32_t* scount; // walk_blocks(Wcap): survivors per block
   RedCtl* ctl;
 };
+// Grid of the walk (and of the decide and commit steps) and the survivor
+// entries per block.
+int walk_blocks(int64_t Wcap);
+int64_t walk_segment(int64_t Wcap);
 hipError_t launch_reduce_init(const RedArgs& a, int64_t E_lim, hipStream_t s);
 // More sorted columns are available: [old E_lim, E_lim).
 hipError_t launch_reduce_extend(const RedArgs& a, int64_t E_lim, hipStream_t s);

@@ -98,89 +98,116 @@ __device__ inline int64_t item_column(const RedCtl* ctl, const int64_t* act, int
 // column.  A column stops on a free row (a survivor) or becomes zero.  For a
 // survivor {a, r} the root of a in the pivot forest (follow part[] down to a
 // free row) is found, and the round-tagged minima for row r and that root
-// are lowered.  The column's state goes back to the ring.
+// are lowered.  The column's state goes back to the ring, and each block
+// lists its survivors in its own segment of `surv` (seg entries per block,
+// the count in scount[block]), so that the decide and commit steps visit
+// survivors only, one block per walk block, with no shared counter.
 __global__ __launch_bounds__(256) void k_walk(const uint64_t* __restrict__ skeys, int ib,
                                               const int32_t* __restrict__ part, Ring ring,
                                               int64_t Wcap, const int64_t* act0,
                                               const int64_t* act1, uint64_t* lowc,
-                                              uint64_t* touch, RedCtl* ctl) {
+                                              uint64_t* touch, int64_t* surv,
+                                              uint32_t* scount, int64_t seg, RedCtl* ctl) {
+  __shared__ uint32_t s_wave[4];
   if (ctl->done) return;
   const int64_t nA = ctl->nA, round = ctl->round, fresh_lo = ctl->fresh_lo;
   const int64_t items = nA + (ctl->fresh_hi - fresh_lo);
   const int64_t* act = ctl->cur ? act1 : act0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const uint64_t imask = (1ull << ib) - 1ull;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t* my_surv = surv + blockIdx.x * seg;
+  uint32_t nsurv = 0;  // this block's survivors so far (same in every thread)
   int64_t adds = 0, finds = 0, words = 0;
   int32_t bad = 0;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < items; t += stride) {
-    int64_t p;
-    int32_t a, r, rlo, prev_steps;
-    if (t < nA) {
-      p = act[t];
-      const int64_t k = p & (Wcap - 1);
-      a = ring.a[k];
-      r = ring.r[k];
-      rlo = ring.rlo[k];
-      prev_steps = ring.st[k] >> 2;
-    } else {
-      p = fresh_lo + (t - nA);
-      const uint64_t key = skeys[p];
-      a = (int32_t)(key & imask);
-      r = (int32_t)((key >> ib) & imask);
-      rlo = a;
-      prev_steps = 0;
-    }
-    int moved = 0;
-    bool zero = false;
-    while (true) {
-      const int x = part[r];
-      ++words;
-      if (x < 0) break;  // row r is free
-      ++moved;
-      if (x == a) {  // {a, r} + {a, r} = 0
-        zero = true;
-        break;
+  for (int64_t t0 = blockIdx.x * (int64_t)blockDim.x; t0 < items; t0 += stride) {
+    const int64_t t = t0 + threadIdx.x;
+    bool survivor = false;
+    int64_t p = 0;
+    if (t < items) {
+      int32_t a, r, rlo, prev_steps;
+      if (t < nA) {
+        p = act[t];
+        const int64_t k = p & (Wcap - 1);
+        a = ring.a[k];
+        r = ring.r[k];
+        rlo = ring.rlo[k];
+        prev_steps = ring.st[k] >> 2;
+      } else {
+        p = fresh_lo + (t - nA);
+        const uint64_t key = skeys[p];
+        a = (int32_t)(key & imask);
+        r = (int32_t)((key >> ib) & imask);
+        rlo = a;
+        prev_steps = 0;
       }
-      if (x >= r) {  // a stored row lies below its low; a corrupt table ends the walk
-        bad = 1;
-        zero = true;
-        break;
-      }
-      // {a, r} + {x, r} = {a, x}
-      const int lo = x < a ? x : a;
-      r = x < a ? a : x;
-      a = lo;
-    }
-    adds += moved;
-    int32_t status = kActive;
-    if (zero) {
-      status = kZero;
-    } else {
-      // Root of row a in the current forest: follow stored columns down.
-      int v = moved ? a : rlo;
+      int moved = 0;
+      bool zero = false;
       while (true) {
-        const int c = part[v];
+        const int x = part[r];
         ++words;
-        if (c < 0) break;  // free row: v is a root
-        ++finds;
-        if (c >= v) {
-          bad = 1;
+        if (x < 0) break;  // row r is free
+        ++moved;
+        if (x == a) {  // {a, r} + {a, r} = 0
+          zero = true;
           break;
         }
-        v = c;
+        if (x >= r) {  // a stored row lies below its low; a corrupt table ends the walk
+          bad = 1;
+          zero = true;
+          break;
+        }
+        // {a, r} + {x, r} = {a, x}
+        const int lo = x < a ? x : a;
+        r = x < a ? a : x;
+        a = lo;
       }
-      rlo = v;
-      const uint64_t e = enc(round, p);
-      filtered_min(&lowc[r], e);
-      filtered_min(&touch[rlo], e);
+      adds += moved;
+      int32_t status = kActive;
+      if (zero) {
+        status = kZero;
+      } else {
+        // Root of row a in the current forest: follow stored columns down.
+        int v = moved ? a : rlo;
+        while (true) {
+          const int c = part[v];
+          ++words;
+          if (c < 0) break;  // free row: v is a root
+          ++finds;
+          if (c >= v) {
+            bad = 1;
+            break;
+          }
+          v = c;
+        }
+        rlo = v;
+        const uint64_t e = enc(round, p);
+        filtered_min(&lowc[r], e);
+        filtered_min(&touch[rlo], e);
+        survivor = true;
+      }
+      const int64_t k = p & (Wcap - 1);
+      ring.a[k] = a;
+      ring.r[k] = r;
+      ring.rlo[k] = rlo;
+      ring.st[k] = status | ((prev_steps + moved) << 2);
+      ring.tag[k] = p;
     }
-    const int64_t k = p & (Wcap - 1);
-    ring.a[k] = a;
-    ring.r[k] = r;
-    ring.rlo[k] = rlo;
-    ring.st[k] = status | ((prev_steps + moved) << 2);
-    ring.tag[k] = p;
+    // Append this pass's survivors to the block's segment.
+    const uint64_t m = __ballot(survivor);
+    if (lane == 0) s_wave[wave] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      before += w < wave ? s_wave[w] : 0u;
+      total += s_wave[w];
+    }
+    if (survivor) my_surv[nsurv + before + __popcll(m & ((1ull << lane) - 1ull))] = p;
+    nsurv += total;
+    __syncthreads();
   }
+  if (threadIdx.x == 0) scount[blockIdx.x] = nsurv;
   // Counters: wave sums -> block totals in LDS -> one atomic per block.
   __shared__ unsigned long long s_cnt[3];
   __shared__ int s_bad;
@@ -245,20 +272,22 @@ __device__ inline int64_t block_excl_i64(int64_t v, int64_t* tmp /* 4 */, int64_
   return base + x - v;
 }
 
-__global__ __launch_bounds__(256) void k_decide(Ring ring, int64_t Wcap, const int64_t* act0,
-                                                const int64_t* act1, const uint64_t* lowc,
-                                                RedCtl* ctl) {
+// First survivor whose low repeats an earlier survivor's low: the lowest
+// survivor p with lowc[r] != its own tag.  One block per walk block, over
+// that block's survivors.
+__global__ __launch_bounds__(256) void k_decide(Ring ring, int64_t Wcap, const int64_t* surv,
+                                                const uint32_t* scount, int64_t seg,
+                                                const uint64_t* lowc, RedCtl* ctl) {
   __shared__ uint64_t tmp[4];
   if (ctl->done) return;
+  const uint32_t cnt = scount[blockIdx.x];
+  if (cnt == 0) return;
   const int64_t round = ctl->round;
-  const int64_t items = ctl->nA + (ctl->fresh_hi - ctl->fresh_lo);
-  const int64_t* act = ctl->cur ? act1 : act0;
+  const int64_t* my = surv + blockIdx.x * seg;
   uint64_t best = kNoValue;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < items;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t p = item_column(ctl, act, t);
+  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const int64_t p = my[i];
     const int64_t k = p & (Wcap - 1);
-    if ((ring.st[k] & 3) != kActive) continue;
     if (lowc[ring.r[k]] != enc(round, p) && (uint64_t)p < best) best = (uint64_t)p;
   }
   best = block_min_u64(best, tmp);
@@ -316,37 +345,39 @@ __device__ void advance_round(RedCtl* ctl_, int64_t n, int64_t E, int64_t Wcap) 
 }
 
 // Commit the survivors the rule allows; append the rest to the next active
-// list.  Two phases per block so that the list needs one atomic per block:
-// commit and count, then (after one block-wide scan) write the stayers.
-__global__ __launch_bounds__(256) void k_commit(Ring ring, int64_t Wcap, int64_t* act0,
-                                                int64_t* act1, const uint64_t* lowc,
-                                                const uint64_t* touch,
-                                                int32_t* part, int64_t* killer,
-                                                RedCtl* ctl) {
+// list.  One block per walk block, over that block's survivors, in two phases
+// so that the list needs one atomic per block: commit and count, then (after
+// one block-wide scan) write the stayers.
+__global__ __launch_bounds__(256) void k_commit(Ring ring, int64_t Wcap, const int64_t* surv,
+                                                const uint32_t* scount, int64_t seg,
+                                                int64_t* act0, int64_t* act1,
+                                                const uint64_t* lowc, const uint64_t* touch,
+                                                int32_t* part, int64_t* killer, RedCtl* ctl) {
   __shared__ int64_t itmp[4];
   __shared__ uint64_t utmp[4];
   __shared__ int64_t s_base;
   if (ctl->done) return;
   const int64_t round = ctl->round;
-  const int64_t items = ctl->nA + (ctl->fresh_hi - ctl->fresh_lo);
-  const int64_t* act = ctl->cur ? act1 : act0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl->firstdup[(round + 1) & 1] = kNoValue;
+    ctl->newF[(round + 1) & 1] = kNoValue;
+  }
+  const uint32_t cnt = scount[blockIdx.x];
+  if (cnt == 0) return;
   int64_t* next = ctl->cur ? act0 : act1;
   const uint64_t fd = ctl->firstdup[round & 1];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t* my = surv + blockIdx.x * seg;
   uint64_t stay_min = kNoValue;
   int64_t npiv = 0, last = -1, nstay = 0;
-  for (int64_t t = t0; t < items; t += stride) {
-    const int64_t p = item_column(ctl, act, t);
+  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const int64_t p = my[i];
     const int64_t k = p & (Wcap - 1);
-    const int32_t st = ring.st[k];
-    if ((st & 3) != kActive) continue;
     const int32_t r = ring.r[k];
     const uint64_t e = enc(round, p);
     if ((uint64_t)p < fd || (lowc[r] == e && touch[r] > e)) {
       part[r] = ring.a[k];  // the stored column {a, r}
       killer[r] = p;
-      ring.st[k] = (st & ~3) | kCommitted;
+      ring.st[k] = (ring.st[k] & ~3) | kCommitted;
       ++npiv;
       last = p > last ? p : last;
     } else {
@@ -361,8 +392,8 @@ __global__ __launch_bounds__(256) void k_commit(Ring ring, int64_t Wcap, int64_t
   __syncthreads();
   if (nstay) {
     int64_t at = s_base + mine;
-    for (int64_t t = t0; t < items; t += stride) {
-      const int64_t p = item_column(ctl, act, t);
+    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+      const int64_t p = my[i];
       if ((ring.st[p & (Wcap - 1)] & 3) == kActive) next[at++] = p;
     }
   }
@@ -376,10 +407,6 @@ __global__ __launch_bounds__(256) void k_commit(Ring ring, int64_t Wcap, int64_t
     }
     if (stay_min != kNoValue)
       atomicMin((unsigned long long*)&ctl->newF[round & 1], (unsigned long long)stay_min);
-    if (blockIdx.x == 0) {
-      ctl->firstdup[(round + 1) & 1] = kNoValue;
-      ctl->newF[(round + 1) & 1] = kNoValue;
-    }
   }
 }
 
@@ -454,16 +481,25 @@ int scan_blocks(int64_t Wcap) {
   return (int)(b < 1 ? 1 : b);
 }
 
+
+}  // namespace
+
 // One lane per column: enough blocks to give every column of a full window
-// its own lane, up to 8 blocks per compute unit.
+// its own lane, up to 2048 blocks (8 per compute unit of MI355X).  Fixed,
+// not queried, so that workspace sizes do not depend on the device.
 int walk_blocks(int64_t Wcap) {
   int64_t b = (Wcap + 255) / 256;
-  const int64_t cap = 8 * (int64_t)device_cus();
+  const int64_t cap = 2048;
   if (b > cap) b = cap;
   return (int)(b < 1 ? 1 : b);
 }
 
-}  // namespace
+// Survivor entries per walk block: the most items one block can see in a
+// round (a round has at most Wcap items).
+int64_t walk_segment(int64_t Wcap) {
+  const int64_t threads = 256 * (int64_t)walk_blocks(Wcap);
+  return 256 * ((Wcap + threads - 1) / threads);
+}
 
 hipError_t launch_reduce_extend(const RedArgs& a, int64_t E_lim, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_extend, dim3(1), dim3(1), 0, s, a.ctl, E_lim);
@@ -487,17 +523,19 @@ hipError_t launch_reduce_init(const RedArgs& a, int64_t E_lim, hipStream_t s) {
 }
 
 hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_walk) {
+  const int wb = walk_blocks(a.Wcap);
+  const int64_t seg = walk_segment(a.Wcap);
   if (ev_walk) (void)hipEventRecord(ev_walk[0], s);
-  hipLaunchKernelGGL(k_walk, dim3((unsigned)walk_blocks(a.Wcap)), dim3(256), 0, s, a.skeys, a.ib,
-                     a.part, a.ring, a.Wcap, a.act[0], a.act[1], a.lowc, a.touch, a.ctl);
+  hipLaunchKernelGGL(k_walk, dim3((unsigned)wb), dim3(256), 0, s, a.skeys, a.ib, a.part, a.ring,
+                     a.Wcap, a.act[0], a.act[1], a.lowc, a.touch, a.surv, a.scount, seg, a.ctl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev_walk) (void)hipEventRecord(ev_walk[1], s);
-  const int sb = scan_blocks(a.Wcap);
-  hipLaunchKernelGGL(k_decide, dim3(sb), dim3(256), 0, s, a.ring, a.Wcap, a.act[0], a.act[1],
-                     a.lowc, a.ctl);
-  hipLaunchKernelGGL(k_commit, dim3(sb), dim3(256), 0, s, a.ring, a.Wcap, a.act[0], a.act[1],
-                     a.lowc, a.touch, a.part, a.killer, a.ctl);
+  hipLaunchKernelGGL(k_decide, dim3((unsigned)wb), dim3(256), 0, s, a.ring, a.Wcap, a.surv,
+                     a.scount, seg, a.lowc, a.ctl);
+  hipLaunchKernelGGL(k_commit, dim3((unsigned)wb), dim3(256), 0, s, a.ring, a.Wcap, a.surv,
+                     a.scount, seg, a.act[0], a.act[1], a.lowc, a.touch, a.part, a.killer,
+                     a.ctl);
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, a.ctl, a.n, a.E, a.Wcap);
   return hipGetLastError();
 }
