@@ -581,9 +581,14 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     }
     prevF = h.F;
     // Bursts grow 2, 4, 8 (then stay): rounds queued past the end cost a few
-    // launches each, so small problems queue few.
+    // launches each, so small problems queue few.  Once every pivot exists
+    // only the columns before the last one remain (a round or two), so the
+    // bursts shrink to single rounds.
     pipelined = true;
-    if (burst < 8) burst *= 2;
+    if (h.pivots >= n - 1)
+      burst = 1;
+    else if (burst < 8)
+      burst *= 2;
     if (q_len == 0) HIPCHK(issue_next());
   }
   S.sort_chunks = chunks;
