@@ -83,6 +83,17 @@ __device__ inline void edge_ij(int64_t e, int* j, int* i) {
   *i = (int)(e - (int64_t)jj * (jj - 1) / 2);
 }
 
+// Step a colex position (j, i) forward by `step` edges (j only grows).
+__device__ inline void edge_advance(int* j, int* i, int step) {
+  int ii = *i + step, jj = *j;
+  while (ii >= jj) {
+    ii -= jj;
+    ++jj;
+  }
+  *i = ii;
+  *j = jj;
+}
+
 __device__ inline uint64_t sqdist(const Shared& S, int d, int i, int j) {
   uint64_t s = 0;
   for (int k = 0; k < d; ++k) {
@@ -374,11 +385,15 @@ __global__ __launch_bounds__(kThreads) void k_batched(BatchArgs A) {
     }
     const int hs = dbits > 10 ? dbits - 10 : 0;
     const int64_t E = (int64_t)n * (n - 1) / 2;
-    // Histogram of delta >> hs over all edges.
-    for (int64_t e = tid; e < E; e += kThreads) {
+    // Histogram of delta >> hs over all edges (each thread steps through
+    // colex positions tid, tid + kThreads, ...).
+    {
       int j, i;
-      edge_ij(e, &j, &i);
-      atomicAdd(&S.hist[(uint32_t)(sqdist(S, d, i, j) >> hs)], 1u);
+      edge_ij(tid < E ? tid : 0, &j, &i);
+      for (int64_t e = tid; e < E; e += kThreads) {
+        atomicAdd(&S.hist[(uint32_t)(sqdist(S, d, i, j) >> hs)], 1u);
+        edge_advance(&j, &i, kThreads);
+      }
     }
     __syncthreads();
     const int bucket = n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : 3;
@@ -396,13 +411,15 @@ __global__ __launch_bounds__(kThreads) void k_batched(BatchArgs A) {
       const uint32_t bin_hi = S.s_bin_hi;
       // Stable compaction of the chunk's edges, in colex order.
       uint32_t cnt = 0;
+      int cj, ci;
+      edge_ij(tid < E ? tid : 0, &cj, &ci);
       for (int64_t e0 = 0; e0 < E; e0 += kThreads) {
         const int64_t e = e0 + tid;
         uint64_t key = 0;
         bool in = false;
         if (e < E) {
-          int j, i;
-          edge_ij(e, &j, &i);
+          const int j = cj, i = ci;
+          edge_advance(&cj, &ci, kThreads);
           const uint64_t dl = sqdist(S, d, i, j);
           const uint32_t b = (uint32_t)(dl >> hs);
           in = b >= bin_lo && b < bin_hi;
