@@ -182,7 +182,11 @@ __device__ void reduce_chunk(Shared& S, const uint64_t* keys, const uint32_t* gr
     }
     nwin += (int)take;
     next += take;
-    if (tid == 0) S.s_fd = kNone;
+    if (tid == 0) {
+      S.s_fd = kNone;
+      S.s_keep = kNone;
+      S.s_count = 0;
+    }
     if ((round & 0x7FFF) == 0 && round > 0) {  // the 15-bit round tag wraps: clear
       for (int k = tid; k < n; k += kThreads) {
         S.lowc[k] = kNone;
@@ -236,19 +240,17 @@ __device__ void reduce_chunk(Shared& S, const uint64_t* keys, const uint32_t* gr
       atomicMin(&S.touch[rlo], e);
     }
     __syncthreads();
-    // First survivor whose low repeats an earlier survivor's low.
-    for (int s = tid; s < nwin; s += kThreads)
-      if (S.wst[s] == kActiveB && S.lowc[S.wr[s]] != benc(round, S.wpos[s]))
-        atomicMin(&S.s_fd, (uint32_t)S.wpos[s]);
+    // First survivor whose low repeats an earlier survivor's low, and the
+    // first survivor of all (it must finalize: it commits; a round in which
+    // it does not reports and stops).
+    for (int s = tid; s < nwin; s += kThreads) {
+      if (S.wst[s] != kActiveB) continue;
+      const uint32_t pos = (uint32_t)S.wpos[s];
+      atomicMin(&S.s_keep, pos);
+      if (S.lowc[S.wr[s]] != benc(round, S.wpos[s])) atomicMin(&S.s_fd, pos);
+    }
     __syncthreads();
     const uint32_t fd = S.s_fd;
-    // The first active column always finalizes (zero, or it commits as the
-    // first survivor); a round that fails to do so reports and stops.
-    if (tid == 0) S.s_keep = kNone;
-    __syncthreads();
-    for (int s = tid; s < nwin; s += kThreads)
-      if (S.wst[s] == kActiveB) atomicMin(&S.s_keep, (uint32_t)S.wpos[s]);
-    __syncthreads();
     const uint32_t first_active = S.s_keep;
     for (int s = tid; s < nwin; s += kThreads) {
       if (S.wst[s] != kActiveB) continue;
@@ -281,6 +283,7 @@ __device__ void reduce_chunk(Shared& S, const uint64_t* keys, const uint32_t* gr
       __syncthreads();
       if (k) {
         const int dsts = (int)(keep + ex);
+        if ((uint32_t)kpos == first_active) S.s_count = 1;  // it did not finalize
         S.wa[dsts] = ka;
         S.wr[dsts] = kr;
         S.wrlo[dsts] = krlo;
@@ -293,16 +296,9 @@ __device__ void reduce_chunk(Shared& S, const uint64_t* keys, const uint32_t* gr
     nwin = (int)keep;
     ++round;
     if (S.s_pivots >= (uint32_t)(n - 1)) break;
-    // Progress guard: the first active column must be gone.
-    bool stuck = false;
-    if (first_active != kNone) {
-      if (tid == 0) S.s_count = 0;
-      __syncthreads();
-      for (int s = tid; s < nwin; s += kThreads)
-        if ((uint32_t)S.wpos[s] == first_active) S.s_count = 1;
-      __syncthreads();
-      stuck = S.s_count != 0;
-    }
+    // Progress guard: the first active column must be gone (flagged during
+    // the compaction above).
+    const bool stuck = S.s_count != 0;
     if (stuck || ++rounds_here > cnt + 2) {
       *err = 5;
       break;
