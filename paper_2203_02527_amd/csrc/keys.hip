@@ -215,6 +215,42 @@ __global__ void k_norms_i8(const int8_t* __restrict__ x, int64_t n, int32_t d,
   }
 }
 
+// Rows of one tile for the single-stage path (d <= 64, 16-byte aligned rows):
+// at most 2 x 64 rows x 4 segments of 16 bytes, two per thread.  Loaded into
+// registers one tile ahead, so the loads of the next tile overlap the
+// current tile's MFMA and epilogue.
+struct TileRegs {
+  int4 v[2];
+};
+
+__device__ inline void tile_regs_load(TileRegs& r, const int8_t* __restrict__ x, int64_t n,
+                                      int32_t d, int64_t i0, int64_t j0, int segs) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int e = threadIdx.x + q * 256;
+    r.v[q] = make_int4(0, 0, 0, 0);
+    if (e < 2 * 64 * segs) {
+      const int side = e / (64 * segs), rem = e - side * 64 * segs;
+      const int pt = rem / segs, sg = rem - pt * segs;
+      const int64_t g = (side ? j0 : i0) + pt;
+      if (g < n && 16 * sg < d) r.v[q] = *reinterpret_cast<const int4*>(x + g * d + 16 * sg);
+    }
+  }
+}
+
+template <int KROW>
+__device__ inline void tile_regs_store(const TileRegs& r, int8_t (*xs)[64][KROW], int segs) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int e = threadIdx.x + q * 256;
+    if (e < 2 * 64 * segs) {
+      const int side = e / (64 * segs), rem = e - side * 64 * segs;
+      const int pt = rem / segs, sg = rem - pt * segs;
+      *reinterpret_cast<int4*>(&xs[side][pt][16 * sg]) = r.v[q];
+    }
+  }
+}
+
 // KMAX int8 dimensions are staged per LDS round (64 for d <= 64, else 256);
 // rows are padded by 16 bytes so that the 32 row reads of a half-wave spread
 // over the LDS banks.  With vec16 (d a multiple of 16 and 16-byte aligned
@@ -237,7 +273,17 @@ __global__ __launch_bounds__(256) void k_keys_mfma(const int8_t* __restrict__ x,
   const int wave = threadIdx.x >> 6;
   const int jsub = wave >> 1, isub = wave & 1;  // 32 x 32 sub-tile of this wave
   const int64_t step = tile_step(kp, MODE);
-  for (int64_t t = blockIdx.x * (MODE == kKeysHist ? kp.sample : 1); t < ntiles; t += step) {
+  const int64_t tfirst = blockIdx.x * (MODE == kKeysHist ? kp.sample : 1);
+  // One-stage tiles with 16-byte rows are loaded a tile ahead.
+  const bool ahead = KMAX == 64 && vec16 && d <= 64;
+  const int segs1 = ((d + 31) & ~31) >> 4;
+  TileRegs pre;
+  if (ahead && tfirst < ntiles) {
+    int64_t jb, ibk;
+    tile_coords(tfirst, &jb, &ibk);
+    tile_regs_load(pre, x, n, d, ibk * kTile, jb * kTile, segs1);
+  }
+  for (int64_t t = tfirst; t < ntiles; t += step) {
     int64_t jb, ibk;
     tile_coords(t, &jb, &ibk);
     const int64_t i0 = ibk * kTile, j0 = jb * kTile;
@@ -252,7 +298,24 @@ __global__ __launch_bounds__(256) void k_keys_mfma(const int8_t* __restrict__ x,
     }
     if (MODE == kKeysEmit && threadIdx.x < kTile)
       rbase[threadIdx.x] = kp.cnt[key_count_index(jb, threadIdx.x, ibk)];
-    for (int k0 = 0; k0 < d; k0 += KMAX) {
+    if (ahead) {
+      tile_regs_store<kRow>(pre, xs, segs1);
+      if (t + step < ntiles) {
+        int64_t jn, in_;
+        tile_coords(t + step, &jn, &in_);
+        tile_regs_load(pre, x, n, d, in_ * kTile, jn * kTile, segs1);
+      }
+      __syncthreads();
+      const int kpad = segs1 * 16;
+      for (int kk = 0; kk < kpad; kk += 32) {
+        const v4i a = *reinterpret_cast<const v4i*>(
+            &xs[1][jsub * 32 + (lane & 31)][kk + 16 * (lane >> 5)]);
+        const v4i b = *reinterpret_cast<const v4i*>(
+            &xs[0][isub * 32 + (lane & 31)][kk + 16 * (lane >> 5)]);
+        c = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+      }
+    }
+    for (int k0 = 0; k0 < (ahead ? 0 : d); k0 += KMAX) {
       const int kc = d - k0 < KMAX ? d - k0 : KMAX;
       const int kpad = (kc + 31) & ~31;
       if (k0 > 0) __syncthreads();
