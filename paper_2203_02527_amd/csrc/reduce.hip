@@ -34,8 +34,6 @@
 // -- equals the sequential left-to-right reduction.  Once N-1 pivots exist
 // the remaining columns must reduce to zero (the complete graph is
 // connected), so the reduction stops there.
-#include <climits>
-
 #include "ph0_internal.h"
 
 namespace ph0 {
@@ -57,12 +55,6 @@ __device__ inline uint64_t shfl64_down(uint64_t v, int delta) {
 __device__ inline uint64_t shfl64_up(uint64_t v, int delta) {
   const uint32_t lo = __shfl_up((uint32_t)v, delta, 64);
   const uint32_t hi = __shfl_up((uint32_t)(v >> 32), delta, 64);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ inline uint64_t shfl64(uint64_t v, int src) {
-  const uint32_t lo = __shfl((uint32_t)v, src, 64);
-  const uint32_t hi = __shfl((uint32_t)(v >> 32), src, 64);
   return ((uint64_t)hi << 32) | lo;
 }
 
