@@ -107,3 +107,24 @@ def test_h1_statistics_count_emergent_and_committed_pairs(torch):
     assert st["emergent"] == emergent
     assert st["bars"] + st["zero_length"] == st["pivots"]
     assert st["walks"] >= st["T"] - st["emergent"]
+
+
+@pytest.mark.parametrize("n", [362, 512])
+def test_h1_full_size_properties(torch, n):
+    # Beyond the oracle's reach in a test (its dense reduction of 8-22 M
+    # triangle columns takes minutes): every positive edge is paired (E - n + 1
+    # pairs, bars of positive length in canonical order), repeated calls are
+    # bit-identical, and relabelling the points leaves the bars unchanged.
+    # These sizes use 16 and 32 words per lane for the dense columns.
+    x = synth.uniform_cloud(n, 3, seed=1)
+    got, toe, st = _run(torch, x)
+    E = n * (n - 1) // 2
+    assert st["pivots"] == E - n + 1 == int((toe >= 0).sum())
+    assert got.shape[0] == st["bars"] and (got[:, 0] < got[:, 1]).all()
+    assert (np.diff(got[:, 0].astype(np.int64)) >= 0).all()
+    again, toe2, _ = _run(torch, x)
+    np.testing.assert_array_equal(again, got)
+    np.testing.assert_array_equal(toe2, toe)
+    perm = np.random.default_rng(n).permutation(n)
+    permuted, _, _ = _run(torch, x[perm])
+    np.testing.assert_array_equal(permuted, got)
