@@ -233,7 +233,8 @@ typedef struct {
 } ph0_h1_stats;
 
 /* Device workspace for ph0_h1_device (dominated by E x ceil(E/64) words of
- * stored columns and 20 bytes per triangle). */
+ * stored columns, 20 bytes per triangle, and a store of up to 16 GB that
+ * keeps survivors' partly reduced columns). */
 int ph0_h1_workspace_bytes(int64_t n, int32_t d, ph0_dtype dt, size_t* bytes);
 
 /* H1 barcode on device memory.  d_bars receives the bars (birth < death, in

@@ -177,25 +177,13 @@ __device__ inline int wcol_low(const WCol<WPL>& x, int nw) {
   return low;
 }
 
-// Walk triangle t's column against the table; returns its final low (-1 for
-// zero) and the number of additions.  `x` holds the column at the end.  Each
+// Continue reducing the column `x`, whose low is `low`, against the table:
+// returns its final low (-1 for zero) and adds the additions to *adds.  Each
 // addition cancels the current low, so the low falls at every step; a row
 // whose top bit is not its index (a corrupt table) ends the walk with -2.
 template <int WPL>
-__device__ inline int h1_walk(const uint64_t* tri, const uint64_t* keys, int ib,
-                              const int32_t* inv, const uint64_t* table, const int32_t* owner,
-                              int64_t LWE, int64_t t, int lane, WCol<WPL>& x, int64_t* adds) {
-  int e0, e1, e2;
-  tri_edges(tri, keys, ib, inv, t, &e0, &e1, &e2);
-  e0 = __builtin_amdgcn_readfirstlane(e0);
-  e1 = __builtin_amdgcn_readfirstlane(e1);
-  e2 = __builtin_amdgcn_readfirstlane(e2);
-#pragma unroll
-  for (int s = 0; s < WPL; ++s) x.c[s] = 0;
-  wcol_set(x, e0, lane);
-  wcol_set(x, e1, lane);
-  wcol_set(x, e2, lane);
-  int low = e2;
+__device__ inline int h1_reduce(const uint64_t* table, const int32_t* owner, int64_t LWE,
+                                int low, int lane, WCol<WPL>& x, int64_t* adds) {
   int64_t a = 0;
   while (true) {
     const int o = __builtin_amdgcn_readfirstlane(owner[low]);
@@ -218,6 +206,46 @@ __device__ inline int h1_walk(const uint64_t* tri, const uint64_t* keys, int ib,
   }
   *adds += a;
   return low;
+}
+
+// Words 0 .. low/64 of a column to or from the column store.
+template <int WPL>
+__device__ inline void wcol_put(const WCol<WPL>& x, uint64_t* dst, int low, int lane) {
+  const int nw = low / 64 + 1;
+#pragma unroll
+  for (int s = 0; s < WPL; ++s) {
+    const int w = s * 64 + lane;
+    if (w < nw) dst[w] = x.c[s];
+  }
+}
+
+template <int WPL>
+__device__ inline void wcol_get(WCol<WPL>& x, const uint64_t* src, int low, int lane) {
+  const int nw = low / 64 + 1;
+#pragma unroll
+  for (int s = 0; s < WPL; ++s) {
+    const int w = s * 64 + lane;
+    x.c[s] = w < nw ? src[w] : 0ull;
+  }
+}
+
+// Walk triangle t's column against the table from its boundary; returns its
+// final low (-1 for zero, -2 for a corrupt table) and the additions.
+template <int WPL>
+__device__ inline int h1_walk(const uint64_t* tri, const uint64_t* keys, int ib,
+                              const int32_t* inv, const uint64_t* table, const int32_t* owner,
+                              int64_t LWE, int64_t t, int lane, WCol<WPL>& x, int64_t* adds) {
+  int e0, e1, e2;
+  tri_edges(tri, keys, ib, inv, t, &e0, &e1, &e2);
+  e0 = __builtin_amdgcn_readfirstlane(e0);
+  e1 = __builtin_amdgcn_readfirstlane(e1);
+  e2 = __builtin_amdgcn_readfirstlane(e2);
+#pragma unroll
+  for (int s = 0; s < WPL; ++s) x.c[s] = 0;
+  wcol_set(x, e0, lane);
+  wcol_set(x, e1, lane);
+  wcol_set(x, e2, lane);
+  return h1_reduce<WPL>(table, owner, LWE, e2, lane, x, adds);
 }
 
 // Per-wave addition and walk counts -> one atomic each per block.
@@ -258,7 +286,10 @@ __global__ __launch_bounds__(256) void k_h1_walk0(const uint64_t* __restrict__ t
                                                   const uint64_t* __restrict__ table,
                                                   const int32_t* __restrict__ owner, int64_t LWE,
                                                   uint64_t* __restrict__ S,
-                                                  uint64_t* __restrict__ minc, H1Ctl* ctl) {
+                                                  uint64_t* __restrict__ minc,
+                                                  uint64_t* __restrict__ store,
+                                                  uint32_t* __restrict__ sadds, int64_t cap,
+                                                  H1Ctl* ctl) {
   const int lane = threadIdx.x & 63;
   const int64_t items = ctl->T;
   const int64_t wid = blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64;
@@ -279,10 +310,16 @@ __global__ __launch_bounds__(256) void k_h1_walk0(const uint64_t* __restrict__ t
       adds += a;  // final: a zero column
       continue;
     }
+    uint32_t k = 0;
     if (lane == 0) {
-      const unsigned long long k = atomicAdd((unsigned long long*)&ctl->nsurv, 1ull);
+      k = (uint32_t)atomicAdd((unsigned long long*)&ctl->nsurv, 1ull);
       S[k] = ((uint64_t)t << 32) | (uint32_t)low;
       atomicMin((unsigned long long*)&minc[low], (unsigned long long)t);
+    }
+    k = __builtin_amdgcn_readfirstlane(k);
+    if (k < cap) {  // keep the column and its additions so far
+      wcol_put<WPL>(x, store + (int64_t)k * LWE, low, lane);
+      if (lane == 0) sadds[k] = (uint32_t)a;
     }
   }
   h1_flush(adds, walks, ctl);
@@ -321,13 +358,14 @@ __global__ __launch_bounds__(256) void k_h1_pick(uint64_t* __restrict__ S,
     const uint64_t v = S[k];
     if ((uint32_t)v == kDead || (v >> 32) >= fd) continue;
     const unsigned long long c = atomicAdd((unsigned long long*)&ctl->ncommit, 1ull);
-    clist[c] = v;
+    clist[c] = ((uint64_t)k << 32) | (uint32_t)v;
     S[k] = v | kDead;
   }
 }
 
-// Each picked survivor walks again (the rows it passes are unchanged) and
-// stores its column in row `low`.  One wave per survivor.
+// Each picked survivor stores its column in row `low`: the kept column, or,
+// for a survivor beyond the store, its walk repeated from the boundary (the
+// rows it passes are unchanged).  One wave per survivor.
 template <int WPL>
 __global__ __launch_bounds__(256) void k_h1_commit(const uint64_t* __restrict__ tri,
                                                    const uint64_t* __restrict__ keys, int ib,
@@ -335,22 +373,31 @@ __global__ __launch_bounds__(256) void k_h1_commit(const uint64_t* __restrict__ 
                                                    uint64_t* __restrict__ table,
                                                    int32_t* __restrict__ owner, int64_t LWE,
                                                    const uint64_t* __restrict__ clist,
-                                                   H1Ctl* ctl) {
+                                                   const uint64_t* __restrict__ S,
+                                                   const uint64_t* __restrict__ store,
+                                                   const uint32_t* __restrict__ sadds,
+                                                   int64_t cap, H1Ctl* ctl) {
   const int lane = threadIdx.x & 63;
   const int64_t nc = ctl->ncommit;
   const int64_t wid = blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64;
   const int64_t wtot = (int64_t)gridDim.x * (blockDim.x / 64);
   int64_t adds = 0, walks = 0;
   for (int64_t c = wid; c < nc; c += wtot) {
-    const int64_t t = (int64_t)(clist[c] >> 32);
+    const uint32_t k = (uint32_t)(clist[c] >> 32);
     const int low = (int)(uint32_t)clist[c];
+    const int64_t t = (int64_t)(S[k] >> 32);
     WCol<WPL> x;
     int64_t a = 0;
-    const int l2 = h1_walk<WPL>(tri, keys, ib, inv, table, owner, LWE, t, lane, x, &a);
-    ++walks;
-    if (l2 != low) {  // a repeated walk must end where the first did
-      if (lane == 0) atomicOr(&ctl->err, 1);
-      continue;
+    if (k < cap) {
+      wcol_get<WPL>(x, store + (int64_t)k * LWE, low, lane);
+      a = sadds[k];
+    } else {
+      const int l2 = h1_walk<WPL>(tri, keys, ib, inv, table, owner, LWE, t, lane, x, &a);
+      ++walks;
+      if (l2 != low) {  // a repeated walk must end where the first did
+        if (lane == 0) atomicOr(&ctl->err, 1);
+        continue;
+      }
     }
     adds += a;
     uint64_t* row = table + (int64_t)low * LWE;
@@ -399,8 +446,10 @@ __global__ __launch_bounds__(256) void k_h1_mark(const uint64_t* __restrict__ S,
   }
 }
 
-// Survivors on taken rows walk again: zero columns die, the others move to
-// their new (free) row.  One wave per survivor.
+// Survivors on taken rows continue: a kept column resumes at its row (now
+// taken, so the stored column there is added next), a survivor beyond the
+// store walks again from its boundary.  Zero columns die, the others move
+// to their new (free) row.  One wave per survivor.
 template <int WPL>
 __global__ __launch_bounds__(256) void k_h1_rewalk(const uint64_t* __restrict__ tri,
                                                    const uint64_t* __restrict__ keys, int ib,
@@ -409,7 +458,10 @@ __global__ __launch_bounds__(256) void k_h1_rewalk(const uint64_t* __restrict__ 
                                                    const int32_t* __restrict__ owner,
                                                    int64_t LWE, uint64_t* __restrict__ S,
                                                    const uint32_t* __restrict__ wlist,
-                                                   uint64_t* __restrict__ minc, H1Ctl* ctl) {
+                                                   uint64_t* __restrict__ minc,
+                                                   uint64_t* __restrict__ store,
+                                                   uint32_t* __restrict__ sadds, int64_t cap,
+                                                   H1Ctl* ctl) {
   const int lane = threadIdx.x & 63;
   const int64_t nw = ctl->nwalk;
   const int64_t wid = blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64;
@@ -417,10 +469,19 @@ __global__ __launch_bounds__(256) void k_h1_rewalk(const uint64_t* __restrict__ 
   int64_t adds = 0, walks = 0;
   for (int64_t i = wid; i < nw; i += wtot) {
     const uint32_t k = wlist[i];
-    const uint64_t t = S[k] >> 32;
+    const uint64_t v = S[k];
+    const uint64_t t = v >> 32;
     WCol<WPL> x;
     int64_t a = 0;
-    const int low = h1_walk<WPL>(tri, keys, ib, inv, table, owner, LWE, (int64_t)t, lane, x, &a);
+    int low;
+    if (k < cap) {
+      const int old = (int)(uint32_t)v;
+      wcol_get<WPL>(x, store + (int64_t)k * LWE, old, lane);
+      a = sadds[k];
+      low = h1_reduce<WPL>(table, owner, LWE, old, lane, x, &a);
+    } else {
+      low = h1_walk<WPL>(tri, keys, ib, inv, table, owner, LWE, (int64_t)t, lane, x, &a);
+    }
     ++walks;
     if (low == -2) {
       if (lane == 0) atomicOr(&ctl->err, 2);
@@ -430,6 +491,10 @@ __global__ __launch_bounds__(256) void k_h1_rewalk(const uint64_t* __restrict__ 
       adds += a;
       if (lane == 0) S[k] = (t << 32) | kDead;
       continue;
+    }
+    if (k < cap) {
+      wcol_put<WPL>(x, store + (int64_t)k * LWE, low, lane);
+      if (lane == 0) sadds[k] = (uint32_t)a;
     }
     if (lane == 0) {
       S[k] = (t << 32) | (uint32_t)low;
@@ -507,7 +572,8 @@ hipError_t first_round(const H1Args& a, hipStream_t s) {
   const int64_t cap = (int64_t)a.cus * 8;
   const int64_t wb = std::min<int64_t>(cap, std::max<int64_t>(1, (a.T + 3) / 4));
   hipLaunchKernelGGL(k_h1_walk0<WPL>, dim3((unsigned)wb), dim3(256), 0, s, a.tri, a.keys, a.ib,
-                     a.inv, a.start, a.table, a.owner, a.LWE, a.surv, a.lowc, a.ctl);
+                     a.inv, a.start, a.table, a.owner, a.LWE, a.surv, a.lowc, a.store, a.sadds,
+                     a.cap, a.ctl);
   hipLaunchKernelGGL(k_h1_live, dim3((unsigned)a.cus), dim3(256), 0, s, a.surv, a.ctl);
   return hipGetLastError();
 }
@@ -521,10 +587,12 @@ hipError_t next_round(const H1Args& a, hipStream_t s) {
   hipLaunchKernelGGL(k_h1_decide, dim3(scan), dim3(256), 0, s, a.surv, a.lowc, a.ctl);
   hipLaunchKernelGGL(k_h1_pick, dim3(scan), dim3(256), 0, s, a.surv, a.clist, a.ctl);
   hipLaunchKernelGGL(k_h1_commit<WPL>, dim3((unsigned)cap), dim3(256), 0, s, a.tri, a.keys, a.ib,
-                     a.inv, a.table, a.owner, a.LWE, a.clist, a.ctl);
+                     a.inv, a.table, a.owner, a.LWE, a.clist, a.surv, a.store, a.sadds, a.cap,
+                     a.ctl);
   hipLaunchKernelGGL(k_h1_mark, dim3(scan), dim3(256), 0, s, a.surv, a.owner, a.wlist, a.ctl);
   hipLaunchKernelGGL(k_h1_rewalk<WPL>, dim3((unsigned)cap), dim3(256), 0, s, a.tri, a.keys, a.ib,
-                     a.inv, a.table, a.owner, a.LWE, a.surv, a.wlist, a.lowc, a.ctl);
+                     a.inv, a.table, a.owner, a.LWE, a.surv, a.wlist, a.lowc, a.store, a.sadds,
+                     a.cap, a.ctl);
   hipLaunchKernelGGL(k_h1_round_end, dim3(1), dim3(1), 0, s, a.ctl);
   hipLaunchKernelGGL(k_h1_live, dim3(pass), dim3(256), 0, s, a.surv, a.ctl);
   return hipGetLastError();

@@ -720,9 +720,10 @@ int plan_batch(const int64_t* offsets, int64_t nclouds, int32_t d, ph0_dtype dt,
 // ---- H1 path ----
 
 struct H1Layout {
-  int64_t E = 0, T = 0, LWE = 0;
+  int64_t E = 0, T = 0, LWE = 0, cap = 0;
   size_t h0 = 0, h0_bytes = 0, keys = 0, inv = 0, grade = 0, cnt = 0, start = 0, scan = 0,
-         tri = 0, owner = 0, lowc = 0, table = 0, surv = 0, clist = 0, wlist = 0, packed = 0,
+         tri = 0, owner = 0, lowc = 0, table = 0, surv = 0, clist = 0, wlist = 0, store = 0,
+         sadds = 0, packed = 0,
          sorted = 0, rcounts = 0, rerr = 0, ctl = 0, total = 0;
 };
 
@@ -752,6 +753,9 @@ int plan_h1(int64_t n, int32_t d, ph0_dtype dt, H1Layout* L) {
   L->surv = take(8 * (size_t)T1);
   L->clist = take(8 * (size_t)E1);
   L->wlist = take(4 * (size_t)T1);
+  L->cap = std::min<int64_t>(L->T, kH1StoreBytes / (8 * std::max<int64_t>(L->LWE, 1)));
+  L->store = take(8 * (size_t)std::max<int64_t>(L->cap, 1) * (size_t)std::max<int64_t>(L->LWE, 1));
+  L->sadds = take(4 * (size_t)std::max<int64_t>(L->cap, 1));
   L->packed = take(8 * (size_t)E1);
   L->sorted = take(8 * (size_t)E1);
   L->rcounts = take(4 * (size_t)radix_count_entries(E1));
@@ -997,6 +1001,9 @@ int ph0_h1_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, ph0_
   A.surv = static_cast<uint64_t*>(at(L.surv));
   A.clist = static_cast<uint64_t*>(at(L.clist));
   A.wlist = static_cast<uint32_t*>(at(L.wlist));
+  A.store = static_cast<uint64_t*>(at(L.store));
+  A.sadds = static_cast<uint32_t*>(at(L.sadds));
+  A.cap = L.cap;
   A.nsurv_host = 0;
   A.cus = device_cu_count();
   A.ctl = static_cast<H1Ctl*>(at(L.ctl));

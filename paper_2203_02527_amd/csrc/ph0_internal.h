@@ -195,6 +195,7 @@ hipError_t launch_batched(const BatchArgs& a, int blocks, hipStream_t s);
 
 // H1: reduction of the edge-by-triangle boundary matrix (h1.hip).
 constexpr int64_t kH1MaxN = 512;  // dense stored columns: E x ceil(E/64) words
+constexpr int64_t kH1StoreBytes = int64_t(16) << 30;  // kept survivor columns, at most
 struct H1Ctl {
   int64_t round;        // rounds completed
   int64_t T;            // triangles, n(n-1)(n-2)/6
@@ -227,6 +228,9 @@ struct H1Args {
   uint64_t* surv;        // T: survivor array, (t << 32) | low, low = ~0 once final
   uint64_t* clist;       // E: survivors committing this round
   uint32_t* wlist;       // T: survivors walking again this round (indices into surv)
+  uint64_t* store;       // cap x LWE words: the columns of survivors 0 .. cap-1
+  uint32_t* sadds;       // cap: additions made so far by those survivors
+  int64_t cap;           // survivors whose column is kept (the rest walk again)
   int64_t nsurv_host;    // entries of surv (for the grid sizes)
   int cus;
   H1Ctl* ctl;
