@@ -480,6 +480,11 @@ def main():
         "algorithmic_bytes_per_launch": round(per_launch),
     }
     if dom == "reduce_walk":
+        roofline["basis"] = ("algorithmic bytes of the dense method: one N-bit column (8 * "
+                             "ceil(N/64) B) per column addition of the sequential reduction + "
+                             "the 8 B key of each column up to the last pivot; the kernel keeps "
+                             "each stored 2-sparse column as one 4-byte index (loaded_*), and "
+                             "traffic is the counter-measured HBM bytes per launch")
         roofline["loaded_bytes_per_launch"] = round(walk_loaded / max(walk_launches, 1))
         roofline["loaded_gbs"] = round(walk_loaded / max(walk_ms, 1e-9) / 1e6, 1)
     if traffic is not None:
