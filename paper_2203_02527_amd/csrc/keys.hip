@@ -13,6 +13,8 @@
 //  * vector ALU, direct differences (any d, int8 or int16; int64 sums);
 //  * int8 MFMA Gram: delta = |x_i|^2 + |x_j|^2 - 2 <x_i, x_j>, the inner
 //    products from v_mfma_i32_32x32x32_i8 (exact int32 for d <= 32768).
+#include <type_traits>
+
 #include "ph0_internal.h"
 
 namespace ph0 {
@@ -256,14 +258,14 @@ __device__ inline void tile_regs_store(const TileRegs& r, int8_t (*xs)[64][KROW]
 // over the LDS banks.  With vec16 (d a multiple of 16 and 16-byte aligned
 // points) the rows are copied with 16-byte loads.
 template <int MODE, int KMAX>
-__global__ __launch_bounds__(256) void k_keys_mfma(const int8_t* __restrict__ x, int64_t n,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_keys_mfma(const int8_t* __restrict__ x, int64_t n,
                                                    int32_t d, int ib, int64_t ntiles,
                                                    const int32_t* __restrict__ norms,
                                                    bool vec16, KeyPass kp) {
   constexpr int kRow = KMAX + 16;
   constexpr bool kHist = MODE == kKeysFull || MODE == kKeysHist;
   __shared__ __attribute__((aligned(16))) int8_t xs[2][kTile][kRow];
-  __shared__ int32_t nrm[2][kTile];
+  __shared__ __attribute__((aligned(16))) int32_t nrm[2][kTile];
   __shared__ uint32_t lh[kHist ? kHistBins : 1];
   __shared__ uint32_t half_cnt[kTile][2];  // kept keys per (row, half of the tile's i)
   __shared__ uint32_t rbase[kTile];        // emit: colex base of each row's kept keys
@@ -274,6 +276,10 @@ __global__ __launch_bounds__(256) void k_keys_mfma(const int8_t* __restrict__ x,
   const int jsub = wave >> 1, isub = wave & 1;  // 32 x 32 sub-tile of this wave
   const int64_t step = tile_step(kp, MODE);
   const int64_t tfirst = blockIdx.x * (MODE == kKeysHist ? kp.sample : 1);
+  // The kept range [dlo, dhi) clamped to 32 bits (delta < 2^31 here).
+  const uint32_t dlo32 = kp.dlo < 0xFFFFFFFFull ? (uint32_t)kp.dlo : 0xFFFFFFFFu;
+  const uint32_t dhi32 = kp.dhi < 0xFFFFFFFFull ? (uint32_t)kp.dhi : 0xFFFFFFFFu;
+  const uint32_t span32 = dhi32 > dlo32 ? dhi32 - dlo32 : 0u;
   // One-stage tiles with 16-byte rows are loaded a tile ahead.
   const bool ahead = KMAX == 64 && vec16 && d <= 64;
   const int segs1 = ((d + 31) & ~31) >> 4;
@@ -351,52 +357,85 @@ __global__ __launch_bounds__(256) void k_keys_mfma(const int8_t* __restrict__ x,
     // D layout of a 32x32 MFMA: lane holds column n = lane % 32 and rows
     // m = 8 * (r / 4) + 4 * (lane / 32) + r % 4 for r = 0..15.  So for one
     // r, each half-wave holds one row j and 32 consecutive i.
+    //
+    // delta < 2^31 on this path (d <= 32768 int8 coordinates: at most
+    // 32768 * 255^2), so it is formed in wrapping 32-bit arithmetic, exact,
+    // and compared against the range clamped to 32 bits.  Tiles strictly
+    // below the diagonal and inside the cloud need no per-edge validity test.
     const int il = isub * 32 + (lane & 31);
     const int64_t i = i0 + il;
-    const int32_t ni = nrm[0][il];
+    const uint32_t ni = (uint32_t)nrm[0][il];
     const int half = lane >> 5;
     const uint64_t half_mask = half ? 0xFFFFFFFF00000000ull : 0x00000000FFFFFFFFull;
+    const int jrow = jsub * 32 + 4 * half;  // row of r = 0; r adds 8 (r / 4) + r % 4
+    // delta of accumulator r, from the four row norms of its group r / 4
+    auto delta_of = [&](const int4& nj, int r) -> uint32_t {
+      const int t = r & 3;
+      const int32_t nv = t == 0 ? nj.x : t == 1 ? nj.y : t == 2 ? nj.z : nj.w;
+      return (uint32_t)nv + ni - 2u * (uint32_t)c[r];
+    };
+    const bool interior = j0 >= i0 + kTile && j0 + kTile <= n;
+    auto epilogue = [&](auto full_tile) {
+      constexpr bool kInterior = decltype(full_tile)::value;
+      uint32_t kept_bits = 0;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int jl = jsub * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-      const int64_t j = j0 + jl;
-      const bool valid = j < n && i < j;
-      const uint64_t delta = (uint64_t)(int64_t)(nrm[1][jl] + ni - 2 * c[r]);
-      if constexpr (kHist) {
-        if (valid) {
-          if (MODE == kKeysFull)
-            kp.keys[j * (j - 1) / 2 + i] =
-                (delta << (2 * ib)) | ((uint64_t)j << ib) | (uint64_t)i;
-          atomicAdd(&lh[delta >> kp.hist_shift], 1u);
-        }
-      } else {
-        const bool kept = valid && delta >= kp.dlo && delta < kp.dhi;
-        const uint64_t m = __ballot(kept) & half_mask;
-        if ((lane & 31) == 0) half_cnt[jl][isub] = (uint32_t)__popcll(m);
-      }
-    }
-    if constexpr (MODE == kKeysCount) {
-      __syncthreads();
-      if (threadIdx.x < kTile)
-        kp.cnt[key_count_index(jb, threadIdx.x, ibk)] =
-            half_cnt[threadIdx.x][0] + half_cnt[threadIdx.x][1];
-    } else if constexpr (MODE == kKeysEmit) {
-      __syncthreads();
+      for (int q = 0; q < 4; ++q) {
+        const int4 nj = *reinterpret_cast<const int4*>(&nrm[1][jrow + 8 * q]);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int jl = jsub * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-        const int64_t j = j0 + jl;
-        const bool valid = j < n && i < j;
-        const uint64_t delta = (uint64_t)(int64_t)(nrm[1][jl] + ni - 2 * c[r]);
-        const bool kept = valid && delta >= kp.dlo && delta < kp.dhi;
-        const uint64_t m = __ballot(kept) & half_mask;
-        if (kept) {
-          const uint32_t below = __popcll(m & ((1ull << lane) - 1ull));
-          const uint32_t pos = rbase[jl] + (isub ? half_cnt[jl][0] : 0u) + below;
-          kp.keys[pos] = (delta << (2 * ib)) | ((uint64_t)j << ib) | (uint64_t)i;
+        for (int t = 0; t < 4; ++t) {
+          const int r = 4 * q + t;
+          const int jl = jrow + 8 * q + t;
+          const int64_t j = j0 + jl;
+          const bool valid = kInterior || (j < n && i < j);
+          const uint32_t delta = delta_of(nj, r);
+          if constexpr (kHist) {
+            if (valid) {
+              if (MODE == kKeysFull)
+                kp.keys[j * (j - 1) / 2 + i] =
+                    ((uint64_t)delta << (2 * ib)) | ((uint64_t)j << ib) | (uint64_t)i;
+              atomicAdd(&lh[(uint32_t)((uint64_t)delta >> kp.hist_shift)], 1u);
+            }
+          } else {
+            const bool kept = valid && delta - dlo32 < span32;
+            kept_bits |= (kept ? 1u : 0u) << r;
+            const uint64_t m = __ballot(kept);
+            const uint32_t hc = half ? (uint32_t)__popc((uint32_t)(m >> 32))
+                                     : (uint32_t)__popc((uint32_t)m);
+            if ((lane & 31) == 0) half_cnt[jl][isub] = hc;
+          }
         }
       }
-    }
+      if constexpr (MODE == kKeysCount) {
+        __syncthreads();
+        if (threadIdx.x < kTile)
+          kp.cnt[key_count_index(jb, threadIdx.x, ibk)] =
+              half_cnt[threadIdx.x][0] + half_cnt[threadIdx.x][1];
+      } else if constexpr (MODE == kKeysEmit) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int4 nj = *reinterpret_cast<const int4*>(&nrm[1][jrow + 8 * q]);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int r = 4 * q + t;
+            const int jl = jrow + 8 * q + t;
+            const bool kept = (kept_bits >> r) & 1u;
+            const uint64_t m = __ballot(kept) & half_mask;
+            if (kept) {
+              const int64_t j = j0 + jl;
+              const uint32_t below = __popcll(m & ((1ull << lane) - 1ull));
+              const uint32_t pos = rbase[jl] + (isub ? half_cnt[jl][0] : 0u) + below;
+              kp.keys[pos] =
+                  ((uint64_t)delta_of(nj, r) << (2 * ib)) | ((uint64_t)j << ib) | (uint64_t)i;
+            }
+          }
+        }
+      }
+    };
+    if (interior)
+      epilogue(std::true_type{});
+    else
+      epilogue(std::false_type{});
   }
   if (kHist) hist_flush(lh, kp.hist);
 }
