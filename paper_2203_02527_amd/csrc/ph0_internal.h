@@ -138,6 +138,8 @@ struct RedArgs {
   Ring ring;
   int64_t* surv;    // walk_blocks(Wcap) x walk_segment(Wcap): each block's survivors
   uint32_t* scount; // walk_blocks(Wcap): survivors per block
+  uint64_t* wstat;  // 3 x walk_blocks(Wcap): each walk block's additions, root-find
+                    // steps and table words, summed into ctl by the finish step
   RedCtl* ctl;
 };
 // Grid of the walk (and of the decide and commit steps) and the survivor

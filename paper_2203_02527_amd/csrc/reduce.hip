@@ -99,7 +99,8 @@ __global__ __launch_bounds__(256) void k_walk(const uint64_t* __restrict__ skeys
                                               int64_t Wcap, const int64_t* act0,
                                               const int64_t* act1, uint64_t* lowc,
                                               uint64_t* touch, int64_t* surv,
-                                              uint32_t* scount, int64_t seg, RedCtl* ctl) {
+                                              uint32_t* scount, int64_t seg,
+                                              uint64_t* wstat, RedCtl* ctl) {
   __shared__ uint32_t s_wave[4];
   if (ctl->done) return;
   const int64_t nA = ctl->nA, round = ctl->round, fresh_lo = ctl->fresh_lo;
@@ -218,12 +219,17 @@ __global__ __launch_bounds__(256) void k_walk(const uint64_t* __restrict__ skeys
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (s_cnt[0]) atomicAdd((unsigned long long*)&ctl->additions_all, s_cnt[0]);
-    if (s_cnt[1]) atomicAdd((unsigned long long*)&ctl->find_steps, s_cnt[1]);
-    if (s_cnt[2]) atomicAdd((unsigned long long*)&ctl->words_read, s_cnt[2]);
+    // The block's own slots (the grid is the same every round), summed once
+    // at the finish: an atomic per block and round on the three shared
+    // counters serializes at one address and showed in the walk's time.
+    uint64_t* mine = wstat + 3 * (int64_t)blockIdx.x;
+    mine[0] += s_cnt[0];
+    mine[1] += s_cnt[1];
+    mine[2] += s_cnt[2];
     if (s_bad) atomicOr(&ctl->err, 1);
   }
 }
+
 
 // Block-wide reductions for the 256-thread decide/commit kernels.
 __device__ inline uint64_t block_min_u64(uint64_t v, uint64_t* tmp /* 4 */) {
@@ -244,6 +250,21 @@ __device__ inline int64_t block_sum_i64(int64_t v, int64_t* tmp /* 4 */) {
   const int64_t r = tmp[0] + tmp[1] + tmp[2] + tmp[3];
   __syncthreads();
   return r;
+}
+
+// Sum of the walk blocks' counter slots into the control block.
+__global__ __launch_bounds__(256) void k_walk_stats(const uint64_t* wstat, int64_t blocks,
+                                                    RedCtl* ctl) {
+  int64_t c[3] = {0, 0, 0};
+  for (int64_t b = threadIdx.x; b < blocks; b += blockDim.x)
+    for (int k = 0; k < 3; ++k) c[k] += (int64_t)wstat[3 * b + k];
+  __shared__ int64_t tmp[4];
+  for (int k = 0; k < 3; ++k) c[k] = block_sum_i64(c[k], tmp);
+  if (threadIdx.x == 0) {
+    atomicAdd((unsigned long long*)&ctl->additions_all, (unsigned long long)c[0]);
+    atomicAdd((unsigned long long*)&ctl->find_steps, (unsigned long long)c[1]);
+    atomicAdd((unsigned long long*)&ctl->words_read, (unsigned long long)c[2]);
+  }
 }
 
 // Exclusive prefix of v over the block (and the block total).
@@ -476,12 +497,15 @@ int scan_blocks(int64_t Wcap) {
 
 }  // namespace
 
-// One lane per column: enough blocks to give every column of a full window
-// its own lane, up to 2048 blocks (8 per compute unit of MI355X).  Fixed,
-// not queried, so that workspace sizes do not depend on the device.
+// One lane per column, up to 512 blocks (two per compute unit of MI355X);
+// beyond that each lane takes several columns in turn.  More blocks cost
+// more than they hide: the decide and commit steps run one block per walk
+// block, each with a few atomics on the shared control block (N=16384:
+// 512 blocks 2.7 ms per barcode against 2.9 ms with 2048).  Fixed, not
+// queried, so that workspace sizes do not depend on the device.
 int walk_blocks(int64_t Wcap) {
   int64_t b = (Wcap + 255) / 256;
-  const int64_t cap = 2048;
+  const int64_t cap = 512;
   if (b > cap) b = cap;
   return (int)(b < 1 ? 1 : b);
 }
@@ -507,6 +531,8 @@ hipError_t launch_reduce_init(const RedArgs& a, int64_t E_lim, hipStream_t s) {
     return e;
   if ((e = launch_fill_u64(a.lowc, kNoValue, a.n, s)) != hipSuccess) return e;
   if ((e = launch_fill_u64(a.touch, kNoValue, a.n, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u64(a.wstat, 0ull, 3 * (int64_t)walk_blocks(a.Wcap), s)) != hipSuccess)
+    return e;
   if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(a.ring.tag), ~0ull, a.Wcap, s)) !=
       hipSuccess)
     return e;
@@ -519,7 +545,8 @@ hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_w
   const int64_t seg = walk_segment(a.Wcap);
   if (ev_walk) (void)hipEventRecord(ev_walk[0], s);
   hipLaunchKernelGGL(k_walk, dim3((unsigned)wb), dim3(256), 0, s, a.skeys, a.ib, a.part, a.ring,
-                     a.Wcap, a.act[0], a.act[1], a.lowc, a.touch, a.surv, a.scount, seg, a.ctl);
+                     a.Wcap, a.act[0], a.act[1], a.lowc, a.touch, a.surv, a.scount, seg,
+                     a.wstat, a.ctl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev_walk) (void)hipEventRecord(ev_walk[1], s);
@@ -533,6 +560,8 @@ hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_w
 }
 
 hipError_t launch_reduce_finish(const RedArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_walk_stats, dim3(1), dim3(256), 0, s, a.wstat,
+                     (int64_t)walk_blocks(a.Wcap), a.ctl);
   hipLaunchKernelGGL(k_overshoot, dim3(scan_blocks(a.Wcap)), dim3(256), 0, s, a.ring, a.Wcap,
                      a.ctl);
   return hipGetLastError();
