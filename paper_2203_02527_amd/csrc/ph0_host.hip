@@ -88,7 +88,7 @@ int64_t ring_for(int64_t n, int64_t E) {
 
 struct Layout {
   int64_t n, E, Wcap, width, tiles;
-  size_t keysA, keysB, counts, hist, err, part, surv, scount, wstat, killer, lowc, touch, act0,
+  size_t keysA, keysB, counts, hist, err, part, surv, scount, wstat, cslot, killer, lowc, touch, act0,
       act1, rtag, ra, rr, rrlo, rst, ctl, dbv, minmax, kcnt, kcnt_tot, norms, total;
 };
 
@@ -115,6 +115,7 @@ Layout make_layout(int64_t n, int32_t d) {
   L.surv = take(8 * (size_t)walk_blocks(L.Wcap) * (size_t)walk_segment(L.Wcap));
   L.scount = take(4 * (size_t)walk_blocks(L.Wcap));
   L.wstat = take(8 * 3 * (size_t)walk_blocks(L.Wcap));
+  L.cslot = take(8 * 3 * (size_t)walk_blocks(L.Wcap));
   L.killer = take(8 * (size_t)n);
   L.lowc = take(8 * (size_t)n);
   L.touch = take(8 * (size_t)n);
@@ -512,6 +513,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   ra.surv = static_cast<int64_t*>(at(L.surv));
   ra.scount = static_cast<uint32_t*>(at(L.scount));
   ra.wstat = static_cast<uint64_t*>(at(L.wstat));
+  ra.cslot = static_cast<uint64_t*>(at(L.cslot));
   ra.killer = static_cast<int64_t*>(at(L.killer));
   ra.lowc = static_cast<uint64_t*>(at(L.lowc));
   ra.touch = static_cast<uint64_t*>(at(L.touch));

@@ -32,11 +32,10 @@ struct RedCtl {
   int64_t fresh_hi;
   int64_t nA;        // carried-over active columns in act[cur]
   int64_t nA_next;   // columns appended to act[cur ^ 1] by this round's commit
-  int64_t pivots;    // committed pivots
+  int64_t pivots;    // committed pivots (summed from the commit blocks' slots)
   int64_t E_eff;     // largest committed column + 1
   int64_t round;
   uint64_t firstdup[2];  // per round parity: first survivor whose low repeats
-  uint64_t newF[2];      // per round parity: first column left active
   int64_t additions_all;
   int64_t find_steps;
   int64_t words_read;
@@ -140,6 +139,8 @@ struct RedArgs {
   uint32_t* scount; // walk_blocks(Wcap): survivors per block
   uint64_t* wstat;  // 3 x walk_blocks(Wcap): each walk block's additions, root-find
                     // steps and table words, summed into ctl by the finish step
+  uint64_t* cslot;  // 3 x walk_blocks(Wcap): each commit block's pivots, end of its
+                    // last pivot and first stayer, reduced by the advance step
   RedCtl* ctl;
 };
 // Grid of the walk (and of the decide and commit steps) and the survivor

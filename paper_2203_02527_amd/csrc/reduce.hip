@@ -312,10 +312,9 @@ __global__ __launch_bounds__(256) void k_decide(Ring ring, int64_t Wcap, const i
 // next window, and the hand-over of the active list (one thread; a separate
 // launch costs less than electing the last commit workgroup with a ticket,
 // whose same-address atomics serialize across the grid).
-__device__ void advance_round(RedCtl* ctl_, int64_t n, int64_t E, int64_t Wcap) {
+__device__ void advance_round(RedCtl* ctl_, int64_t n, int64_t E, int64_t Wcap, uint64_t nf) {
   volatile RedCtl* ctl = ctl_;
   const int64_t round = ctl->round;
-  const uint64_t nf = ctl->newF[round & 1];
   const int64_t F = nf == kNoValue ? ctl->Wend : (int64_t)nf;
   int64_t Wend = ctl->Wend;
   if (ctl->pivots >= n - 1) {
@@ -365,18 +364,25 @@ __global__ __launch_bounds__(256) void k_commit(Ring ring, int64_t Wcap, const i
                                                 const uint32_t* scount, int64_t seg,
                                                 int64_t* act0, int64_t* act1,
                                                 const uint64_t* lowc, const uint64_t* touch,
-                                                int32_t* part, int64_t* killer, RedCtl* ctl) {
+                                                int32_t* part, int64_t* killer,
+                                                uint64_t* cslot, RedCtl* ctl) {
   __shared__ int64_t itmp[4];
   __shared__ uint64_t utmp[4];
   __shared__ int64_t s_base;
   if (ctl->done) return;
   const int64_t round = ctl->round;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctl->firstdup[(round + 1) & 1] = kNoValue;
-    ctl->newF[(round + 1) & 1] = kNoValue;
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->firstdup[(round + 1) & 1] = kNoValue;
+  // This block's slot: pivots committed, end of the last one, first stayer.
+  uint64_t* slot = cslot + 3 * (int64_t)blockIdx.x;
   const uint32_t cnt = scount[blockIdx.x];
-  if (cnt == 0) return;
+  if (cnt == 0) {
+    if (threadIdx.x == 0) {
+      slot[0] = 0;
+      slot[1] = 0;
+      slot[2] = kNoValue;
+    }
+    return;
+  }
   int64_t* next = ctl->cur ? act0 : act1;
   const uint64_t fd = ctl->firstdup[round & 1];
   const int64_t* my = surv + blockIdx.x * seg;
@@ -414,18 +420,39 @@ __global__ __launch_bounds__(256) void k_commit(Ring ring, int64_t Wcap, const i
   const uint64_t last_c = block_min_u64(~(uint64_t)(last + 1), utmp);
   stay_min = block_min_u64(stay_min, utmp);
   if (threadIdx.x == 0) {
-    if (npiv) {
-      atomicAdd((unsigned long long*)&ctl->pivots, (unsigned long long)npiv);
-      atomicMax((long long*)&ctl->E_eff, (long long)~last_c);
-    }
-    if (stay_min != kNoValue)
-      atomicMin((unsigned long long*)&ctl->newF[round & 1], (unsigned long long)stay_min);
+    slot[0] = (uint64_t)npiv;
+    slot[1] = ~last_c;  // last committed position + 1, or 0
+    slot[2] = stay_min;
   }
 }
 
-__global__ void k_advance(RedCtl* ctl, int64_t n, int64_t E, int64_t Wcap) {
+// The commit blocks' slots (pivot counts, pivot ends, first stayers) are
+// reduced here, by one block, instead of three atomics per commit block on
+// the shared control block; then the round advances.
+__global__ __launch_bounds__(256) void k_advance(RedCtl* ctl, const uint64_t* cslot,
+                                                 int64_t blocks, int64_t n, int64_t E,
+                                                 int64_t Wcap) {
+  __shared__ int64_t itmp[4];
+  __shared__ uint64_t utmp[4];
   if (ctl->done) return;
-  advance_round(ctl, n, E, Wcap);
+  int64_t piv = 0;
+  uint64_t end_c = kNoValue, stay = kNoValue;  // end_c: complement, so a min finds the max
+  for (int64_t b = threadIdx.x; b < blocks; b += blockDim.x) {
+    piv += (int64_t)cslot[3 * b];
+    const uint64_t e = ~cslot[3 * b + 1];
+    end_c = e < end_c ? e : end_c;
+    stay = cslot[3 * b + 2] < stay ? cslot[3 * b + 2] : stay;
+  }
+  piv = block_sum_i64(piv, itmp);
+  end_c = block_min_u64(end_c, utmp);
+  stay = block_min_u64(stay, utmp);
+  if (threadIdx.x == 0) {
+    volatile RedCtl* vc = ctl;
+    vc->pivots = vc->pivots + piv;
+    const int64_t end = (int64_t)~end_c;
+    if (end > vc->E_eff) vc->E_eff = end;
+    advance_round(ctl, n, E, Wcap, stay);
+  }
 }
 
 __global__ void k_reduce_extend(RedCtl* ctl, int64_t E_lim) {
@@ -452,7 +479,6 @@ __global__ void k_reduce_init(RedCtl* ctl, int64_t E_lim, int64_t width, int64_t
   c.fresh_lo = 0;
   c.fresh_hi = c.Wend;
   c.firstdup[0] = c.firstdup[1] = kNoValue;
-  c.newF[0] = c.newF[1] = kNoValue;
   c.done = (n <= 1 || E_lim == 0) ? 1 : 0;
   *ctl = c;
 }
@@ -554,8 +580,9 @@ hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_w
                      a.scount, seg, a.lowc, a.ctl);
   hipLaunchKernelGGL(k_commit, dim3((unsigned)wb), dim3(256), 0, s, a.ring, a.Wcap, a.surv,
                      a.scount, seg, a.act[0], a.act[1], a.lowc, a.touch, a.part, a.killer,
-                     a.ctl);
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, a.ctl, a.n, a.E, a.Wcap);
+                     a.cslot, a.ctl);
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(256), 0, s, a.ctl, a.cslot, (int64_t)wb, a.n,
+                     a.E, a.Wcap);
   return hipGetLastError();
 }
 
