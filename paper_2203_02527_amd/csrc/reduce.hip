@@ -308,52 +308,63 @@ __global__ __launch_bounds__(256) void k_decide(Ring ring, int64_t Wcap, const i
     atomicMin((unsigned long long*)&ctl->firstdup[round & 1], (unsigned long long)best);
 }
 
-// End of a round: the next window start F (first column left active), the
-// next window, and the hand-over of the active list (one thread; a separate
-// launch costs less than electing the last commit workgroup with a ticket,
-// whose same-address atomics serialize across the grid).
-__device__ void advance_round(RedCtl* ctl_, int64_t n, int64_t E, int64_t Wcap, uint64_t nf) {
-  volatile RedCtl* ctl = ctl_;
-  const int64_t round = ctl->round;
-  const int64_t F = nf == kNoValue ? ctl->Wend : (int64_t)nf;
-  int64_t Wend = ctl->Wend;
-  if (ctl->pivots >= n - 1) {
+// End of a round: the pivots and E_eff with this round's commits, the next
+// window start F (first column left active, nf; none: the window end), the
+// next window, and the hand-over of the active list (one thread of its own
+// launch; electing the last commit workgroup with a ticket instead costs
+// more, its same-address atomics serialize across the grid).
+__device__ void advance_round(RedCtl* ctl, int64_t n, int64_t E, int64_t Wcap, uint64_t nf,
+                              int64_t new_pivots, int64_t end) {
+  // The control block is read once, up front, and written at the end: one
+  // thread that read a field back after writing it could get the old value
+  // from the scalar cache.
+  const RedCtl c = *ctl;
+  const int64_t pivots = c.pivots + new_pivots;
+  const int64_t E_eff = end > c.E_eff ? end : c.E_eff;
+  const int64_t F = nf == kNoValue ? c.Wend : (int64_t)nf;
+  int64_t Wend = c.Wend, width = c.width;
+  int32_t done = c.done, need_more = c.need_more, err = c.err;
+  if (pivots >= n - 1) {
     // Every later column reduces to zero; only columns before the last
     // pivot still need finishing (for the exact addition count).
-    if (F >= ctl->E_eff) ctl->done = 1;
+    if (F >= E_eff) done = 1;
   } else {
-    const int64_t lim = ctl->E_lim;
+    const int64_t lim = c.E_lim;
     // Window width: doubles (up to the ring's capacity) while almost every
     // column of a round becomes final, halves (down to the base width) when
     // many stay.  The end never moves back: columns already in the window
     // stay there.
-    int64_t width = ctl->width;
-    const int64_t stay = ctl->nA_next;
+    const int64_t stay = c.nA_next;
     if (stay < width / 256)
       width = 2 * width < Wcap ? 2 * width : Wcap;
     else if (stay > width / 16)
-      width = width / 2 > ctl->width_min ? width / 2 : ctl->width_min;
-    ctl->width = width;
+      width = width / 2 > c.width_min ? width / 2 : c.width_min;
     const int64_t want = F + width < lim ? F + width : lim;
     Wend = want > Wend ? want : Wend;
     if (F >= lim) {
       if (lim < E) {
-        ctl->need_more = 1;  // the host sorts the next distance range
+        need_more = 1;  // the host sorts the next distance range
       } else {
-        ctl->done = 1;
-        ctl->err |= 2;
+        done = 1;
+        err |= 2;
       }
     }
   }
-  ctl->fresh_lo = ctl->Wend;
+  ctl->pivots = pivots;
+  ctl->E_eff = E_eff;
+  ctl->width = width;
+  ctl->done = done;
+  ctl->need_more = need_more;
+  ctl->err = err;
+  ctl->fresh_lo = c.Wend;
   ctl->fresh_hi = Wend;
-  ctl->nA = ctl->nA_next;
+  ctl->nA = c.nA_next;
   ctl->nA_next = 0;
-  ctl->cur ^= 1;
+  ctl->cur = c.cur ^ 1;
   ctl->F = F;
   ctl->Wend = Wend;
-  if (Wend > ctl->maxWend) ctl->maxWend = Wend;
-  ctl->round = round + 1;
+  ctl->maxWend = Wend > c.maxWend ? Wend : c.maxWend;
+  ctl->round = c.round + 1;
 }
 
 // Commit the survivors the rule allows; append the rest to the next active
@@ -446,13 +457,7 @@ __global__ __launch_bounds__(256) void k_advance(RedCtl* ctl, const uint64_t* cs
   piv = block_sum_i64(piv, itmp);
   end_c = block_min_u64(end_c, utmp);
   stay = block_min_u64(stay, utmp);
-  if (threadIdx.x == 0) {
-    volatile RedCtl* vc = ctl;
-    vc->pivots = vc->pivots + piv;
-    const int64_t end = (int64_t)~end_c;
-    if (end > vc->E_eff) vc->E_eff = end;
-    advance_round(ctl, n, E, Wcap, stay);
-  }
+  if (threadIdx.x == 0) advance_round(ctl, n, E, Wcap, stay, piv, (int64_t)~end_c);
 }
 
 __global__ void k_reduce_extend(RedCtl* ctl, int64_t E_lim) {
