@@ -248,11 +248,16 @@ hipError_t launch_radix_pass(const uint64_t* in, uint64_t* out, int64_t count, i
   uint32_t* totals = counts + 256 * tiles;
   hipLaunchKernelGGL(k_radix_count, dim3((unsigned)tiles), dim3(kThreads), 0, s, in, count,
                      shift, bits, tiles, counts, f);
-  hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)nblocks), dim3(kThreads), 0, s, counts, len,
-                     totals);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, s, totals, nblocks);
-  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblocks), dim3(kThreads), 0, s, counts, len,
-                     totals);
+  if (nblocks == 1) {  // the counts fit one scan block: its base is 0
+    hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kThreads), 0, s, counts, len,
+                       (const uint32_t*)nullptr);
+  } else {
+    hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)nblocks), dim3(kThreads), 0, s, counts, len,
+                       totals);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, s, totals, nblocks);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblocks), dim3(kThreads), 0, s, counts, len,
+                       totals);
+  }
   hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)tiles), dim3(kThreads), 0, s, in, out,
                      count, shift, bits, tiles, counts, err, f, out_count);
   return hipGetLastError();
