@@ -550,9 +550,12 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   int64_t prevF = -1;
   int next_slot = 0, q_head = 0, q_len = 0;
   int queue[2];
+  int qburst[2] = {0, 0};  // rounds in each queued burst, by slot
+  int64_t prev_piv = 0, prev_round = 0;
   auto issue_next = [&]() -> hipError_t {
     const hipError_t e = issue(next_slot);
     queue[(q_head + q_len) & 1] = next_slot;
+    qburst[next_slot] = burst;
     ++q_len;
     next_slot ^= 1;
     return e;
@@ -585,14 +588,25 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     }
     prevF = h.F;
     // Bursts grow 2, 4, 8 (then stay): rounds queued past the end cost a few
-    // launches each, so small problems queue few.  Once every pivot exists
-    // only the columns before the last one remain (a round or two), so the
-    // bursts shrink to single rounds.
+    // launches each, so small problems queue few.  A burst is also cut to
+    // the rounds still needed at the last burst's pivot rate, less those
+    // already queued, plus one to finish the columns before the last pivot.
+    // Once every pivot exists only those columns remain (a round or two), so
+    // the bursts shrink to single rounds.
     pipelined = true;
-    if (h.pivots >= n - 1)
+    if (h.pivots >= n - 1) {
       burst = 1;
-    else if (burst < 8)
-      burst *= 2;
+    } else {
+      if (burst < 8) burst *= 2;
+      const int64_t rate = (h.pivots - prev_piv) / std::max<int64_t>(1, h.round - prev_round);
+      if (rate > 0) {
+        const int64_t queued = q_len ? qburst[queue[q_head]] : 0;
+        const int64_t need = (n - 1 - h.pivots + rate - 1) / rate + 1 - queued;
+        burst = (int)std::max<int64_t>(1, std::min<int64_t>(burst, need));
+      }
+    }
+    prev_piv = h.pivots;
+    prev_round = h.round;
     if (q_len == 0) HIPCHK(issue_next());
   }
   S.sort_chunks = chunks;
