@@ -236,7 +236,8 @@ struct KernelClock {
 // Two pinned control-block copies and their events per host thread: the
 // reduction loop inspects one burst's copy while the next burst runs.
 struct CtlReadback {
-  RedCtl* hc = nullptr;  // [2]
+  RedCtl* hc = nullptr;      // [2]
+  uint32_t* words = nullptr;  // [3]: radix error flag, distinct grades, pivot columns
   hipEvent_t ev[2] = {nullptr, nullptr};
   bool ok = false;
 };
@@ -244,8 +245,12 @@ struct CtlReadback {
 CtlReadback* pinned_ctl() {
   thread_local CtlReadback rb;
   if (!rb.ok) {
-    if (hipHostMalloc((void**)&rb.hc, 2 * sizeof(RedCtl), hipHostMallocDefault) != hipSuccess)
+    // Pinned, so that copies into it are asynchronous (a copy into pageable
+    // memory waits for the stream).
+    if (hipHostMalloc((void**)&rb.hc, 2 * sizeof(RedCtl) + 16, hipHostMallocDefault) !=
+        hipSuccess)
       return nullptr;
+    rb.words = reinterpret_cast<uint32_t*>(rb.hc + 2);
     for (int k = 0; k < 2; ++k)
       if (hipEventCreateWithFlags(&rb.ev[k], hipEventDisableTiming) != hipSuccess) return nullptr;
     rb.ok = true;
@@ -613,11 +618,11 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   S.sorted_keys = E_lim;
   HIPCHK(launch_reduce_finish(ra, s));
   HIPCHK(hipMemcpyAsync(hc, ra.ctl, sizeof(RedCtl), hipMemcpyDeviceToHost, s));
-  int32_t herr = 0;
-  HIPCHK(hipMemcpyAsync(&herr, serr, 4, hipMemcpyDeviceToHost, s));
+  uint32_t* hw = rb->words;
+  HIPCHK(hipMemcpyAsync(&hw[0], serr, 4, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   tm.mark();  // 4
-  if (herr) return fail(PH0_EDEVICE, "radix sort digit counts were inconsistent");
+  if (hw[0]) return fail(PH0_EDEVICE, "radix sort digit counts were inconsistent");
   if (hc->err & 1) return fail(PH0_EDEVICE, "a reduced column did not have exactly two rows");
   if (hc->err & 2 || hc->pivots != n - 1)
     return fail(PH0_EDEVICE, "reduction ended with %lld pivots, expected %lld",
@@ -632,19 +637,19 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   // Grades over [0, E_eff), per-vertex deaths and the barcode, in one
   // ordered pass over the pivot positions (scratch: the spare key buffer).
   uint32_t* dbv = out.dbv ? out.dbv : static_cast<uint32_t*>(at(L.dbv));
-  uint32_t distinct = 0, npiv = 0;
   if (grades_work_bytes(hc->E_eff) > 8 * (size_t)std::max<int64_t>(L.E, 2 * n + 64))
     return fail(PH0_EDEVICE, "grade scratch does not fit the key buffer");
   HIPCHK(launch_grades_and_bars(skeys, hc->E_eff, 2 * ib, ra.killer, n, spare, dbv,
-                                reinterpret_cast<uint32_t*>(out.bars), s, &distinct, &npiv));
+                                reinterpret_cast<uint32_t*>(out.bars), s, &hw[1], &hw[2]));
   tm.mark();  // 5
   if (out.killer_pos || out.killer_edge || out.killer_sqdist || out.partner)
     HIPCHK(launch_pairs_detail(ra.killer, skeys, ib, ra.part, n, out.killer_pos,
                                out.killer_edge, out.killer_sqdist, out.partner, s));
   tm.mark();  // 6
-  HIPCHK(hipMemcpyAsync(&herr, serr, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&hw[0], serr, 4, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (herr) return fail(PH0_EDEVICE, "radix sort digit counts were inconsistent");
+  const uint32_t distinct = hw[1], npiv = hw[2];
+  if (hw[0]) return fail(PH0_EDEVICE, "radix sort digit counts were inconsistent");
   if (npiv != (uint32_t)(n - 1))
     return fail(PH0_EDEVICE, "found %u pivot columns, expected %lld", npiv, (long long)(n - 1));
   S.distinct_eff = 1 + distinct;
