@@ -137,6 +137,7 @@ __global__ __launch_bounds__(256) void k_keys_alu(const T* __restrict__ x, int64
   __shared__ uint32_t lh[kHistBins];
   constexpr bool kHist = MODE == kKeysFull || MODE == kKeysHist;
   if (kHist) hist_zero(lh);
+  const int hs = kHist && kp.hist_shift_dev ? *kp.hist_shift_dev : kp.hist_shift;
 
   const int il = threadIdx.x & 63;   // i inside the tile (one per lane)
   const int jl0 = threadIdx.x >> 6;  // first j of this wave; j = jl0 + 4q
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(256) void k_keys_alu(const T* __restrict__ x, int64
       if constexpr (kHist) {
         if (valid) {
           if (MODE == kKeysFull) kp.keys[j * (j - 1) / 2 + i] = key;
-          atomicAdd(&lh[delta >> kp.hist_shift], 1u);
+          atomicAdd(&lh[delta >> hs], 1u);
         }
       } else {
         // One wave covers the 64 i of row j: a ballot counts and ranks.
@@ -270,6 +271,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   __shared__ uint32_t half_cnt[kTile][2];  // kept keys per (row, half of the tile's i)
   __shared__ uint32_t rbase[kTile];        // emit: colex base of each row's kept keys
   if (kHist) hist_zero(lh);
+  const int hs = kHist && kp.hist_shift_dev ? *kp.hist_shift_dev : kp.hist_shift;
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -393,7 +395,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
               if (MODE == kKeysFull)
                 kp.keys[j * (j - 1) / 2 + i] =
                     ((uint64_t)delta << (2 * ib)) | ((uint64_t)j << ib) | (uint64_t)i;
-              atomicAdd(&lh[(uint32_t)((uint64_t)delta >> kp.hist_shift)], 1u);
+              atomicAdd(&lh[(uint32_t)((uint64_t)delta >> hs)], 1u);
             }
           } else {
             const bool kept = valid && delta - dlo32 < span32;
@@ -438,6 +440,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       epilogue(std::false_type{});
   }
   if (kHist) hist_flush(lh, kp.hist);
+}
+
+// Histogram shift from the coordinate ranges (lo[0..d) then hi[0..d)): the
+// bit length b of sum_k (hi_k - lo_k)^2 (64 if the sum overflows), then
+// max(b - 11, 0), the same rule the host applies to the ranges it reads.
+__global__ __launch_bounds__(256) void k_dist_shift(const int32_t* __restrict__ minmax,
+                                                    int32_t d, int32_t* shift) {
+  __shared__ unsigned long long s_sum;
+  __shared__ int s_over;
+  if (threadIdx.x == 0) {
+    s_sum = 0;
+    s_over = 0;
+  }
+  __syncthreads();
+  unsigned long long b = 0;
+  int over = 0;
+  for (int32_t k = threadIdx.x; k < d; k += blockDim.x) {
+    const unsigned long long w = (unsigned long long)((int64_t)minmax[d + k] - minmax[k]);
+    const unsigned long long q = w * w;
+    over |= b + q < b;
+    b += q;
+  }
+  const unsigned long long before = atomicAdd(&s_sum, b);
+  over |= before + b < before;
+  if (over) atomicOr(&s_over, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int bits = 64;
+    if (!s_over) {
+      bits = 0;
+      while (bits < 64 && (s_sum >> bits) != 0) ++bits;
+    }
+    shift[0] = bits > 11 ? bits - 11 : 0;
+  }
 }
 
 int grid_for(int64_t count, int per_block, int cap) {
@@ -546,14 +582,20 @@ hipError_t launch_keys_pass(const void* pts, int elem_bytes, int64_t n, int32_t 
 
 hipError_t launch_keys(const void* pts, int elem_bytes, int64_t n, int32_t d, int ib,
                        uint64_t* keys, bool use_mfma, int hist_shift, uint32_t* hist,
-                       int32_t* norms, hipStream_t s) {
+                       int32_t* norms, hipStream_t s, const int32_t* hist_shift_dev) {
   KeyPass kp;
   kp.mode = kKeysFull;
   kp.keys = keys;
   kp.hist = hist;
   kp.hist_shift = hist_shift;
+  kp.hist_shift_dev = hist_shift_dev;
   kp.norms = norms;
   return launch_keys_pass(pts, elem_bytes, n, d, ib, use_mfma, kp, s);
+}
+
+hipError_t launch_dist_shift(const int32_t* minmax, int32_t d, int32_t* shift, hipStream_t s) {
+  hipLaunchKernelGGL(k_dist_shift, dim3(1), dim3(256), 0, s, minmax, d, shift);
+  return hipGetLastError();
 }
 
 }  // namespace ph0

@@ -89,7 +89,7 @@ int64_t ring_for(int64_t n, int64_t E) {
 struct Layout {
   int64_t n, E, Wcap, width, tiles;
   size_t keysA, keysB, counts, hist, err, part, surv, scount, wstat, cslot, killer, lowc, touch, act0,
-      act1, rtag, ra, rr, rrlo, rst, ctl, dbv, minmax, kcnt, kcnt_tot, norms, total;
+      act1, rtag, ra, rr, rrlo, rst, ctl, dbv, minmax, hshift, kcnt, kcnt_tot, norms, total;
 };
 
 Layout make_layout(int64_t n, int32_t d) {
@@ -129,6 +129,7 @@ Layout make_layout(int64_t n, int32_t d) {
   L.ctl = take(sizeof(RedCtl));
   L.dbv = take(4 * (size_t)n);
   L.minmax = take(8 * (size_t)d);
+  L.hshift = take(4);
   const int64_t kc = key_count_len(n) + 1;  // + 1: the scan leaves the total there
   L.kcnt = take(4 * (size_t)kc);
   L.kcnt_tot = take(4 * (size_t)scan_totals_len(kc));
@@ -238,9 +239,24 @@ struct KernelClock {
 struct CtlReadback {
   RedCtl* hc = nullptr;      // [2]
   uint32_t* words = nullptr;  // [3]: radix error flag, distinct grades, pivot columns
+  void* buf = nullptr;        // coordinate ranges and histogram, grown on demand
+  size_t buf_bytes = 0;
   hipEvent_t ev[2] = {nullptr, nullptr};
   bool ok = false;
 };
+
+// The calling thread's pinned read-back area of at least `bytes` bytes
+// (nothing is in flight into it between calls: every call ends synchronized).
+void* pinned_buf(CtlReadback* rb, size_t bytes) {
+  if (rb->buf_bytes < bytes) {
+    if (rb->buf) (void)hipHostFree(rb->buf);
+    rb->buf = nullptr;
+    rb->buf_bytes = 0;
+    if (hipHostMalloc(&rb->buf, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    rb->buf_bytes = bytes;
+  }
+  return rb->buf;
+}
 
 CtlReadback* pinned_ctl() {
   thread_local CtlReadback rb;
@@ -307,28 +323,21 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   PoolScope pool_scope;
   Timer tm(st != nullptr, s);
   tm.mark();  // 0
-  // Bound on the squared distance from the per-dimension coordinate ranges
-  // (lo[0..d) then hi[0..d)).
+  // The per-dimension coordinate ranges (lo[0..d) then hi[0..d)) bound the
+  // squared distance.  The histogram's shift follows from them on the
+  // device, and the host reads the ranges back with the histogram, so the
+  // bound costs no wait of its own; it is checked before any key is used.
+  CtlReadback* rb = pinned_ctl();
+  if (!rb) return fail(PH0_ENOMEM, "pinned host allocation failed");
+  const size_t ranges_bytes = align_up(8 * (size_t)d);
+  char* back = static_cast<char*>(pinned_buf(rb, ranges_bytes + 4 * (size_t)kHistBins));
+  if (!back) return fail(PH0_ENOMEM, "pinned host allocation failed");
+  const int32_t* ranges = reinterpret_cast<const int32_t*>(back);
+  const uint32_t* h = reinterpret_cast<const uint32_t*>(back + ranges_bytes);
   int32_t* mm = static_cast<int32_t*>(at(L.minmax));
-  std::vector<int32_t> ranges(2 * (size_t)d);
+  int32_t* dshift = static_cast<int32_t*>(at(L.hshift));
   HIPCHK(launch_coord_range(d_points, eb, n, d, mm, s));
-  HIPCHK(hipMemcpyAsync(ranges.data(), mm, 8 * (size_t)d, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  unsigned __int128 bound = 0;
-  for (int32_t k = 0; k < d; ++k) {
-    const int64_t w = (int64_t)ranges[d + k] - ranges[k];
-    bound += (unsigned __int128)(w * w);
-  }
-  int dbits = 0;
-  while (dbits < 100 && (bound >> dbits) != 0) ++dbits;
-  S.delta_bits = dbits;
-  if (2 * ib + dbits > 64)
-    return fail(PH0_ERANGE,
-                "packed key needs %d distance bits + 2 x %d index bits > 64 (reduce the "
-                "coordinate range)",
-                dbits, ib);
-  const SortPlan sp = plan_sort(ib, dbits);
-  S.sort_passes = sp.passes;
+  HIPCHK(launch_dist_shift(mm, d, dshift, s));
   const bool mfma = (eb == 1) && d >= 8 && d <= 32768;
   S.keys_path = mfma ? 1 : 0;
 
@@ -337,7 +346,6 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   uint32_t* counts = static_cast<uint32_t*>(at(L.counts));
   uint32_t* hist = static_cast<uint32_t*>(at(L.hist));
   int32_t* serr = static_cast<int32_t*>(at(L.err));
-  const int hist_shift = dbits > 11 ? dbits - 11 : 0;
   int32_t* norms = static_cast<int32_t*>(at(L.norms));
 
   // Large problems never store all keys: a sampled histogram picks the
@@ -355,14 +363,36 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     kp.mode = kKeysHist;
     kp.norms = norms;
     kp.hist = hist;
-    kp.hist_shift = hist_shift;
+    kp.hist_shift_dev = dshift;
     kp.sample = sample;
     HIPCHK(launch_keys_pass(d_points, eb, n, d, ib, mfma, kp, s));
   } else {
-    HIPCHK(launch_keys(d_points, eb, n, d, ib, keysA, mfma, hist_shift, hist, norms, s));
+    HIPCHK(launch_keys(d_points, eb, n, d, ib, keysA, mfma, 0, hist, norms, s, dshift));
     keys_full = true;
   }
   tm.mark();  // 2
+  // One wait: the ranges, and the histogram when the reduction follows.
+  HIPCHK(hipMemcpyAsync(back, mm, 8 * (size_t)d, hipMemcpyDeviceToHost, s));
+  if (stop == kStopAll)
+    HIPCHK(hipMemcpyAsync(back + ranges_bytes, hist, 4 * (size_t)kHistBins,
+                          hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  unsigned __int128 bound = 0;
+  for (int32_t k = 0; k < d; ++k) {
+    const int64_t w = (int64_t)ranges[d + k] - ranges[k];
+    bound += (unsigned __int128)(w * w);
+  }
+  int dbits = 0;
+  while (dbits < 100 && (bound >> dbits) != 0) ++dbits;
+  S.delta_bits = dbits;
+  if (2 * ib + dbits > 64)
+    return fail(PH0_ERANGE,
+                "packed key needs %d distance bits + 2 x %d index bits > 64 (reduce the "
+                "coordinate range)",
+                dbits, ib);
+  const SortPlan sp = plan_sort(ib, dbits);
+  S.sort_passes = sp.passes;
+  const int hist_shift = dbits > 11 ? dbits - 11 : 0;  // as the device computed it
   if (stop == kStopKeys) {
     HIPCHK(hipMemcpyAsync(out.keys, keysA, 8 * (size_t)L.E, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -416,9 +446,6 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   // geometrically): a chunk's keys are picked out of all keys by the first
   // LSD pass and sorted into the next positions of the sorted array, which
   // therefore always holds an exact prefix of the full order.
-  std::vector<uint32_t> h(kHistBins);
-  HIPCHK(hipMemcpyAsync(h.data(), hist, 4 * (size_t)kHistBins, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
   int64_t E_lim = 0;
   int bin_next = 0, chunks = 0;
   bool whole = false;
@@ -528,8 +555,6 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   ra.ring.rlo = static_cast<int32_t*>(at(L.rrlo));
   ra.ring.st = static_cast<int32_t*>(at(L.rst));
   ra.ctl = static_cast<RedCtl*>(at(L.ctl));
-  CtlReadback* rb = pinned_ctl();
-  if (!rb) return fail(PH0_ENOMEM, "pinned host allocation failed");
   RedCtl* hc = rb->hc;
   HIPCHK(launch_reduce_init(ra, E_lim, s));
   // Rounds go out in bursts, each followed by an asynchronous copy of the

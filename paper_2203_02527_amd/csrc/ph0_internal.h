@@ -72,9 +72,15 @@ hipError_t launch_coord_range(const void* pts, int elem_bytes, int64_t n, int32_
 // delta >> hist_shift over kHistBins bins (added into `hist`).  `norms`
 // (n words) is scratch for the int8 Gram path.
 constexpr int kHistBins = 2048;
+// `hist_shift_dev`, when non-null, holds the shift on the device (written by
+// launch_dist_shift) and takes the place of `hist_shift`.
 hipError_t launch_keys(const void* pts, int elem_bytes, int64_t n, int32_t d, int ib,
                        uint64_t* keys, bool use_mfma, int hist_shift, uint32_t* hist,
-                       int32_t* norms, hipStream_t s);
+                       int32_t* norms, hipStream_t s, const int32_t* hist_shift_dev = nullptr);
+// The histogram shift from the coordinate ranges (lo[0..d) then hi[0..d)):
+// max(b - 11, 0) for b the bit length of sum_k (hi_k - lo_k)^2 (64 when the
+// sum overflows), written to shift[0] on the device.
+hipError_t launch_dist_shift(const int32_t* minmax, int32_t d, int32_t* shift, hipStream_t s);
 
 // One pass of the key kernels over all tiles of the distance matrix.
 //  * kKeysFull:  every key at its colex position, and the histogram;
@@ -94,6 +100,7 @@ struct KeyPass {
   uint64_t* keys = nullptr;
   uint32_t* hist = nullptr;
   int hist_shift = 0;
+  const int32_t* hist_shift_dev = nullptr;  // when set, the shift is read here
   int64_t sample = 1;
   uint64_t dlo = 0, dhi = 0;
   uint32_t* cnt = nullptr;
