@@ -70,7 +70,8 @@ typedef struct {
   int64_t additions_all; /* column additions performed, incl. columns >= E_eff */
   int64_t find_steps;    /* root look-ups made by the parallel commit rule */
   int64_t words_read;    /* pivot-table entries (4 bytes each) loaded by the reduction */
-  int64_t rounds;        /* reduction rounds (walk, decide, commit) */
+  int64_t rounds;        /* reduction rounds (walk, decide, commit), including rounds that
+                            found nothing to do while the next distance range was sorted */
   int64_t window;        /* columns reduced side by side in one round */
   int32_t sort_passes;   /* LSD radix passes over the distance bits */
   int32_t delta_bits;    /* bits of the squared-distance bound */
