@@ -74,22 +74,33 @@ class _H1Stats(ctypes.Structure):
 _lib = None
 
 
+def _bind(lib):
+    P = ctypes.c_void_p
+    lib.ph0o_barcode.argtypes = [P, ctypes.c_int, ctypes.c_int64, ctypes.c_int32,
+                                 ctypes.c_int, P, P, P, P, ctypes.POINTER(_Stats)]
+    lib.ph0o_barcode.restype = ctypes.c_int
+    lib.ph0o_sorted_edges.argtypes = [P, ctypes.c_int, ctypes.c_int64, ctypes.c_int32,
+                                      P, P, P, P, P, ctypes.POINTER(ctypes.c_int64)]
+    lib.ph0o_sorted_edges.restype = ctypes.c_int
+    lib.ph0o_h1.argtypes = [P, ctypes.c_int, ctypes.c_int64, ctypes.c_int32, ctypes.c_int,
+                            P, P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                            ctypes.POINTER(_H1Stats)]
+    lib.ph0o_h1.restype = ctypes.c_int
+    return lib
+
+
+def build_planted(define: str, out_dir: str):
+    """The oracle compiled with one PH0O_PLANT_* switch (a known mistake),
+    loaded from out_dir: only for the tests that show a pin catches it."""
+    lib = os.path.join(out_dir, "libph0_oracle_%s.so" % define.lower())
+    _compile(_SRC, lib, ["-D" + define], True)
+    return _bind(ctypes.CDLL(lib))
+
+
 def _load():
     global _lib
     if _lib is None:
-        lib = ctypes.CDLL(build())
-        P = ctypes.c_void_p
-        lib.ph0o_barcode.argtypes = [P, ctypes.c_int, ctypes.c_int64, ctypes.c_int32,
-                                     ctypes.c_int, P, P, P, P, ctypes.POINTER(_Stats)]
-        lib.ph0o_barcode.restype = ctypes.c_int
-        lib.ph0o_sorted_edges.argtypes = [P, ctypes.c_int, ctypes.c_int64, ctypes.c_int32,
-                                          P, P, P, P, P, ctypes.POINTER(ctypes.c_int64)]
-        lib.ph0o_sorted_edges.restype = ctypes.c_int
-        lib.ph0o_h1.argtypes = [P, ctypes.c_int, ctypes.c_int64, ctypes.c_int32, ctypes.c_int,
-                                P, P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
-                                ctypes.POINTER(_H1Stats)]
-        lib.ph0o_h1.restype = ctypes.c_int
-        _lib = lib
+        _lib = _bind(ctypes.CDLL(build()))
     return _lib
 
 
@@ -171,16 +182,17 @@ class H1Result:
     columns: int
 
 
-def h1_barcode(points: np.ndarray, early_exit: bool = True) -> H1Result:
+def h1_barcode(points: np.ndarray, early_exit: bool = True, lib=None) -> H1Result:
     """H1 of the same filtration: dense F2 reduction of the edge-by-triangle
-    boundary matrix (readings in ph0_oracle.cpp)."""
+    boundary matrix (readings in ph0_oracle.cpp).  `lib` selects a planted
+    build (build_planted) in the pin tests."""
     x, eb = _points(points)
     n, d = x.shape
     if n < 1 or d < 1:
         raise ValueError("need N >= 1 and d >= 1")
     E = n * (n - 1) // 2
     cap = max(E - n + 1, 0)
-    lib = _load()
+    lib = lib or _load()
     toe = np.empty(E, np.int64)
     b = np.empty(max(cap, 1), np.uint32)
     dd = np.empty(max(cap, 1), np.uint32)

@@ -38,7 +38,11 @@
 //
 // Parity unpinned: none.  Every output is pinned in the test suite against
 // something other than this file (Kruskal and union-find, brute-force
-// component counts, closed forms, library distance/sort routines).
+// component counts, closed forms, library distance/sort routines; for H1,
+// persistent Betti numbers, the rank form of the pairing lemma and a
+// set-based reduction).  The PH0O_PLANT_* switches plant known mistakes for
+// the tests that show those pins catch them; the library is never built
+// with them.
 
 #include <algorithm>
 #include <chrono>
@@ -294,7 +298,11 @@ int ph0o_h1(const void* points, int elem_bytes, int64_t n, int32_t d, int early_
         tris.push_back(Tri{e[0], e[1], e[2], static_cast<int32_t>(third)});
       }
   std::sort(tris.begin(), tris.end(), [](const Tri& x, const Tri& y) {
+#ifdef PH0O_PLANT_H1_ORDER  // planted mistake for the pin tests only: ties by third
+    return x.e2 != y.e2 ? x.e2 < y.e2 : x.k > y.k;  // vertex descending
+#else
     return x.e2 != y.e2 ? x.e2 < y.e2 : x.k < y.k;
+#endif
   });
   s.T = static_cast<int64_t>(tris.size());
 
@@ -311,8 +319,11 @@ int ph0o_h1(const void* points, int elem_bytes, int64_t n, int32_t d, int early_
     int64_t low = low_of(col);
     while (low >= 0 && !slot[low].empty()) {
       for (int64_t w = 0; w < words; ++w) col[w] ^= slot[low][w];
-      ++s.additions;
       low = low_of(col);
+#ifdef PH0O_PLANT_H1_COUNT  // planted mistake for the pin tests only: the addition
+      if (low >= 0)          // that clears a column goes uncounted
+#endif
+      ++s.additions;
     }
     if (low >= 0) {
       slot[low] = col;

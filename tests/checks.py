@@ -192,3 +192,103 @@ def sparse_pair_walk(points: np.ndarray, early_exit: bool = True):
             e_eff = p + 1
     return dict(partner=partner, vertex_deaths=death, additions=adds, E_eff=e_eff,
                 killer=killer)
+
+
+# ---- H1 (edge-by-triangle) checks ----
+#
+# Both are written apart from the oracle.  ``h1_pairing_by_ranks`` reads the
+# pairing off ranks of submatrices of the boundary matrix (the pairing lemma
+# of persistence: row e is the low of reduced column t exactly when
+# r(>=e, <=t) - r(>=e, <t) - r(>e, <=t) + r(>e, <t) = 1, r = F2 rank of the
+# rows and columns named), so it fixes which triangle each edge pairs with
+# without performing any reduction.  ``h1_reduction_sets`` repeats the left to
+# right reduction with each column kept as a Python set of edge rows, for the
+# number of column additions.
+
+
+def h1_boundary(points: np.ndarray):
+    """Edge grades in sorted (delta, j, i) order and the triangle columns.
+
+    Triangles are ordered by (sorted position of their latest edge, the vertex
+    not on that edge); each column is the set of its three edge positions.
+    Returns (grades uint32[E], list of (latest, third, frozenset))."""
+    n = points.shape[0]
+    ds, ii, jj, gr = sorted_order(points)
+    pos = {}
+    for q in range(ds.size):
+        pos[(int(ii[q]), int(jj[q]))] = q
+    cols = []
+    for a in range(n):
+        for b in range(a + 1, n):
+            for c in range(b + 1, n):
+                sides = {(a, b): c, (a, c): b, (b, c): a}
+                q = {pos[s]: v for s, v in sides.items()}
+                latest = max(q)
+                cols.append((latest, q[latest], frozenset(q)))
+    cols.sort(key=lambda t: (t[0], t[1]))
+    return gr, cols
+
+
+def _rank_profile(masks, lo_row):
+    """F2 ranks of the first k columns restricted to rows >= lo_row, k = 0..T.
+
+    Columns are int bitmasks over edge rows; elimination keys on the lowest
+    set bit (any pivot rule gives the same rank)."""
+    keep = ~((1 << lo_row) - 1)
+    basis = {}
+    out = [0]
+    r = 0
+    for m in masks:
+        v = m & keep
+        while v:
+            lb = v & -v
+            if lb in basis:
+                v ^= basis[lb]
+            else:
+                basis[lb] = v
+                r += 1
+                break
+        out.append(r)
+    return out
+
+
+def h1_pairing_by_ranks(points: np.ndarray) -> np.ndarray:
+    """tri_of_edge[E]: the triangle index (in triangle order) paired with the
+    edge at each sorted position, -1 if none, from the pairing lemma."""
+    gr, cols = h1_boundary(points)
+    E = gr.size
+    masks = [sum(1 << e for e in c[2]) for c in cols]
+    prof = [_rank_profile(masks, lo) for lo in range(E + 1)]  # prof[e][t + 1] = r(>=e, <=t)
+    out = np.full(E, -1, np.int64)
+    for e in range(E):
+        for t in range(len(cols)):
+            mu = prof[e][t + 1] - prof[e][t] - prof[e + 1][t + 1] + prof[e + 1][t]
+            assert mu in (0, 1)
+            if mu == 1:
+                assert out[e] == -1
+                out[e] = t
+    return out
+
+
+def h1_reduction_sets(points: np.ndarray, early_exit: bool = True):
+    """Left to right reduction of the triangle columns kept as sets of edge
+    rows (low = largest row).  Returns dict(tri_of_edge, additions, pivots)."""
+    n = points.shape[0]
+    gr, cols = h1_boundary(points)
+    E = gr.size
+    want = E - (n - 1)
+    stored = {}
+    paired = np.full(E, -1, np.int64)
+    adds = pivots = 0
+    for t, (_, _, col) in enumerate(cols):
+        if early_exit and pivots == want:
+            break
+        c = set(col)
+        while c and max(c) in stored:
+            c ^= stored[max(c)]
+            adds += 1
+        if c:
+            stored[max(c)] = c
+            paired[max(c)] = t
+            pivots += 1
+    return dict(tri_of_edge=paired, additions=adds, pivots=pivots)

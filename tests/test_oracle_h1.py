@@ -135,3 +135,64 @@ def test_h1_pair_count_and_invariance(seed):
     np.testing.assert_array_equal(lit.bars, res.bars)
     np.testing.assert_array_equal(lit.tri_of_edge, res.tri_of_edge)
     assert lit.additions >= res.additions and lit.columns == res.T
+
+
+# ---- pairing and addition count, pinned apart from the oracle ----
+
+from tests import checks  # noqa: E402
+
+
+def _pin_clouds():
+    """The tiny clouds above, eight with heavy ties (N up to 9) and eight with
+    N = 10 to 16, where more pairs are not a triangle's own latest edge."""
+    rng = np.random.default_rng(77)
+    out = list(_tiny_clouds())
+    for k in range(8):
+        n = int(rng.integers(5, 10))
+        out.append(rng.integers(0, 3, size=(n, 2)).astype(np.int8))
+    for k in range(8):
+        n = int(rng.integers(10, 17))
+        hi = int(rng.choice([2, 40]))
+        out.append(rng.integers(-hi, hi + 1, size=(n, 2)).astype(np.int16))
+    return out
+
+
+@pytest.mark.parametrize("k", range(40))
+def test_h1_pairing_matches_pairing_lemma(k):
+    # Which triangle each edge pairs with, from ranks of submatrices of the
+    # boundary matrix alone: no column reduction is performed.
+    x = _pin_clouds()[k]
+    res = oracle.h1_barcode(x)
+    np.testing.assert_array_equal(res.tri_of_edge, checks.h1_pairing_by_ranks(x))
+
+
+@pytest.mark.parametrize("k", range(40))
+def test_h1_additions_match_set_reduction(k):
+    x = _pin_clouds()[k]
+    for early in (True, False):
+        res = oracle.h1_barcode(x, early_exit=early)
+        ref = checks.h1_reduction_sets(x, early_exit=early)
+        assert res.additions == ref["additions"]
+        np.testing.assert_array_equal(res.tri_of_edge, ref["tri_of_edge"])
+        assert res.pivots == ref["pivots"]
+
+
+def test_h1_pins_catch_planted_mistakes(tmp_path):
+    # Triangles of one latest edge taken in the wrong order (third vertex
+    # descending): the pairing-lemma pin must fail on some cloud.  An uncounted clearing addition must fail the
+    # set-reduction pin.  (Both mistakes leave the bars unchanged.)
+    clouds = _pin_clouds()
+    order = oracle.build_planted("PH0O_PLANT_H1_ORDER", str(tmp_path))
+    by_pairing = by_count = 0
+    for x in clouds:
+        got = oracle.h1_barcode(x, lib=order)
+        np.testing.assert_array_equal(got.bars, oracle.h1_barcode(x).bars)  # bars blind to it
+        by_pairing += not np.array_equal(got.tri_of_edge, checks.h1_pairing_by_ranks(x))
+        by_count += got.additions != checks.h1_reduction_sets(x)["additions"]
+    assert by_pairing >= 2 and by_count >= 10
+    count = oracle.build_planted("PH0O_PLANT_H1_COUNT", str(tmp_path))
+    caught = 0
+    for x in clouds:
+        got = oracle.h1_barcode(x, lib=count).additions
+        caught += got != checks.h1_reduction_sets(x)["additions"]
+    assert caught >= 10
