@@ -258,8 +258,13 @@ void* pinned_buf(CtlReadback* rb, size_t bytes) {
   return rb->buf;
 }
 
-CtlReadback* pinned_ctl() {
+CtlReadback& thread_readback() {
   thread_local CtlReadback rb;
+  return rb;
+}
+
+CtlReadback* pinned_ctl() {
+  CtlReadback& rb = thread_readback();
   if (!rb.ok) {
     // Pinned, so that copies into it are asynchronous (a copy into pageable
     // memory waits for the stream).
@@ -272,6 +277,35 @@ CtlReadback* pinned_ctl() {
     rb.ok = true;
   }
   return &rb;
+}
+
+// Waits for the stream when a call leaves before its own final wait (an
+// error return after work was queued): kernels still queued could otherwise
+// write into the caller's workspace and outputs after the call returned.
+// Success paths end synchronized and disarm it.
+struct StreamDrain {
+  hipStream_t s;
+  bool armed = true;
+  explicit StreamDrain(hipStream_t st) : s(st) {}
+  ~StreamDrain() {
+    if (armed) (void)hipStreamSynchronize(s);
+  }
+};
+
+// Frees the calling thread's pinned read-back area and timing events.  A
+// server worker calls it before it exits (the HIP runtime is alive then);
+// threads that live until process exit keep theirs (see EventPool).
+void release_thread_resources() {
+  CtlReadback& rb = thread_readback();
+  if (rb.hc) (void)hipHostFree(rb.hc);
+  if (rb.buf) (void)hipHostFree(rb.buf);
+  for (auto& e : rb.ev)
+    if (e) (void)hipEventDestroy(e);
+  rb = CtlReadback();
+  EventPool& pool = event_pool();
+  for (hipEvent_t e : pool.ev) (void)hipEventDestroy(e);
+  pool.ev.clear();
+  pool.used = 0;
 }
 
 enum Stop { kStopKeys = 1, kStopSorted = 2, kStopAll = 3 };
@@ -303,6 +337,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   S.E = L.E;
   S.index_bits = ib;
   S.window = L.width;
+  StreamDrain drain(s);
 
   if (n == 1) {
     if (stop != kStopAll) return PH0_OK;
@@ -316,6 +351,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     if (out.killer_sqdist) HIPCHK(launch_fill_u64((uint64_t*)out.killer_sqdist, ~0ull, 1, s));
     if (out.partner) HIPCHK(launch_fill_u32((uint32_t*)out.partner, ~0u, 1, s));
     HIPCHK(hipStreamSynchronize(s));
+    drain.armed = false;
     if (st) *st = S;
     return PH0_OK;
   }
@@ -396,6 +432,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   if (stop == kStopKeys) {
     HIPCHK(hipMemcpyAsync(out.keys, keysA, 8 * (size_t)L.E, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
+    drain.armed = false;
     return PH0_OK;
   }
 
@@ -437,6 +474,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     HIPCHK(hipMemcpyAsync(out.keys, skeys, 8 * (size_t)L.E, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(&herr, serr, 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    drain.armed = false;
     if (herr) return fail(PH0_EDEVICE, "radix sort digit counts were inconsistent");
     return PH0_OK;
   }
@@ -673,6 +711,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   tm.mark();  // 6
   HIPCHK(hipMemcpyAsync(&hw[0], serr, 4, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  drain.armed = false;
   const uint32_t distinct = hw[1], npiv = hw[2];
   if (hw[0]) return fail(PH0_EDEVICE, "radix sort digit counts were inconsistent");
   if (npiv != (uint32_t)(n - 1))
@@ -934,6 +973,7 @@ int ph0_barcodes_batched_device(const void* d_points, ph0_dtype dt, const int64_
   char* ws = static_cast<char*>(d_ws);
   const int eb = dt == PH0_I8 ? 1 : 2;
   PoolScope pool_scope;
+  StreamDrain drain(s);
   Timer tm(st != nullptr, s);
   tm.mark();
   HIPCHK(hipMemcpyAsync(ws + P.offs, offsets, 8 * (size_t)(nclouds + 1), hipMemcpyHostToDevice, s));
@@ -973,6 +1013,7 @@ int ph0_barcodes_batched_device(const void* d_points, ph0_dtype dt, const int64_
   std::vector<int32_t> errs((size_t)nclouds);
   HIPCHK(hipMemcpyAsync(errs.data(), ws + P.errs, 4 * (size_t)nclouds, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  drain.armed = false;
   for (int64_t c = 0; c < nclouds; ++c)
     if (errs[c])
       return fail(errs[c] == 3 ? PH0_ERANGE : PH0_EDEVICE,
@@ -1019,11 +1060,13 @@ int ph0_h1_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, ph0_
   S.T = L.T;
   *n_bars = 0;
   PoolScope pool_scope;
+  StreamDrain drain(s);
   Timer tm(st != nullptr, s);
   tm.mark();
   if (n < 3) {  // no triangle, no cycle
     if (d_tri_of_edge && L.E > 0) HIPCHK(launch_fill_u64((uint64_t*)d_tri_of_edge, ~0ull, L.E, s));
     HIPCHK(hipStreamSynchronize(s));
+    drain.armed = false;
     if (st) *st = S;
     return PH0_OK;
   }
@@ -1109,6 +1152,7 @@ int ph0_h1_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, ph0_
   if (d_tri_of_edge) HIPCHK(launch_h1_owner_out(A.owner, L.E, d_tri_of_edge, s));
   tm.mark();
   HIPCHK(hipStreamSynchronize(s));
+  drain.armed = false;
   *n_bars = m;
   if (st) {
     S.rounds = rounds;
@@ -1263,6 +1307,9 @@ void serve_worker(ph0_server* S) {
                     hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess))
       rc = fail(PH0_EDEVICE, "copy of the barcode failed");
+    // Whatever the outcome, nothing of this request may still run on the
+    // stream when its pool region goes to the next request.
+    if (s) (void)hipStreamSynchronize(s);
     R->status = rc;
     {
       std::lock_guard<std::mutex> lk(S->mu);
@@ -1272,6 +1319,7 @@ void serve_worker(ph0_server* S) {
     }
   }
   if (s) (void)hipStreamDestroy(s);
+  release_thread_resources();
 }
 
 }  // namespace

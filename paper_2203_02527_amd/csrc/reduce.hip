@@ -504,7 +504,7 @@ __global__ __launch_bounds__(256) void k_overshoot(Ring ring, int64_t Wcap, RedC
     atomicAdd((unsigned long long*)&ctl->additions_overshoot, (unsigned long long)s);
 }
 
-// Resident-sized grids: the walk keeps about 32 waves per CU busy and loops.
+// Grid of the end-of-reduction sweep: up to four 256-thread blocks per CU.
 int device_cus() {
   static int cus = 0;
   if (!cus) {

@@ -195,9 +195,28 @@ def test_key_budget_error(torch):
     x = np.zeros((4097, 128), np.int16)
     x[0, :] = -32768
     x[1, :] = 32767
+    stream = torch.cuda.Stream()
     with pytest.raises(ph0.Ph0Error) as ei:
-        ph0.ph0_barcodes_device(_dev(torch, x))
+        ph0.ph0_barcodes_device(_dev(torch, x), stream=stream)
     assert ei.value.code == -2
+    # an error return leaves nothing queued on the caller's stream
+    assert stream.query()
+
+
+def test_batched_error_return_leaves_stream_idle(torch):
+    # A fused cloud, then an oversized cloud (single-cloud path) whose key
+    # budget fails: the call reports ERANGE with nothing left running.
+    small = _cloud(9, 100, 64, -100, 100, np.int16)
+    big = np.zeros((8193, 64), np.int16)  # 38 distance bits + 2 x 14 index bits
+    big[0, :] = -32768
+    big[1, :] = 32767
+    pts = np.concatenate([small, big])
+    offsets = np.array([0, 100, 8293], np.int64)
+    stream = torch.cuda.Stream()
+    with pytest.raises(ph0.Ph0Error) as ei:
+        ph0.ph0_barcodes_batched_device(_dev(torch, pts), offsets, stream=stream)
+    assert ei.value.code == -2
+    assert stream.query()
 
 
 def test_uniform_workload_n256(torch):
