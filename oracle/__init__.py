@@ -97,6 +97,15 @@ def build_planted(define: str, out_dir: str):
     return _bind(ctypes.CDLL(lib))
 
 
+def build_native(out_dir: str):
+    """The oracle compiled with -O3 -march=native for the host it runs on,
+    loaded from out_dir: for timing it as the CPU baseline (the source is the
+    same; only the instruction set the compiler may use differs)."""
+    lib = os.path.join(out_dir, "libph0_oracle_native.so")
+    _compile(_SRC, lib, ["-march=native"], True)
+    return _bind(ctypes.CDLL(lib))
+
+
 def _load():
     global _lib
     if _lib is None:
@@ -142,13 +151,14 @@ class OracleResult:
         return out
 
 
-def barcode(points: np.ndarray, early_exit: bool = True) -> OracleResult:
-    """Run the full oracle on an N x d int8/int16 cloud."""
+def barcode(points: np.ndarray, early_exit: bool = True, lib=None) -> OracleResult:
+    """Run the full oracle on an N x d int8/int16 cloud (`lib`: a build from
+    build_native, else the portable one)."""
     x, eb = _points(points)
     n, d = x.shape
     if n < 1 or d < 1:
         raise ValueError("need N >= 1 and d >= 1")
-    lib = _load()
+    lib = lib or _load()
     dv = np.empty(n, np.uint32)
     can = np.empty(n, np.uint32)
     kp = np.empty(n, np.int64)

@@ -3,7 +3,10 @@
 Calls only the CPU oracle (oracle/) on the seeded generators; no value here
 comes from the GPU library.  Run from the repository root:
 
-    python tests/golden/make_golden.py [workload ...]
+    python tests/golden/make_golden.py [--seeds A-B] [workload ...]
+
+Seeds 0-9 of every workload are stored (the parity seeds); --seeds limits
+the run to a range.
 """
 import hashlib
 import json
@@ -47,14 +50,21 @@ def record(name: str, seed: int) -> dict:
     }
 
 
-def main(names):
+def main(names, seeds):
     for name in names:
-        rec = record(name, 0)
-        with open(os.path.join(HERE, "oracle_%s_s0.json" % name), "w") as f:
-            json.dump(rec, f, indent=1, sort_keys=True)
-            f.write("\n")
-        print(name, rec["E_eff"], rec["additions"], flush=True)
+        for seed in seeds:
+            rec = record(name, seed)
+            with open(os.path.join(HERE, "oracle_%s_s%d.json" % (name, seed)), "w") as f:
+                json.dump(rec, f, indent=1, sort_keys=True)
+                f.write("\n")
+            print(name, seed, rec["E_eff"], rec["additions"], flush=True)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or list(synth.WORKLOADS))
+    args = sys.argv[1:]
+    seeds = range(10)
+    if args and args[0] == "--seeds":
+        lo, hi = args[1].split("-")
+        seeds = range(int(lo), int(hi) + 1)
+        args = args[2:]
+    main(args or list(synth.WORKLOADS), seeds)

@@ -50,10 +50,11 @@ def test_batch_workload_sample_matches_oracle(torch):
     _check(bars, pts, offsets)
 
 
-@pytest.mark.skip(reason="this case hung an MI355X run (killed after 180 s of silence); a "
-                  "thread-level CPU emulation of the fused kernel on the same clouds terminates "
-                  "and matches the oracle, so the cause is not yet shown; kept off the GPU "
-                  "until it is")
+@pytest.mark.skip(reason="this case hung an MI355X run with the first version of the fused "
+                  "kernel (killed after 180 s of silence); the cause was never shown.  The "
+                  "current kernel runs the same fused clouds correctly in a bounds-checked "
+                  "CPU emulation (tests/test_batched_emulation.py), which shows no cause "
+                  "either, so the case stays off the GPU")
 def test_edge_cases_and_oversized_clouds(torch):
     rng = np.random.default_rng(3)
     clouds = [
@@ -71,6 +72,17 @@ def test_edge_cases_and_oversized_clouds(torch):
     pts, offsets = _concat(clouds)
     bars = _run(torch, pts, offsets)
     _check(bars, pts, offsets)
+
+
+def test_host_entry_point_matches_device_entry_point(torch):
+    pts, offsets = synth.batch_clouds(count=120, seed=5)
+    dev = _run(torch, pts, offsets)
+    host = ph0.ph0_barcodes_batched(pts, offsets)
+    np.testing.assert_array_equal(host, dev)
+    tuned = ph0.ph0_barcodes_batched(pts, offsets,
+                                     tune_json='{"chunk_mult": [1, 2, 3, 1000], "blocks_per_cu": 1}')
+    np.testing.assert_array_equal(tuned, dev)
+    _check(host, pts, offsets, which=range(0, 120, 7))
 
 
 def test_int8_high_dimension_clouds(torch):

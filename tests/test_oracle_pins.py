@@ -2,6 +2,8 @@
 than the oracle itself (hand-derived closed forms, Kruskal/union-find,
 scipy's MST and distance routines, brute-force component counts, the 2-sparse
 pair walk, and invariants of the barcode).  CPU only."""
+import os
+
 import numpy as np
 import pytest
 
@@ -186,3 +188,31 @@ def test_unit_square_generator_is_a_fixed_point_grid():
     # the grid is rint(u * scale) of the seeded uniform draws
     u = np.random.default_rng(9).random((500, 2))
     np.testing.assert_array_equal(x, np.rint(u * synth.UNIT_SCALE).astype(np.int16))
+
+
+def test_stored_workload_records_are_the_oracles():
+    """The stored full-size records (tests/golden/oracle_*_s*.json) exist for
+    seeds 0-9 of every single-cloud workload, match the generator's points,
+    and -- for the 256-point workload, cheap enough here -- equal a fresh
+    oracle run."""
+    import hashlib
+    import json
+
+    from paper_2203_02527_amd import synth
+    from tests.conftest import GOLDEN
+
+    def sha(a, dt):
+        return hashlib.sha256(np.ascontiguousarray(a).astype(dt).tobytes()).hexdigest()
+
+    for name in synth.WORKLOADS:
+        for seed in range(10):
+            rec = json.load(open(os.path.join(GOLDEN, "oracle_%s_s%d.json" % (name, seed))))
+            assert rec["workload"] == name and rec["seed"] == seed
+            assert rec["pivots"] == rec["n"] - 1
+            if name == "uniform_n256_d3_i16":
+                x = synth.workload(name, seed=seed)
+                assert sha(x, x.dtype) == rec["points_sha256"]
+                res = oracle.barcode(x)
+                assert sha(res.canonical, "<u4") == rec["canonical_sha256"]
+                assert sha(res.partner, "<i4") == rec["partner_sha256"]
+                assert (res.E_eff, res.additions) == (rec["E_eff"], rec["additions"])

@@ -201,3 +201,36 @@ def test_h1_round_rules_reproduce_the_sequential_reduction():
             got[q] = t
         np.testing.assert_array_equal(got, ref.tri_of_edge)
         assert adds == ref.additions
+
+
+def test_first_repeat_from_returning_minima():
+    """The round kernel finds the first survivor whose low repeats an earlier
+    survivor's low without a pass of its own: each survivor lowers the
+    per-row minimum with an atomic that returns the previous value, and
+    when that value is another survivor of the same round, the larger of the
+    two positions is a candidate.  Whatever order the atomics land in, the
+    smallest candidate is the second-smallest survivor of some row and no
+    candidate is smaller -- exactly the sequential definition."""
+    rng = np.random.default_rng(11)
+    for _ in range(400):
+        m = int(rng.integers(1, 40))
+        pos = rng.choice(10_000, size=m, replace=False)
+        low = rng.integers(0, max(1, m // 3 + 1), size=m)
+        # the definition: smallest position whose low already occurred earlier
+        want = None
+        seen = set()
+        for p, r in sorted(zip(pos.tolist(), low.tolist())):
+            if r in seen and want is None:
+                want = p
+            seen.add(r)
+        for _ in range(5):
+            cur = {}
+            cand = None
+            for k in rng.permutation(m):
+                p, r = int(pos[k]), int(low[k])
+                old = cur.get(r)
+                if old is not None:
+                    hi = max(old, p)
+                    cand = hi if cand is None else min(cand, hi)
+                cur[r] = p if old is None else min(old, p)
+            assert cand == want
