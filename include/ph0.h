@@ -171,6 +171,21 @@ int ph0_barcodes_batched_device(const void* d_points, ph0_dtype dt, const int64_
                                 size_t ws_bytes, const ph0_batch_tuning* tune,
                                 void* hip_stream, ph0_stats* st);
 
+/* The same batched computation on host memory: points (offsets[nclouds] x d
+ * rows, host), out (offsets[nclouds] bars, host; cloud c's canonical barcode
+ * in rows offsets[c] .. offsets[c+1]-1).  The library allocates its device
+ * buffers (points, bars, workspace) and a stream, copies in, runs
+ * ph0_barcodes_batched_device, copies out and frees everything before it
+ * returns.  tune_json (NULL = built-in table) is a JSON object with only the
+ * members "chunk_mult" (up to four non-negative integers, per size bucket as
+ * in ph0_batch_tuning) and "blocks_per_cu" (a non-negative integer); zero
+ * means built-in.  Any other member, or malformed text, is EINVAL before any
+ * device call.  `st` may be NULL.  Errors as ph0_barcodes_batched_device, and
+ * ENOMEM when the device allocation fails. */
+int ph0_barcodes_batched(const void* points, ph0_dtype dt, const int64_t* offsets,
+                         int64_t nclouds, int32_t d, ph0_bar* out, const char* tune_json,
+                         ph0_stats* st);
+
 /* ---- Serving: continuous batching of independent requests -------------- */
 
 /* A server owns one device memory pool of mem_budget_bytes and up to

@@ -1170,6 +1170,122 @@ int ph0_h1_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, ph0_
   return PH0_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Tuning text of ph0_barcodes_batched: a JSON object whose only members are
+// "chunk_mult" (an array of up to four non-negative integers) and
+// "blocks_per_cu" (a non-negative integer), e.g.
+//   {"chunk_mult": [6, 6, 8, 48], "blocks_per_cu": 2}
+// Anything else is rejected, so a misspelt key cannot pass silently.
+struct JsonCursor {
+  const char* p;
+  void ws() {
+    while (*p == ' ' || *p == '\t' || *p == '\n' || *p == '\r') ++p;
+  }
+  bool eat(char c) {
+    ws();
+    if (*p != c) return false;
+    ++p;
+    return true;
+  }
+  bool integer(int32_t* v) {
+    ws();
+    if (*p < '0' || *p > '9') return false;
+    int64_t x = 0;
+    while (*p >= '0' && *p <= '9') {
+      x = 10 * x + (*p++ - '0');
+      if (x > 1000000) return false;
+    }
+    *v = (int32_t)x;
+    return true;
+  }
+  bool key(char* buf, size_t cap) {
+    if (!eat('"')) return false;
+    size_t k = 0;
+    while (*p && *p != '"') {
+      if (k + 1 >= cap) return false;
+      buf[k++] = *p++;
+    }
+    buf[k] = 0;
+    if (*p != '"') return false;
+    ++p;
+    return true;
+  }
+};
+
+int parse_tuning(const char* text, ph0_batch_tuning* t) {
+  *t = ph0_batch_tuning{};
+  JsonCursor c{text};
+  if (!c.eat('{')) return fail(PH0_EINVAL, "tuning: expected a JSON object");
+  bool closed = c.eat('}');
+  while (!closed) {
+    char k[32];
+    if (!c.key(k, sizeof(k)) || !c.eat(':')) return fail(PH0_EINVAL, "tuning: expected \"key\":");
+    if (!strcmp(k, "chunk_mult")) {
+      if (!c.eat('[')) return fail(PH0_EINVAL, "tuning: chunk_mult must be an array");
+      int m = 0;
+      if (!c.eat(']')) {
+        while (true) {
+          if (m >= 4 || !c.integer(&t->chunk_mult[m++]))
+            return fail(PH0_EINVAL, "tuning: chunk_mult takes up to 4 non-negative integers");
+          if (c.eat(']')) break;
+          if (!c.eat(',')) return fail(PH0_EINVAL, "tuning: expected ',' or ']'");
+        }
+      }
+    } else if (!strcmp(k, "blocks_per_cu")) {
+      if (!c.integer(&t->blocks_per_cu))
+        return fail(PH0_EINVAL, "tuning: blocks_per_cu must be a non-negative integer");
+    } else {
+      return fail(PH0_EINVAL, "tuning: unknown key \"%s\"", k);
+    }
+    if (c.eat('}')) closed = true;
+    else if (!c.eat(',')) return fail(PH0_EINVAL, "tuning: expected ',' or '}'");
+  }
+  c.ws();
+  if (*c.p) return fail(PH0_EINVAL, "tuning: trailing text after the object");
+  return PH0_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ph0_barcodes_batched(const void* points, ph0_dtype dt, const int64_t* offsets,
+                         int64_t nclouds, int32_t d, ph0_bar* out, const char* tune_json,
+                         ph0_stats* st) {
+  if (!points) return fail(PH0_EINVAL, "points pointer is NULL");
+  if (!out) return fail(PH0_EINVAL, "output pointer is NULL");
+  ph0_batch_tuning tune = {};
+  int rc = PH0_OK;
+  if (tune_json && (rc = parse_tuning(tune_json, &tune))) return rc;
+  size_t ws = 0;
+  if ((rc = ph0_batched_workspace_bytes(offsets, nclouds, d, dt, &tune, &ws))) return rc;
+  const int64_t rows = offsets[nclouds];
+  const size_t pbytes = (size_t)rows * d * (dt == PH0_I8 ? 1 : 2);
+  const size_t obytes = 8 * (size_t)rows;
+  DeviceBuffer dp, dout, dws;
+  if (hipMalloc(&dp.p, std::max<size_t>(pbytes, 1)) != hipSuccess ||
+      hipMalloc(&dout.p, std::max<size_t>(obytes, 8)) != hipSuccess ||
+      hipMalloc(&dws.p, ws) != hipSuccess)
+    return fail(PH0_ENOMEM, "device allocation of %zu bytes failed", ws + pbytes + obytes);
+  hipStream_t s;
+  HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  if (pbytes && hipMemcpyAsync(dp.p, points, pbytes, hipMemcpyHostToDevice, s) != hipSuccess)
+    rc = fail(PH0_EDEVICE, "copy of points to the device failed");
+  if (!rc)
+    rc = ph0_barcodes_batched_device(dp.p, dt, offsets, nclouds, d,
+                                     static_cast<ph0_bar*>(dout.p), dws.p, ws, &tune, s, st);
+  if (!rc && obytes &&
+      (hipMemcpyAsync(out, dout.p, obytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
+       hipStreamSynchronize(s) != hipSuccess))
+    rc = fail(PH0_EDEVICE, "copy of the barcodes to the host failed");
+  (void)hipStreamSynchronize(s);
+  (void)hipStreamDestroy(s);
+  return rc;
+}
+
 int ph0_barcodes(const void* points, ph0_dtype dt, int64_t n, int32_t d, ph0_bar* out,
                  ph0_stats* st) {
   int rc = check_args(points, dt, n, d);

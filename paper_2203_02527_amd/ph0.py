@@ -10,6 +10,7 @@ current torch stream (or the one given); host entry points take numpy.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 from dataclasses import dataclass
 
@@ -106,6 +107,8 @@ _SIGS = {
                                     ctypes.c_int),
     "ph0_barcodes_batched_device": ([_P, ctypes.c_int, _P, _I64, _I32, _P, _P, ctypes.c_size_t, _P, _P,
                                      ctypes.POINTER(ph0_stats)], ctypes.c_int),
+    "ph0_barcodes_batched": ([_P, ctypes.c_int, _P, _I64, _I32, _P, ctypes.c_char_p,
+                              ctypes.POINTER(ph0_stats)], ctypes.c_int),
     "ph0_server_create": ([ctypes.c_size_t, _I32, ctypes.POINTER(_P)], ctypes.c_int),
     "ph0_server_request_bytes": ([_I64, _I32, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "ph0_server_submit": ([_P, _P, ctypes.c_int, _I64, _I32, ctypes.c_uint64], ctypes.c_int),
@@ -394,6 +397,38 @@ def ph0_barcodes_batched_device(points, offsets, out=None, workspace=None, tunin
         _ptr(x), _dtype_code(x.dtype), o.ctypes.data_as(_P), o.size - 1, d, _ptr(out),
         _ptr(workspace), workspace.numel(), None if tuning is None else ctypes.byref(tuning),
         _stream_ptr(stream), ctypes.byref(st)))
+    return (out, st.to_dict()) if with_stats else out
+
+
+def _default_tune_json():
+    """The autotuner's table as the tuning text ph0_barcodes_batched takes."""
+    t = default_tuning()
+    if t is None:
+        return None
+    return json.dumps({"chunk_mult": list(t.chunk_mult), "blocks_per_cu": t.blocks_per_cu})
+
+
+def ph0_barcodes_batched(points: np.ndarray, offsets, tune_json=None, with_stats=False):
+    """Barcodes of many clouds on host memory (the library copies in and out).
+
+    Returns an (offsets[-1], 2) uint32 array, each cloud's canonical barcode
+    in its own rows.  tune_json: the tuning text (None: the autotuner's table,
+    or the built-in values when there is none).
+    """
+    x = np.ascontiguousarray(points)
+    if x.ndim != 2:
+        raise ValueError("points must be a 2-D (rows, d) array")
+    o = _offsets(offsets)
+    if int(o[-1]) != x.shape[0]:
+        raise ValueError("offsets[-1] must equal the number of rows")
+    if tune_json is None:
+        tune_json = _default_tune_json()
+    out = np.empty((x.shape[0], 2), np.uint32)
+    st = ph0_stats()
+    _check(lib().ph0_barcodes_batched(
+        x.ctypes.data_as(_P), _dtype_code(x.dtype), o.ctypes.data_as(_P), o.size - 1, x.shape[1],
+        out.ctypes.data_as(_P), None if tune_json is None else tune_json.encode(),
+        ctypes.byref(st)))
     return (out, st.to_dict()) if with_stats else out
 
 

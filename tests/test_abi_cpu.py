@@ -91,3 +91,18 @@ def test_h1_workspace_bytes_and_size_limit():
     with pytest.raises(ph0.Ph0Error) as ei:
         ph0.ph0_h1_workspace_bytes(0, 3, np.int16)
     assert ei.value.code == -1
+
+
+def test_batched_host_entry_rejects_bad_tuning_text_before_device_use():
+    pts = np.zeros((6, 3), np.int16)
+    offsets = np.array([0, 2, 6], np.int64)
+    for bad in ('', '[]', '{"chunk_mult": [1, 2, 3, 4, 5]}', '{"chunk_mult": [-1]}',
+                '{"blocks": 1}', '{"blocks_per_cu": 1,}', '{"blocks_per_cu": 1} x',
+                '{"chunk_mult": [1, 2', '{"chunk_mult"'):
+        with pytest.raises(ph0.Ph0Error) as ei:
+            ph0.ph0_barcodes_batched(pts, offsets, tune_json=bad)
+        assert ei.value.code == -1, bad
+        assert "tuning" in str(ei.value), bad
+    with pytest.raises(ph0.Ph0Error) as ei:  # offsets checked before any device call
+        ph0.ph0_barcodes_batched(pts, np.array([1, 2, 6], np.int64), tune_json="{}")
+    assert ei.value.code == -1
