@@ -186,6 +186,29 @@ int ph0_barcodes_batched(const void* points, ph0_dtype dt, const int64_t* offset
                          int64_t nclouds, int32_t d, ph0_bar* out, const char* tune_json,
                          ph0_stats* st);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same batched
+ * computation as ph0_barcodes_batched_device, with no workspace argument.
+ * Its workspace is a fixed 128 MiB device array inside the library (one per
+ * device, held from the library's load until the process ends); the call
+ * makes no device or pinned-host allocation and no hipFree.
+ *   - Only clouds the fused kernel takes are accepted: every cloud needs
+ *     n <= 512, n * d <= 8192 and d <= 64, otherwise EINVAL (nothing runs).
+ *   - The workgroup count is lowered until 20 * emax bytes per workgroup
+ *     (emax = n(n-1)/2 of the largest cloud) plus 16 bytes per cloud fit the
+ *     array; when even one workgroup does not fit (more than about 8 million
+ *     clouds), ENOMEM (nothing runs).
+ *   - All calls on one device share the array: calls that overlap on one
+ *     device (two host threads, or two streams without an ordering between
+ *     them) race and give undefined results.  Each call clears what must
+ *     start at zero, so sequential calls are independent.
+ * Returns after the work is complete, like the other stream calls.  Results
+ * are identical to ph0_barcodes_batched_device on the same clouds. */
+int ph0_barcodes_batched_device_noalloc(const void* d_points, ph0_dtype dt,
+                                        const int64_t* offsets, int64_t nclouds, int32_t d,
+                                        ph0_bar* d_out, const ph0_batch_tuning* tune,
+                                        void* hip_stream);
+
 /* ---- Serving: continuous batching of independent requests -------------- */
 
 /* A server owns one device memory pool of mem_budget_bytes and up to

@@ -58,6 +58,9 @@ constexpr int32_t kBlocksPerCu = 2;
 // round trips cost more than the stored keys).
 constexpr int64_t kRecomputeMinE = int64_t(1) << 22;
 constexpr size_t kAlign = 256;
+// Size of the fixed device array that ph0_barcodes_batched_device_noalloc
+// uses as its workspace (per device, held until the process ends).
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -755,8 +758,11 @@ int device_cu_count() {
   return cus;
 }
 
+// `cap_bytes` (0 = none) caps the workspace: the workgroup count is lowered
+// until the per-workgroup scratch fits, and ENOMEM results when even one
+// workgroup does not.
 int plan_batch(const int64_t* offsets, int64_t nclouds, int32_t d, ph0_dtype dt,
-               const ph0_batch_tuning* tune, BatchPlan* P) {
+               const ph0_batch_tuning* tune, BatchPlan* P, size_t cap_bytes = 0) {
   if (!offsets) return fail(PH0_EINVAL, "offsets pointer is NULL");
   if (nclouds < 1) return fail(PH0_EINVAL, "nclouds must be >= 1");
   if (d < 1) return fail(PH0_EINVAL, "d must be >= 1");
@@ -797,6 +803,16 @@ int plan_batch(const int64_t* offsets, int64_t nclouds, int32_t d, ph0_dtype dt,
   P->ord = take(4 * std::max<size_t>(P->order.size(), 1));
   P->errs = take(4 * (size_t)nclouds);
   P->queue = take(4);
+  const size_t per_block = 20 * (size_t)std::max<int64_t>(P->emax, 1);  // 2 keys + a grade
+  if (cap_bytes) {
+    const size_t fixed = o + 2 * kAlign + P->plain_bytes;
+    const int64_t fit = cap_bytes > fixed ? (int64_t)((cap_bytes - fixed) / per_block) : 0;
+    if (fit < 1)
+      return fail(PH0_ENOMEM,
+                  "the batch needs %zu bytes of fixed workspace plus %zu per workgroup; "
+                  "only %zu are available", fixed, per_block, cap_bytes);
+    P->blocks = std::min<int64_t>(P->blocks, fit);
+  }
   P->scratch = take(16 * (size_t)std::max<int64_t>(P->emax, 1) * (size_t)P->blocks);
   P->grades = take(4 * (size_t)std::max<int64_t>(P->emax, 1) * (size_t)P->blocks);
   P->plain = take(P->plain_bytes);
@@ -957,20 +973,18 @@ int ph0_batched_workspace_bytes(const int64_t* offsets, int64_t nclouds, int32_t
   return PH0_OK;
 }
 
-int ph0_barcodes_batched_device(const void* d_points, ph0_dtype dt, const int64_t* offsets,
-                                int64_t nclouds, int32_t d, ph0_bar* d_out, void* d_ws,
-                                size_t ws_bytes, const ph0_batch_tuning* tune,
-                                void* hip_stream, ph0_stats* st) {
-  if (!d_points) return fail(PH0_EINVAL, "points pointer is NULL");
-  if (!d_out) return fail(PH0_EINVAL, "output pointer is NULL");
-  if (!d_ws) return fail(PH0_EINVAL, "workspace pointer is NULL");
-  BatchPlan P;
-  int rc = plan_batch(offsets, nclouds, d, dt, tune, &P);
-  if (rc) return rc;
-  if (ws_bytes < P.total)
-    return fail(PH0_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, P.total);
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  char* ws = static_cast<char*>(d_ws);
+}  // extern "C"
+
+namespace {
+
+// The batched call once its plan is made and its workspace (P.total bytes
+// at ws) is known: copies of the offsets and the processing order, the
+// fused launch, the single-cloud path for the clouds it does not take, and
+// the per-cloud error codes.
+int batched_run(const void* d_points, ph0_dtype dt, const int64_t* offsets, int64_t nclouds,
+                int32_t d, ph0_bar* d_out, char* ws, const BatchPlan& P,
+                const ph0_batch_tuning* tune, hipStream_t s, ph0_stats* st) {
+  int rc = PH0_OK;
   const int eb = dt == PH0_I8 ? 1 : 2;
   PoolScope pool_scope;
   StreamDrain drain(s);
@@ -1027,6 +1041,86 @@ int ph0_barcodes_batched_device(const void* d_points, ph0_dtype dt, const int64_
     *st = S;
   }
   return PH0_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ph0_barcodes_batched_device(const void* d_points, ph0_dtype dt, const int64_t* offsets,
+                                int64_t nclouds, int32_t d, ph0_bar* d_out, void* d_ws,
+                                size_t ws_bytes, const ph0_batch_tuning* tune,
+                                void* hip_stream, ph0_stats* st) {
+  if (!d_points) return fail(PH0_EINVAL, "points pointer is NULL");
+  if (!d_out) return fail(PH0_EINVAL, "output pointer is NULL");
+  if (!d_ws) return fail(PH0_EINVAL, "workspace pointer is NULL");
+  BatchPlan P;
+  int rc = plan_batch(offsets, nclouds, d, dt, tune, &P);
+  if (rc) return rc;
+  if (ws_bytes < P.total)
+    return fail(PH0_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, P.total);
+  return batched_run(d_points, dt, offsets, nclouds, d, d_out, static_cast<char*>(d_ws), P, tune,
+                     static_cast<hipStream_t>(hip_stream), st);
+}
+
+}  // extern "C"
+
+// Workspace of ph0_barcodes_batched_device_noalloc: a fixed device array, so
+// that the call allocates nothing.  Host code never passes this name to a
+// kernel or a copy (in host code it is only a stand-in for the symbol): the
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_at[kMaxDevices] = {};
+
+// Address of `scratch` on the current device (each device holds its own copy
+// of the array), looked up on the first call made on that device.
+int scratch_address(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(PH0_EDEVICE, "device %d is beyond the %d devices supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(PH0_EDEVICE, "no device address for the fixed scratch array");
+    g_scratch_at[dev] = p;
+  }
+  *out = g_scratch_at[dev];
+  return PH0_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ph0_barcodes_batched_device_noalloc(const void* d_points, ph0_dtype dt,
+                                        const int64_t* offsets, int64_t nclouds, int32_t d,
+                                        ph0_bar* d_out, const ph0_batch_tuning* tune,
+                                        void* hip_stream) {
+  if (!d_points) return fail(PH0_EINVAL, "points pointer is NULL");
+  if (!d_out) return fail(PH0_EINVAL, "output pointer is NULL");
+  BatchPlan P;
+  int rc = plan_batch(offsets, nclouds, d, dt, tune, &P);
+  if (rc) return rc;
+  if (!P.big.empty()) {
+    const int32_t c = P.big.front();
+    return fail(PH0_EINVAL,
+                "cloud %d (n = %lld, d = %d) is too large for the allocation-free call: it "
+                "takes clouds with n <= %d, n * d <= %d and d <= 64 only",
+                c, (long long)(offsets[c + 1] - offsets[c]), d, kBatchMaxN, kBatchMaxPts);
+  }
+  P = BatchPlan();
+  if ((rc = plan_batch(offsets, nclouds, d, dt, tune, &P, kNoAllocScratchBytes))) return rc;
+  void* ws = nullptr;
+  if ((rc = scratch_address(&ws))) return rc;
+  return batched_run(d_points, dt, offsets, nclouds, d, d_out, static_cast<char*>(ws), P, tune,
+                     static_cast<hipStream_t>(hip_stream), nullptr);
 }
 
 int ph0_h1_workspace_bytes(int64_t n, int32_t d, ph0_dtype dt, size_t* bytes) {

@@ -109,6 +109,8 @@ _SIGS = {
                                      ctypes.POINTER(ph0_stats)], ctypes.c_int),
     "ph0_barcodes_batched": ([_P, ctypes.c_int, _P, _I64, _I32, _P, ctypes.c_char_p,
                               ctypes.POINTER(ph0_stats)], ctypes.c_int),
+    "ph0_barcodes_batched_device_noalloc": ([_P, ctypes.c_int, _P, _I64, _I32, _P, _P, _P],
+                                            ctypes.c_int),
     "ph0_server_create": ([ctypes.c_size_t, _I32, ctypes.POINTER(_P)], ctypes.c_int),
     "ph0_server_request_bytes": ([_I64, _I32, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "ph0_server_submit": ([_P, _P, ctypes.c_int, _I64, _I32, ctypes.c_uint64], ctypes.c_int),
@@ -398,6 +400,25 @@ def ph0_barcodes_batched_device(points, offsets, out=None, workspace=None, tunin
         _ptr(workspace), workspace.numel(), None if tuning is None else ctypes.byref(tuning),
         _stream_ptr(stream), ctypes.byref(st)))
     return (out, st.to_dict()) if with_stats else out
+
+
+def ph0_barcodes_batched_device_noalloc(points, offsets, out=None, tuning=None, stream=None):
+    """ph0_barcodes_batched_device without a workspace: the library's fixed
+    device array serves as one, and the C call allocates nothing (clouds
+    must have n <= 512, n * d <= 8192, d <= 64).  `out` (offsets[-1] x 2
+    int32 on the device) is allocated here only when not given."""
+    torch = _torch()
+    x = _points_dev(points)
+    o = _offsets(offsets)
+    tuning = default_tuning() if tuning is None else tuning
+    if int(o[-1]) != x.shape[0]:
+        raise ValueError("offsets[-1] must equal the number of rows")
+    if out is None:
+        out = torch.empty((x.shape[0], 2), dtype=torch.int32, device=x.device)
+    _check(lib().ph0_barcodes_batched_device_noalloc(
+        _ptr(x), _dtype_code(x.dtype), o.ctypes.data_as(_P), o.size - 1, x.shape[1], _ptr(out),
+        None if tuning is None else ctypes.byref(tuning), _stream_ptr(stream)))
+    return out
 
 
 def _default_tune_json():

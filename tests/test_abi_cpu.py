@@ -106,3 +106,17 @@ def test_batched_host_entry_rejects_bad_tuning_text_before_device_use():
     with pytest.raises(ph0.Ph0Error) as ei:  # offsets checked before any device call
         ph0.ph0_barcodes_batched(pts, np.array([1, 2, 6], np.int64), tune_json="{}")
     assert ei.value.code == -1
+
+
+def test_noalloc_batched_entry_limits_checked_before_device_use():
+    import ctypes
+
+    f = ph0.lib().ph0_barcodes_batched_device_noalloc
+    dummy = ctypes.c_void_p(16)  # never dereferenced: both calls fail in planning
+    big = np.array([0, 40, 553], np.int64)  # a 513-point cloud
+    rc = f(dummy, ph0.PH0_I16, big.ctypes.data_as(ctypes.c_void_p), 2, 3, dummy, None, None)
+    assert rc == -1 and "allocation-free" in ph0.ph0_last_error()
+    many = np.zeros(9_000_001, np.int64)  # 9 million empty clouds: 144 MB of fixed workspace
+    rc = f(dummy, ph0.PH0_I16, many.ctypes.data_as(ctypes.c_void_p), many.size - 1, 3, dummy,
+           None, None)
+    assert rc == -3 and "available" in ph0.ph0_last_error()
