@@ -92,7 +92,7 @@ int64_t ring_for(int64_t n, int64_t E) {
 struct Layout {
   int64_t n, E, Wcap, width, tiles;
   size_t keysA, keysB, counts, hist, err, part, surv, scount, wstat, cslot, killer, lowc, touch, act0,
-      act1, rtag, ra, rr, rrlo, rst, ctl, dbv, minmax, hshift, kcnt, kcnt_tot, norms, total;
+      act1, part16, ra, rr, rrlo, rst, ctl, dbv, minmax, hshift, kcnt, kcnt_tot, norms, total;
 };
 
 Layout make_layout(int64_t n, int32_t d) {
@@ -124,7 +124,7 @@ Layout make_layout(int64_t n, int32_t d) {
   L.touch = take(8 * (size_t)n);
   L.act0 = take(8 * (size_t)L.Wcap);
   L.act1 = take(8 * (size_t)L.Wcap);
-  L.rtag = take(8 * (size_t)L.Wcap);
+  L.part16 = take(2 * (size_t)std::max<int64_t>(part16_len(n), 8));
   L.ra = take(4 * (size_t)L.Wcap);
   L.rr = take(4 * (size_t)L.Wcap);
   L.rrlo = take(4 * (size_t)L.Wcap);
@@ -590,7 +590,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   ra.killer = static_cast<int64_t*>(at(L.killer));
   ra.lowc = static_cast<uint64_t*>(at(L.lowc));
   ra.touch = static_cast<uint64_t*>(at(L.touch));
-  ra.ring.tag = static_cast<int64_t*>(at(L.rtag));
+  ra.part16 = part16_len(n) ? static_cast<uint16_t*>(at(L.part16)) : nullptr;
   ra.ring.a = static_cast<int32_t*>(at(L.ra));
   ra.ring.r = static_cast<int32_t*>(at(L.rr));
   ra.ring.rlo = static_cast<int32_t*>(at(L.rrlo));

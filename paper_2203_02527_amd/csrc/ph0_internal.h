@@ -49,7 +49,6 @@ struct RedCtl {
 
 // Per-column state of the reduction window, a ring indexed by p % Wcap.
 struct Ring {
-  int64_t* tag;  // column p that owns the entry (-1 = none)
   int32_t* a;    // smaller nonzero row of the partially reduced column
   int32_t* r;    // its low (larger nonzero row)
   int32_t* rlo;  // root of row a in the pivot forest seen last round
@@ -137,6 +136,8 @@ struct RedArgs {
   int64_t n, E, Wcap;  // Wcap: ring capacity, a power of two
   int64_t width;       // base window width (<= Wcap)
   int32_t* part;  // n: other row of the column stored with low r, -1 = free
+  uint16_t* part16;  // part16_len(n): the same as 16-bit rows (0xFFFF = free), or
+                     // null when n > kPart16MaxN
   int64_t* killer;
   uint64_t* lowc;
   uint64_t* touch;
@@ -154,6 +155,9 @@ struct RedArgs {
 // entries per block.
 int walk_blocks(int64_t Wcap);
 int64_t walk_segment(int64_t Wcap);
+// Largest n whose table has a 16-bit mirror (staged in LDS by the walk).
+constexpr int64_t kPart16MaxN = 32768;
+int64_t part16_len(int64_t n);
 hipError_t launch_reduce_init(const RedArgs& a, int64_t E_lim, hipStream_t s);
 // More sorted columns are available: [old E_lim, E_lim).
 hipError_t launch_reduce_extend(const RedArgs& a, int64_t E_lim, hipStream_t s);

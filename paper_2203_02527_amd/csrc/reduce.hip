@@ -14,8 +14,12 @@
 // stored columns, the same count -- only its representation is sparse; the
 // oracle reduces dense bitset columns and the results agree bit for bit.
 //
-// The walk gives each column one lane: a chain of dependent 4-byte loads
-// (x = part[r]), 64 independent chains per wavefront.
+// The walk gives each column one lane: a chain of dependent table loads
+// (x = part[r]), 64 independent chains per wavefront.  For n <= 32768 each
+// walk workgroup first copies a 16-bit mirror of the table (part16, kept in
+// step with part by the commit step; 32 KB at n = 16384) into its LDS, so
+// every step of a chain is an LDS load rather than an L2 round trip, and the
+// walk runs 1024-lane workgroups, two per compute unit (full occupancy).
 
 // Rounds.  A window of consecutive sorted columns [F, Wend) is reduced side
 // by side against the table as committed so far (every slot there belongs to
@@ -41,6 +45,10 @@ namespace ph0 {
 namespace {
 
 constexpr uint64_t kNoValue = ~0ull;
+constexpr uint16_t kFree16 = 0xFFFF;  // a free row in the 16-bit table mirror
+constexpr int kWalkThreads = 1024;
+constexpr int kWalkWaves = kWalkThreads / 64;
+constexpr int kHashBits = 11;  // log2 of the LDS hash slots (2 x kWalkThreads)
 
 __device__ inline uint64_t enc(int64_t round, int64_t p) {
   return ((uint64_t)(0xFFFFFF - (round & 0xFFFFFF)) << 40) | (uint64_t)p;
@@ -73,12 +81,30 @@ __device__ inline int64_t wave_sum_i64(int64_t v) {
   return v;
 }
 
-// atomicMin that first looks at the current value: rows that many survivors
-// share would otherwise serialize on one address.  A stale read only costs
-// an unneeded atomic.
-__device__ inline void filtered_min(uint64_t* addr, uint64_t v) {
-  if (*(volatile uint64_t*)addr > v)
-    atomicMin((unsigned long long*)addr, (unsigned long long)v);
+// Per-workgroup aggregation of the survivors' row minima.  Survivors of one
+// row are many (up to 2e5 on the root of a large component when clusters
+// merge) and same-address global atomics serialize, while spreading them
+// over random rows makes each one a separate memory transaction.  So the
+// lanes of a walk workgroup first meet in an LDS hash table keyed by row
+// (open addressing, kHashSlots >= 2 x the lanes of one pass, so an insert
+// always finds a slot); the value is the smallest position offset p - F.
+// Only the lane holding the row's minimum then lowers the global entry:
+// one global atomic per (workgroup, pass, row).
+constexpr int kHashSlots = 2 * kWalkThreads;
+constexpr uint32_t kHashEmpty = 0, kRelNone = 0xFFFFFFFFu;
+static_assert(kHashSlots == 1 << kHashBits, "hash slots must be 2^kHashBits");
+
+__device__ inline int hash_insert(uint32_t* keys, uint32_t* vals, int row, uint32_t rel) {
+  const uint32_t key = (uint32_t)row + 1u;
+  uint32_t h = (key * 0x9E3779B1u) >> (32 - kHashBits);
+  while (true) {
+    const uint32_t prev = atomicCAS(&keys[h], kHashEmpty, key);
+    if (prev == kHashEmpty || prev == key) {
+      atomicMin(&vals[h], rel);
+      return (int)h;
+    }
+    h = (h + 1) & (kHashSlots - 1);
+  }
 }
 
 __device__ inline int64_t item_column(const RedCtl* ctl, const int64_t* act, int64_t t) {
@@ -90,35 +116,67 @@ __device__ inline int64_t item_column(const RedCtl* ctl, const int64_t* act, int
 // column.  A column stops on a free row (a survivor) or becomes zero.  For a
 // survivor {a, r} the root of a in the pivot forest (follow part[] down to a
 // free row) is found, and the round-tagged minima for row r and that root
-// are lowered.  The column's state goes back to the ring, and each block
-// lists its survivors in its own segment of `surv` (seg entries per block,
-// the count in scount[block]), so that the decide and commit steps visit
+// are lowered.  A survivor's state goes back to the ring; a zero column only
+// leaves its addition count there (for the overshoot sum).  Each block lists
+// its survivors in its own segment of `surv` (seg entries per block, the
+// count in scount[block]), so that the decide and commit steps visit
 // survivors only, one block per walk block, with no shared counter.
-__global__ __launch_bounds__(256) void k_walk(const uint64_t* __restrict__ skeys, int ib,
-                                              const int32_t* __restrict__ part, Ring ring,
-                                              int64_t Wcap, const int64_t* act0,
-                                              const int64_t* act1, uint64_t* lowc,
-                                              uint64_t* touch, int64_t* surv,
-                                              uint32_t* scount, int64_t seg,
-                                              uint64_t* wstat, RedCtl* ctl) {
-  __shared__ uint32_t s_wave[4];
+// kLds: the table is read from the block's LDS copy of part16 (0xFFFF =
+// free), else from part in global memory.
+template <bool kLds>
+__global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_walk(
+    const uint64_t* __restrict__ skeys, int ib, const int32_t* __restrict__ part,
+    const uint16_t* __restrict__ part16, int64_t n16, Ring ring, int64_t Wcap,
+    const int64_t* act0, const int64_t* act1, uint64_t* lowc, uint64_t* touch, int64_t* surv,
+    uint32_t* scount, int64_t seg, uint64_t* wstat, RedCtl* ctl) {
+  extern __shared__ uint4 s_tab4[];  // kLds: n16 / 8 entries of 8 table rows
+  __shared__ uint32_t s_wave[kWalkWaves];
+  __shared__ unsigned long long s_cnt[3];
+  __shared__ int s_bad;
+  // Row-minimum hash tables: [0] by low r (lowc), [1] by root rlo (touch).
+  __shared__ uint32_t s_hkey[2][kHashSlots];
+  __shared__ uint32_t s_hval[2][kHashSlots];
   if (ctl->done) return;
   const int64_t nA = ctl->nA, round = ctl->round, fresh_lo = ctl->fresh_lo;
+  const int64_t F = ctl->F;  // every item p has F <= p < F + Wcap
   const int64_t items = nA + (ctl->fresh_hi - fresh_lo);
+  if ((int64_t)blockIdx.x * kWalkThreads >= items) {  // nothing for this block
+    if (threadIdx.x == 0) scount[blockIdx.x] = 0;
+    return;
+  }
+  for (int k = threadIdx.x; k < kHashSlots; k += kWalkThreads) {
+    s_hkey[0][k] = s_hkey[1][k] = kHashEmpty;
+    s_hval[0][k] = s_hval[1][k] = kRelNone;
+  }
+  if (kLds) {
+    const uint4* src = reinterpret_cast<const uint4*>(part16);
+    for (int64_t k = threadIdx.x; k < n16 / 8; k += kWalkThreads) s_tab4[k] = src[k];
+  }
+  __syncthreads();
+  const uint16_t* s_tab = reinterpret_cast<const uint16_t*>(s_tab4);
+  auto lookup = [&](int row) -> int {
+    if (kLds) {
+      const uint16_t v = s_tab[row];
+      return v == kFree16 ? -1 : (int)v;
+    }
+    return part[row];
+  };
   const int64_t* act = ctl->cur ? act1 : act0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t stride = (int64_t)gridDim.x * kWalkThreads;
   const uint64_t imask = (1ull << ib) - 1ull;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int64_t* my_surv = surv + blockIdx.x * seg;
   uint32_t nsurv = 0;  // this block's survivors so far (same in every thread)
   int64_t adds = 0, finds = 0, words = 0;
   int32_t bad = 0;
-  for (int64_t t0 = blockIdx.x * (int64_t)blockDim.x; t0 < items; t0 += stride) {
+  for (int64_t t0 = blockIdx.x * (int64_t)kWalkThreads; t0 < items; t0 += stride) {
     const int64_t t = t0 + threadIdx.x;
     bool survivor = false;
     int64_t p = 0;
+    int32_t a, r, rlo;
+    int hs_low = 0, hs_root = 0;  // this survivor's hash slots
     if (t < items) {
-      int32_t a, r, rlo, prev_steps;
+      int32_t prev_steps;
       if (t < nA) {
         p = act[t];
         const int64_t k = p & (Wcap - 1);
@@ -137,7 +195,7 @@ __global__ __launch_bounds__(256) void k_walk(const uint64_t* __restrict__ skeys
       int moved = 0;
       bool zero = false;
       while (true) {
-        const int x = part[r];
+        const int x = lookup(r);
         ++words;
         if (x < 0) break;  // row r is free
         ++moved;
@@ -156,14 +214,14 @@ __global__ __launch_bounds__(256) void k_walk(const uint64_t* __restrict__ skeys
         a = lo;
       }
       adds += moved;
-      int32_t status = kActive;
+      const int64_t k = p & (Wcap - 1);
       if (zero) {
-        status = kZero;
+        ring.st[k] = kZero | ((prev_steps + moved) << 2);
       } else {
         // Root of row a in the current forest: follow stored columns down.
         int v = moved ? a : rlo;
         while (true) {
-          const int c = part[v];
+          const int c = lookup(v);
           ++words;
           if (c < 0) break;  // free row: v is a root
           ++finds;
@@ -174,36 +232,46 @@ __global__ __launch_bounds__(256) void k_walk(const uint64_t* __restrict__ skeys
           v = c;
         }
         rlo = v;
-        const uint64_t e = enc(round, p);
-        filtered_min(&lowc[r], e);
-        filtered_min(&touch[rlo], e);
+        const uint32_t rel = (uint32_t)(p - F);
+        hs_low = hash_insert(s_hkey[0], s_hval[0], r, rel);
+        hs_root = hash_insert(s_hkey[1], s_hval[1], rlo, rel);
         survivor = true;
+        ring.a[k] = a;
+        ring.r[k] = r;
+        ring.rlo[k] = rlo;
+        ring.st[k] = kActive | ((prev_steps + moved) << 2);
       }
-      const int64_t k = p & (Wcap - 1);
-      ring.a[k] = a;
-      ring.r[k] = r;
-      ring.rlo[k] = rlo;
-      ring.st[k] = status | ((prev_steps + moved) << 2);
-      ring.tag[k] = p;
     }
-    // Append this pass's survivors to the block's segment.
+    // Append this pass's survivors to the block's segment; the lane holding
+    // a row's smallest position lowers that row's global minimum.
     const uint64_t m = __ballot(survivor);
     if (lane == 0) s_wave[wave] = (uint32_t)__popcll(m);
     __syncthreads();
+    if (survivor) {
+      const uint32_t rel = (uint32_t)(p - F);
+      const uint64_t e = enc(round, p);
+      if (s_hval[0][hs_low] == rel) atomicMin((unsigned long long*)&lowc[r], e);
+      if (s_hval[1][hs_root] == rel) atomicMin((unsigned long long*)&touch[rlo], e);
+    }
     uint32_t before = 0, total = 0;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < kWalkWaves; ++w) {
       before += w < wave ? s_wave[w] : 0u;
       total += s_wave[w];
     }
     if (survivor) my_surv[nsurv + before + __popcll(m & ((1ull << lane) - 1ull))] = p;
     nsurv += total;
     __syncthreads();
+    if (survivor) {  // empty the slots for the next pass (every used slot has a survivor)
+      s_hkey[0][hs_low] = kHashEmpty;
+      s_hval[0][hs_low] = kRelNone;
+      s_hkey[1][hs_root] = kHashEmpty;
+      s_hval[1][hs_root] = kRelNone;
+    }
+    __syncthreads();
   }
   if (threadIdx.x == 0) scount[blockIdx.x] = nsurv;
-  // Counters: wave sums -> block totals in LDS -> one atomic per block.
-  __shared__ unsigned long long s_cnt[3];
-  __shared__ int s_bad;
+  // Counters: wave sums -> block totals in LDS -> the block's own slots.
   if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
@@ -375,8 +443,9 @@ __global__ __launch_bounds__(256) void k_commit(Ring ring, int64_t Wcap, const i
                                                 const uint32_t* scount, int64_t seg,
                                                 int64_t* act0, int64_t* act1,
                                                 const uint64_t* lowc, const uint64_t* touch,
-                                                int32_t* part, int64_t* killer,
-                                                uint64_t* cslot, RedCtl* ctl) {
+                                                int32_t* part, uint16_t* part16,
+                                                int64_t* killer, uint64_t* cslot,
+                                                RedCtl* ctl) {
   __shared__ int64_t itmp[4];
   __shared__ uint64_t utmp[4];
   __shared__ int64_t s_base;
@@ -405,7 +474,9 @@ __global__ __launch_bounds__(256) void k_commit(Ring ring, int64_t Wcap, const i
     const int32_t r = ring.r[k];
     const uint64_t e = enc(round, p);
     if ((uint64_t)p < fd || (lowc[r] == e && touch[r] > e)) {
-      part[r] = ring.a[k];  // the stored column {a, r}
+      const int32_t a = ring.a[k];
+      part[r] = a;  // the stored column {a, r}
+      if (part16) part16[r] = (uint16_t)a;
       killer[r] = p;
       ring.st[k] = (ring.st[k] & ~3) | kCommitted;
       ++npiv;
@@ -490,14 +561,16 @@ __global__ void k_reduce_init(RedCtl* ctl, int64_t E_lim, int64_t width, int64_t
 
 // Additions of columns at or after E_eff (walked before the last pivot was
 // known) are not part of the sequential count; sum them for subtraction.
+// Every column of [E_eff, maxWend) was walked and still owns its ring entry:
+// the reduction ends with the window start F >= E_eff, the window [F, maxWend)
+// is at most Wcap wide and holds every column walked since F, so no later
+// column has reused an entry of that range.
 __global__ __launch_bounds__(256) void k_overshoot(Ring ring, int64_t Wcap, RedCtl* ctl) {
   const int64_t lo = ctl->E_eff, hi = ctl->maxWend;
   int64_t s = 0;
   for (int64_t p = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < hi;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t k = p & (Wcap - 1);
-    if (ring.tag[k] == p) s += ring.st[k] >> 2;
-  }
+       p += (int64_t)gridDim.x * blockDim.x)
+    s += ring.st[p & (Wcap - 1)] >> 2;
   __shared__ int64_t tmp[4];
   s = block_sum_i64(s, tmp);  // one atomic per block: same-address atomics serialize
   if (threadIdx.x == 0 && s)
@@ -528,14 +601,13 @@ int scan_blocks(int64_t Wcap) {
 
 }  // namespace
 
-// One lane per column, up to 512 blocks (two per compute unit of MI355X);
-// beyond that each lane takes several columns in turn.  More blocks cost
-// more than they hide: the decide and commit steps run one block per walk
-// block, each with a few atomics on the shared control block (N=16384:
-// 512 blocks 2.7 ms per barcode against 2.9 ms with 2048).  Fixed, not
-// queried, so that workspace sizes do not depend on the device.
+// One lane per column, up to 512 workgroups of 1024 lanes (two per compute
+// unit of MI355X: 32 waves per CU); beyond that each lane takes several
+// columns in turn.  The decide and commit steps run one block per walk
+// block.  Fixed, not queried, so that workspace sizes do not depend on the
+// device.
 int walk_blocks(int64_t Wcap) {
-  int64_t b = (Wcap + 255) / 256;
+  int64_t b = (Wcap + kWalkThreads - 1) / kWalkThreads;
   const int64_t cap = 512;
   if (b > cap) b = cap;
   return (int)(b < 1 ? 1 : b);
@@ -544,9 +616,13 @@ int walk_blocks(int64_t Wcap) {
 // Survivor entries per walk block: the most items one block can see in a
 // round (a round has at most Wcap items).
 int64_t walk_segment(int64_t Wcap) {
-  const int64_t threads = 256 * (int64_t)walk_blocks(Wcap);
-  return 256 * ((Wcap + threads - 1) / threads);
+  const int64_t threads = kWalkThreads * (int64_t)walk_blocks(Wcap);
+  return kWalkThreads * ((Wcap + threads - 1) / threads);
 }
+
+// Entries of the 16-bit table mirror (a multiple of 8, so that the walk
+// copies it in 16-byte pieces), or 0 when n is too large for 16 bits.
+int64_t part16_len(int64_t n) { return n <= kPart16MaxN ? (n + 7) / 8 * 8 : 0; }
 
 hipError_t launch_reduce_extend(const RedArgs& a, int64_t E_lim, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_extend, dim3(1), dim3(1), 0, s, a.ctl, E_lim);
@@ -564,28 +640,40 @@ hipError_t launch_reduce_init(const RedArgs& a, int64_t E_lim, hipStream_t s) {
   if ((e = launch_fill_u64(a.touch, kNoValue, a.n, s)) != hipSuccess) return e;
   if ((e = launch_fill_u64(a.wstat, 0ull, 3 * (int64_t)walk_blocks(a.Wcap), s)) != hipSuccess)
     return e;
-  if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(a.ring.tag), ~0ull, a.Wcap, s)) !=
-      hipSuccess)
+  if (a.part16 && (e = launch_fill_u32(reinterpret_cast<uint32_t*>(a.part16), 0xFFFFFFFFu,
+                                       part16_len(a.n) / 2, s)) != hipSuccess)
     return e;
   hipLaunchKernelGGL(k_reduce_init, dim3(1), dim3(1), 0, s, a.ctl, E_lim, a.width, a.n);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_walk) {
+  // The LDS table copy of the largest n (64 KB) is beyond the default
+  // dynamic LDS limit of a workgroup; two such workgroups still fit a CU.
+  static const hipError_t attr = hipFuncSetAttribute(
+      (const void*)k_walk<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+      (int)(2 * kPart16MaxN));
+  if (attr != hipSuccess) return attr;
   const int wb = walk_blocks(a.Wcap);
   const int64_t seg = walk_segment(a.Wcap);
   if (ev_walk) (void)hipEventRecord(ev_walk[0], s);
-  hipLaunchKernelGGL(k_walk, dim3((unsigned)wb), dim3(256), 0, s, a.skeys, a.ib, a.part, a.ring,
-                     a.Wcap, a.act[0], a.act[1], a.lowc, a.touch, a.surv, a.scount, seg,
-                     a.wstat, a.ctl);
+  const int64_t n16 = a.part16 ? part16_len(a.n) : 0;
+  if (a.part16)
+    hipLaunchKernelGGL(k_walk<true>, dim3((unsigned)wb), dim3(kWalkThreads), 2 * n16, s,
+                       a.skeys, a.ib, a.part, a.part16, n16, a.ring, a.Wcap, a.act[0], a.act[1],
+                       a.lowc, a.touch, a.surv, a.scount, seg, a.wstat, a.ctl);
+  else
+    hipLaunchKernelGGL(k_walk<false>, dim3((unsigned)wb), dim3(kWalkThreads), 0, s, a.skeys,
+                       a.ib, a.part, a.part16, n16, a.ring, a.Wcap, a.act[0], a.act[1], a.lowc,
+                       a.touch, a.surv, a.scount, seg, a.wstat, a.ctl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev_walk) (void)hipEventRecord(ev_walk[1], s);
   hipLaunchKernelGGL(k_decide, dim3((unsigned)wb), dim3(256), 0, s, a.ring, a.Wcap, a.surv,
                      a.scount, seg, a.lowc, a.ctl);
   hipLaunchKernelGGL(k_commit, dim3((unsigned)wb), dim3(256), 0, s, a.ring, a.Wcap, a.surv,
-                     a.scount, seg, a.act[0], a.act[1], a.lowc, a.touch, a.part, a.killer,
-                     a.cslot, a.ctl);
+                     a.scount, seg, a.act[0], a.act[1], a.lowc, a.touch, a.part, a.part16,
+                     a.killer, a.cslot, a.ctl);
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(256), 0, s, a.ctl, a.cslot, (int64_t)wb, a.n,
                      a.E, a.Wcap);
   return hipGetLastError();
