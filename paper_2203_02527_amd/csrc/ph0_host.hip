@@ -91,8 +91,9 @@ int64_t ring_for(int64_t n, int64_t E) {
 
 struct Layout {
   int64_t n, E, Wcap, width, tiles;
-  size_t keysA, keysB, counts, hist, err, part, surv, scount, wstat, cslot, killer, lowc, touch, act0,
-      act1, part16, ra, rr, rrlo, rst, ctl, dbv, minmax, hshift, kcnt, kcnt_tot, norms, total;
+  size_t keysA, keysB, counts, hist, err, part, surv, scount, fdslot, wstat, cslot, osum, killer,
+      lowc, touch, act0, act1, kpre, part16, ra, rr, rrlo, rst, ctl, dbv, minmax, hshift, kcnt,
+      kcnt_tot, norms, total;
 };
 
 Layout make_layout(int64_t n, int32_t d) {
@@ -115,15 +116,18 @@ Layout make_layout(int64_t n, int32_t d) {
   L.hist = take(4 * (size_t)kHistBins);
   L.err = take(4);
   L.part = take(4 * (size_t)n);
-  L.surv = take(8 * (size_t)walk_blocks(L.Wcap) * (size_t)walk_segment(L.Wcap));
-  L.scount = take(4 * (size_t)walk_blocks(L.Wcap));
-  L.wstat = take(8 * 3 * (size_t)walk_blocks(L.Wcap));
-  L.cslot = take(8 * 3 * (size_t)walk_blocks(L.Wcap));
+  const size_t wb = (size_t)walk_blocks(L.Wcap), segs = wb * (size_t)walk_segment(L.Wcap);
+  L.surv = take(8 * segs);
+  L.scount = take(4 * wb);
+  L.fdslot = take(8 * wb);
+  L.wstat = take(8 * 3 * wb);
+  L.cslot = take(8 * 4 * wb);
+  L.kpre = take(8 * (wb + 1));
   L.killer = take(8 * (size_t)n);
   L.lowc = take(8 * (size_t)n);
   L.touch = take(8 * (size_t)n);
-  L.act0 = take(8 * (size_t)L.Wcap);
-  L.act1 = take(8 * (size_t)L.Wcap);
+  L.act0 = take(8 * segs);
+  L.act1 = take(8 * segs);
   L.part16 = take(2 * (size_t)std::max<int64_t>(part16_len(n), 8));
   L.ra = take(4 * (size_t)L.Wcap);
   L.rr = take(4 * (size_t)L.Wcap);
@@ -580,11 +584,15 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   ra.E = L.E;
   ra.Wcap = L.Wcap;
   ra.width = L.width;
+  ra.seg = walk_segment(L.Wcap);
+  ra.nblocks = walk_blocks(L.Wcap);
+  ra.kpre = static_cast<int64_t*>(at(L.kpre));
   ra.act[0] = static_cast<int64_t*>(at(L.act0));
   ra.act[1] = static_cast<int64_t*>(at(L.act1));
   ra.part = static_cast<int32_t*>(at(L.part));
   ra.surv = static_cast<int64_t*>(at(L.surv));
   ra.scount = static_cast<uint32_t*>(at(L.scount));
+  ra.fdslot = static_cast<uint64_t*>(at(L.fdslot));
   ra.wstat = static_cast<uint64_t*>(at(L.wstat));
   ra.cslot = static_cast<uint64_t*>(at(L.cslot));
   ra.killer = static_cast<int64_t*>(at(L.killer));
@@ -640,8 +648,9 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     --q_len;
     HIPCHK(hipEventSynchronize(rb->ev[k]));
     const RedCtl& h = hc[k];
+    const int32_t herr = h.err;
     if (h.done) break;
-    if (h.need_more && !h.err) {
+    if (h.need_more && !herr) {
       if (whole) return fail(PH0_EDEVICE, "reduction asked for columns past the last one");
       HIPCHK(hipStreamSynchronize(s));  // any queued burst found nothing to do
       q_len = 0;
@@ -652,10 +661,10 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
       HIPCHK(issue_next());
       continue;
     }
-    if (h.F <= prevF || h.err) {
+    if (h.F <= prevF || herr) {
       HIPCHK(hipStreamSynchronize(s));
       return fail(PH0_EDEVICE, "reduction stalled at column %lld (err %d)", (long long)h.F,
-                  h.err);
+                  herr);
     }
     prevF = h.F;
     // Bursts grow 2, 4, 8 (then stay): rounds queued past the end cost a few
@@ -689,23 +698,24 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   HIPCHK(hipStreamSynchronize(s));
   tm.mark();  // 4
   if (hw[0]) return fail(PH0_EDEVICE, "radix sort digit counts were inconsistent");
+  const RedCtl* fin = hc;
   if (hc->err & 1) return fail(PH0_EDEVICE, "a reduced column did not have exactly two rows");
-  if (hc->err & 2 || hc->pivots != n - 1)
+  if (fin->err & 2 || fin->pivots != n - 1)
     return fail(PH0_EDEVICE, "reduction ended with %lld pivots, expected %lld",
-                (long long)hc->pivots, (long long)(n - 1));
-  S.E_eff = hc->E_eff;
-  S.additions_all = hc->additions_all;
-  S.additions = hc->additions_all - hc->additions_overshoot;
-  S.find_steps = hc->find_steps;
-  S.words_read = hc->words_read;
-  S.rounds = hc->round;
+                (long long)fin->pivots, (long long)(n - 1));
+  S.E_eff = fin->E_eff;
+  S.additions_all = fin->additions_all;
+  S.additions = fin->additions_all - fin->additions_overshoot;
+  S.find_steps = fin->find_steps;
+  S.words_read = fin->words_read;
+  S.rounds = fin->round;
 
   // Grades over [0, E_eff), per-vertex deaths and the barcode, in one
   // ordered pass over the pivot positions (scratch: the spare key buffer).
   uint32_t* dbv = out.dbv ? out.dbv : static_cast<uint32_t*>(at(L.dbv));
-  if (grades_work_bytes(hc->E_eff) > 8 * (size_t)std::max<int64_t>(L.E, 2 * n + 64))
+  if (grades_work_bytes(fin->E_eff) > 8 * (size_t)std::max<int64_t>(L.E, 2 * n + 64))
     return fail(PH0_EDEVICE, "grade scratch does not fit the key buffer");
-  HIPCHK(launch_grades_and_bars(skeys, hc->E_eff, 2 * ib, ra.killer, n, spare, dbv,
+  HIPCHK(launch_grades_and_bars(skeys, fin->E_eff, 2 * ib, ra.killer, n, spare, dbv,
                                 reinterpret_cast<uint32_t*>(out.bars), s, &hw[1], &hw[2]));
   tm.mark();  // 5
   if (out.killer_pos || out.killer_edge || out.killer_sqdist || out.partner)

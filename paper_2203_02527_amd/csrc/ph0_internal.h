@@ -18,9 +18,10 @@ struct SortPlan {
   int bits[kMaxPasses];   // digit width (1..8)
 };
 
-// Control block of the round-based reduction, resident in device memory.
-// A round works on "items": first the nA columns carried over in the active
-// list act[cur], then the fresh columns [fresh_lo, fresh_hi) entering the
+// State of the round-based reduction entering a round, resident in device
+// memory.  A round works on "items": first the nA columns kept by the
+// previous round's commit (listed in the commit workgroups' segments, at the
+// offsets kpre), then the fresh columns [fresh_lo, fresh_hi) entering the
 // window this round.
 struct RedCtl {
   int64_t F;         // first column that is not final
@@ -30,21 +31,20 @@ struct RedCtl {
   int64_t maxWend;   // largest Wend ever used
   int64_t fresh_lo;  // columns entering this round
   int64_t fresh_hi;
-  int64_t nA;        // carried-over active columns in act[cur]
-  int64_t nA_next;   // columns appended to act[cur ^ 1] by this round's commit
-  int64_t pivots;    // committed pivots (summed from the commit blocks' slots)
+  int64_t nA;        // kept columns carried into this round
+  int64_t pivots;    // committed pivots
   int64_t E_eff;     // largest committed column + 1
-  int64_t round;
-  uint64_t firstdup[2];  // per round parity: first survivor whose low repeats
-  int64_t additions_all;
-  int64_t find_steps;
-  int64_t words_read;
-  int64_t additions_overshoot;  // additions of walked columns >= E_eff
+  int64_t round;     // rounds completed
+  int64_t additions_all;        // set by the finish step
+  int64_t find_steps;           // set by the finish step
+  int64_t words_read;           // set by the finish step
+  int64_t additions_overshoot;  // additions of walked columns >= E_eff (finish step)
   int64_t E_lim;     // sorted columns available so far (a prefix of the order)
-  int32_t cur;
   int32_t done;
-  int32_t err;  // bit 0: a reduced column had weight != 2; bit 1: ran out of columns
+  int32_t err;        // bit 0: a walk met a stored row below its low (corrupt table);
+                      // bit 1: ran out of columns
   int32_t need_more;  // every available column is final and pivots are missing
+  int32_t pad;
 };
 
 // Per-column state of the reduction window, a ring indexed by p % Wcap.
@@ -130,29 +130,34 @@ hipError_t launch_radix_pass(const uint64_t* in, uint64_t* out, int64_t count, i
                              KeyFilter f = KeyFilter(), int64_t expect = -1);
 
 // Steps 4-5: round-based reduction.
+constexpr int kMaxWalkBlocks = 512;  // walk (and commit) workgroups per round, at most
 struct RedArgs {
   const uint64_t* skeys;
   int ib;
+  int32_t nblocks;     // walk_blocks(Wcap)
   int64_t n, E, Wcap;  // Wcap: ring capacity, a power of two
   int64_t width;       // base window width (<= Wcap)
+  int64_t seg;         // walk_segment(Wcap): entries per workgroup segment
   int32_t* part;  // n: other row of the column stored with low r, -1 = free
   uint16_t* part16;  // part16_len(n): the same as 16-bit rows (0xFFFF = free), or
                      // null when n > kPart16MaxN
   int64_t* killer;
-  uint64_t* lowc;
-  uint64_t* touch;
-  int64_t* act[2];  // active lists, Wcap entries each
+  uint64_t* lowc;   // n: round-tagged smallest survivor with low r
+  uint64_t* touch;  // n: round-tagged smallest survivor whose other row has root r
+  int64_t* act[2];  // kept columns, one segment per commit workgroup (by round parity)
+  int64_t* kpre;    // nblocks + 1: kept columns before each segment, and their total
   Ring ring;
-  int64_t* surv;    // walk_blocks(Wcap) x walk_segment(Wcap): each block's survivors
-  uint32_t* scount; // walk_blocks(Wcap): survivors per block
-  uint64_t* wstat;  // 3 x walk_blocks(Wcap): each walk block's additions, root-find
-                    // steps and table words, summed into ctl by the finish step
-  uint64_t* cslot;  // 3 x walk_blocks(Wcap): each commit block's pivots, end of its
-                    // last pivot and first stayer, reduced by the advance step
+  int64_t* surv;    // nblocks x seg: each walk workgroup's survivors
+  uint32_t* scount; // nblocks: survivors per walk workgroup
+  uint64_t* fdslot; // nblocks: each walk workgroup's smallest survivor whose low repeats
+                    // an earlier survivor's low
+  uint64_t* wstat;  // 3 x nblocks: each walk workgroup's additions, root-find steps and
+                    // table words, summed by the finish step
+  uint64_t* cslot;  // 4 x nblocks: each commit workgroup's pivots, end of its last
+                    // pivot, first kept column and number kept
   RedCtl* ctl;
 };
-// Grid of the walk (and of the decide and commit steps) and the survivor
-// entries per block.
+// Grid of the walk (and of the commit) and the segment entries per workgroup.
 int walk_blocks(int64_t Wcap);
 int64_t walk_segment(int64_t Wcap);
 // Largest n whose table has a 16-bit mirror (staged in LDS by the walk).
@@ -161,8 +166,8 @@ int64_t part16_len(int64_t n);
 hipError_t launch_reduce_init(const RedArgs& a, int64_t E_lim, hipStream_t s);
 // More sorted columns are available: [old E_lim, E_lim).
 hipError_t launch_reduce_extend(const RedArgs& a, int64_t E_lim, hipStream_t s);
-// One round: walk, decide, commit, advance.  When `ev_walk` is non-null its
-// two events are recorded around the walk kernel.
+// One round: walk, commit, advance.  When `ev_walk` is non-null its two
+// events are recorded around the walk kernel.
 hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_walk);
 hipError_t launch_reduce_finish(const RedArgs& a, hipStream_t s);
 

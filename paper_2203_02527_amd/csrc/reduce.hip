@@ -38,6 +38,21 @@
 // -- equals the sequential left-to-right reduction.  Once N-1 pivots exist
 // the remaining columns must reduce to zero (the complete graph is
 // connected), so the reduction stops there.
+//
+// A round is three launches -- walk, commit, advance -- and its control uses
+// no atomic on a shared address (on MI355X same-address atomics from
+// hundreds of workgroups serialize; a grid-wide barrier costs several times
+// a launch, and so does a chain of dependent loads at the start of every
+// walk workgroup):
+//   * the walk also finds the first survivor whose low repeats an earlier
+//     one: within a workgroup from its LDS hash of row minima, across
+//     workgroups from the values the row-minimum atomics return; each
+//     workgroup leaves its candidate in a slot of its own;
+//   * the commit workgroup of a walk workgroup's survivors commits or keeps
+//     them, writes the kept ones to a segment of its own and its totals to a
+//     slot of its own;
+//   * one advance workgroup reduces the slots into the next round's state
+//     and the offsets of the kept segments.
 #include "ph0_internal.h"
 
 namespace ph0 {
@@ -48,10 +63,21 @@ constexpr uint64_t kNoValue = ~0ull;
 constexpr uint16_t kFree16 = 0xFFFF;  // a free row in the 16-bit table mirror
 constexpr int kWalkThreads = 1024;
 constexpr int kWalkWaves = kWalkThreads / 64;
+constexpr int kCommitThreads = 256;
+constexpr int kAdvanceThreads = 512;  // one thread per commit slot (kMaxWalkBlocks)
 constexpr int kHashBits = 11;  // log2 of the LDS hash slots (2 x kWalkThreads)
 
+// Row minima carry the round in their top bits, so that a value left by an
+// earlier round is larger than any of this round's and never matches.
+constexpr int kPosBits = 40;
 __device__ inline uint64_t enc(int64_t round, int64_t p) {
-  return ((uint64_t)(0xFFFFFF - (round & 0xFFFFFF)) << 40) | (uint64_t)p;
+  return ((uint64_t)(0xFFFFFF - (round & 0xFFFFFF)) << kPosBits) | (uint64_t)p;
+}
+__device__ inline bool same_round(uint64_t v, int64_t round) {
+  return (v >> kPosBits) == (uint64_t)(0xFFFFFF - (round & 0xFFFFFF));
+}
+__device__ inline int64_t enc_pos(uint64_t v) {
+  return (int64_t)(v & ((1ull << kPosBits) - 1ull));
 }
 
 __device__ inline uint64_t shfl64_down(uint64_t v, int delta) {
@@ -75,10 +101,80 @@ __device__ inline uint64_t wave_min_u64(uint64_t v) {
   return v;
 }
 
+__device__ inline uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t w = shfl64_down(v, o);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
 __device__ inline int64_t wave_sum_i64(int64_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += (int64_t)shfl64_down((uint64_t)v, o);
   return v;
+}
+
+// Block-wide reductions and scans; `tmp` holds one entry per wave.  Every
+// thread of the block must call them (they synchronize).
+template <int kWaves>
+__device__ inline uint64_t block_min_u64(uint64_t v, uint64_t* tmp) {
+  v = wave_min_u64(v);
+  if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint64_t r = tmp[0];
+#pragma unroll
+  for (int w = 1; w < kWaves; ++w) r = tmp[w] < r ? tmp[w] : r;
+  __syncthreads();
+  return r;
+}
+
+template <int kWaves>
+__device__ inline uint64_t block_max_u64(uint64_t v, uint64_t* tmp) {
+  v = wave_max_u64(v);
+  if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint64_t r = tmp[0];
+#pragma unroll
+  for (int w = 1; w < kWaves; ++w) r = tmp[w] > r ? tmp[w] : r;
+  __syncthreads();
+  return r;
+}
+
+template <int kWaves>
+__device__ inline int64_t block_sum_i64(int64_t v, int64_t* tmp) {
+  v = wave_sum_i64(v);
+  if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int64_t r = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) r += tmp[w];
+  __syncthreads();
+  return r;
+}
+
+// Exclusive prefix of v over the block, and the block total.
+template <int kWaves>
+__device__ inline int64_t block_excl_i64(int64_t v, int64_t* tmp, int64_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = (int64_t)shfl64_up((uint64_t)x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) tmp[wave] = x;
+  __syncthreads();
+  int64_t base = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    base += w < wave ? tmp[w] : 0;
+    all += tmp[w];
+  }
+  *total = all;
+  __syncthreads();
+  return base + x - v;
 }
 
 // Per-workgroup aggregation of the survivors' row minima.  Survivors of one
@@ -107,53 +203,57 @@ __device__ inline int hash_insert(uint32_t* keys, uint32_t* vals, int row, uint3
   }
 }
 
-__device__ inline int64_t item_column(const RedCtl* ctl, const int64_t* act, int64_t t) {
-  return t < ctl->nA ? act[t] : ctl->fresh_lo + (t - ctl->nA);
-}
-
-// One round's walk: every item (carried active column or fresh column of the
-// window) is reduced against the table as committed so far, one lane per
-// column.  A column stops on a free row (a survivor) or becomes zero.  For a
-// survivor {a, r} the root of a in the pivot forest (follow part[] down to a
-// free row) is found, and the round-tagged minima for row r and that root
-// are lowered.  A survivor's state goes back to the ring; a zero column only
-// leaves its addition count there (for the overshoot sum).  Each block lists
-// its survivors in its own segment of `surv` (seg entries per block, the
-// count in scount[block]), so that the decide and commit steps visit
-// survivors only, one block per walk block, with no shared counter.
-// kLds: the table is read from the block's LDS copy of part16 (0xFFFF =
+// One round's walk.  Every item -- a column kept by the previous commit
+// (listed in the commit workgroups' segments, at the offsets in kpre) or a
+// fresh column of the window -- is reduced against the table as committed
+// so far, one lane per column.  A column stops on a free row (a survivor) or
+// becomes zero.  For a survivor {a, r} the root of a in the pivot forest
+// (follow part[] down to a free row) is found, and the round-tagged minima
+// for row r (lowc) and that root (touch) are lowered.  A survivor's state
+// goes back to the ring; a zero column only leaves its addition count there
+// (for the overshoot sum).  Each workgroup lists its survivors in its own
+// segment of `surv`, and leaves in fdslot[block] the smallest survivor it
+// saw whose low repeats an earlier survivor's low.
+// kLds: the table is read from the workgroup's LDS copy of part16 (0xFFFF =
 // free), else from part in global memory.
 template <bool kLds>
-__global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_walk(
-    const uint64_t* __restrict__ skeys, int ib, const int32_t* __restrict__ part,
-    const uint16_t* __restrict__ part16, int64_t n16, Ring ring, int64_t Wcap,
-    const int64_t* act0, const int64_t* act1, uint64_t* lowc, uint64_t* touch, int64_t* surv,
-    uint32_t* scount, int64_t seg, uint64_t* wstat, RedCtl* ctl) {
+__global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
+void k_walk(RedArgs A, int64_t n16) {
   extern __shared__ uint4 s_tab4[];  // kLds: n16 / 8 entries of 8 table rows
   __shared__ uint32_t s_wave[kWalkWaves];
+  __shared__ uint64_t s_u64[kWalkWaves];
   __shared__ unsigned long long s_cnt[3];
   __shared__ int s_bad;
+  __shared__ int64_t s_pre[kMaxWalkBlocks + 1];  // kept columns before each commit segment
   // Row-minimum hash tables: [0] by low r (lowc), [1] by root rlo (touch).
   __shared__ uint32_t s_hkey[2][kHashSlots];
   __shared__ uint32_t s_hval[2][kHashSlots];
-  if (ctl->done) return;
-  const int64_t nA = ctl->nA, round = ctl->round, fresh_lo = ctl->fresh_lo;
-  const int64_t F = ctl->F;  // every item p has F <= p < F + Wcap
+  const int nb = (int)gridDim.x;
+  const int tid = threadIdx.x;
+  const RedCtl* ctl = A.ctl;
+  if (ctl->done || ctl->need_more) return;  // the commit and advance steps return too
+  const int64_t nA = ctl->nA, round = ctl->round, fresh_lo = ctl->fresh_lo, F = ctl->F;
   const int64_t items = nA + (ctl->fresh_hi - fresh_lo);
+  int64_t* my_surv = A.surv + blockIdx.x * A.seg;
   if ((int64_t)blockIdx.x * kWalkThreads >= items) {  // nothing for this block
-    if (threadIdx.x == 0) scount[blockIdx.x] = 0;
+    if (tid == 0) {
+      A.scount[blockIdx.x] = 0;
+      A.fdslot[blockIdx.x] = kNoValue;
+    }
     return;
   }
-  for (int k = threadIdx.x; k < kHashSlots; k += kWalkThreads) {
-    s_hkey[0][k] = s_hkey[1][k] = kHashEmpty;
-    s_hval[0][k] = s_hval[1][k] = kRelNone;
+  if (nA > 0 && tid <= nb) s_pre[tid] = A.kpre[tid];
+  for (int h = tid; h < kHashSlots; h += kWalkThreads) {
+    s_hkey[0][h] = s_hkey[1][h] = kHashEmpty;
+    s_hval[0][h] = s_hval[1][h] = kRelNone;
   }
   if (kLds) {
-    const uint4* src = reinterpret_cast<const uint4*>(part16);
-    for (int64_t k = threadIdx.x; k < n16 / 8; k += kWalkThreads) s_tab4[k] = src[k];
+    const uint4* src = reinterpret_cast<const uint4*>(A.part16);
+    for (int64_t h = tid; h < n16 / 8; h += kWalkThreads) s_tab4[h] = src[h];
   }
   __syncthreads();
   const uint16_t* s_tab = reinterpret_cast<const uint16_t*>(s_tab4);
+  const int32_t* __restrict__ part = A.part;
   auto lookup = [&](int row) -> int {
     if (kLds) {
       const uint16_t v = s_tab[row];
@@ -161,29 +261,42 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
     }
     return part[row];
   };
-  const int64_t* act = ctl->cur ? act1 : act0;
+  const int64_t* kept_cols = A.act[(round - 1) & 1];  // the previous commit's segments
+  const uint64_t* __restrict__ skeys = A.skeys;
+  const int ib = A.ib;
+  const Ring ring = A.ring;
+  const int64_t Wcap = A.Wcap, seg = A.seg;
   const int64_t stride = (int64_t)gridDim.x * kWalkThreads;
   const uint64_t imask = (1ull << ib) - 1ull;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int64_t* my_surv = surv + blockIdx.x * seg;
+  const int lane = tid & 63, wave = tid >> 6;
   uint32_t nsurv = 0;  // this block's survivors so far (same in every thread)
-  int64_t adds = 0, finds = 0, words = 0;
+  uint32_t adds = 0, finds = 0, words = 0;  // this lane's counts (a few columns' chains)
+  uint64_t fd = kNoValue;  // smallest repeated-low survivor seen by this lane
   int32_t bad = 0;
   for (int64_t t0 = blockIdx.x * (int64_t)kWalkThreads; t0 < items; t0 += stride) {
-    const int64_t t = t0 + threadIdx.x;
+    const int64_t t = t0 + tid;
     bool survivor = false;
     int64_t p = 0;
-    int32_t a, r, rlo;
+    int32_t a = 0, r = 0, rlo = 0;
     int hs_low = 0, hs_root = 0;  // this survivor's hash slots
     if (t < items) {
       int32_t prev_steps;
       if (t < nA) {
-        p = act[t];
-        const int64_t k = p & (Wcap - 1);
-        a = ring.a[k];
-        r = ring.r[k];
-        rlo = ring.rlo[k];
-        prev_steps = ring.st[k] >> 2;
+        // The segment holding kept column t: the last sg with s_pre[sg] <= t.
+        int lo = 0, hi = nb;  // s_pre[lo] <= t < s_pre[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_pre[mid] <= t)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        p = kept_cols[lo * seg + (t - s_pre[lo])];
+        const int64_t kk = p & (Wcap - 1);
+        a = ring.a[kk];
+        r = ring.r[kk];
+        rlo = ring.rlo[kk];
+        prev_steps = ring.st[kk] >> 2;
       } else {
         p = fresh_lo + (t - nA);
         const uint64_t key = skeys[p];
@@ -209,14 +322,14 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
           break;
         }
         // {a, r} + {x, r} = {a, x}
-        const int lo = x < a ? x : a;
+        const int lo2 = x < a ? x : a;
         r = x < a ? a : x;
-        a = lo;
+        a = lo2;
       }
       adds += moved;
-      const int64_t k = p & (Wcap - 1);
+      const int64_t kk = p & (Wcap - 1);
       if (zero) {
-        ring.st[k] = kZero | ((prev_steps + moved) << 2);
+        ring.st[kk] = kZero | ((prev_steps + moved) << 2);
       } else {
         // Root of row a in the current forest: follow stored columns down.
         int v = moved ? a : rlo;
@@ -236,10 +349,10 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
         hs_low = hash_insert(s_hkey[0], s_hval[0], r, rel);
         hs_root = hash_insert(s_hkey[1], s_hval[1], rlo, rel);
         survivor = true;
-        ring.a[k] = a;
-        ring.r[k] = r;
-        ring.rlo[k] = rlo;
-        ring.st[k] = kActive | ((prev_steps + moved) << 2);
+        ring.a[kk] = a;
+        ring.r[kk] = r;
+        ring.rlo[kk] = rlo;
+        ring.st[kk] = kActive | ((prev_steps + moved) << 2);
       }
     }
     // Append this pass's survivors to the block's segment; the lane holding
@@ -250,8 +363,19 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
     if (survivor) {
       const uint32_t rel = (uint32_t)(p - F);
       const uint64_t e = enc(round, p);
-      if (s_hval[0][hs_low] == rel) atomicMin((unsigned long long*)&lowc[r], e);
-      if (s_hval[1][hs_root] == rel) atomicMin((unsigned long long*)&touch[rlo], e);
+      if (s_hval[0][hs_low] == rel) {
+        // Across workgroups: of two survivors on one row, the later one is a
+        // repeat; the value the atomic returns names every such pair with
+        // the row's second-smallest survivor among them.
+        const uint64_t old = atomicMin((unsigned long long*)&A.lowc[r], e);
+        if (same_round(old, round)) {
+          const uint64_t later = old > e ? old : e;
+          fd = (uint64_t)enc_pos(later) < fd ? (uint64_t)enc_pos(later) : fd;
+        }
+      } else {
+        fd = (uint64_t)p < fd ? (uint64_t)p : fd;  // an earlier survivor here has low r
+      }
+      if (s_hval[1][hs_root] == rel) atomicMin((unsigned long long*)&A.touch[rlo], e);
     }
     uint32_t before = 0, total = 0;
 #pragma unroll
@@ -270,142 +394,160 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) scount[blockIdx.x] = nsurv;
+  fd = block_min_u64<kWalkWaves>(fd, s_u64);
+  if (tid == 0) {
+    A.scount[blockIdx.x] = nsurv;
+    A.fdslot[blockIdx.x] = fd;
+  }
   // Counters: wave sums -> block totals in LDS -> the block's own slots.
-  if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
-  if (threadIdx.x == 0) s_bad = 0;
+  if (tid < 3) s_cnt[tid] = 0;
+  if (tid == 0) s_bad = 0;
   __syncthreads();
-  adds = wave_sum_i64(adds);
-  finds = wave_sum_i64(finds);
-  words = wave_sum_i64(words);
+  const int64_t wadds = wave_sum_i64(adds);
+  const int64_t wfinds = wave_sum_i64(finds);
+  const int64_t wwords = wave_sum_i64(words);
   if (__ballot(bad != 0)) bad = 1;
-  if ((threadIdx.x & 63) == 0) {
-    if (adds) atomicAdd(&s_cnt[0], (unsigned long long)adds);
-    if (finds) atomicAdd(&s_cnt[1], (unsigned long long)finds);
-    if (words) atomicAdd(&s_cnt[2], (unsigned long long)words);
+  if ((tid & 63) == 0) {
+    if (wadds) atomicAdd(&s_cnt[0], (unsigned long long)wadds);
+    if (wfinds) atomicAdd(&s_cnt[1], (unsigned long long)wfinds);
+    if (wwords) atomicAdd(&s_cnt[2], (unsigned long long)wwords);
     if (bad) s_bad = 1;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     // The block's own slots (the grid is the same every round), summed once
-    // at the finish: an atomic per block and round on the three shared
-    // counters serializes at one address and showed in the walk's time.
-    uint64_t* mine = wstat + 3 * (int64_t)blockIdx.x;
+    // at the finish.
+    uint64_t* mine = A.wstat + 3 * (int64_t)blockIdx.x;
     mine[0] += s_cnt[0];
     mine[1] += s_cnt[1];
     mine[2] += s_cnt[2];
-    if (s_bad) atomicOr(&ctl->err, 1);
+    if (s_bad) atomicOr(&A.ctl->err, 1);
   }
 }
 
-
-// Block-wide reductions for the 256-thread decide/commit kernels.
-__device__ inline uint64_t block_min_u64(uint64_t v, uint64_t* tmp /* 4 */) {
-  v = wave_min_u64(v);
-  if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = v;
-  __syncthreads();
-  uint64_t r = tmp[0];
-#pragma unroll
-  for (int w = 1; w < 4; ++w) r = tmp[w] < r ? tmp[w] : r;
-  __syncthreads();
-  return r;
-}
-
-__device__ inline int64_t block_sum_i64(int64_t v, int64_t* tmp /* 4 */) {
-  v = wave_sum_i64(v);
-  if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = v;
-  __syncthreads();
-  const int64_t r = tmp[0] + tmp[1] + tmp[2] + tmp[3];
-  __syncthreads();
-  return r;
-}
-
-// Sum of the walk blocks' counter slots into the control block.
-__global__ __launch_bounds__(256) void k_walk_stats(const uint64_t* wstat, int64_t blocks,
-                                                    RedCtl* ctl) {
-  int64_t c[3] = {0, 0, 0};
-  for (int64_t b = threadIdx.x; b < blocks; b += blockDim.x)
-    for (int k = 0; k < 3; ++k) c[k] += (int64_t)wstat[3 * b + k];
-  __shared__ int64_t tmp[4];
-  for (int k = 0; k < 3; ++k) c[k] = block_sum_i64(c[k], tmp);
-  if (threadIdx.x == 0) {
-    atomicAdd((unsigned long long*)&ctl->additions_all, (unsigned long long)c[0]);
-    atomicAdd((unsigned long long*)&ctl->find_steps, (unsigned long long)c[1]);
-    atomicAdd((unsigned long long*)&ctl->words_read, (unsigned long long)c[2]);
+// Commit, one workgroup per walk workgroup, over that workgroup's survivors:
+// a survivor commits if it precedes the round's first repeated low (the
+// smallest of the walk's slots) or is the first survivor on its row and no
+// earlier survivor has that row as its root; the others are kept, in this
+// workgroup's own segment of the next list.  The slot gets the pivots
+// committed, the end of the last one, the first column kept and the number
+// kept.
+__global__ __launch_bounds__(kCommitThreads) void k_commit(RedArgs A) {
+  constexpr int kWaves = kCommitThreads / 64;
+  __shared__ uint64_t utmp[kWaves];
+  __shared__ int64_t itmp[kWaves];
+  const int tid = threadIdx.x;
+  const int nb = (int)gridDim.x;
+  uint64_t* slot = A.cslot + 4 * (int64_t)blockIdx.x;
+  const RedCtl* ctl = A.ctl;
+  if (ctl->done || ctl->need_more) return;
+  const uint32_t cnt = A.scount[blockIdx.x];
+  if (cnt == 0) {
+    if (tid == 0) {
+      slot[0] = 0;
+      slot[1] = 0;
+      slot[2] = kNoValue;
+      slot[3] = 0;
+    }
+    return;
   }
-}
-
-// Exclusive prefix of v over the block (and the block total).
-__device__ inline int64_t block_excl_i64(int64_t v, int64_t* tmp /* 4 */, int64_t* total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int64_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int64_t y = (int64_t)shfl64_up((uint64_t)x, o);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) tmp[wave] = x;
-  __syncthreads();
-  int64_t base = 0;
-  for (int w = 0; w < wave; ++w) base += tmp[w];
-  *total = tmp[0] + tmp[1] + tmp[2] + tmp[3];
-  __syncthreads();
-  return base + x - v;
-}
-
-// First survivor whose low repeats an earlier survivor's low: the lowest
-// survivor p with lowc[r] != its own tag.  One block per walk block, over
-// that block's survivors.
-__global__ __launch_bounds__(256) void k_decide(Ring ring, int64_t Wcap, const int64_t* surv,
-                                                const uint32_t* scount, int64_t seg,
-                                                const uint64_t* lowc, RedCtl* ctl) {
-  __shared__ uint64_t tmp[4];
-  if (ctl->done) return;
-  const uint32_t cnt = scount[blockIdx.x];
-  if (cnt == 0) return;
   const int64_t round = ctl->round;
-  const int64_t* my = surv + blockIdx.x * seg;
-  uint64_t best = kNoValue;
-  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-    const int64_t p = my[i];
-    const int64_t k = p & (Wcap - 1);
-    if (lowc[ring.r[k]] != enc(round, p) && (uint64_t)p < best) best = (uint64_t)p;
+  uint64_t fd = kNoValue;
+  for (int b = tid; b < nb; b += kCommitThreads) fd = A.fdslot[b] < fd ? A.fdslot[b] : fd;
+  fd = block_min_u64<kWaves>(fd, utmp);
+  const Ring ring = A.ring;
+  const int64_t Wcap = A.Wcap;
+  const int64_t* my = A.surv + blockIdx.x * A.seg;
+  int64_t* kept_out = A.act[round & 1] + blockIdx.x * A.seg;
+  uint64_t stay_min = kNoValue;
+  int64_t npiv = 0, last = -1, nkept = 0;
+  for (uint32_t i0 = 0; i0 < cnt; i0 += kCommitThreads) {
+    const uint32_t i = i0 + tid;
+    bool keep = false;
+    int64_t p = 0;
+    if (i < cnt) {
+      p = my[i];
+      const int64_t kk = p & (Wcap - 1);
+      const int32_t r = ring.r[kk];
+      const uint64_t e = enc(round, p);
+      if ((uint64_t)p < fd || (A.lowc[r] == e && A.touch[r] > e)) {
+        const int32_t a = ring.a[kk];
+        A.part[r] = a;  // the stored column {a, r}
+        if (A.part16) A.part16[r] = (uint16_t)a;
+        A.killer[r] = p;
+        ring.st[kk] = (ring.st[kk] & ~3) | kCommitted;
+        ++npiv;
+        last = p > last ? p : last;
+      } else {
+        keep = true;
+        stay_min = (uint64_t)p < stay_min ? (uint64_t)p : stay_min;
+      }
+    }
+    int64_t total;
+    const int64_t at = block_excl_i64<kWaves>(keep ? 1 : 0, itmp, &total);
+    if (keep) kept_out[nkept + at] = p;
+    nkept += total;
   }
-  best = block_min_u64(best, tmp);
-  if (threadIdx.x == 0 && best != kNoValue)
-    atomicMin((unsigned long long*)&ctl->firstdup[round & 1], (unsigned long long)best);
+  npiv = block_sum_i64<kWaves>(npiv, itmp);
+  const uint64_t last_end = block_max_u64<kWaves>((uint64_t)(last + 1), utmp);
+  stay_min = block_min_u64<kWaves>(stay_min, utmp);
+  if (tid == 0) {
+    slot[0] = (uint64_t)npiv;
+    slot[1] = last_end;
+    slot[2] = stay_min;
+    slot[3] = (uint64_t)nkept;
+  }
 }
 
-// End of a round: the pivots and E_eff with this round's commits, the next
-// window start F (first column left active, nf; none: the window end), the
-// next window, and the hand-over of the active list (one thread of its own
-// launch; electing the last commit workgroup with a ticket instead costs
-// more, its same-address atomics serialize across the grid).
-__device__ void advance_round(RedCtl* ctl, int64_t n, int64_t E, int64_t Wcap, uint64_t nf,
-                              int64_t new_pivots, int64_t end) {
-  // The control block is read once, up front, and written at the end: one
-  // thread that read a field back after writing it could get the old value
-  // from the scalar cache.
+// End of a round, one workgroup: the commit slots are reduced (pivots
+// committed, end of the last pivot, first column kept, columns kept), the
+// offsets of the kept segments are written for the next walk, and the
+// state advances.  The window start F is the first column not yet final;
+// the window end never moves back; the width doubles (up to the ring's
+// capacity) while almost every column of a round becomes final and halves
+// (down to the base width) when many stay.  The control block is read once
+// and written once, by one thread.
+__global__ __launch_bounds__(kAdvanceThreads) void k_advance(RedArgs A) {
+  constexpr int kWaves = kAdvanceThreads / 64;
+  __shared__ int64_t itmp[kWaves];
+  __shared__ uint64_t utmp[kWaves];
+  RedCtl* ctl = A.ctl;
+  if (ctl->done || ctl->need_more) return;
+  const int tid = threadIdx.x;
+  const int nb = A.nblocks;
+  int64_t piv = 0, kept = 0;
+  uint64_t end = 0, stay = kNoValue;
+  if (tid < nb) {
+    const uint64_t* cs = A.cslot + 4 * (int64_t)tid;
+    piv = (int64_t)cs[0];
+    end = cs[1];
+    stay = cs[2];
+    kept = (int64_t)cs[3];
+  }
+  int64_t all_kept = 0;
+  const int64_t before = block_excl_i64<kWaves>(kept, itmp, &all_kept);
+  if (tid < nb) A.kpre[tid] = before;
+  if (tid == 0) A.kpre[nb] = all_kept;
+  piv = block_sum_i64<kWaves>(piv, itmp);
+  end = block_max_u64<kWaves>(end, utmp);
+  stay = block_min_u64<kWaves>(stay, utmp);
+  if (tid != 0) return;
   const RedCtl c = *ctl;
-  const int64_t pivots = c.pivots + new_pivots;
-  const int64_t E_eff = end > c.E_eff ? end : c.E_eff;
-  const int64_t F = nf == kNoValue ? c.Wend : (int64_t)nf;
+  const int64_t n = A.n, E = A.E, Wcap = A.Wcap;
+  const int64_t pivots = c.pivots + piv;
+  const int64_t E_eff = (int64_t)end > c.E_eff ? (int64_t)end : c.E_eff;
+  const int64_t F = stay == kNoValue ? c.Wend : (int64_t)stay;
   int64_t Wend = c.Wend, width = c.width;
-  int32_t done = c.done, need_more = c.need_more, err = c.err;
+  int32_t done = 0, need_more = 0, err = c.err;
   if (pivots >= n - 1) {
     // Every later column reduces to zero; only columns before the last
     // pivot still need finishing (for the exact addition count).
     if (F >= E_eff) done = 1;
   } else {
     const int64_t lim = c.E_lim;
-    // Window width: doubles (up to the ring's capacity) while almost every
-    // column of a round becomes final, halves (down to the base width) when
-    // many stay.  The end never moves back: columns already in the window
-    // stay there.
-    const int64_t stay = c.nA_next;
-    if (stay < width / 256)
+    if (all_kept < width / 256)
       width = 2 * width < Wcap ? 2 * width : Wcap;
-    else if (stay > width / 16)
+    else if (all_kept > width / 16)
       width = width / 2 > c.width_min ? width / 2 : c.width_min;
     const int64_t want = F + width < lim ? F + width : lim;
     Wend = want > Wend ? want : Wend;
@@ -426,122 +568,40 @@ __device__ void advance_round(RedCtl* ctl, int64_t n, int64_t E, int64_t Wcap, u
   ctl->err = err;
   ctl->fresh_lo = c.Wend;
   ctl->fresh_hi = Wend;
-  ctl->nA = c.nA_next;
-  ctl->nA_next = 0;
-  ctl->cur = c.cur ^ 1;
+  ctl->nA = all_kept;
   ctl->F = F;
   ctl->Wend = Wend;
   ctl->maxWend = Wend > c.maxWend ? Wend : c.maxWend;
   ctl->round = c.round + 1;
 }
 
-// Commit the survivors the rule allows; append the rest to the next active
-// list.  One block per walk block, over that block's survivors, in two phases
-// so that the list needs one atomic per block: commit and count, then (after
-// one block-wide scan) write the stayers.
-__global__ __launch_bounds__(256) void k_commit(Ring ring, int64_t Wcap, const int64_t* surv,
-                                                const uint32_t* scount, int64_t seg,
-                                                int64_t* act0, int64_t* act1,
-                                                const uint64_t* lowc, const uint64_t* touch,
-                                                int32_t* part, uint16_t* part16,
-                                                int64_t* killer, uint64_t* cslot,
-                                                RedCtl* ctl) {
-  __shared__ int64_t itmp[4];
-  __shared__ uint64_t utmp[4];
-  __shared__ int64_t s_base;
-  if (ctl->done) return;
-  const int64_t round = ctl->round;
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->firstdup[(round + 1) & 1] = kNoValue;
-  // This block's slot: pivots committed, end of the last one, first stayer.
-  uint64_t* slot = cslot + 3 * (int64_t)blockIdx.x;
-  const uint32_t cnt = scount[blockIdx.x];
-  if (cnt == 0) {
-    if (threadIdx.x == 0) {
-      slot[0] = 0;
-      slot[1] = 0;
-      slot[2] = kNoValue;
-    }
-    return;
-  }
-  int64_t* next = ctl->cur ? act0 : act1;
-  const uint64_t fd = ctl->firstdup[round & 1];
-  const int64_t* my = surv + blockIdx.x * seg;
-  uint64_t stay_min = kNoValue;
-  int64_t npiv = 0, last = -1, nstay = 0;
-  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-    const int64_t p = my[i];
-    const int64_t k = p & (Wcap - 1);
-    const int32_t r = ring.r[k];
-    const uint64_t e = enc(round, p);
-    if ((uint64_t)p < fd || (lowc[r] == e && touch[r] > e)) {
-      const int32_t a = ring.a[k];
-      part[r] = a;  // the stored column {a, r}
-      if (part16) part16[r] = (uint16_t)a;
-      killer[r] = p;
-      ring.st[k] = (ring.st[k] & ~3) | kCommitted;
-      ++npiv;
-      last = p > last ? p : last;
-    } else {
-      ++nstay;
-      if ((uint64_t)p < stay_min) stay_min = (uint64_t)p;
-    }
-  }
-  int64_t total;
-  const int64_t mine = block_excl_i64(nstay, itmp, &total);
-  if (threadIdx.x == 0 && total)
-    s_base = (int64_t)atomicAdd((unsigned long long*)&ctl->nA_next, (unsigned long long)total);
-  __syncthreads();
-  if (nstay) {
-    int64_t at = s_base + mine;
-    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-      const int64_t p = my[i];
-      if ((ring.st[p & (Wcap - 1)] & 3) == kActive) next[at++] = p;
-    }
-  }
-  npiv = block_sum_i64(npiv, itmp);
-  const uint64_t last_c = block_min_u64(~(uint64_t)(last + 1), utmp);
-  stay_min = block_min_u64(stay_min, utmp);
+// Sum of the walk blocks' counter slots into the control block.
+__global__ __launch_bounds__(256) void k_walk_stats(const uint64_t* wstat, int64_t blocks,
+                                                    RedCtl* ctl) {
+  __shared__ int64_t tmp[4];
+  int64_t c[3] = {0, 0, 0};
+  for (int64_t b = threadIdx.x; b < blocks; b += blockDim.x)
+    for (int q = 0; q < 3; ++q) c[q] += (int64_t)wstat[3 * b + q];
+  for (int q = 0; q < 3; ++q) c[q] = block_sum_i64<4>(c[q], tmp);
   if (threadIdx.x == 0) {
-    slot[0] = (uint64_t)npiv;
-    slot[1] = ~last_c;  // last committed position + 1, or 0
-    slot[2] = stay_min;
+    ctl->additions_all = c[0];
+    ctl->find_steps = c[1];
+    ctl->words_read = c[2];
   }
 }
 
-// The commit blocks' slots (pivot counts, pivot ends, first stayers) are
-// reduced here, by one block, instead of three atomics per commit block on
-// the shared control block; then the round advances.
-__global__ __launch_bounds__(256) void k_advance(RedCtl* ctl, const uint64_t* cslot,
-                                                 int64_t blocks, int64_t n, int64_t E,
-                                                 int64_t Wcap) {
-  __shared__ int64_t itmp[4];
-  __shared__ uint64_t utmp[4];
-  if (ctl->done) return;
-  int64_t piv = 0;
-  uint64_t end_c = kNoValue, stay = kNoValue;  // end_c: complement, so a min finds the max
-  for (int64_t b = threadIdx.x; b < blocks; b += blockDim.x) {
-    piv += (int64_t)cslot[3 * b];
-    const uint64_t e = ~cslot[3 * b + 1];
-    end_c = e < end_c ? e : end_c;
-    stay = cslot[3 * b + 2] < stay ? cslot[3 * b + 2] : stay;
-  }
-  piv = block_sum_i64(piv, itmp);
-  end_c = block_min_u64(end_c, utmp);
-  stay = block_min_u64(stay, utmp);
-  if (threadIdx.x == 0) advance_round(ctl, n, E, Wcap, stay, piv, (int64_t)~end_c);
-}
-
+// More sorted columns are available (the last round stopped with need_more,
+// every column before the old limit final, none kept): the window continues
+// behind its old end at its current width.
 __global__ void k_reduce_extend(RedCtl* ctl, int64_t E_lim) {
-  // All columns before the old limit are final here (F == old limit).
+  const RedCtl c = *ctl;
+  const int64_t Wend = c.F + c.width < E_lim ? c.F + c.width : E_lim;
   ctl->E_lim = E_lim;
   ctl->need_more = 0;
-  const int64_t F = ctl->F;
-  const int64_t width = ctl->width;
-  const int64_t Wend = F + width < E_lim ? F + width : E_lim;
-  ctl->fresh_lo = ctl->Wend;
+  ctl->fresh_lo = c.Wend;
   ctl->fresh_hi = Wend;
   ctl->Wend = Wend;
-  if (Wend > ctl->maxWend) ctl->maxWend = Wend;
+  if (Wend > c.maxWend) ctl->maxWend = Wend;
 }
 
 __global__ void k_reduce_init(RedCtl* ctl, int64_t E_lim, int64_t width, int64_t n) {
@@ -554,7 +614,6 @@ __global__ void k_reduce_init(RedCtl* ctl, int64_t E_lim, int64_t width, int64_t
   c.maxWend = c.Wend;
   c.fresh_lo = 0;
   c.fresh_hi = c.Wend;
-  c.firstdup[0] = c.firstdup[1] = kNoValue;
   c.done = (n <= 1 || E_lim == 0) ? 1 : 0;
   *ctl = c;
 }
@@ -566,13 +625,13 @@ __global__ void k_reduce_init(RedCtl* ctl, int64_t E_lim, int64_t width, int64_t
 // is at most Wcap wide and holds every column walked since F, so no later
 // column has reused an entry of that range.
 __global__ __launch_bounds__(256) void k_overshoot(Ring ring, int64_t Wcap, RedCtl* ctl) {
+  __shared__ int64_t tmp[4];
   const int64_t lo = ctl->E_eff, hi = ctl->maxWend;
   int64_t s = 0;
   for (int64_t p = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < hi;
        p += (int64_t)gridDim.x * blockDim.x)
     s += ring.st[p & (Wcap - 1)] >> 2;
-  __shared__ int64_t tmp[4];
-  s = block_sum_i64(s, tmp);  // one atomic per block: same-address atomics serialize
+  s = block_sum_i64<4>(s, tmp);  // one atomic per block
   if (threadIdx.x == 0 && s)
     atomicAdd((unsigned long long*)&ctl->additions_overshoot, (unsigned long long)s);
 }
@@ -598,23 +657,21 @@ int scan_blocks(int64_t Wcap) {
   return (int)(b < 1 ? 1 : b);
 }
 
-
 }  // namespace
 
-// One lane per column, up to 512 workgroups of 1024 lanes (two per compute
-// unit of MI355X: 32 waves per CU); beyond that each lane takes several
-// columns in turn.  The decide and commit steps run one block per walk
-// block.  Fixed, not queried, so that workspace sizes do not depend on the
-// device.
+// One lane per column, up to kMaxWalkBlocks workgroups of 1024 lanes (two
+// per compute unit of MI355X: 32 waves per CU); beyond that each lane takes
+// several columns in turn.  The commit runs one workgroup per walk
+// workgroup.  Fixed, not queried, so that workspace sizes do not depend on
+// the device.
 int walk_blocks(int64_t Wcap) {
   int64_t b = (Wcap + kWalkThreads - 1) / kWalkThreads;
-  const int64_t cap = 512;
-  if (b > cap) b = cap;
+  if (b > kMaxWalkBlocks) b = kMaxWalkBlocks;
   return (int)(b < 1 ? 1 : b);
 }
 
-// Survivor entries per walk block: the most items one block can see in a
-// round (a round has at most Wcap items).
+// Survivor (and kept-column) entries per walk workgroup: the most items one
+// workgroup can see in a round (a round has at most Wcap items).
 int64_t walk_segment(int64_t Wcap) {
   const int64_t threads = kWalkThreads * (int64_t)walk_blocks(Wcap);
   return kWalkThreads * ((Wcap + threads - 1) / threads);
@@ -630,52 +687,42 @@ hipError_t launch_reduce_extend(const RedArgs& a, int64_t E_lim, hipStream_t s) 
 }
 
 hipError_t launch_reduce_init(const RedArgs& a, int64_t E_lim, hipStream_t s) {
+  const int wb = walk_blocks(a.Wcap);
   hipError_t e;
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(a.part), 0xFFFFFFFFu, a.n, s)) !=
       hipSuccess)
+    return e;
+  if (a.part16 && (e = launch_fill_u32(reinterpret_cast<uint32_t*>(a.part16), 0xFFFFFFFFu,
+                                       part16_len(a.n) / 2, s)) != hipSuccess)
     return e;
   if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(a.killer), ~0ull, a.n, s)) != hipSuccess)
     return e;
   if ((e = launch_fill_u64(a.lowc, kNoValue, a.n, s)) != hipSuccess) return e;
   if ((e = launch_fill_u64(a.touch, kNoValue, a.n, s)) != hipSuccess) return e;
-  if ((e = launch_fill_u64(a.wstat, 0ull, 3 * (int64_t)walk_blocks(a.Wcap), s)) != hipSuccess)
-    return e;
-  if (a.part16 && (e = launch_fill_u32(reinterpret_cast<uint32_t*>(a.part16), 0xFFFFFFFFu,
-                                       part16_len(a.n) / 2, s)) != hipSuccess)
-    return e;
+  if ((e = launch_fill_u64(a.wstat, 0ull, 3 * (int64_t)wb, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_init, dim3(1), dim3(1), 0, s, a.ctl, E_lim, a.width, a.n);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_walk) {
   // The LDS table copy of the largest n (64 KB) is beyond the default
-  // dynamic LDS limit of a workgroup; two such workgroups still fit a CU.
+  // dynamic LDS limit of a workgroup.
   static const hipError_t attr = hipFuncSetAttribute(
       (const void*)k_walk<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
       (int)(2 * kPart16MaxN));
   if (attr != hipSuccess) return attr;
   const int wb = walk_blocks(a.Wcap);
-  const int64_t seg = walk_segment(a.Wcap);
   if (ev_walk) (void)hipEventRecord(ev_walk[0], s);
   const int64_t n16 = a.part16 ? part16_len(a.n) : 0;
   if (a.part16)
-    hipLaunchKernelGGL(k_walk<true>, dim3((unsigned)wb), dim3(kWalkThreads), 2 * n16, s,
-                       a.skeys, a.ib, a.part, a.part16, n16, a.ring, a.Wcap, a.act[0], a.act[1],
-                       a.lowc, a.touch, a.surv, a.scount, seg, a.wstat, a.ctl);
+    hipLaunchKernelGGL(k_walk<true>, dim3((unsigned)wb), dim3(kWalkThreads), 2 * n16, s, a, n16);
   else
-    hipLaunchKernelGGL(k_walk<false>, dim3((unsigned)wb), dim3(kWalkThreads), 0, s, a.skeys,
-                       a.ib, a.part, a.part16, n16, a.ring, a.Wcap, a.act[0], a.act[1], a.lowc,
-                       a.touch, a.surv, a.scount, seg, a.wstat, a.ctl);
+    hipLaunchKernelGGL(k_walk<false>, dim3((unsigned)wb), dim3(kWalkThreads), 0, s, a, n16);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev_walk) (void)hipEventRecord(ev_walk[1], s);
-  hipLaunchKernelGGL(k_decide, dim3((unsigned)wb), dim3(256), 0, s, a.ring, a.Wcap, a.surv,
-                     a.scount, seg, a.lowc, a.ctl);
-  hipLaunchKernelGGL(k_commit, dim3((unsigned)wb), dim3(256), 0, s, a.ring, a.Wcap, a.surv,
-                     a.scount, seg, a.act[0], a.act[1], a.lowc, a.touch, a.part, a.part16,
-                     a.killer, a.cslot, a.ctl);
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(256), 0, s, a.ctl, a.cslot, (int64_t)wb, a.n,
-                     a.E, a.Wcap);
+  hipLaunchKernelGGL(k_commit, dim3((unsigned)wb), dim3(kCommitThreads), 0, s, a);
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(kAdvanceThreads), 0, s, a);
   return hipGetLastError();
 }
 
