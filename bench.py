@@ -5,7 +5,11 @@
 A step is one whole barcode -- distances, LSD radix sort, grades, F2 column
 reduction, read-off -- of the N=16384, d=64 int8 Gaussian-mixture cloud (32
 clusters, std 12, seed 0), from points already resident in HBM to the
-canonical barcode in HBM, through ph0_barcodes_device.
+canonical barcode in HBM, through ph0_barcodes_device.  The K timed steps
+run without statistics; the same number of steps with the library's HIP
+events then gives the stage and kernel times (the rooflines).  First-call
+latency (module load, workspace allocation), the host<->HBM copies and the
+host-memory entry point are reported separately, never as the headline.
 
 value = E_eff / step time: sorted edge columns up to the last pivot, i.e. the
 columns the reduction actually processes (the remaining E - E_eff columns are
@@ -31,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = "mixture_n16384_d64_i8"
 HBM_PEAK_GBS = 8000.0
+RECOMPUTE_MIN_E = 1 << 22  # edges from which the library recomputes keys per distance range
 
 
 def note(msg):
@@ -51,7 +56,7 @@ def parse():
     ap.add_argument("--no-h1", action="store_true")
     ap.add_argument("--h1-only", action="store_true",
                     help="only run the H1 leg (no CPU oracle) and print its JSON")
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--paper-scaling", action="store_true",
                     help="only run the paper's experiment: N uniform points in [0,1]^2 (on a "
                          "fixed-point grid), N = 50..700 and beyond, GPU and CPU-oracle time "
@@ -185,13 +190,34 @@ def calibrate_copy(mib):
     print(json.dumps({"calibrate_copy_bytes": mib << 20, "copies": 5}), flush=True)
 
 
+def host_cpu():
+    """Model name and logical CPU count of this host (from /proc/cpuinfo), and
+    the CPUs this process may run on."""
+    model, logical = "unknown", 0
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name") and model == "unknown":
+                    model = line.split(":", 1)[1].strip()
+                if line.startswith("processor"):
+                    logical += 1
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"model": model, "logical_cpus": logical or os.cpu_count(), "usable_cpus": usable}
+
+
 def cpu_baseline(points, n_sample):
-    """The CPU oracle (single-threaded) on the first n_sample points."""
+    """The CPU oracle (single-threaded, the same source built with -O3
+    -march=native for this host) on the first n_sample points."""
+    import tempfile
+
     import oracle
 
+    lib = oracle.build_native(tempfile.mkdtemp(prefix="ph0_native_"))
     sub = points[:n_sample].copy()
     t0 = time.perf_counter()
-    res = oracle.barcode(sub)
+    res = oracle.barcode(sub, lib=lib)
     t = time.perf_counter() - t0
     return {
         "value": res.E_eff / t,
@@ -199,11 +225,13 @@ def cpu_baseline(points, n_sample):
         "cores": 1,
         "kind": "oracle",
         "sample": "%s (N=%d, E=%d, E_eff=%d), one whole oracle run (distances, std::sort, "
-                  "grades, dense F2 reduction with early exit, read-off) in %.2f s"
+                  "grades, dense F2 reduction with early exit, read-off), g++ -O3 -march=native, "
+                  "one thread, in %.2f s"
                   % ("the whole benchmark cloud" if n_sample >= len(points) else
                      "the first %d points of the benchmark cloud" % n_sample,
                      n_sample, res.E, res.E_eff, t),
         "seconds": res.seconds,
+        "host": host_cpu(),
     }
 
 
@@ -260,7 +288,8 @@ def bench_h1(torch, ph0, synth, with_cpu, reps=5):
     cloud: whole calls from HBM-resident points, the oracle beside it on a
     128-point cloud of the same recipe, and the dense-column rate: each
     column addition of the dense method moves one E-bit column (the kernel
-    reads only the part of it at or below the stored column's low)."""
+    reads only the part of it at or below the stored column's low; the stored
+    columns stay in the last-level cache, so the rate is not an HBM one)."""
     x = synth.uniform_cloud(H1_N, 3, seed=0)
     xd = torch.from_numpy(x).to("cuda:0")
     ws = torch.empty(ph0.ph0_h1_workspace_bytes(H1_N, 3, x.dtype), dtype=torch.uint8,
@@ -285,8 +314,10 @@ def bench_h1(torch, ph0, synth, with_cpu, reps=5):
         "additions_per_s": st["additions"] / t,
         "pairs": st["pivots"], "emergent": st["emergent"], "bars": st["bars"],
         "rounds": st["rounds"], "walks": st["walks"],
-        "dense_column_gbs": round(dense_bytes / t / 1e9, 1),
-        "dense_column_frac_of_hbm": round(dense_bytes / t / 1e9 / HBM_PEAK_GBS, 4),
+        # E-bit stored columns: 2.1 MB per column at N=256 x E/64 words; the
+        # table of E columns (0.13 GB) lives in the 256 MB last-level cache,
+        # so this is a rate through the cache hierarchy, not an HBM fraction.
+        "dense_column_gbs_cached": round(dense_bytes / t / 1e9, 1),
     }
     if with_cpu:
         import oracle
@@ -308,28 +339,39 @@ def bench_h1(torch, ph0, synth, with_cpu, reps=5):
     return rec
 
 
-def bench_serving(ph0, synth, count):
-    """Mixed request stream: closed-loop saturation, then Poisson at 0.8x."""
+SERVE_LOADS = (0.5, 0.8, 0.95)
+
+
+def bench_serving(ph0, synth, count, warm=200):
+    """Mixed request stream: `warm` warm-up requests, then `count` requests
+    closed-loop (the saturation rate), then the same `count` requests with
+    Poisson arrivals at 0.5, 0.8 and 0.95 x saturation; the same requests one
+    at a time through the single-cloud path beside them."""
     from paper_2203_02527_amd import serve
 
-    reqs = synth.serving_requests(count, seed=0)
-    serve.serve(reqs[:8], rate=None, mem_budget=8 << 30, slots=4)  # warm-up
+    reqs = synth.serving_requests(warm + count, seed=0)
+    warmup, reqs = reqs[:warm], reqs[warm:]
+    serve.serve(warmup, rate=None, mem_budget=8 << 30, slots=4)
     sat = serve.serve(reqs, rate=None, mem_budget=8 << 30, slots=4)
-    rate = 0.8 * sat["clouds_per_s"]
-    pois = serve.serve(reqs, rate=rate, mem_budget=8 << 30, slots=4, seed=1)
+    points = []
+    for load in SERVE_LOADS:
+        rate = load * sat["clouds_per_s"]
+        r = serve.serve(reqs, rate=rate, mem_budget=8 << 30, slots=4, seed=1)
+        points.append({"load": load, "rate": round(rate, 1),
+                       "clouds_per_s": round(r["clouds_per_s"], 1),
+                       "p50_ms": round(r["p50_ms"], 3), "p99_ms": round(r["p99_ms"], 3)})
+        note("serving at %.2f x saturation: p50 %.2f ms p99 %.2f ms"
+             % (load, r["p50_ms"], r["p99_ms"]))
     pl = serve.plain(reqs)
     pl.pop("results")
     return {
-        "workload": "%d requests, N log-uniform in [64,8192], d in {3,16,64}, int8/int16 "
-                    "mixtures, seed 0; 4 slots, 8 GiB pool" % count,
-        "saturation_clouds_per_s": sat["clouds_per_s"],
-        "poisson_rate": rate,
-        "clouds_per_s": pois["clouds_per_s"],
-        "p50_ms": pois["p50_ms"],
-        "p99_ms": pois["p99_ms"],
-        "plain_clouds_per_s": pl["clouds_per_s"],
-        "plain_p50_ms": pl["p50_ms"],
-        "plain_p99_ms": pl["p99_ms"],
+        "workload": "%d requests after %d warm-up, N log-uniform in [64,8192], d in {3,16,64}, "
+                    "int8/int16 mixtures, seed 0; 4 slots, 8 GiB pool" % (count, warm),
+        "saturation_clouds_per_s": round(sat["clouds_per_s"], 1),
+        "poisson": points,
+        "plain_clouds_per_s": round(pl["clouds_per_s"], 1),
+        "plain_p50_ms": round(pl["p50_ms"], 3),
+        "plain_p99_ms": round(pl["p99_ms"], 3),
     }
 
 
@@ -363,19 +405,36 @@ def measured_traffic(kernel, workload):
 
 
 def sort_bytes(st):
-    """Algorithmic bytes of one call's radix passes: a pass reads its input
-    keys once and writes its output keys once (8 bytes each).  A distance
-    chunk's first pass reads all E keys and keeps the chunk's; its later
-    passes read and write the chunk's keys only.  When the sort finished
-    with one whole sort, that sort moves all E keys in every pass (the
-    chunks sorted before it are then not counted, which only lowers the
-    figure)."""
+    """Algorithmic bytes of one call's radix passes: a pass reads each of its
+    input keys once and writes each output key once (8 bytes each).  Above
+    2^22 edges the keys of a distance range are recomputed and written only
+    for that range (sorted_keys of them), so every pass moves 16 bytes per
+    sorted key.  Below it all E keys are stored: a distance range's first
+    pass reads all E keys and keeps the range's, its later passes move the
+    range's keys; a sort that ends whole moves all E keys in every pass."""
     E, P, k, c = st["E"], st["sort_passes"], st["sorted_keys"], st["sort_chunks"]
     if P == 0:
         return 0.0
+    if E >= RECOMPUTE_MIN_E:
+        return 16.0 * k * P
     if k < E:
         return 8.0 * E * c + 8.0 * k + 16.0 * (P - 1) * k
     return 8.0 * E * (c - 1) + 16.0 * E * P
+
+
+def walk_bytes(st):
+    """Algorithmic bytes of one call's reduction walks, counted for the
+    2-sparse representation the kernel uses: a column addition reads one
+    4-byte table entry (additions of the sequential count), each column up
+    to the last pivot reads its 8-byte sorted key, and each of the n - 1
+    pivots writes one 4-byte table entry."""
+    return 4.0 * st["additions"] + 8.0 * st["E_eff"] + 4.0 * (st["n"] - 1)
+
+
+def dense_walk_bytes(st):
+    """The same reduction counted for the dense method of the survey's
+    per-unit figure: one N-bit column (8 * ceil(N/64) bytes) per addition."""
+    return 8.0 * ((st["n"] + 63) // 64) * st["additions"] + 8.0 * st["E_eff"]
 
 
 def main():
@@ -411,58 +470,75 @@ def main():
     pts = synth.workload(args.workload, seed=args.seed)
     n, d = pts.shape
     dev = torch.device("cuda:0")
+    torch.zeros(1, device=dev)
+    torch.cuda.synchronize()
+    # Host -> HBM copy of the points; first call (kernel module load, workspace
+    # allocation, first launch); HBM -> host copy of the barcode.
+    t0 = time.perf_counter()
     x = torch.from_numpy(pts).to(dev)
+    torch.cuda.synchronize()
+    h2d_ms = 1000.0 * (time.perf_counter() - t0)
+    t0 = time.perf_counter()
     ws = ph0.alloc_workspace(n, d, pts.dtype, dev)
     out = torch.empty((n, 2), dtype=torch.int32, device=dev)
+    ph0.ph0_barcodes_device(x, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    first_call_ms = 1000.0 * (time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    bars_host = out.cpu()
+    d2h_ms = 1000.0 * (time.perf_counter() - t0)
+    del bars_host
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
         ph0.ph0_barcodes_device(x, out=out, workspace=ws, stream=stream)
     torch.cuda.synchronize()
 
-    # The timed steps record the library's HIP events (stage marks and one
-    # pair around every walk and radix launch, on the call's stream; the
-    # events come from a reused pool, so recording them costs no measurable
-    # time): kernel durations below are those of the timed steps themselves.
+    # The timed steps: whole barcodes from HBM-resident points, no statistics
+    # (each call returns when its work is complete, so per-step wall times
+    # are exact too).
+    step_ms = []
     torch.cuda.synchronize()
-    stats = []
     t0 = time.perf_counter()
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        ph0.ph0_barcodes_device(x, out=out, workspace=ws, stream=stream)
+        step_ms.append(1000.0 * (time.perf_counter() - t1))
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    ms_step = 1000.0 * t / args.steps
+
+    # The same number of steps again with the library's HIP events (stage
+    # marks and one pair around every walk and radix launch, on the call's
+    # stream): stage and kernel times come from these.
+    stats = []
     for _ in range(args.steps):
         _, st = ph0.ph0_barcodes_device(x, out=out, workspace=ws, stream=stream, with_stats=True)
         stats.append(st)
     torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    ms_step = 1000.0 * t / args.steps
     for st in stats:
         st["radix_bytes"] = sort_bytes(st)
+        st["walk_bytes"] = walk_bytes(st)
+        st["dense_walk_bytes"] = dense_walk_bytes(st)
     st0 = stats[-1]
     E, E_eff = st0["E"], st0["E_eff"]
 
     def mean(k):
         return float(np.mean([s[k] for s in stats]))
 
-    # Kernel rooflines from the library's event timings over the timed steps.
-    # Walk: the algorithmic bytes are those of the dense method -- one N-bit
-    # pivot column (LW 64-bit words) per column addition of the sequential
-    # reduction, plus the 8-byte key of each column up to the last pivot.
-    # The kernel holds each stored column as its other row (a 2-sparse
-    # column is fixed by it) and loads one 4-byte entry per step, which it
-    # reports as words_read; both rates are given.
-    LW = (n + 63) // 64
+    # Kernel rooflines from the event timings.  Walk: the bytes of the
+    # 2-sparse reduction (walk_bytes); the dense method's figure is given
+    # beside it.  Radix: 16 bytes per key per pass (sort_bytes).
     walk_ms = mean("ms_walk_kernel")
     walk_launches = mean("walk_launches")
-    walk_bytes = 8.0 * LW * mean("additions") + 8.0 * mean("E_eff")
-    walk_loaded = 4.0 * mean("words_read")
     radix_ms = mean("ms_radix_kernel")
     radix_launches = mean("radix_launches")
-    radix_bytes = mean("radix_bytes")
     kern = {
-        "reduce_walk": dict(ms=walk_ms, launches=walk_launches, bytes=walk_bytes,
-                            per_launch_ms=walk_ms / max(walk_launches, 1)),
-        "radix_pass": dict(ms=radix_ms, launches=radix_launches, bytes=radix_bytes,
-                           per_launch_ms=radix_ms / max(radix_launches, 1)),
+        "reduce_walk": dict(ms=walk_ms, launches=walk_launches, bytes=mean("walk_bytes")),
+        "radix_pass": dict(ms=radix_ms, launches=radix_launches, bytes=mean("radix_bytes")),
     }
     for k in kern.values():
+        k["per_launch_ms"] = k["ms"] / max(k["launches"], 1)
         k["achieved_gbs"] = k["bytes"] / max(k["ms"], 1e-9) / 1e6
     dom = max(kern, key=lambda k: kern[k]["ms"])
     kd = kern[dom]
@@ -480,17 +556,20 @@ def main():
         "algorithmic_bytes_per_launch": round(per_launch),
     }
     if dom == "reduce_walk":
-        roofline["basis"] = ("algorithmic bytes of the dense method: one N-bit column (8 * "
-                             "ceil(N/64) B) per column addition of the sequential reduction + "
-                             "the 8 B key of each column up to the last pivot; the kernel keeps "
-                             "each stored 2-sparse column as one 4-byte index (loaded_*), and "
-                             "traffic is the counter-measured HBM bytes per launch")
-        roofline["loaded_bytes_per_launch"] = round(walk_loaded / max(walk_launches, 1))
-        roofline["loaded_gbs"] = round(walk_loaded / max(walk_ms, 1e-9) / 1e6, 1)
+        roofline["basis"] = ("bytes of the 2-sparse reduction: 4 B table entry per column "
+                             "addition of the sequential count + 8 B sorted key per column up "
+                             "to the last pivot + 4 B per pivot written; the walk is bound by "
+                             "chains of dependent table loads and by row-minimum atomics, not "
+                             "by HBM bandwidth")
+        roofline["dense_equivalent_gbs"] = round(mean("dense_walk_bytes") / max(walk_ms, 1e-9)
+                                                 / 1e6, 1)
+    else:
+        roofline["basis"] = "16 B per sorted key per radix pass (read once, written once)"
     if traffic is not None:
         roofline["traffic_gbs"] = round(traffic / (kd["per_launch_ms"] * 1e6), 1)
-    others = {k: {"achieved_gbs": round(v["achieved_gbs"], 1), "ms_per_step": round(v["ms"], 3),
-                  "launches": v["launches"]} for k, v in kern.items()}
+    others = {k: {"achieved_gbs": round(v["achieved_gbs"], 1), "frac": round(
+        v["achieved_gbs"] / HBM_PEAK_GBS, 4), "ms_per_step": round(v["ms"], 3),
+        "launches": v["launches"]} for k, v in kern.items()}
 
     rec = {
         "metric": "edge columns reduced/s at N=16384",
@@ -500,6 +579,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "ms_per_step_median": round(float(np.median(step_ms)), 4),
+        "ms_per_step_min": round(float(np.min(step_ms)), 4),
+        "ms_per_step_max": round(float(np.max(step_ms)), 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -512,11 +594,15 @@ def main():
             "edges_per_s_all_E": E / (ms_step / 1000.0),
             "window": st0["window"],
         },
+        "first_call_ms": round(first_call_ms, 3),
+        "h2d_points_ms": round(h2d_ms, 3),
+        "d2h_bars_ms": round(d2h_ms, 3),
         "stages_ms": {k: round(mean(k), 4) for k in
                       ("ms_keys", "ms_sort", "ms_reduce", "ms_rank", "ms_emit", "ms_total")},
         "reduction": {k: st0[k] for k in ("additions", "additions_all", "find_steps",
                                           "words_read", "rounds", "distinct_eff",
-                                          "sort_passes", "delta_bits", "keys_path")},
+                                          "sort_passes", "sort_chunks", "sorted_keys",
+                                          "delta_bits", "keys_path")},
         "roofline": roofline,
         "kernels": others,
         "rates": {
@@ -527,6 +613,15 @@ def main():
             "all_edges_per_s": E / (ms_step / 1000.0),
         },
     }
+    # The host-memory entry point (copies in, barcode, copies out, and its own
+    # device allocations) for the PCIe-inclusive rate; never the headline.
+    ph0.ph0_barcodes(pts)
+    t0 = time.perf_counter()
+    for _ in range(3):
+        ph0.ph0_barcodes(pts)
+    host_ms = 1000.0 * (time.perf_counter() - t0) / 3
+    rec["host_entry_point"] = {"ms_per_call": round(host_ms, 3),
+                               "edge_columns_per_s": E_eff / (host_ms / 1000.0)}
     note("timed %d steps: %.3f ms/step" % (args.steps, ms_step))
     if not args.no_batched:
         rec["batched"] = bench_batched(torch, ph0, synth)
