@@ -104,7 +104,10 @@ int ph0_barcodes(const void* points, ph0_dtype dt, int64_t n, int32_t d, ph0_bar
 
 /* The whole barcode on device memory: d_points (n*d elements), d_out (n bars,
  * canonical order), d_workspace of at least ph0_workspace_bytes() bytes.  No
- * device allocation is made.  `st` may be NULL. */
+ * device allocation is made.  `st` may be NULL.  With st NULL, clouds with
+ * n <= 256, n * d <= 8192 and d <= 64 run in one workgroup (the fused kernel
+ * of the batched path); with st given they take the grid-wide passes, which
+ * report the counters.  The barcode is the same either way. */
 int ph0_barcodes_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d,
                         ph0_bar* d_out, void* d_workspace, size_t ws_bytes,
                         void* hip_stream, ph0_stats* st);

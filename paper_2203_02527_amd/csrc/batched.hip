@@ -318,15 +318,26 @@ __global__ __launch_bounds__(kThreads) void k_batched(BatchArgs A) {
   uint64_t* bufB = bufA + A.emax;
   uint32_t* gr = A.grades + (int64_t)blockIdx.x * A.emax;
   const T* X = static_cast<const T*>(A.pts);
+  // One cloud (single_n > 0): rows 0 .. single_n - 1, one workgroup, its
+  // status always written to errs[0]; otherwise clouds from the queue.
+  bool single_done = false;
   while (true) {
-    if (tid == 0) S.s_cloud = atomicAdd(A.queue, 1u);
-    __syncthreads();
-    const uint32_t ci = S.s_cloud;
-    __syncthreads();
-    if (ci >= (uint32_t)A.nclouds) break;
-    const int c = A.order[ci];
-    const int64_t row0 = A.offsets[c];
-    const int n = (int)(A.offsets[c + 1] - row0);
+    uint32_t ci;
+    if (A.single_n > 0) {
+      if (single_done) break;
+      single_done = true;
+      ci = 0;
+    } else {
+      if (tid == 0) S.s_cloud = atomicAdd(A.queue, 1u);
+      __syncthreads();
+      ci = S.s_cloud;
+      __syncthreads();
+      if (ci >= (uint32_t)A.nclouds) break;
+    }
+    const int c = A.single_n > 0 ? 0 : A.order[ci];
+    const int64_t row0 = A.single_n > 0 ? 0 : A.offsets[c];
+    const int n = A.single_n > 0 ? (int)A.single_n : (int)(A.offsets[c + 1] - row0);
+    if (A.single_n > 0 && tid == 0) A.errs[0] = 0;
     uint32_t* bars = A.bars + 2 * row0;
     if (n < 1) continue;
     if (n > kMaxN || (int64_t)n * d > kMaxPts || d > 64) {

@@ -125,9 +125,29 @@ __device__ inline int64_t key_count_index(int64_t J, int jl, int64_t I) {
 }
 
 // Tiles a pass visits: all, or every kp.sample-th one for the sampled
-// histogram.
-__device__ inline int64_t tile_step(const KeyPass& kp, int mode) {
-  return (int64_t)gridDim.x * (mode == kKeysHist ? kp.sample : 1);
+// histogram.  The full passes stride over the tiles by the grid; the sampled
+// pass gives each workgroup a contiguous run of the visited tiles (tile
+// t = v * sample for v in [v0, v1)), so that it runs with few workgroups,
+// each flushing its LDS histogram once.
+struct TileRange {
+  int64_t v0, v1, step, sample;
+};
+__device__ inline TileRange tile_range(const KeyPass& kp, int mode, int64_t ntiles) {
+  TileRange r;
+  if (mode == kKeysHist) {
+    r.sample = kp.sample;
+    const int64_t visited = (ntiles + r.sample - 1) / r.sample;
+    const int64_t per = (visited + gridDim.x - 1) / gridDim.x;
+    r.v0 = blockIdx.x * per;
+    r.v1 = r.v0 + per < visited ? r.v0 + per : visited;
+    r.step = 1;
+  } else {
+    r.sample = 1;
+    r.v0 = blockIdx.x;
+    r.v1 = ntiles;
+    r.step = gridDim.x;
+  }
+  return r;
 }
 
 template <typename T, int MODE>
@@ -141,8 +161,9 @@ __global__ __launch_bounds__(256) void k_keys_alu(const T* __restrict__ x, int64
 
   const int il = threadIdx.x & 63;   // i inside the tile (one per lane)
   const int jl0 = threadIdx.x >> 6;  // first j of this wave; j = jl0 + 4q
-  const int64_t step = tile_step(kp, MODE);
-  for (int64_t t = blockIdx.x * (MODE == kKeysHist ? kp.sample : 1); t < ntiles; t += step) {
+  const TileRange tr = tile_range(kp, MODE, ntiles);
+  for (int64_t v = tr.v0; v < tr.v1; v += tr.step) {
+    const int64_t t = v * tr.sample;
     int64_t jb, ibk;
     tile_coords(t, &jb, &ibk);
     const int64_t i0 = ibk * kTile, j0 = jb * kTile;
@@ -276,8 +297,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int jsub = wave >> 1, isub = wave & 1;  // 32 x 32 sub-tile of this wave
-  const int64_t step = tile_step(kp, MODE);
-  const int64_t tfirst = blockIdx.x * (MODE == kKeysHist ? kp.sample : 1);
+  const TileRange tr = tile_range(kp, MODE, ntiles);
   // The kept range [dlo, dhi) clamped to 32 bits (delta < 2^31 here).
   const uint32_t dlo32 = kp.dlo < 0xFFFFFFFFull ? (uint32_t)kp.dlo : 0xFFFFFFFFu;
   const uint32_t dhi32 = kp.dhi < 0xFFFFFFFFull ? (uint32_t)kp.dhi : 0xFFFFFFFFu;
@@ -286,12 +306,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const bool ahead = KMAX == 64 && vec16 && d <= 64;
   const int segs1 = ((d + 31) & ~31) >> 4;
   TileRegs pre;
-  if (ahead && tfirst < ntiles) {
+  if (ahead && tr.v0 < tr.v1) {
     int64_t jb, ibk;
-    tile_coords(tfirst, &jb, &ibk);
+    tile_coords(tr.v0 * tr.sample, &jb, &ibk);
     tile_regs_load(pre, x, n, d, ibk * kTile, jb * kTile, segs1);
   }
-  for (int64_t t = tfirst; t < ntiles; t += step) {
+  for (int64_t v = tr.v0; v < tr.v1; v += tr.step) {
+    const int64_t t = v * tr.sample;
     int64_t jb, ibk;
     tile_coords(t, &jb, &ibk);
     const int64_t i0 = ibk * kTile, j0 = jb * kTile;
@@ -308,9 +329,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       rbase[threadIdx.x] = kp.cnt[key_count_index(jb, threadIdx.x, ibk)];
     if (ahead) {
       tile_regs_store<kRow>(pre, xs, segs1);
-      if (t + step < ntiles) {
+      if (v + tr.step < tr.v1) {
         int64_t jn, in_;
-        tile_coords(t + step, &jn, &in_);
+        tile_coords((v + tr.step) * tr.sample, &jn, &in_);
         tile_regs_load(pre, x, n, d, in_ * kTile, jn * kTile, segs1);
       }
       __syncthreads();
@@ -567,7 +588,10 @@ hipError_t launch_keys_pass(const void* pts, int elem_bytes, int64_t n, int32_t 
   }
   const int64_t sample = kp.mode == kKeysHist ? (kp.sample > 0 ? kp.sample : 1) : 1;
   const int64_t visited = (ntiles + sample - 1) / sample;
-  const int64_t cap = 8 * (int64_t)cus;
+  // The sampled histogram pass uses two workgroups per CU: every workgroup
+  // flushes its LDS histogram (up to kHistBins global atomics on the same
+  // kHistBins addresses), so fewer, longer workgroups cost less.
+  const int64_t cap = (kp.mode == kKeysHist ? 2 : 8) * (int64_t)cus;
   const int grid = (int)(visited < cap ? visited : cap);
   KeyPass k = kp;
   k.sample = sample;

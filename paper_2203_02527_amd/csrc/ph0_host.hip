@@ -58,6 +58,10 @@ constexpr int32_t kBlocksPerCu = 2;
 // round trips cost more than the stored keys).
 constexpr int64_t kRecomputeMinE = int64_t(1) << 22;
 constexpr size_t kAlign = 256;
+// Largest single cloud that ph0_barcodes_device computes in one workgroup
+// (measured on MI355X: faster than the grid-wide passes up to n of about
+// 300 at d = 3 and 16; 256 keeps a margin).
+constexpr int64_t kFusedSingleMaxN = 256;
 // Size of the fixed device array that ph0_barcodes_batched_device_noalloc
 // uses as its workspace (per device, held until the process ends).
 constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
@@ -362,6 +366,46 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     HIPCHK(hipStreamSynchronize(s));
     drain.armed = false;
     if (st) *st = S;
+    return PH0_OK;
+  }
+
+  // Small clouds, when only the barcode is asked for (no statistics, no
+  // per-vertex detail): the whole computation in one workgroup -- the fused
+  // kernel of the batched path, on this one cloud -- instead of the
+  // grid-wide passes, whose launches and host round trips dominate there.
+  if (stop == kStopAll && !st && out.bars && !out.dbv && !out.killer_pos && !out.killer_edge &&
+      !out.killer_sqdist && !out.partner && n <= kFusedSingleMaxN && n * d <= kBatchMaxPts &&
+      d <= 64) {
+    CtlReadback* rb = pinned_ctl();
+    if (!rb) return fail(PH0_ENOMEM, "pinned host allocation failed");
+    const size_t scratch = align_up(16 * (size_t)L.E), grades = align_up(4 * (size_t)L.E);
+    if (scratch + grades + kAlign > L.total)
+      return fail(PH0_EDEVICE, "fused scratch does not fit the workspace");
+    BatchArgs A;
+    A.pts = d_points;
+    A.elem_bytes = eb;
+    A.d = d;
+    A.offsets = nullptr;
+    A.order = nullptr;
+    A.nclouds = 1;
+    A.bars = reinterpret_cast<uint32_t*>(out.bars);
+    A.scratch = reinterpret_cast<uint64_t*>(ws);
+    A.grades = reinterpret_cast<uint32_t*>(ws + scratch);
+    A.emax = L.E;
+    A.queue = nullptr;
+    A.errs = reinterpret_cast<int32_t*>(ws + scratch + grades);
+    for (int b = 0; b < 4; ++b) A.chunk_mult[b] = kChunkMult[b];
+    A.single_n = n;
+    HIPCHK(launch_batched(A, 1, s));
+    HIPCHK(hipMemcpyAsync(&rb->words[0], A.errs, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    drain.armed = false;
+    const int32_t code = (int32_t)rb->words[0];
+    if (code)
+      return fail(code == 3 ? PH0_ERANGE : PH0_EDEVICE,
+                  code == 3 ? "packed key needs more than 64 bits (reduce the coordinate range)"
+                            : "the fused kernel reported an inconsistency (code %d)",
+                  code);
     return PH0_OK;
   }
 

@@ -208,6 +208,8 @@ struct BatchArgs {
   int32_t* errs;            // per cloud, zero at launch
   int32_t chunk_mult[4];    // first chunk holds about chunk_mult[b] * n edges, for
                             // size buckets b: n <= 64, <= 128, <= 256, <= 512
+  int64_t single_n = 0;     // > 0: one cloud of single_n rows, one workgroup, no queue,
+                            // offsets or order; its status always goes to errs[0]
 };
 size_t batched_shared_bytes();
 hipError_t launch_batched(const BatchArgs& a, int blocks, hipStream_t s);

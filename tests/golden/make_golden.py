@@ -4,6 +4,7 @@ Calls only the CPU oracle (oracle/) on the seeded generators; no value here
 comes from the GPU library.  Run from the repository root:
 
     python tests/golden/make_golden.py [--seeds A-B] [workload ...]
+    python tests/golden/make_golden.py --h1 N SEED     (H1 of the uniform N-point cloud)
 
 Seeds 0-9 of every workload are stored (the parity seeds); --seeds limits
 the run to a range.
@@ -50,6 +51,27 @@ def record(name: str, seed: int) -> dict:
     }
 
 
+def record_h1(n: int, seed: int) -> dict:
+    """H1 of the uniform integer cloud (the H1 benchmark recipe), literal
+    mode (every column reduced, as the GPU does)."""
+    pts = synth.uniform_cloud(n, 3, seed=seed)
+    res = oracle.h1_barcode(pts, early_exit=False)
+    return {
+        "workload": "h1_uniform_n%d_d3_i16" % n,
+        "seed": seed,
+        "n": n,
+        "points_sha256": digest(pts),
+        "E": res.E,
+        "T": res.T,
+        "pivots": res.pivots,
+        "additions": res.additions,
+        "zero_length": res.zero_length,
+        "bars": int(res.bars.shape[0]),
+        "bars_sha256": digest(res.bars.astype("<u4")),
+        "tri_of_edge_sha256": digest(res.tri_of_edge.astype("<i8")),
+    }
+
+
 def main(names, seeds):
     for name in names:
         for seed in seeds:
@@ -62,6 +84,14 @@ def main(names, seeds):
 
 if __name__ == "__main__":
     args = sys.argv[1:]
+    if args and args[0] == "--h1":  # python tests/golden/make_golden.py --h1 N SEED
+        n, seed = int(args[1]), int(args[2])
+        rec = record_h1(n, seed)
+        with open(os.path.join(HERE, "oracle_h1_uniform_n%d_d3_i16_s%d.json" % (n, seed)), "w") as f:
+            json.dump(rec, f, indent=1, sort_keys=True)
+            f.write("\n")
+        print(rec["workload"], seed, rec["pivots"], rec["additions"], flush=True)
+        sys.exit(0)
     seeds = range(10)
     if args and args[0] == "--seeds":
         lo, hi = args[1].split("-")

@@ -128,3 +128,23 @@ def test_h1_full_size_properties(torch, n):
     perm = np.random.default_rng(n).permutation(n)
     permuted, _, _ = _run(torch, x[perm])
     np.testing.assert_array_equal(permuted, got)
+
+
+def test_h1_benchmark_cloud_against_stored_oracle(torch):
+    # The cloud the benchmark times (uniform N=256, d=3 int16, seed 0), against
+    # the oracle's stored record (tests/golden/make_golden.py --h1 256 0, oracle
+    # only; literal mode, about a minute on one core).
+    import hashlib
+    import json
+    import os
+
+    from tests.conftest import GOLDEN
+
+    rec = json.load(open(os.path.join(GOLDEN, "oracle_h1_uniform_n256_d3_i16_s0.json")))
+    x = synth.uniform_cloud(256, 3, seed=0)
+    assert hashlib.sha256(np.ascontiguousarray(x).tobytes()).hexdigest() == rec["points_sha256"]
+    got, toe, st = _run(torch, x)
+    assert hashlib.sha256(got.astype("<u4").tobytes()).hexdigest() == rec["bars_sha256"]
+    assert hashlib.sha256(toe.astype("<i8").tobytes()).hexdigest() == rec["tri_of_edge_sha256"]
+    assert st["pivots"] == rec["pivots"] and st["additions"] == rec["additions"]
+    assert st["bars"] == rec["bars"] and st["zero_length"] == rec["zero_length"]

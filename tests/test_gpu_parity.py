@@ -255,9 +255,18 @@ def _sha(a, dt):
     return hashlib.sha256(np.ascontiguousarray(a).astype(dt).tobytes()).hexdigest()
 
 
-def test_mixture_workload_n16384_against_stored_oracle(torch):
-    rec = json.load(open(os.path.join(GOLDEN, "oracle_mixture_n16384_d64_i8_s0.json")))
-    x = synth.workload("mixture_n16384_d64_i8", seed=0)
+def _stored_records():
+    names = (f[len("oracle_"):-len(".json")] for f in os.listdir(GOLDEN)
+             if f.startswith("oracle_") and f.endswith(".json"))
+    return sorted(r for r in names if r.rsplit("_s", 1)[0] in synth.WORKLOADS)
+
+
+@pytest.mark.parametrize("record", _stored_records())
+def test_workload_seeds_against_stored_oracle(torch, record):
+    """Seeds 0-9 of the three single-cloud workloads, against the oracle's
+    stored hashes (tests/golden/make_golden.py, oracle only)."""
+    rec = json.load(open(os.path.join(GOLDEN, "oracle_%s.json" % record)))
+    x = synth.workload(rec["workload"], seed=rec["seed"])
     assert _sha(x, x.dtype) == rec["points_sha256"]
     xd = _dev(torch, x)
     bars, st = ph0.ph0_barcodes_device(xd, with_stats=True)
@@ -277,3 +286,43 @@ def test_mixture_workload_n16384_against_stored_oracle(torch):
 def test_unit_square_workload(torch, n):
     # The paper's experiment: uniform points in [0,1]^2 on a fixed-point grid.
     _check_full(torch, synth.unit_square_cloud(n, seed=n))
+
+
+# Single clouds of n <= 256 without statistics run in one workgroup (the fused
+# kernel); with statistics they take the grid-wide passes.  Both must equal the
+# oracle, at the size limit and beside it too.
+@pytest.mark.parametrize("n,d,lo,hi,dtype", [
+    (2, 1, -5, 5, np.int8),
+    (3, 3, -100, 100, np.int16),
+    (17, 2, 0, 2, np.int8),          # heavy ties
+    (64, 64, -128, 127, np.int8),    # full int8 range, n * d = 4096
+    (100, 16, -127, 127, np.int8),
+    (128, 64, -128, 127, np.int8),   # n * d = 8192, the LDS limit
+    (200, 3, -16000, 16000, np.int16),
+    (256, 3, -100, 100, np.int16),   # the largest fused single cloud
+    (257, 3, -100, 100, np.int16),   # the grid-wide path
+])
+def test_small_single_clouds_fused_and_grid_paths(torch, n, d, lo, hi, dtype):
+    x = _cloud(n + 1000 * d, n, d, lo, hi, dtype)
+    print("small single cloud n=%d d=%d %s" % (n, d, np.dtype(dtype).name), flush=True)
+    ref = oracle.barcode(x).canonical
+    xd = _dev(torch, x)
+    fused = ph0.ph0_barcodes_device(xd)
+    grid, _ = ph0.ph0_barcodes_device(xd, with_stats=True)
+    torch.cuda.synchronize()
+    for got in (fused, grid):
+        b = got.cpu().numpy().view(np.uint32)
+        assert (b[:, 0] == 0).all()
+        np.testing.assert_array_equal(b[:, 1], ref)
+
+
+def test_small_single_cloud_full_int16_range(torch):
+    # 38 distance bits + 2 x 8 index bits: the widest keys a fused single cloud
+    # can have (n * d <= 8192 keeps the distance bound below 2^48).
+    x = _cloud(77, 200, 40, -1000, 1000, np.int16)
+    x[0, :] = -32768
+    x[1, :] = 32767
+    bars = ph0.ph0_barcodes_device(_dev(torch, x))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(bars.cpu().numpy().view(np.uint32)[:, 1],
+                                  oracle.barcode(x).canonical)
