@@ -686,9 +686,13 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     return e;
   };
   bool pipelined = false;
+  // Once every pivot exists exactly one more round remains: its walks all end
+  // in zero (the only free row, vertex 0, can never be a column's low), so
+  // nothing is queued behind the round that follows that state.
+  bool last_round_queued = false;
   HIPCHK(issue_next());
   while (true) {
-    if (pipelined && q_len < 2) HIPCHK(issue_next());
+    if (pipelined && q_len < 2 && !last_round_queued) HIPCHK(issue_next());
     const int k = queue[q_head];
     q_head ^= 1;
     --q_len;
@@ -722,6 +726,10 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     pipelined = true;
     if (h.pivots >= n - 1) {
       burst = 1;
+      if (q_len > 0) {
+        last_round_queued = true;  // the queued burst's first round finishes
+        continue;
+      }
     } else {
       if (burst < 8) burst *= 2;
       const int64_t rate = (h.pivots - prev_piv) / std::max<int64_t>(1, h.round - prev_round);
