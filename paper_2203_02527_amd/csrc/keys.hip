@@ -13,6 +13,8 @@
 //  * vector ALU, direct differences (any d, int8 or int16; int64 sums);
 //  * int8 MFMA Gram: delta = |x_i|^2 + |x_j|^2 - 2 <x_i, x_j>, the inner
 //    products from v_mfma_i32_32x32x32_i8 (exact int32 for d <= 32768).
+#include <algorithm>
+#include <atomic>
 #include <type_traits>
 
 #include "ph0_internal.h"
@@ -22,6 +24,7 @@ namespace ph0 {
 namespace {
 
 constexpr int kTile = 64;  // points per tile side; a tile covers 64 x 64 edges
+constexpr int kSegTiles = 4;  // tiles per count segment of the MFMA passes
 
 __device__ inline void tile_coords(int64_t t, int64_t* jb, int64_t* ib) {
   // Tiles with ib <= jb, numbered row by row: t = jb(jb+1)/2 + ib.
@@ -116,12 +119,20 @@ __device__ inline void hist_flush(const uint32_t* lh, uint32_t* hist) {
     if (lh[b]) atomicAdd(&hist[b], lh[b]);
 }
 
-// Flattened index of the count of (64-row band J, row jl of the band, tile
-// I <= J): bands in order, then rows, then tiles, so that an exclusive scan
-// of the counts gives each (row, tile) the colex position of its first kept
-// key among all kept keys.
-__device__ inline int64_t key_count_index(int64_t J, int jl, int64_t I) {
-  return 64 * (J * (J + 1) / 2) + (int64_t)jl * (J + 1) + I;
+// Counts of the count pass are kept per (64-row band J, row of the band,
+// segment s): segment s of band J covers its tiles I in [sS, min(sS + S,
+// J + 1)), S tiles per segment (S = 1: one count per tile).  Flattened
+// bands in order, then rows, then segments, so that an exclusive scan of the
+// counts gives each (row, segment) the colex position of its first kept key
+// among all kept keys.
+__host__ __device__ inline int32_t seg_count(int64_t J, int S) { return (int32_t)(J / S) + 1; }
+// Segments of the bands before J: sum over J' < J of (J' / S + 1).
+__host__ __device__ inline int64_t seg_base(int64_t J, int S) {
+  const int64_t q = J / S, r = J - q * S;
+  return J + S * (q * (q - 1) / 2) + q * r;
+}
+__device__ inline int64_t key_count_index(int64_t J, int jl, int64_t s, int S) {
+  return 64 * seg_base(J, S) + (int64_t)jl * seg_count(J, S) + s;
 }
 
 // Tiles a pass visits: all, or every kp.sample-th one for the sampled
@@ -206,7 +217,7 @@ __global__ __launch_bounds__(256) void k_keys_alu(const T* __restrict__ x, int64
         // One wave covers the 64 i of row j: a ballot counts and ranks.
         const bool kept = valid && delta >= kp.dlo && delta < kp.dhi;
         const uint64_t m = __ballot(kept);
-        const int64_t ci = key_count_index(jb, jl, ibk);
+        const int64_t ci = key_count_index(jb, jl, ibk, 1);
         if (MODE == kKeysCount) {
           if (il == 0) kp.cnt[ci] = (uint32_t)__popcll(m);
         } else if (kept) {
@@ -278,61 +289,163 @@ __device__ inline void tile_regs_store(const TileRegs& r, int8_t (*xs)[64][KROW]
 // KMAX int8 dimensions are staged per LDS round (64 for d <= 64, else 256);
 // rows are padded by 16 bytes so that the 32 row reads of a half-wave spread
 // over the LDS banks.  With vec16 (d a multiple of 16 and 16-byte aligned
-// points) the rows are copied with 16-byte loads.
-template <int MODE, int KMAX>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_keys_mfma(const int8_t* __restrict__ x, int64_t n,
+// points) the rows are copied with 16-byte loads.  AHEAD (d <= 64, vec16)
+// loads each tile's rows, norms and (emit) row bases while the previous tile
+// computes; it is an instantiation of its own so that no wait of the general
+// path's loads lands in its loop.
+//
+// Work is handed out in items: a count segment (up to kSegTiles consecutive
+// tiles I of one band J) for the full, count and emit passes, one sampled
+// tile for the histogram pass.  The count pass leaves one count per (row,
+// segment), the emit pass starts each segment's rows at their scanned counts
+// and advances them tile by tile.
+//
+// Waves per SIMD each pass is compiled for at least: four for the emit pass
+// (a few bytes spill), three for the others (which then fit five).
+constexpr int keys_waves(int mode) { return mode == kKeysEmit ? 4 : 3; }
+
+// The tile being worked on and the item it belongs to (ok = 0 past the
+// workgroup's last item).
+struct Cursor {
+  int64_t item;
+  int32_t J, I, I0, I1;  // band, tile, the item's first tile and its end
+  int32_t ok;
+};
+
+// The item's band and tiles: a sampled tile (sample > 0), else count
+// segment `item` of the nb bands.
+__device__ inline Cursor item_cursor(int64_t item, int64_t item_end, int64_t sample, int32_t nb,
+                                     int S) {
+  Cursor cu;
+  cu.item = item;
+  cu.ok = item < item_end;
+  cu.J = cu.I = cu.I0 = cu.I1 = 0;
+  if (!cu.ok) return cu;
+  if (sample > 0) {
+    int64_t jb, ibk;
+    tile_coords(item * sample, &jb, &ibk);
+    cu.J = (int32_t)jb;
+    cu.I0 = cu.I = (int32_t)ibk;
+    cu.I1 = cu.I + 1;
+  } else {
+    // the band: seg_base(J) <= item < seg_base(J + 1)
+    int32_t lo = 0, hi = nb;
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (seg_base(mid, S) <= item) lo = mid; else hi = mid;
+    }
+    cu.J = lo;
+    cu.I0 = cu.I = (int32_t)(item - seg_base(lo, S)) * S;
+    cu.I1 = cu.I0 + S < lo + 1 ? cu.I0 + S : lo + 1;
+  }
+  return cu;
+}
+
+template <int MODE, int KMAX, bool AHEAD>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_waves(MODE)))) void k_keys_mfma(const int8_t* __restrict__ x, int64_t n,
                                                    int32_t d, int ib, int64_t ntiles,
                                                    const int32_t* __restrict__ norms,
                                                    bool vec16, KeyPass kp) {
   constexpr int kRow = KMAX + 16;
   constexpr bool kHist = MODE == kKeysFull || MODE == kKeysHist;
+  constexpr int S = kSegTiles;
   __shared__ __attribute__((aligned(16))) int8_t xs[2][kTile][kRow];
   __shared__ __attribute__((aligned(16))) int32_t nrm[2][kTile];
   __shared__ uint32_t lh[kHist ? kHistBins : 1];
-  __shared__ uint32_t half_cnt[kTile][2];  // kept keys per (row, half of the tile's i)
-  __shared__ uint32_t rbase[kTile];        // emit: colex base of each row's kept keys
+  __shared__ __attribute__((aligned(16))) uint32_t half_cnt[kTile][2];  // kept keys per (row, half of the tile's i)
+  __shared__ __attribute__((aligned(16))) uint32_t rbase[kTile];  // emit: colex base of each row's kept keys
   if (kHist) hist_zero(lh);
   const int hs = kHist && kp.hist_shift_dev ? *kp.hist_shift_dev : kp.hist_shift;
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int jsub = wave >> 1, isub = wave & 1;  // 32 x 32 sub-tile of this wave
-  const TileRange tr = tile_range(kp, MODE, ntiles);
   // The kept range [dlo, dhi) clamped to 32 bits (delta < 2^31 here).
   const uint32_t dlo32 = kp.dlo < 0xFFFFFFFFull ? (uint32_t)kp.dlo : 0xFFFFFFFFu;
   const uint32_t dhi32 = kp.dhi < 0xFFFFFFFFull ? (uint32_t)kp.dhi : 0xFFFFFFFFu;
   const uint32_t span32 = dhi32 > dlo32 ? dhi32 - dlo32 : 0u;
-  // One-stage tiles with 16-byte rows are loaded a tile ahead.
-  const bool ahead = KMAX == 64 && vec16 && d <= 64;
+  constexpr bool ahead = AHEAD && KMAX == 64;
   const int segs1 = ((d + 31) & ~31) >> 4;
-  TileRegs pre;
-  if (ahead && tr.v0 < tr.v1) {
-    int64_t jb, ibk;
-    tile_coords(tr.v0 * tr.sample, &jb, &ibk);
-    tile_regs_load(pre, x, n, d, ibk * kTile, jb * kTile, segs1);
+  const int32_t nb = (int32_t)((n + kTile - 1) / kTile);
+
+  // Items of this workgroup: a contiguous run of sampled tiles, or the
+  // segments blockIdx.x, blockIdx.x + gridDim.x, ...
+  int64_t item_end, item_step, item0;
+  if (MODE == kKeysHist) {
+    const int64_t visited = (ntiles + kp.sample - 1) / kp.sample;
+    const int64_t per = (visited + gridDim.x - 1) / gridDim.x;
+    item0 = blockIdx.x * per;
+    item_end = item0 + per < visited ? item0 + per : visited;
+    item_step = 1;
+  } else {
+    item0 = blockIdx.x;
+    item_end = seg_base(nb, S);
+    item_step = gridDim.x;
   }
-  for (int64_t v = tr.v0; v < tr.v1; v += tr.step) {
-    const int64_t t = v * tr.sample;
-    int64_t jb, ibk;
-    tile_coords(t, &jb, &ibk);
-    const int64_t i0 = ibk * kTile, j0 = jb * kTile;
+  const int64_t sample = MODE == kKeysHist ? kp.sample : 0;
+  auto next_of = [&](Cursor cu) {
+    if (cu.I + 1 < cu.I1) {
+      ++cu.I;
+      return cu;
+    }
+    return item_cursor(cu.item + item_step, item_end, sample, nb, S);
+  };
+  // The count slot of (band, row, segment) for the tile's segment.
+  auto count_slot = [&](const Cursor& cu, int row) {
+    return key_count_index(cu.J, row, cu.I0 / S, S);
+  };
+
+  TileRegs pre;
+  int32_t pre_nrm = 0;
+  uint32_t pre_rb = 0;
+  auto side_load = [&](const Cursor& cu) {
+    if (threadIdx.x < 2 * kTile) {
+      const int side = threadIdx.x >> 6, pt = threadIdx.x & 63;
+      const int64_t g = (int64_t)(side ? cu.J : cu.I) * kTile + pt;
+      pre_nrm = g < n ? norms[g] : 0;
+    }
+    if (MODE == kKeysEmit && threadIdx.x < kTile && cu.I == cu.I0)
+      pre_rb = kp.cnt[count_slot(cu, threadIdx.x)];
+  };
+  Cursor cur = item_cursor(item0, item_end, sample, nb, S);
+  if (ahead && cur.ok) {
+    tile_regs_load(pre, x, n, d, (int64_t)cur.I * kTile, (int64_t)cur.J * kTile, segs1);
+    side_load(cur);
+  }
+  uint32_t row_acc = 0;  // count / emit: thread tid < 64's row, over the segment so far
+  while (cur.ok) {
+    const int64_t i0 = (int64_t)cur.I * kTile, j0 = (int64_t)cur.J * kTile;
+    const bool seg_first = cur.I == cur.I0, seg_last = cur.I + 1 == cur.I1;
     v16i c;
 #pragma unroll
     for (int r = 0; r < 16; ++r) c[r] = 0;
     __syncthreads();  // the previous tile's readers of LDS are done
-    if (threadIdx.x < 2 * kTile) {
-      const int side = threadIdx.x >> 6, pt = threadIdx.x & 63;
-      const int64_t g = (side ? j0 : i0) + pt;
-      nrm[side][pt] = g < n ? norms[g] : 0;
+    if constexpr (MODE == kKeysEmit) {
+      // The row's next output position: its segment base, advanced by the
+      // previous tile's kept keys (still in half_cnt).
+      if (threadIdx.x < kTile) {
+        if (seg_first)
+          row_acc = ahead ? pre_rb : kp.cnt[count_slot(cur, threadIdx.x)];
+        else
+          row_acc += half_cnt[threadIdx.x][0] + half_cnt[threadIdx.x][1];
+        rbase[threadIdx.x] = row_acc;
+      }
     }
-    if (MODE == kKeysEmit && threadIdx.x < kTile)
-      rbase[threadIdx.x] = kp.cnt[key_count_index(jb, threadIdx.x, ibk)];
-    if (ahead) {
+    if constexpr (ahead) {
+      if (threadIdx.x < 2 * kTile) nrm[threadIdx.x >> 6][threadIdx.x & 63] = pre_nrm;
+    } else {
+      if (threadIdx.x < 2 * kTile) {
+        const int side = threadIdx.x >> 6, pt = threadIdx.x & 63;
+        const int64_t g = (side ? j0 : i0) + pt;
+        nrm[side][pt] = g < n ? norms[g] : 0;
+      }
+    }
+    const Cursor nxt = next_of(cur);
+    if constexpr (ahead) {
       tile_regs_store<kRow>(pre, xs, segs1);
-      if (v + tr.step < tr.v1) {
-        int64_t jn, in_;
-        tile_coords((v + tr.step) * tr.sample, &jn, &in_);
-        tile_regs_load(pre, x, n, d, in_ * kTile, jn * kTile, segs1);
+      if (nxt.ok) {
+        tile_regs_load(pre, x, n, d, (int64_t)nxt.I * kTile, (int64_t)nxt.J * kTile, segs1);
+        side_load(nxt);
       }
       __syncthreads();
       const int kpad = segs1 * 16;
@@ -389,7 +502,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int64_t i = i0 + il;
     const uint32_t ni = (uint32_t)nrm[0][il];
     const int half = lane >> 5;
-    const uint64_t half_mask = half ? 0xFFFFFFFF00000000ull : 0x00000000FFFFFFFFull;
     const int jrow = jsub * 32 + 4 * half;  // row of r = 0; r adds 8 (r / 4) + r % 4
     // delta of accumulator r, from the four row norms of its group r / 4
     auto delta_of = [&](const int4& nj, int r) -> uint32_t {
@@ -401,6 +513,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     auto epilogue = [&](auto full_tile) {
       constexpr bool kInterior = decltype(full_tile)::value;
       uint32_t kept_bits = 0;
+      uint32_t dl[16];  // emit: the deltas, kept past the accumulators
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int4 nj = *reinterpret_cast<const int4*>(&nrm[1][jrow + 8 * q]);
@@ -421,6 +534,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
           } else {
             const bool kept = valid && delta - dlo32 < span32;
             kept_bits |= (kept ? 1u : 0u) << r;
+            dl[r] = delta;
             const uint64_t m = __ballot(kept);
             const uint32_t hc = half ? (uint32_t)__popc((uint32_t)(m >> 32))
                                      : (uint32_t)__popc((uint32_t)m);
@@ -430,26 +544,44 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
       if constexpr (MODE == kKeysCount) {
         __syncthreads();
-        if (threadIdx.x < kTile)
-          kp.cnt[key_count_index(jb, threadIdx.x, ibk)] =
-              half_cnt[threadIdx.x][0] + half_cnt[threadIdx.x][1];
+        if (threadIdx.x < kTile) {
+          row_acc = (seg_first ? 0u : row_acc) + half_cnt[threadIdx.x][0] +
+                    half_cnt[threadIdx.x][1];
+          if (seg_last) kp.cnt[count_slot(cur, threadIdx.x)] = row_acc;
+        }
       } else if constexpr (MODE == kKeysEmit) {
         __syncthreads();
+        // (j << b | i) of r = 0; r adds (8 (r / 4) + r % 4) << b.
+        const uint64_t ji0 = ((uint64_t)(j0 + jrow) << ib) | (uint64_t)i;
+        const uint32_t upper = half ? 0xFFFFFFFFu : 0u;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int4 nj = *reinterpret_cast<const int4*>(&nrm[1][jrow + 8 * q]);
+          // First output position of this lane's row for r = 4q .. 4q + 3:
+          // the row's colex base, after the lower i-half's keys for the
+          // upper half.
+          uint4 base = *reinterpret_cast<const uint4*>(&rbase[jrow + 8 * q]);
+          if (isub) {
+            const uint4 h0 = *reinterpret_cast<const uint4*>(&half_cnt[jrow + 8 * q][0]);
+            const uint4 h1 = *reinterpret_cast<const uint4*>(&half_cnt[jrow + 8 * q + 2][0]);
+            base.x += h0.x;
+            base.y += h0.z;
+            base.z += h1.x;
+            base.w += h1.z;
+          }
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const int r = 4 * q + t;
-            const int jl = jrow + 8 * q + t;
             const bool kept = (kept_bits >> r) & 1u;
-            const uint64_t m = __ballot(kept) & half_mask;
+            const uint64_t m = __ballot(kept);
             if (kept) {
-              const int64_t j = j0 + jl;
-              const uint32_t below = __popcll(m & ((1ull << lane) - 1ull));
-              const uint32_t pos = rbase[jl] + (isub ? half_cnt[jl][0] : 0u) + below;
-              kp.keys[pos] =
-                  ((uint64_t)delta_of(nj, r) << (2 * ib)) | ((uint64_t)j << ib) | (uint64_t)i;
+              // kept lanes below this one in its half-wave
+              const uint32_t below =
+                  __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) -
+                  ((uint32_t)__popc((uint32_t)m) & upper);
+              const uint32_t b = t == 0 ? base.x : t == 1 ? base.y : t == 2 ? base.z : base.w;
+              kp.keys[b + below] = ((uint64_t)dl[r] << (2 * ib)) |
+                                   (ji0 + ((uint64_t)(8 * q + t) << ib));
             }
           }
         }
@@ -459,6 +591,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       epilogue(std::true_type{});
     else
       epilogue(std::false_type{});
+    cur = nxt;
   }
   if (kHist) hist_flush(lh, kp.hist);
 }
@@ -543,32 +676,83 @@ hipError_t launch_coord_range(const void* pts, int elem_bytes, int64_t n, int32_
   return hipGetLastError();
 }
 
-int64_t key_count_len(int64_t n) {
+int64_t key_count_len(int64_t n, bool mfma) {
   const int64_t nb = (n + kTile - 1) / kTile;
-  return 64 * (nb * (nb + 1) / 2);
+  return 64 * seg_base(nb, mfma ? kSegTiles : 1);
 }
 
+// CUs of the current device, read once per device.
+int device_cus_cached() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  int c = cache[dev].load(std::memory_order_relaxed);
+  if (c <= 0) {
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        c <= 0)
+      c = 256;
+    cache[dev].store(c, std::memory_order_relaxed);
+  }
+  return c;
+}
+
+// Workgroups of 256 threads that one CU holds at once for `kernel` (its
+// register and LDS use decide), read once per kernel through `slot`.
+int per_cu_blocks(const void* kernel, std::atomic<int>& slot) {
+  int b = slot.load(std::memory_order_relaxed);
+  if (b <= 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, 256, 0) != hipSuccess || b <= 0)
+      b = 1;
+    slot.store(b, std::memory_order_relaxed);
+  }
+  return b;
+}
+
+// The grid is what the device holds at once (every workgroup loops over
+// tiles, and no second wave of workgroups runs on a partly empty device),
+// capped at `cap_per_cu` workgroups per CU and at `visited` tiles.
 template <int MODE>
 void keys_launch(const void* pts, int elem_bytes, int64_t n, int32_t d, int ib, bool use_mfma,
-                 int64_t ntiles, int grid, const KeyPass& kp, hipStream_t s) {
+                 int64_t ntiles, int64_t visited, int cap_per_cu, const KeyPass& kp,
+                 hipStream_t s) {
+  static std::atomic<int> occ[5];
+  const int64_t cus = device_cus_cached();
+  auto grid_of = [&](const void* kernel, int which) {
+    int64_t g = std::min<int64_t>(per_cu_blocks(kernel, occ[which]), cap_per_cu) * cus;
+    if (g > visited) g = visited;
+    return dim3((unsigned)(g < 1 ? 1 : g));
+  };
   if (use_mfma && elem_bytes == 1) {
+    if (MODE != kKeysHist) {  // the MFMA passes hand out count segments
+      const int64_t nb = (n + kTile - 1) / kTile;
+      visited = seg_base(nb, kSegTiles);
+    }
     const bool vec16 = (d % 16) == 0 && (reinterpret_cast<uintptr_t>(pts) % 16) == 0;
     if (!kp.norms_ready)
       hipLaunchKernelGGL(k_norms_i8, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s,
                          static_cast<const int8_t*>(pts), n, d, kp.norms);
-    if (d <= 64)
-      hipLaunchKernelGGL((k_keys_mfma<MODE, 64>), dim3(grid), dim3(256), 0, s,
+    if (d <= 64 && vec16)
+      hipLaunchKernelGGL((k_keys_mfma<MODE, 64, true>),
+                         grid_of((const void*)k_keys_mfma<MODE, 64, true>, 0), dim3(256), 0, s,
+                         static_cast<const int8_t*>(pts), n, d, ib, ntiles,
+                         (const int32_t*)kp.norms, vec16, kp);
+    else if (d <= 64)
+      hipLaunchKernelGGL((k_keys_mfma<MODE, 64, false>),
+                         grid_of((const void*)k_keys_mfma<MODE, 64, false>, 4), dim3(256), 0, s,
                          static_cast<const int8_t*>(pts), n, d, ib, ntiles,
                          (const int32_t*)kp.norms, vec16, kp);
     else
-      hipLaunchKernelGGL((k_keys_mfma<MODE, 256>), dim3(grid), dim3(256), 0, s,
+      hipLaunchKernelGGL((k_keys_mfma<MODE, 256, false>),
+                         grid_of((const void*)k_keys_mfma<MODE, 256, false>, 1), dim3(256), 0, s,
                          static_cast<const int8_t*>(pts), n, d, ib, ntiles,
                          (const int32_t*)kp.norms, vec16, kp);
   } else if (elem_bytes == 1)
-    hipLaunchKernelGGL((k_keys_alu<int8_t, MODE>), dim3(grid), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_keys_alu<int8_t, MODE>),
+                       grid_of((const void*)k_keys_alu<int8_t, MODE>, 2), dim3(256), 0, s,
                        static_cast<const int8_t*>(pts), n, d, ib, ntiles, kp);
   else
-    hipLaunchKernelGGL((k_keys_alu<int16_t, MODE>), dim3(grid), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_keys_alu<int16_t, MODE>),
+                       grid_of((const void*)k_keys_alu<int16_t, MODE>, 3), dim3(256), 0, s,
                        static_cast<const int16_t*>(pts), n, d, ib, ntiles, kp);
 }
 
@@ -576,30 +760,19 @@ hipError_t launch_keys_pass(const void* pts, int elem_bytes, int64_t n, int32_t 
                             bool use_mfma, const KeyPass& kp, hipStream_t s) {
   const int64_t nb = (n + kTile - 1) / kTile;
   const int64_t ntiles = nb * (nb + 1) / 2;
-  // Resident-sized grid: each workgroup loops over tiles, so its histogram
-  // is flushed once.
-  int cus = 256;
-  {
-    int dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
-        prop.multiProcessorCount > 0)
-      cus = prop.multiProcessorCount;
-  }
   const int64_t sample = kp.mode == kKeysHist ? (kp.sample > 0 ? kp.sample : 1) : 1;
   const int64_t visited = (ntiles + sample - 1) / sample;
-  // The sampled histogram pass uses two workgroups per CU: every workgroup
-  // flushes its LDS histogram (up to kHistBins global atomics on the same
-  // kHistBins addresses), so fewer, longer workgroups cost less.
-  const int64_t cap = (kp.mode == kKeysHist ? 2 : 8) * (int64_t)cus;
-  const int grid = (int)(visited < cap ? visited : cap);
+  // The sampled histogram pass uses at most two workgroups per CU: every
+  // workgroup flushes its LDS histogram (up to kHistBins global atomics on
+  // the same kHistBins addresses), so fewer, longer workgroups cost less.
+  const int cap = kp.mode == kKeysHist ? 2 : 8;
   KeyPass k = kp;
   k.sample = sample;
   switch (kp.mode) {
-    case kKeysFull: keys_launch<kKeysFull>(pts, elem_bytes, n, d, ib, use_mfma, ntiles, grid, k, s); break;
-    case kKeysHist: keys_launch<kKeysHist>(pts, elem_bytes, n, d, ib, use_mfma, ntiles, grid, k, s); break;
-    case kKeysCount: keys_launch<kKeysCount>(pts, elem_bytes, n, d, ib, use_mfma, ntiles, grid, k, s); break;
-    default: keys_launch<kKeysEmit>(pts, elem_bytes, n, d, ib, use_mfma, ntiles, grid, k, s); break;
+    case kKeysFull: keys_launch<kKeysFull>(pts, elem_bytes, n, d, ib, use_mfma, ntiles, visited, cap, k, s); break;
+    case kKeysHist: keys_launch<kKeysHist>(pts, elem_bytes, n, d, ib, use_mfma, ntiles, visited, cap, k, s); break;
+    case kKeysCount: keys_launch<kKeysCount>(pts, elem_bytes, n, d, ib, use_mfma, ntiles, visited, cap, k, s); break;
+    default: keys_launch<kKeysEmit>(pts, elem_bytes, n, d, ib, use_mfma, ntiles, visited, cap, k, s); break;
   }
   return hipGetLastError();
 }

@@ -119,8 +119,9 @@ Layout make_layout(int64_t n, int32_t d) {
   L.keysA = take(8 * (size_t)keys);
   L.keysB = take(8 * (size_t)keys);
   L.counts = take(4 * (size_t)radix_count_entries(keys));
-  L.hist = take(4 * (size_t)kHistBins);
-  L.err = take(4);
+  // The error word follows the histogram, so one fill clears both.
+  L.hist = take(4 * (size_t)(kHistBins + 1));
+  L.err = L.hist + 4 * (size_t)kHistBins;
   L.part = take(4 * (size_t)n);
   const size_t wb = (size_t)walk_blocks(L.Wcap), segs = wb * (size_t)walk_segment(L.Wcap);
   L.surv = take(8 * segs);
@@ -143,7 +144,8 @@ Layout make_layout(int64_t n, int32_t d) {
   L.dbv = take(4 * (size_t)n);
   L.minmax = take(8 * (size_t)d);
   L.hshift = take(4);
-  const int64_t kc = key_count_len(n) + 1;  // + 1: the scan leaves the total there
+  // Sized for the finer (per-tile) layout; + 1: the scan leaves the total there.
+  const int64_t kc = key_count_len(n, false) + 1;
   L.kcnt = take(4 * (size_t)kc);
   L.kcnt_tot = take(4 * (size_t)scan_totals_len(kc));
   L.norms = take(4 * (size_t)n);
@@ -444,8 +446,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   const int64_t nbk = (n + 63) / 64;
   const int64_t sample = std::max<int64_t>(1, nbk * (nbk + 1) / 2 / 2048);
   bool keys_full = false;  // keysA holds every key at its colex position
-  HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t*>(serr), 0u, 1, s));
-  HIPCHK(launch_fill_u32(hist, 0u, kHistBins, s));
+  HIPCHK(launch_fill_u32(hist, 0u, kHistBins + 1, s));  // the histogram and serr
   tm.mark();  // 1
   if (recompute) {
     KeyPass kp;
@@ -541,7 +542,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   int bin_next = 0, chunks = 0;
   bool whole = false;
   uint32_t* kcnt = static_cast<uint32_t*>(at(L.kcnt));
-  const int64_t kcnt_len = key_count_len(n);
+  const int64_t kcnt_len = key_count_len(n, mfma);
   // Exact number of keys in bins [blo, bhi), with their colex bases left in
   // kcnt for the emit pass.
   auto count_range = [&](int blo, int bhi, int64_t* cnt) -> hipError_t {

@@ -85,11 +85,12 @@ hipError_t launch_dist_shift(const int32_t* minmax, int32_t d, int32_t* shift, h
 //  * kKeysFull:  every key at its colex position, and the histogram;
 //  * kKeysHist:  the histogram only, over every `sample`-th tile;
 //  * kKeysCount: for the keys with dlo <= delta < dhi, their number per
-//                (64-row band J, row j in the band, tile I <= J), stored at
-//                key_count_index(J, j - 64 J, I);
+//                (64-row band J, row j in the band, segment of tiles
+//                I <= J), bands, then rows, then segments (key_count_len);
 //  * kKeysEmit:  those keys again, each written at (the exclusive scan of
-//                the counts at its (J, row, I)) + (its rank among the kept
-//                keys of its row in the tile), i.e. in colex order.
+//                the counts at its (J, row, segment)) + (the kept keys of
+//                its row in the segment's earlier tiles) + (its rank among
+//                the kept keys of its row in the tile), i.e. in colex order.
 // The selected keys of a distance range are thus written without ever
 // storing the others: distances are recomputed, which costs a few MFMA
 // instructions per tile, instead of 8 bytes of HBM traffic per edge.
@@ -108,8 +109,9 @@ struct KeyPass {
 };
 hipError_t launch_keys_pass(const void* pts, int elem_bytes, int64_t n, int32_t d, int ib,
                             bool use_mfma, const KeyPass& kp, hipStream_t s);
-// Entries of the per-(band, row, tile) count array (64 per tile).
-int64_t key_count_len(int64_t n);
+// Entries of the count array: per (band, row, segment of 4 tiles) on the
+// int8 MFMA path, per (band, row, tile) on the vector ALU path.
+int64_t key_count_len(int64_t n, bool mfma);
 // Exclusive prefix sum of v[0..len) in place; `totals` holds
 // scan_totals_len(len) words of scratch.
 int64_t scan_totals_len(int64_t len);

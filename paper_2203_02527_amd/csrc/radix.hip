@@ -2,11 +2,12 @@
 // stable least-significant-digit radix passes over 64-bit keys.
 //
 // Each pass is reduce-then-scan, with no workgroup ever waiting on another:
-//   count   -- every 4096-key tile counts its digits;
-//   scan    -- one exclusive scan over the counts laid out digit-major
-//              (all tiles' counts of digit 0, then digit 1, ...) gives every
-//              (digit, tile) its first output position;
-//   scatter -- every tile ranks its keys among equal digits and writes them.
+//   count   -- every 4096-key tile histograms its digits in LDS;
+//   scan    -- one workgroup per digit scans that digit's tile counts
+//              (exclusive, in place) and leaves the digit's total;
+//   scatter -- every tile scans the 256 digit totals for the digits' first
+//              output positions, ranks its keys among equal digits and
+//              writes them.
 // Inside a tile (4 waves x 16 rounds x 64 lanes) each wave owns a contiguous
 // quarter; a key's rank among equal digits comes from wave ballots on the
 // digit bits, so equal digits keep their order.  That stability is what turns
@@ -45,12 +46,15 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* >= 4 *
   return base + x - v;
 }
 
-// Load this wave's 16 x 64 keys of the tile and rank each among equal
-// digits inside the wave (running counts per wave in wcnt).
+// Whether a key passes the pass's range filter (the first pass of a chunk
+// picks the chunk's distance range out of all keys).
 __device__ inline bool kept(uint64_t key, const KeyFilter& f) {
   const uint64_t v = key >> f.fshift;
   return v >= f.flo && v < f.fhi;
 }
+
+// Load this wave's 16 x 64 keys of the tile and rank each among equal
+// digits inside the wave (running counts per wave in wcnt).
 
 __device__ inline void load_and_rank(const uint64_t* __restrict__ in, int64_t count, int64_t base,
                                      int shift, int bits, uint32_t dmask, const KeyFilter& f,
@@ -92,25 +96,57 @@ __global__ __launch_bounds__(kThreads) void k_radix_count(const uint64_t* __rest
                                                           int64_t ntiles,
                                                           uint32_t* __restrict__ counts,
                                                           KeyFilter f) {
-  __shared__ uint32_t wcnt[kWaves][256];
-  const int tid = threadIdx.x, wave = tid >> 6;
+  __shared__ uint32_t h[kWaves][256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t nbins = 1u << bits, dmask = nbins - 1u;
-  for (int b = tid; b < 256; b += kThreads)
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) wcnt[w][b] = 0;
+  for (int w = 0; w < kWaves; ++w) h[w][tid] = 0;
   __syncthreads();
   const int64_t tile = blockIdx.x;
   const int64_t base = tile * kTileKeys + (int64_t)wave * 64 * kRounds;
   uint64_t key[kRounds];
-  uint32_t rank[kRounds];
-  load_and_rank(in, count, base, shift, bits, dmask, f, key, rank, wcnt[wave]);
-  __syncthreads();
-  if ((uint32_t)tid < nbins) {
-    uint32_t c = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) c += wcnt[w][tid];
-    counts[(int64_t)tid * ntiles + tile] = c;
+  for (int k = 0; k < kRounds; ++k) {
+    const int64_t idx = base + k * 64 + lane;
+    key[k] = idx < count ? in[idx] : 0;
   }
+#pragma unroll
+  for (int k = 0; k < kRounds; ++k)
+    if (base + k * 64 + lane < count && kept(key[k], f))
+      atomicAdd(&h[wave][(uint32_t)(key[k] >> shift) & dmask], 1u);
+  __syncthreads();
+  if ((uint32_t)tid < nbins)
+    counts[(int64_t)tid * ntiles + tile] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
+}
+
+// One workgroup per digit: exclusive scan, in place, of that digit's tile
+// counts (tile order); the digit's total goes to totals[digit].
+__global__ __launch_bounds__(kThreads) void k_radix_digit_scan(uint32_t* __restrict__ counts,
+                                                               int64_t ntiles,
+                                                               uint32_t* __restrict__ totals) {
+  __shared__ uint32_t tmp[4];
+  constexpr int kPer = kScanBlock / kThreads;  // 16 consecutive counts per thread
+  uint32_t* c = counts + (int64_t)blockIdx.x * ntiles;
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < ntiles; b0 += kScanBlock) {
+    const int64_t p0 = b0 + threadIdx.x * kPer;
+    uint32_t x[kPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      x[q] = p0 + q < ntiles ? c[p0 + q] : 0;
+      sum += x[q];
+    }
+    uint32_t all;
+    uint32_t run = carry + block_exclusive_scan(sum, tmp, &all);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      if (p0 + q < ntiles) c[p0 + q] = run;
+      run += x[q];
+    }
+    carry += all;
+  }
+  if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
 // Exclusive scan of `len` counts: per-block totals, a scan of the totals,
@@ -168,6 +204,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint64_t* __re
                                                             int64_t count, int shift, int bits,
                                                             int64_t ntiles,
                                                             const uint32_t* __restrict__ offsets,
+                                                            const uint32_t* __restrict__ totals,
                                                             int32_t* err, KeyFilter f,
                                                             int64_t out_count) {
   __shared__ uint32_t wcnt[kWaves][256];
@@ -178,6 +215,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint64_t* __re
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t nbins = 1u << bits, dmask = nbins - 1u;
+  // The digit's first output position: the totals of the smaller digits.
+  const uint32_t dstart = block_exclusive_scan((uint32_t)tid < nbins ? totals[tid] : 0u, scan_tmp);
   for (int b = tid; b < 256; b += kThreads)
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) wcnt[w][b] = 0;
@@ -204,7 +243,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint64_t* __re
   uint32_t tile_kept;
   const uint32_t start = block_exclusive_scan(total, scan_tmp, &tile_kept);
   tile_start[tid] = start;
-  gbase[tid] = (uint32_t)tid < nbins ? offsets[(int64_t)tid * ntiles + tile] : 0;
+  gbase[tid] = (uint32_t)tid < nbins ? dstart + offsets[(int64_t)tid * ntiles + tile] : 0;
   __syncthreads();
 
 #pragma unroll
@@ -232,10 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint64_t* __re
 
 int64_t radix_tiles(int64_t count) { return (count + kTileKeys - 1) / kTileKeys; }
 
-int64_t radix_count_entries(int64_t count) {
-  const int64_t len = 256 * radix_tiles(count);
-  return len + (len + kScanBlock - 1) / kScanBlock + 1;
-}
+int64_t radix_count_entries(int64_t count) { return 256 * radix_tiles(count) + 256; }
 
 hipError_t launch_radix_pass(const uint64_t* in, uint64_t* out, int64_t count, int shift,
                              int bits, uint32_t* counts, int32_t* err, hipStream_t s,
@@ -243,23 +279,15 @@ hipError_t launch_radix_pass(const uint64_t* in, uint64_t* out, int64_t count, i
   const int64_t out_count = expect >= 0 ? expect : count;
   const int64_t tiles = radix_tiles(count);
   if (tiles == 0) return hipSuccess;
-  const int64_t len = (int64_t)(1 << bits) * tiles;
-  const int64_t nblocks = (len + kScanBlock - 1) / kScanBlock;
+  const unsigned nbins = 1u << bits;
   uint32_t* totals = counts + 256 * tiles;
   hipLaunchKernelGGL(k_radix_count, dim3((unsigned)tiles), dim3(kThreads), 0, s, in, count,
                      shift, bits, tiles, counts, f);
-  if (nblocks == 1) {  // the counts fit one scan block: its base is 0
-    hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(kThreads), 0, s, counts, len,
-                       (const uint32_t*)nullptr);
-  } else {
-    hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)nblocks), dim3(kThreads), 0, s, counts, len,
-                       totals);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, s, totals, nblocks);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblocks), dim3(kThreads), 0, s, counts, len,
-                       totals);
-  }
+  hipLaunchKernelGGL(k_radix_digit_scan, dim3(nbins), dim3(kThreads), 0, s, counts, tiles,
+                     totals);
   hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)tiles), dim3(kThreads), 0, s, in, out,
-                     count, shift, bits, tiles, counts, err, f, out_count);
+                     count, shift, bits, tiles, (const uint32_t*)counts,
+                     (const uint32_t*)totals, err, f, out_count);
   return hipGetLastError();
 }
 

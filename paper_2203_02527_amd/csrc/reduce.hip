@@ -53,6 +53,8 @@
 //     slot of its own;
 //   * one advance workgroup reduces the slots into the next round's state
 //     and the offsets of the kept segments.
+#include <algorithm>
+
 #include "ph0_internal.h"
 
 namespace ph0 {
@@ -604,18 +606,34 @@ __global__ void k_reduce_extend(RedCtl* ctl, int64_t E_lim) {
   if (Wend > c.maxWend) ctl->maxWend = Wend;
 }
 
-__global__ void k_reduce_init(RedCtl* ctl, int64_t E_lim, int64_t width, int64_t n) {
-  RedCtl c = {};
-  c.F = 0;
-  c.E_lim = E_lim;
-  c.width = width;
-  c.width_min = width;
-  c.Wend = width < E_lim ? width : E_lim;
-  c.maxWend = c.Wend;
-  c.fresh_lo = 0;
-  c.fresh_hi = c.Wend;
-  c.done = (n <= 1 || E_lim == 0) ? 1 : 0;
-  *ctl = c;
+// The reduction's starting state in one launch: an empty pivot table (part,
+// its 16-bit mirror and killer all free), no row minima or touches, zeroed
+// per-block counters, and the control block of the first window.
+__global__ __launch_bounds__(256) void k_reduce_init(RedArgs A, int64_t E_lim, int64_t n16,
+                                                     int64_t nwstat) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int64_t i = g; i < A.n; i += stride) {
+    A.part[i] = -1;
+    A.killer[i] = -1;
+    A.lowc[i] = kNoValue;
+    A.touch[i] = kNoValue;
+  }
+  for (int64_t i = g; i < n16; i += stride) A.part16[i] = kFree16;
+  for (int64_t i = g; i < nwstat; i += stride) A.wstat[i] = 0;
+  if (g == 0) {
+    RedCtl c = {};
+    c.F = 0;
+    c.E_lim = E_lim;
+    c.width = A.width;
+    c.width_min = A.width;
+    c.Wend = A.width < E_lim ? A.width : E_lim;
+    c.maxWend = c.Wend;
+    c.fresh_lo = 0;
+    c.fresh_hi = c.Wend;
+    c.done = (A.n <= 1 || E_lim == 0) ? 1 : 0;
+    *A.ctl = c;
+  }
 }
 
 // Additions of columns at or after E_eff (walked before the last pivot was
@@ -687,20 +705,13 @@ hipError_t launch_reduce_extend(const RedArgs& a, int64_t E_lim, hipStream_t s) 
 }
 
 hipError_t launch_reduce_init(const RedArgs& a, int64_t E_lim, hipStream_t s) {
-  const int wb = walk_blocks(a.Wcap);
-  hipError_t e;
-  if ((e = launch_fill_u32(reinterpret_cast<uint32_t*>(a.part), 0xFFFFFFFFu, a.n, s)) !=
-      hipSuccess)
-    return e;
-  if (a.part16 && (e = launch_fill_u32(reinterpret_cast<uint32_t*>(a.part16), 0xFFFFFFFFu,
-                                       part16_len(a.n) / 2, s)) != hipSuccess)
-    return e;
-  if ((e = launch_fill_u64(reinterpret_cast<uint64_t*>(a.killer), ~0ull, a.n, s)) != hipSuccess)
-    return e;
-  if ((e = launch_fill_u64(a.lowc, kNoValue, a.n, s)) != hipSuccess) return e;
-  if ((e = launch_fill_u64(a.touch, kNoValue, a.n, s)) != hipSuccess) return e;
-  if ((e = launch_fill_u64(a.wstat, 0ull, 3 * (int64_t)wb, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_init, dim3(1), dim3(1), 0, s, a.ctl, E_lim, a.width, a.n);
+  const int64_t n16 = a.part16 ? part16_len(a.n) : 0;
+  const int64_t nwstat = 3 * (int64_t)walk_blocks(a.Wcap);
+  const int64_t most = std::max(std::max(a.n, n16), nwstat);
+  const int64_t blocks = std::min<int64_t>(std::max<int64_t>((most + 255) / 256, 1),
+                                           4 * (int64_t)device_cus());
+  hipLaunchKernelGGL(k_reduce_init, dim3((unsigned)blocks), dim3(256), 0, s, a, E_lim, n16,
+                     nwstat);
   return hipGetLastError();
 }
 
