@@ -47,6 +47,12 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t count) {
     p[i] = v;
 }
 
+// Workgroup k copies entry k of the list.
+__global__ __launch_bounds__(256) void k_gather(Gather g) {
+  const int k = blockIdx.x;
+  for (int i = threadIdx.x; i < g.words[k]; i += blockDim.x) g.dst[k][i] = g.src[k][i];
+}
+
 // Per-dimension coordinate ranges: lo[k] = min x_ik, hi[k] = max x_ik
 // (minmax = lo[0..d) then hi[0..d)).  A coalesced grid-stride pass over all
 // coordinates folds each into LDS per-dimension minima and maxima (d <= kRangeLds),
@@ -647,6 +653,13 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t s
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count, 256, 4096)), dim3(256), 0, s, p, v, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const Gather& g, hipStream_t s) {
+  if (g.count <= 0) return hipSuccess;
+  if (g.count > 4) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gather, dim3(g.count), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 

@@ -462,10 +462,12 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   }
   tm.mark();  // 2
   // One wait: the ranges, and the histogram when the reduction follows.
-  HIPCHK(hipMemcpyAsync(back, mm, 8 * (size_t)d, hipMemcpyDeviceToHost, s));
-  if (stop == kStopAll)
-    HIPCHK(hipMemcpyAsync(back + ranges_bytes, hist, 4 * (size_t)kHistBins,
-                          hipMemcpyDeviceToHost, s));
+  {
+    Gather g;
+    g.add(mm, back, 8 * (size_t)d);
+    if (stop == kStopAll) g.add(hist, back + ranges_bytes, 4 * (size_t)kHistBins);
+    HIPCHK(launch_gather(g, s));
+  }
   HIPCHK(hipStreamSynchronize(s));
   unsigned __int128 bound = 0;
   for (int32_t k = 0; k < d; ++k) {
@@ -653,8 +655,8 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   ra.ctl = static_cast<RedCtl*>(at(L.ctl));
   RedCtl* hc = rb->hc;
   HIPCHK(launch_reduce_init(ra, E_lim, s));
-  // Rounds go out in bursts, each followed by an asynchronous copy of the
-  // control block and an event.  The host inspects a burst's copy while the
+  // Rounds go out in bursts, each followed by an event; the burst's last
+  // round leaves a copy of the control block in pinned host memory.  The host inspects a burst's copy while the
   // next burst already runs, so the GPU never waits for the host; rounds
   // issued after the end find `done` (or an empty range) and return at once.
   // Every round finalizes at least the first unfinished column (it either
@@ -664,12 +666,12 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   int burst = 2;  // grows to 8
   auto issue = [&](int slot) -> hipError_t {
     for (int t = 0; t < burst; ++t) {
-      const hipError_t e = launch_reduce_round(ra, s, walk_clock.pair());
+      // the burst's last round leaves the control block in the slot
+      const hipError_t e =
+          launch_reduce_round(ra, s, walk_clock.pair(), t + 1 == burst ? &hc[slot] : nullptr);
       if (e != hipSuccess) return e;
     }
-    hipError_t e = hipMemcpyAsync(&hc[slot], ra.ctl, sizeof(RedCtl), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipEventRecord(rb->ev[slot], s);
-    return e;
+    return hipEventRecord(rb->ev[slot], s);
   };
   // Up to two bursts in flight (slots alternate; a slot is reused only after
   // it was inspected); the first burst is inspected alone.
@@ -747,9 +749,13 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   S.sort_chunks = chunks;
   S.sorted_keys = E_lim;
   HIPCHK(launch_reduce_finish(ra, s));
-  HIPCHK(hipMemcpyAsync(hc, ra.ctl, sizeof(RedCtl), hipMemcpyDeviceToHost, s));
   uint32_t* hw = rb->words;
-  HIPCHK(hipMemcpyAsync(&hw[0], serr, 4, hipMemcpyDeviceToHost, s));
+  {
+    Gather g;
+    g.add(ra.ctl, hc, sizeof(RedCtl));
+    g.add(serr, &hw[0], 4);
+    HIPCHK(launch_gather(g, s));
+  }
   HIPCHK(hipStreamSynchronize(s));
   tm.mark();  // 4
   if (hw[0]) return fail(PH0_EDEVICE, "radix sort digit counts were inconsistent");
@@ -770,14 +776,21 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   uint32_t* dbv = out.dbv ? out.dbv : static_cast<uint32_t*>(at(L.dbv));
   if (grades_work_bytes(fin->E_eff) > 8 * (size_t)std::max<int64_t>(L.E, 2 * n + 64))
     return fail(PH0_EDEVICE, "grade scratch does not fit the key buffer");
+  const uint32_t *d_distinct = nullptr, *d_npiv = nullptr;
   HIPCHK(launch_grades_and_bars(skeys, fin->E_eff, 2 * ib, ra.killer, n, spare, dbv,
-                                reinterpret_cast<uint32_t*>(out.bars), s, &hw[1], &hw[2]));
+                                reinterpret_cast<uint32_t*>(out.bars), s, &d_distinct, &d_npiv));
   tm.mark();  // 5
   if (out.killer_pos || out.killer_edge || out.killer_sqdist || out.partner)
     HIPCHK(launch_pairs_detail(ra.killer, skeys, ib, ra.part, n, out.killer_pos,
                                out.killer_edge, out.killer_sqdist, out.partner, s));
   tm.mark();  // 6
-  HIPCHK(hipMemcpyAsync(&hw[0], serr, 4, hipMemcpyDeviceToHost, s));
+  {
+    Gather g;
+    g.add(serr, &hw[0], 4);
+    g.add(d_distinct, &hw[1], 4);
+    g.add(d_npiv, &hw[2], 4);
+    HIPCHK(launch_gather(g, s));
+  }
   HIPCHK(hipStreamSynchronize(s));
   drain.armed = false;
   const uint32_t distinct = hw[1], npiv = hw[2];

@@ -61,6 +61,25 @@ enum : int32_t { kActive = 0, kZero = 1, kCommitted = 2 };
 
 hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
+// Up to four small device -> host (pinned) copies in one launch.
+struct Gather {
+  const uint32_t* src[4];
+  uint32_t* dst[4];
+  int32_t words[4];
+  int count = 0;
+  void add(const void* from, void* to, size_t bytes) {
+    if (count == 4) {  // full: launch_gather rejects the list
+      count = 5;
+      return;
+    }
+    if (count > 4) return;
+    src[count] = static_cast<const uint32_t*>(from);
+    dst[count] = static_cast<uint32_t*>(to);
+    words[count] = (int32_t)(bytes / 4);
+    ++count;
+  }
+};
+hipError_t launch_gather(const Gather& g, hipStream_t s);
 
 // Per-dimension coordinate range -> bound on the squared distance.
 hipError_t launch_coord_range(const void* pts, int elem_bytes, int64_t n, int32_t d,
@@ -158,6 +177,9 @@ struct RedArgs {
   uint64_t* cslot;  // 4 x nblocks: each commit workgroup's pivots, end of its last
                     // pivot, first kept column and number kept
   RedCtl* ctl;
+  // When set (pinned host memory), the round's advance step also leaves the
+  // control block there, so the host reads it without a copy of its own.
+  RedCtl* publish = nullptr;
 };
 // Grid of the walk (and of the commit) and the segment entries per workgroup.
 int walk_blocks(int64_t Wcap);
@@ -170,7 +192,8 @@ hipError_t launch_reduce_init(const RedArgs& a, int64_t E_lim, hipStream_t s);
 hipError_t launch_reduce_extend(const RedArgs& a, int64_t E_lim, hipStream_t s);
 // One round: walk, commit, advance.  When `ev_walk` is non-null its two
 // events are recorded around the walk kernel.
-hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_walk);
+hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_walk,
+                               RedCtl* publish = nullptr);
 hipError_t launch_reduce_finish(const RedArgs& a, hipStream_t s);
 
 // Steps 3 and 5 together, over the first E_eff sorted keys: the grade of a
@@ -180,12 +203,13 @@ hipError_t launch_reduce_finish(const RedArgs& a, hipStream_t s);
 // positions writes both the canonical barcode and the per-vertex deaths,
 // with no sort.  `work` holds grades_work_bytes(E_eff) bytes; dbv may be the
 // caller's or scratch (n words); bars may be null.  *distinct receives the
-// number of distinct distances in the prefix, *pivots the pivot count.
+// device address of the number of distinct distances in the prefix, *pivots
+// that of the pivot count (both in `work`, valid once the stream has run).
 size_t grades_work_bytes(int64_t E_eff);
 hipError_t launch_grades_and_bars(const uint64_t* skeys, int64_t E_eff, int shift,
                                   const int64_t* killer, int64_t n, void* work, uint32_t* dbv,
-                                  uint32_t* bars, hipStream_t s, uint32_t* distinct,
-                                  uint32_t* pivots);
+                                  uint32_t* bars, hipStream_t s, const uint32_t** distinct,
+                                  const uint32_t** pivots);
 hipError_t launch_pairs_detail(const int64_t* killer, const uint64_t* skeys, int ib,
                                const int32_t* part, int64_t n,
                                int64_t* killer_pos, uint64_t* killer_edge,

@@ -167,8 +167,8 @@ size_t grades_work_bytes(int64_t E_eff) {
 
 hipError_t launch_grades_and_bars(const uint64_t* skeys, int64_t E_eff, int shift,
                                   const int64_t* killer, int64_t n, void* work, uint32_t* dbv,
-                                  uint32_t* bars, hipStream_t s, uint32_t* distinct,
-                                  uint32_t* pivots) {
+                                  uint32_t* bars, hipStream_t s, const uint32_t** distinct,
+                                  const uint32_t** pivots) {
   const int64_t ng = (E_eff + kGroup - 1) / kGroup;
   const int64_t words = (E_eff + 31) / 32;
   int32_t* prow = static_cast<int32_t*>(work);
@@ -188,8 +188,9 @@ hipError_t launch_grades_and_bars(const uint64_t* skeys, int64_t E_eff, int shif
   if ((e = launch_scan_u32(cp, ng + 1, tot_p, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_grade_emit, dim3(g), dim3(kGroup), 0, s, skeys, E_eff, shift, bitmap,
                      prow, cc, cp, dbv, bars, n);
-  if ((e = hipMemcpyAsync(distinct, cc + ng, 4, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
-  return hipMemcpyAsync(pivots, cp + ng, 4, hipMemcpyDeviceToHost, s);
+  *distinct = cc + ng;
+  *pivots = cp + ng;
+  return hipGetLastError();
 }
 
 hipError_t launch_pairs_detail(const int64_t* killer, const uint64_t* skeys, int ib,

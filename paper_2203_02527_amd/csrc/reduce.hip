@@ -514,7 +514,10 @@ __global__ __launch_bounds__(kAdvanceThreads) void k_advance(RedArgs A) {
   __shared__ int64_t itmp[kWaves];
   __shared__ uint64_t utmp[kWaves];
   RedCtl* ctl = A.ctl;
-  if (ctl->done || ctl->need_more) return;
+  if (ctl->done || ctl->need_more) {
+    if (A.publish && threadIdx.x == 0) *A.publish = *ctl;
+    return;
+  }
   const int tid = threadIdx.x;
   const int nb = A.nblocks;
   int64_t piv = 0, kept = 0;
@@ -562,19 +565,22 @@ __global__ __launch_bounds__(kAdvanceThreads) void k_advance(RedArgs A) {
       }
     }
   }
-  ctl->pivots = pivots;
-  ctl->E_eff = E_eff;
-  ctl->width = width;
-  ctl->done = done;
-  ctl->need_more = need_more;
-  ctl->err = err;
-  ctl->fresh_lo = c.Wend;
-  ctl->fresh_hi = Wend;
-  ctl->nA = all_kept;
-  ctl->F = F;
-  ctl->Wend = Wend;
-  ctl->maxWend = Wend > c.maxWend ? Wend : c.maxWend;
-  ctl->round = c.round + 1;
+  RedCtl u = c;
+  u.pivots = pivots;
+  u.E_eff = E_eff;
+  u.width = width;
+  u.done = done;
+  u.need_more = need_more;
+  u.err = err;
+  u.fresh_lo = c.Wend;
+  u.fresh_hi = Wend;
+  u.nA = all_kept;
+  u.F = F;
+  u.Wend = Wend;
+  u.maxWend = Wend > c.maxWend ? Wend : c.maxWend;
+  u.round = c.round + 1;
+  *ctl = u;
+  if (A.publish) *A.publish = u;
 }
 
 // Sum of the walk blocks' counter slots into the control block.
@@ -715,7 +721,8 @@ hipError_t launch_reduce_init(const RedArgs& a, int64_t E_lim, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_walk) {
+hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_walk,
+                               RedCtl* publish) {
   // The LDS table copy of the largest n (64 KB) is beyond the default
   // dynamic LDS limit of a workgroup.
   static const hipError_t attr = hipFuncSetAttribute(
@@ -733,7 +740,9 @@ hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_w
   if (e != hipSuccess) return e;
   if (ev_walk) (void)hipEventRecord(ev_walk[1], s);
   hipLaunchKernelGGL(k_commit, dim3((unsigned)wb), dim3(kCommitThreads), 0, s, a);
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(kAdvanceThreads), 0, s, a);
+  RedArgs adv = a;
+  adv.publish = publish;
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(kAdvanceThreads), 0, s, adv);
   return hipGetLastError();
 }
 
