@@ -307,8 +307,9 @@ __device__ inline void tile_regs_store(const TileRegs& r, int8_t (*xs)[64][KROW]
 // and advances them tile by tile.
 //
 // Waves per SIMD each pass is compiled for at least: four for the emit pass
-// (a few bytes spill), three for the others (which then fit five).
-constexpr int keys_waves(int mode) { return mode == kKeysEmit ? 4 : 3; }
+// with d <= 64 (a few bytes spill), three for the others (the count and
+// histogram passes then fit five).
+constexpr int keys_waves(int mode, int kmax) { return mode == kKeysEmit && kmax == 64 ? 4 : 3; }
 
 // The tile being worked on and the item it belongs to (ok = 0 past the
 // workgroup's last item).
@@ -348,7 +349,7 @@ __device__ inline Cursor item_cursor(int64_t item, int64_t item_end, int64_t sam
 }
 
 template <int MODE, int KMAX, bool AHEAD>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_waves(MODE)))) void k_keys_mfma(const int8_t* __restrict__ x, int64_t n,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_waves(MODE, KMAX)))) void k_keys_mfma(const int8_t* __restrict__ x, int64_t n,
                                                    int32_t d, int ib, int64_t ntiles,
                                                    const int32_t* __restrict__ norms,
                                                    bool vec16, KeyPass kp) {
@@ -360,6 +361,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_waves(
   __shared__ uint32_t lh[kHist ? kHistBins : 1];
   __shared__ __attribute__((aligned(16))) uint32_t half_cnt[kTile][2];  // kept keys per (row, half of the tile's i)
   __shared__ __attribute__((aligned(16))) uint32_t rbase[kTile];  // emit: colex base of each row's kept keys
+  // emit: each wave's queue of kept keys (delta << 32 | r << 6 | lane) for
+  // one half of its accumulators, and where each r's entries start
+  constexpr int kQueue = MODE == kKeysEmit ? 512 : 1;
+  __shared__ uint64_t q_keys[4][kQueue];
+  __shared__ uint32_t q_start[4][16];
   if (kHist) hist_zero(lh);
   const int hs = kHist && kp.hist_shift_dev ? *kp.hist_shift_dev : kp.hist_shift;
 
@@ -518,33 +524,67 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_waves(
     const bool interior = j0 >= i0 + kTile && j0 + kTile <= n;
     auto epilogue = [&](auto full_tile) {
       constexpr bool kInterior = decltype(full_tile)::value;
-      uint32_t kept_bits = 0;
-      uint32_t dl[16];  // emit: the deltas, kept past the accumulators
+      // Two halves of the accumulators (r < 8, r >= 8: disjoint rows).  The
+      // emit pass queues each half's kept keys per wave in LDS (r by r, each
+      // r's lower half-wave first, lanes in order), then writes the queue
+      // out 64 keys per store, each key at its row's base plus its rank.
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int4 nj = *reinterpret_cast<const int4*>(&nrm[1][jrow + 8 * q]);
+      for (int hf = 0; hf < 2; ++hf) {
+        uint32_t wq = 0;  // emit: this wave's queued keys of this half
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int r = 4 * q + t;
-          const int jl = jrow + 8 * q + t;
-          const int64_t j = j0 + jl;
-          const bool valid = kInterior || (j < n && i < j);
-          const uint32_t delta = delta_of(nj, r);
-          if constexpr (kHist) {
-            if (valid) {
-              if (MODE == kKeysFull)
-                kp.keys[j * (j - 1) / 2 + i] =
-                    ((uint64_t)delta << (2 * ib)) | ((uint64_t)j << ib) | (uint64_t)i;
-              atomicAdd(&lh[(uint32_t)((uint64_t)delta >> hs)], 1u);
+        for (int qq = 0; qq < 2; ++qq) {
+          const int q = 2 * hf + qq;
+          const int4 nj = *reinterpret_cast<const int4*>(&nrm[1][jrow + 8 * q]);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int r = 4 * q + t;
+            const int jl = jrow + 8 * q + t;
+            const int64_t j = j0 + jl;
+            const bool valid = kInterior || (j < n && i < j);
+            const uint32_t delta = delta_of(nj, r);
+            if constexpr (kHist) {
+              if (valid) {
+                if (MODE == kKeysFull)
+                  kp.keys[j * (j - 1) / 2 + i] =
+                      ((uint64_t)delta << (2 * ib)) | ((uint64_t)j << ib) | (uint64_t)i;
+                atomicAdd(&lh[(uint32_t)((uint64_t)delta >> hs)], 1u);
+              }
+            } else {
+              const bool kept = valid && delta - dlo32 < span32;
+              const uint64_t m = __ballot(kept);
+              const uint32_t hc = half ? (uint32_t)__popc((uint32_t)(m >> 32))
+                                       : (uint32_t)__popc((uint32_t)m);
+              if ((lane & 31) == 0) {
+                half_cnt[jl][isub] = hc;
+                if (MODE == kKeysEmit && lane == 0) q_start[wave][r] = wq;
+              }
+              if constexpr (MODE == kKeysEmit) {
+                if (kept) {
+                  const uint32_t at =
+                      wq + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                  q_keys[wave][at] = ((uint64_t)delta << 32) | (uint32_t)((r << 6) | lane);
+                }
+                wq += (uint32_t)__popcll(m);
+              }
             }
-          } else {
-            const bool kept = valid && delta - dlo32 < span32;
-            kept_bits |= (kept ? 1u : 0u) << r;
-            dl[r] = delta;
-            const uint64_t m = __ballot(kept);
-            const uint32_t hc = half ? (uint32_t)__popc((uint32_t)(m >> 32))
-                                     : (uint32_t)__popc((uint32_t)m);
-            if ((lane & 31) == 0) half_cnt[jl][isub] = hc;
+          }
+        }
+        if constexpr (MODE == kKeysEmit) {
+          __syncthreads();  // every wave's half_cnt of this half is in LDS
+          for (uint32_t e = lane; e < wq; e += 64) {
+            const uint64_t qk = q_keys[wave][e];
+            const uint32_t meta = (uint32_t)qk;
+            const int r = (int)(meta >> 6), ln = (int)(meta & 63), h = ln >> 5;
+            const int row0 = jsub * 32 + 8 * (r >> 2) + (r & 3);  // row of r's lower half-wave
+            const int jl = row0 + 4 * h;
+            // rank among the kept keys of its half-row in this wave
+            uint32_t rank = e - q_start[wave][r];
+            if (h) rank -= half_cnt[row0][isub];
+            // after the lower i-half's keys of the row (the other wave)
+            const uint32_t pos = rbase[jl] + (isub ? half_cnt[jl][0] : 0u) + rank;
+            const uint64_t jj = (uint64_t)(j0 + jl), ii = (uint64_t)(i0 + isub * 32 + (ln & 31));
+            kp.keys[pos] = ((qk >> 32) << (2 * ib)) | (jj << ib) | ii;
           }
         }
       }
@@ -554,42 +594,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_waves(
           row_acc = (seg_first ? 0u : row_acc) + half_cnt[threadIdx.x][0] +
                     half_cnt[threadIdx.x][1];
           if (seg_last) kp.cnt[count_slot(cur, threadIdx.x)] = row_acc;
-        }
-      } else if constexpr (MODE == kKeysEmit) {
-        __syncthreads();
-        // (j << b | i) of r = 0; r adds (8 (r / 4) + r % 4) << b.
-        const uint64_t ji0 = ((uint64_t)(j0 + jrow) << ib) | (uint64_t)i;
-        const uint32_t upper = half ? 0xFFFFFFFFu : 0u;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          // First output position of this lane's row for r = 4q .. 4q + 3:
-          // the row's colex base, after the lower i-half's keys for the
-          // upper half.
-          uint4 base = *reinterpret_cast<const uint4*>(&rbase[jrow + 8 * q]);
-          if (isub) {
-            const uint4 h0 = *reinterpret_cast<const uint4*>(&half_cnt[jrow + 8 * q][0]);
-            const uint4 h1 = *reinterpret_cast<const uint4*>(&half_cnt[jrow + 8 * q + 2][0]);
-            base.x += h0.x;
-            base.y += h0.z;
-            base.z += h1.x;
-            base.w += h1.z;
-          }
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int r = 4 * q + t;
-            const bool kept = (kept_bits >> r) & 1u;
-            const uint64_t m = __ballot(kept);
-            if (kept) {
-              // kept lanes below this one in its half-wave
-              const uint32_t below =
-                  __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) -
-                  ((uint32_t)__popc((uint32_t)m) & upper);
-              const uint32_t b = t == 0 ? base.x : t == 1 ? base.y : t == 2 ? base.z : base.w;
-              kp.keys[b + below] = ((uint64_t)dl[r] << (2 * ib)) |
-                                   (ji0 + ((uint64_t)(8 * q + t) << ib));
-            }
-          }
         }
       }
     };

@@ -2,13 +2,13 @@
 // stable least-significant-digit radix passes over 64-bit keys.
 //
 // Each pass is reduce-then-scan, with no workgroup ever waiting on another:
-//   count   -- every 4096-key tile histograms its digits in LDS;
+//   count   -- every 2048-key tile histograms its digits in LDS;
 //   scan    -- one workgroup per digit scans that digit's tile counts
 //              (exclusive, in place) and leaves the digit's total;
 //   scatter -- every tile scans the 256 digit totals for the digits' first
 //              output positions, ranks its keys among equal digits and
 //              writes them.
-// Inside a tile (4 waves x 16 rounds x 64 lanes) each wave owns a contiguous
+// Inside a tile (4 waves x 8 rounds x 64 lanes) each wave owns a contiguous
 // quarter; a key's rank among equal digits comes from wave ballots on the
 // digit bits, so equal digits keep their order.  That stability is what turns
 // sorting on the distance bits alone into the (delta, j, i) order.  The tile
@@ -22,8 +22,8 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kRounds = 16;
-constexpr int kTileKeys = kThreads * kRounds;  // 4096
+constexpr int kRounds = 8;
+constexpr int kTileKeys = kThreads * kRounds;  // 2048
 constexpr int kScanBlock = 4096;                // counts scanned per block
 
 // Exclusive scan of one value per thread over a 256-thread block (the block
@@ -53,7 +53,7 @@ __device__ inline bool kept(uint64_t key, const KeyFilter& f) {
   return v >= f.flo && v < f.fhi;
 }
 
-// Load this wave's 16 x 64 keys of the tile and rank each among equal
+// Load this wave's kRounds x 64 keys of the tile and rank each among equal
 // digits inside the wave (running counts per wave in wcnt).
 
 __device__ inline void load_and_rank(const uint64_t* __restrict__ in, int64_t count, int64_t base,
@@ -125,10 +125,11 @@ __global__ __launch_bounds__(kThreads) void k_radix_digit_scan(uint32_t* __restr
                                                                int64_t ntiles,
                                                                uint32_t* __restrict__ totals) {
   __shared__ uint32_t tmp[4];
-  constexpr int kPer = kScanBlock / kThreads;  // 16 consecutive counts per thread
+  constexpr int kPer = 32;  // consecutive counts per thread
+  constexpr int kSpan = kPer * kThreads;
   uint32_t* c = counts + (int64_t)blockIdx.x * ntiles;
   uint32_t carry = 0;
-  for (int64_t b0 = 0; b0 < ntiles; b0 += kScanBlock) {
+  for (int64_t b0 = 0; b0 < ntiles; b0 += kSpan) {
     const int64_t p0 = b0 + threadIdx.x * kPer;
     uint32_t x[kPer];
     uint32_t sum = 0;
