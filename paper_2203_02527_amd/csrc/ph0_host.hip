@@ -98,7 +98,7 @@ int64_t ring_for(int64_t n, int64_t E) {
 struct Layout {
   int64_t n, E, Wcap, width, tiles;
   size_t keysA, keysB, counts, hist, err, part, surv, scount, fdslot, wstat, cslot, osum, killer,
-      lowc, touch, act0, act1, kpre, part16, ra, rr, rrlo, rst, ctl, dbv, minmax, hshift, kcnt,
+      lowc, touch, act0, act1, werr, part16, ra, rr, rrlo, rst, ctl, dbv, minmax, hshift, kcnt,
       kcnt_tot, norms, total;
 };
 
@@ -129,7 +129,7 @@ Layout make_layout(int64_t n, int32_t d) {
   L.fdslot = take(8 * wb);
   L.wstat = take(8 * 3 * wb);
   L.cslot = take(8 * 4 * wb);
-  L.kpre = take(8 * (wb + 1));
+  L.werr = take(4);
   L.killer = take(8 * (size_t)n);
   L.lowc = take(8 * (size_t)n);
   L.touch = take(8 * (size_t)n);
@@ -140,7 +140,7 @@ Layout make_layout(int64_t n, int32_t d) {
   L.rr = take(4 * (size_t)L.Wcap);
   L.rrlo = take(4 * (size_t)L.Wcap);
   L.rst = take(4 * (size_t)L.Wcap);
-  L.ctl = take(sizeof(RedCtl));
+  L.ctl = take(2 * sizeof(RedCtl));  // the two round states
   L.dbv = take(4 * (size_t)n);
   L.minmax = take(8 * (size_t)d);
   L.hshift = take(4);
@@ -635,7 +635,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   ra.width = L.width;
   ra.seg = walk_segment(L.Wcap);
   ra.nblocks = walk_blocks(L.Wcap);
-  ra.kpre = static_cast<int64_t*>(at(L.kpre));
+  ra.werr = static_cast<int32_t*>(at(L.werr));
   ra.act[0] = static_cast<int64_t*>(at(L.act0));
   ra.act[1] = static_cast<int64_t*>(at(L.act1));
   ra.part = static_cast<int32_t*>(at(L.part));
@@ -664,14 +664,19 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   // The first burst is short and inspected before anything else is queued,
   // so that small problems (a round or two) do not queue idle rounds.
   int burst = 2;  // grows to 8
+  int64_t R = 0;  // rounds launched
   auto issue = [&](int slot) -> hipError_t {
     for (int t = 0; t < burst; ++t) {
-      // the burst's last round leaves the control block in the slot
-      const hipError_t e =
-          launch_reduce_round(ra, s, walk_clock.pair(), t + 1 == burst ? &hc[slot] : nullptr);
+      // A burst's first round starts from a state advanced already (the
+      // initial one, or the previous burst's); the others advance it in
+      // their walk.
+      const hipError_t e = launch_reduce_round(ra, s, walk_clock.pair(), R, t == 0);
       if (e != hipSuccess) return e;
+      ++R;
     }
-    return hipEventRecord(rb->ev[slot], s);
+    // The state after the burst, also into the slot's pinned copy.
+    const hipError_t e = launch_reduce_advance(ra, R, &hc[slot], s);
+    return e == hipSuccess ? hipEventRecord(rb->ev[slot], s) : e;
   };
   // Up to two bursts in flight (slots alternate; a slot is reused only after
   // it was inspected); the first burst is inspected alone.
@@ -709,7 +714,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
       q_len = 0;
       HIPCHK(next_chunk());
       ra.skeys = skeys;
-      HIPCHK(launch_reduce_extend(ra, E_lim, s));
+      HIPCHK(launch_reduce_extend(ra, E_lim, R, s));
       prevF = -1;
       HIPCHK(issue_next());
       continue;
@@ -748,11 +753,11 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   }
   S.sort_chunks = chunks;
   S.sorted_keys = E_lim;
-  HIPCHK(launch_reduce_finish(ra, s));
+  HIPCHK(launch_reduce_finish(ra, R, s));
   uint32_t* hw = rb->words;
   {
     Gather g;
-    g.add(ra.ctl, hc, sizeof(RedCtl));
+    g.add(reduce_state(ra, R), hc, sizeof(RedCtl));
     g.add(serr, &hw[0], 4);
     HIPCHK(launch_gather(g, s));
   }

@@ -19,10 +19,11 @@ struct SortPlan {
 };
 
 // State of the round-based reduction entering a round, resident in device
-// memory.  A round works on "items": first the nA columns kept by the
-// previous round's commit (listed in the commit workgroups' segments, at the
-// offsets kpre), then the fresh columns [fresh_lo, fresh_hi) entering the
-// window this round.
+// memory (two copies, by the parity of the rounds launched: round k reads
+// the state entering round k - 1 and writes the one entering round k).  A
+// round works on "items": first the nA columns kept by the previous round's
+// commit (listed in the commit workgroups' segments, in workgroup order),
+// then the fresh columns [fresh_lo, fresh_hi) entering the window this round.
 struct RedCtl {
   int64_t F;         // first column that is not final
   int64_t Wend;      // end of the window [F, Wend); Wend - F <= Wcap
@@ -166,7 +167,6 @@ struct RedArgs {
   uint64_t* lowc;   // n: round-tagged smallest survivor with low r
   uint64_t* touch;  // n: round-tagged smallest survivor whose other row has root r
   int64_t* act[2];  // kept columns, one segment per commit workgroup (by round parity)
-  int64_t* kpre;    // nblocks + 1: kept columns before each segment, and their total
   Ring ring;
   int64_t* surv;    // nblocks x seg: each walk workgroup's survivors
   uint32_t* scount; // nblocks: survivors per walk workgroup
@@ -176,10 +176,8 @@ struct RedArgs {
                     // table words, summed by the finish step
   uint64_t* cslot;  // 4 x nblocks: each commit workgroup's pivots, end of its last
                     // pivot, first kept column and number kept
-  RedCtl* ctl;
-  // When set (pinned host memory), the round's advance step also leaves the
-  // control block there, so the host reads it without a copy of its own.
-  RedCtl* publish = nullptr;
+  RedCtl* ctl;       // [2]: the round states, by parity of the rounds launched
+  int32_t* werr;     // a walk met a stored row below its low (folded into err)
 };
 // Grid of the walk (and of the commit) and the segment entries per workgroup.
 int walk_blocks(int64_t Wcap);
@@ -187,14 +185,26 @@ int64_t walk_segment(int64_t Wcap);
 // Largest n whose table has a 16-bit mirror (staged in LDS by the walk).
 constexpr int64_t kPart16MaxN = 32768;
 int64_t part16_len(int64_t n);
+// The state entering round `rounds` (after that many rounds were launched),
+// once the walk of that round or launch_reduce_advance has run.
+inline RedCtl* reduce_state(const RedArgs& a, int64_t rounds) { return a.ctl + (rounds & 1); }
+// The state entering round 0.
 hipError_t launch_reduce_init(const RedArgs& a, int64_t E_lim, hipStream_t s);
-// More sorted columns are available: [old E_lim, E_lim).
-hipError_t launch_reduce_extend(const RedArgs& a, int64_t E_lim, hipStream_t s);
-// One round: walk, commit, advance.  When `ev_walk` is non-null its two
-// events are recorded around the walk kernel.
-hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_walk,
-                               RedCtl* publish = nullptr);
-hipError_t launch_reduce_finish(const RedArgs& a, hipStream_t s);
+// More sorted columns are available: [old E_lim, E_lim) (after `rounds`
+// rounds and launch_reduce_advance).
+hipError_t launch_reduce_extend(const RedArgs& a, int64_t E_lim, int64_t rounds, hipStream_t s);
+// Round `k` (the k-th launched, from 0): the walk, which first advances the
+// state past round k - 1 unless `advanced` (round 0, or launch_reduce_advance
+// ran since), then the commit.  When `ev_walk` is non-null its two events
+// are recorded around the walk kernel.
+hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_walk, int64_t k,
+                               bool advanced);
+// The state entering round `rounds` on its own (one wave), also left in
+// `publish` (pinned host memory) when given.
+hipError_t launch_reduce_advance(const RedArgs& a, int64_t rounds, RedCtl* publish,
+                                 hipStream_t s);
+// Totals into the state entering round `rounds` (after launch_reduce_advance).
+hipError_t launch_reduce_finish(const RedArgs& a, int64_t rounds, hipStream_t s);
 
 // Steps 3 and 5 together, over the first E_eff sorted keys: the grade of a
 // sorted position p is 1 + the number of distance changes in 1..p (dense

@@ -119,14 +119,16 @@ __global__ __launch_bounds__(kThreads) void k_radix_count(const uint64_t* __rest
     counts[(int64_t)tid * ntiles + tile] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
 }
 
-// One workgroup per digit: exclusive scan, in place, of that digit's tile
-// counts (tile order); the digit's total goes to totals[digit].
-__global__ __launch_bounds__(kThreads) void k_radix_digit_scan(uint32_t* __restrict__ counts,
-                                                               int64_t ntiles,
-                                                               uint32_t* __restrict__ totals) {
-  __shared__ uint32_t tmp[4];
-  constexpr int kPer = 32;  // consecutive counts per thread
-  constexpr int kSpan = kPer * kThreads;
+// One 1024-thread workgroup per digit: exclusive scan, in place, of that
+// digit's tile counts (tile order); the digit's total goes to totals[digit].
+constexpr int kDigitScanThreads = 1024;
+__global__ __launch_bounds__(kDigitScanThreads) void k_radix_digit_scan(
+    uint32_t* __restrict__ counts, int64_t ntiles, uint32_t* __restrict__ totals) {
+  constexpr int kW = kDigitScanThreads / 64;
+  constexpr int kPer = 8;  // consecutive counts per thread
+  constexpr int kSpan = kPer * kDigitScanThreads;
+  __shared__ uint32_t wsum[kW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t* c = counts + (int64_t)blockIdx.x * ntiles;
   uint32_t carry = 0;
   for (int64_t b0 = 0; b0 < ntiles; b0 += kSpan) {
@@ -138,8 +140,23 @@ __global__ __launch_bounds__(kThreads) void k_radix_digit_scan(uint32_t* __restr
       x[q] = p0 + q < ntiles ? c[p0 + q] : 0;
       sum += x[q];
     }
-    uint32_t all;
-    uint32_t run = carry + block_exclusive_scan(sum, tmp, &all);
+    // exclusive scan of the thread sums over the block
+    uint32_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kW; ++w) {
+      before += w < wave ? wsum[w] : 0u;
+      all += wsum[w];
+    }
+    __syncthreads();
+    uint32_t run = carry + before + incl - sum;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       if (p0 + q < ntiles) c[p0 + q] = run;
@@ -284,8 +301,8 @@ hipError_t launch_radix_pass(const uint64_t* in, uint64_t* out, int64_t count, i
   uint32_t* totals = counts + 256 * tiles;
   hipLaunchKernelGGL(k_radix_count, dim3((unsigned)tiles), dim3(kThreads), 0, s, in, count,
                      shift, bits, tiles, counts, f);
-  hipLaunchKernelGGL(k_radix_digit_scan, dim3(nbins), dim3(kThreads), 0, s, counts, tiles,
-                     totals);
+  hipLaunchKernelGGL(k_radix_digit_scan, dim3(nbins), dim3(kDigitScanThreads), 0, s, counts,
+                     tiles, totals);
   hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)tiles), dim3(kThreads), 0, s, in, out,
                      count, shift, bits, tiles, (const uint32_t*)counts,
                      (const uint32_t*)totals, err, f, out_count);

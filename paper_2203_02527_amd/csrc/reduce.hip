@@ -39,20 +39,24 @@
 // the remaining columns must reduce to zero (the complete graph is
 // connected), so the reduction stops there.
 //
-// A round is three launches -- walk, commit, advance -- and its control uses
-// no atomic on a shared address (on MI355X same-address atomics from
-// hundreds of workgroups serialize; a grid-wide barrier costs several times
-// a launch, and so does a chain of dependent loads at the start of every
-// walk workgroup):
+// A round is two launches -- walk, commit -- and its control uses no atomic
+// on a shared address (on MI355X same-address atomics from hundreds of
+// workgroups serialize, and a grid-wide barrier costs several times a
+// launch):
+//   * the first wave of every walk workgroup reduces the previous commit's
+//     slots into the state entering this round (the same in each;
+//     workgroup 0 stores it, into the other of two state copies, for the
+//     commit and the next round), with the offsets of the kept segments in
+//     its LDS;
 //   * the walk also finds the first survivor whose low repeats an earlier
 //     one: within a workgroup from its LDS hash of row minima, across
 //     workgroups from the values the row-minimum atomics return; each
 //     workgroup leaves its candidate in a slot of its own;
 //   * the commit workgroup of a walk workgroup's survivors commits or keeps
 //     them, writes the kept ones to a segment of its own and its totals to a
-//     slot of its own;
-//   * one advance workgroup reduces the slots into the next round's state
-//     and the offsets of the kept segments.
+//     slot of its own.
+// Where the host looks at the state (the end of a burst of rounds), one
+// wave advances it on its own and leaves a copy in host memory.
 #include <algorithm>
 
 #include "ph0_internal.h"
@@ -66,7 +70,6 @@ constexpr uint16_t kFree16 = 0xFFFF;  // a free row in the 16-bit table mirror
 constexpr int kWalkThreads = 1024;
 constexpr int kWalkWaves = kWalkThreads / 64;
 constexpr int kCommitThreads = 256;
-constexpr int kAdvanceThreads = 512;  // one thread per commit slot (kMaxWalkBlocks)
 constexpr int kHashBits = 11;  // log2 of the LDS hash slots (2 x kWalkThreads)
 
 // Row minima carry the round in their top bits, so that a value left by an
@@ -91,6 +94,12 @@ __device__ inline uint64_t shfl64_down(uint64_t v, int delta) {
 __device__ inline uint64_t shfl64_up(uint64_t v, int delta) {
   const uint32_t lo = __shfl_up((uint32_t)v, delta, 64);
   const uint32_t hi = __shfl_up((uint32_t)(v >> 32), delta, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t shfl64_idx(uint64_t v, int src) {
+  const uint32_t lo = __shfl((uint32_t)v, src, 64);
+  const uint32_t hi = __shfl((uint32_t)(v >> 32), src, 64);
   return ((uint64_t)hi << 32) | lo;
 }
 
@@ -179,6 +188,173 @@ __device__ inline int64_t block_excl_i64(int64_t v, int64_t* tmp, int64_t* total
   return base + x - v;
 }
 
+// The fields of a round state the walk uses.
+struct RoundView {
+  int64_t nA, round, fresh_lo, fresh_hi, F;
+  int32_t done, need_more;
+};
+
+// The view held in scalar registers (the values are the same in every lane).
+__device__ inline int64_t uniform64(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ inline RoundView uniform_view(RoundView v) {
+  v.nA = uniform64(v.nA);
+  v.round = uniform64(v.round);
+  v.fresh_lo = uniform64(v.fresh_lo);
+  v.fresh_hi = uniform64(v.fresh_hi);
+  v.F = uniform64(v.F);
+  v.done = (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)v.done);
+  v.need_more = (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)v.need_more);
+  return v;
+}
+
+__device__ inline RoundView round_view(const RedCtl* c) {
+  RoundView v;
+  v.nA = c->nA;
+  v.round = c->round;
+  v.fresh_lo = c->fresh_lo;
+  v.fresh_hi = c->fresh_hi;
+  v.F = c->F;
+  v.done = c->done;
+  v.need_more = c->need_more;
+  return v;
+}
+
+// dst = src, by thread 0.
+__device__ inline void copy_state(RedCtl* dst, const RedCtl* src) {
+  static_assert(sizeof(RedCtl) % 8 == 0, "the state is copied in 8-byte words");
+  const uint64_t* s = reinterpret_cast<const uint64_t*>(src);
+  uint64_t* d = reinterpret_cast<uint64_t*>(dst);
+  for (int w = 0; w < (int)(sizeof(RedCtl) / 8); ++w) d[w] = s[w];
+}
+
+// The state entering the next round, formed by one wave (lane l reduces
+// the commit slots 8l .. 8l + 7 of the round just committed: pivots, end of
+// the last pivot, first kept column, columns kept) from the state `c`
+// entering that round; lane 0 stores it to `out` and `publish` when given.
+// pre[0..nblocks] (LDS) receives the kept columns before each commit
+// segment and their total.  With `compute` false, `c` is the state already
+// (only pre is formed).  A state that is done or waits for more columns
+// carries over unchanged.  The window start moves to the first column that
+// is not final; the window end never moves back; the width doubles (up to
+// the ring's capacity) while almost every column of a round becomes final
+// and halves (down to the base width) when many stay.  Every lane gets the
+// same view back.
+__device__ RoundView advance_wave(const RedArgs& A, const RedCtl* c, bool compute, RedCtl* out,
+                                  RedCtl* publish, int64_t* pre) {
+  const int lane = threadIdx.x & 63;
+  const RoundView cv = round_view(c);
+  if (cv.done || cv.need_more) {
+    if (compute && lane == 0) {
+      if (out) copy_state(out, c);
+      if (publish) copy_state(publish, c);
+    }
+    return cv;
+  }
+  if (!compute && cv.nA == 0) return cv;  // no kept columns to place
+  constexpr int kPer = kMaxWalkBlocks / 64;
+  const int nb = A.nblocks;
+  int64_t piv = 0, lane_kept = 0;
+  uint64_t end = 0, stay = kNoValue;
+  int64_t kept[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int b = lane * kPer + q;
+    kept[q] = 0;
+    if (b < nb) {
+      const uint64_t* cs = A.cslot + 4 * (int64_t)b;
+      kept[q] = (int64_t)cs[3];
+      if (compute) {
+        piv += (int64_t)cs[0];
+        end = cs[1] > end ? cs[1] : end;
+        stay = cs[2] < stay ? cs[2] : stay;
+      }
+    }
+    lane_kept += kept[q];
+  }
+  int64_t incl = lane_kept;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = (int64_t)shfl64_up((uint64_t)incl, o);
+    if (lane >= o) incl += y;
+  }
+  int64_t run = incl - lane_kept;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int b = lane * kPer + q;
+    if (b < nb) pre[b] = run;
+    run += kept[q];
+  }
+  const int64_t all_kept = uniform64((int64_t)shfl64_idx((uint64_t)incl, 63));
+  if (lane == 0) pre[nb] = all_kept;
+  if (!compute) return cv;
+  piv = uniform64(wave_sum_i64(piv));
+  end = (uint64_t)uniform64((int64_t)wave_max_u64(end));
+  stay = (uint64_t)uniform64((int64_t)wave_min_u64(stay));
+  const int64_t n = A.n, E = A.E, Wcap = A.Wcap;
+  const int64_t c_Wend = c->Wend, c_E_eff = c->E_eff;
+  const int64_t pivots = c->pivots + piv;
+  const int64_t E_eff = (int64_t)end > c_E_eff ? (int64_t)end : c_E_eff;
+  const int64_t F = stay == kNoValue ? c_Wend : (int64_t)stay;
+  int64_t Wend = c_Wend, width = c->width;
+  int32_t done = 0, need_more = 0;
+  int32_t err = c->err | __hip_atomic_load(A.werr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (pivots >= n - 1) {
+    // Every later column reduces to zero; only columns before the last
+    // pivot still need finishing (for the exact addition count).
+    if (F >= E_eff) done = 1;
+  } else {
+    const int64_t lim = c->E_lim;
+    if (all_kept < width / 256)
+      width = 2 * width < Wcap ? 2 * width : Wcap;
+    else if (all_kept > width / 16)
+      width = width / 2 > c->width_min ? width / 2 : c->width_min;
+    const int64_t want = F + width < lim ? F + width : lim;
+    Wend = want > Wend ? want : Wend;
+    if (F >= lim) {
+      if (lim < E) {
+        need_more = 1;  // the host sorts the next distance range
+      } else {
+        done = 1;
+        err |= 2;
+      }
+    }
+  }
+  RoundView v;
+  v.nA = all_kept;
+  v.round = cv.round + 1;
+  v.fresh_lo = c_Wend;
+  v.fresh_hi = Wend;
+  v.F = F;
+  v.done = done;
+  v.need_more = need_more;
+  if (lane == 0) {
+    const int64_t maxWend = Wend > c->maxWend ? Wend : c->maxWend;
+    for (int t = 0; t < 2; ++t) {
+      RedCtl* o = t ? publish : out;
+      if (!o) continue;
+      copy_state(o, c);
+      o->pivots = pivots;
+      o->E_eff = E_eff;
+      o->width = width;
+      o->done = done;
+      o->need_more = need_more;
+      o->err = err;
+      o->fresh_lo = v.fresh_lo;
+      o->fresh_hi = v.fresh_hi;
+      o->nA = v.nA;
+      o->F = F;
+      o->Wend = Wend;
+      o->maxWend = maxWend;
+      o->round = v.round;
+    }
+  }
+  return v;
+}
+
 // Per-workgroup aggregation of the survivors' row minima.  Survivors of one
 // row are many (up to 2e5 on the root of a large component when clusters
 // merge) and same-address global atomics serialize, while spreading them
@@ -206,7 +382,7 @@ __device__ inline int hash_insert(uint32_t* keys, uint32_t* vals, int row, uint3
 }
 
 // One round's walk.  Every item -- a column kept by the previous commit
-// (listed in the commit workgroups' segments, at the offsets in kpre) or a
+// (listed in the commit workgroups' segments, in workgroup order) or a
 // fresh column of the window -- is reduced against the table as committed
 // so far, one lane per column.  A column stops on a free row (a survivor) or
 // becomes zero.  For a survivor {a, r} the root of a in the pivot forest
@@ -220,10 +396,11 @@ __device__ inline int hash_insert(uint32_t* keys, uint32_t* vals, int row, uint3
 // free), else from part in global memory.
 template <bool kLds>
 __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8, 8)))
-void k_walk(RedArgs A, int64_t n16) {
+void k_walk(RedArgs A, int64_t n16, int64_t k, int advanced) {
   extern __shared__ uint4 s_tab4[];  // kLds: n16 / 8 entries of 8 table rows
   __shared__ uint32_t s_wave[kWalkWaves];
   __shared__ uint64_t s_u64[kWalkWaves];
+  __shared__ int64_t s_view[6];
   __shared__ unsigned long long s_cnt[3];
   __shared__ int s_bad;
   __shared__ int64_t s_pre[kMaxWalkBlocks + 1];  // kept columns before each commit segment
@@ -232,10 +409,39 @@ void k_walk(RedArgs A, int64_t n16) {
   __shared__ uint32_t s_hval[2][kHashSlots];
   const int nb = (int)gridDim.x;
   const int tid = threadIdx.x;
-  const RedCtl* ctl = A.ctl;
-  if (ctl->done || ctl->need_more) return;  // the commit and advance steps return too
-  const int64_t nA = ctl->nA, round = ctl->round, fresh_lo = ctl->fresh_lo, F = ctl->F;
-  const int64_t items = nA + (ctl->fresh_hi - fresh_lo);
+  const int lane = tid & 63, wave = tid >> 6;
+  // The state entering this round: advanced here past round k - 1 by the
+  // first wave (every workgroup forms the same; workgroup 0 stores it for
+  // the commit and the next round), or already advanced.  A state that is
+  // done or waits for more columns carries over unchanged, and the round
+  // does nothing.  The first wave also places the previous commit's kept
+  // columns (s_pre).
+  if (wave == 0) {
+    const RoundView v =
+        advance_wave(A, A.ctl + ((advanced ? k : k - 1) & 1), !advanced,
+                     !advanced && blockIdx.x == 0 ? A.ctl + (k & 1) : nullptr, nullptr, s_pre);
+    if (lane == 0) {
+      s_view[0] = v.nA;
+      s_view[1] = v.round;
+      s_view[2] = v.fresh_lo;
+      s_view[3] = v.fresh_hi;
+      s_view[4] = v.F;
+      s_view[5] = (int64_t)(v.done | (v.need_more << 1));
+    }
+  }
+  __syncthreads();
+  RoundView c;
+  c.nA = s_view[0];
+  c.round = s_view[1];
+  c.fresh_lo = s_view[2];
+  c.fresh_hi = s_view[3];
+  c.F = s_view[4];
+  c.done = (int32_t)(s_view[5] & 1);
+  c.need_more = (int32_t)(s_view[5] >> 1);
+  c = uniform_view(c);
+  if (c.done || c.need_more) return;  // the commit returns too
+  const int64_t nA = c.nA, round = c.round, fresh_lo = c.fresh_lo, F = c.F;
+  const int64_t items = nA + (c.fresh_hi - fresh_lo);
   int64_t* my_surv = A.surv + blockIdx.x * A.seg;
   if ((int64_t)blockIdx.x * kWalkThreads >= items) {  // nothing for this block
     if (tid == 0) {
@@ -244,7 +450,6 @@ void k_walk(RedArgs A, int64_t n16) {
     }
     return;
   }
-  if (nA > 0 && tid <= nb) s_pre[tid] = A.kpre[tid];
   for (int h = tid; h < kHashSlots; h += kWalkThreads) {
     s_hkey[0][h] = s_hkey[1][h] = kHashEmpty;
     s_hval[0][h] = s_hval[1][h] = kRelNone;
@@ -270,7 +475,6 @@ void k_walk(RedArgs A, int64_t n16) {
   const int64_t Wcap = A.Wcap, seg = A.seg;
   const int64_t stride = (int64_t)gridDim.x * kWalkThreads;
   const uint64_t imask = (1ull << ib) - 1ull;
-  const int lane = tid & 63, wave = tid >> 6;
   uint32_t nsurv = 0;  // this block's survivors so far (same in every thread)
   uint32_t adds = 0, finds = 0, words = 0;  // this lane's counts (a few columns' chains)
   uint64_t fd = kNoValue;  // smallest repeated-low survivor seen by this lane
@@ -423,7 +627,7 @@ void k_walk(RedArgs A, int64_t n16) {
     mine[0] += s_cnt[0];
     mine[1] += s_cnt[1];
     mine[2] += s_cnt[2];
-    if (s_bad) atomicOr(&A.ctl->err, 1);
+    if (s_bad) atomicOr(A.werr, 1);
   }
 }
 
@@ -434,14 +638,14 @@ void k_walk(RedArgs A, int64_t n16) {
 // workgroup's own segment of the next list.  The slot gets the pivots
 // committed, the end of the last one, the first column kept and the number
 // kept.
-__global__ __launch_bounds__(kCommitThreads) void k_commit(RedArgs A) {
+__global__ __launch_bounds__(kCommitThreads) void k_commit(RedArgs A, int64_t k) {
   constexpr int kWaves = kCommitThreads / 64;
   __shared__ uint64_t utmp[kWaves];
   __shared__ int64_t itmp[kWaves];
   const int tid = threadIdx.x;
   const int nb = (int)gridDim.x;
   uint64_t* slot = A.cslot + 4 * (int64_t)blockIdx.x;
-  const RedCtl* ctl = A.ctl;
+  const RedCtl* ctl = A.ctl + (k & 1);  // the state the walk of this round used
   if (ctl->done || ctl->need_more) return;
   const uint32_t cnt = A.scount[blockIdx.x];
   if (cnt == 0) {
@@ -501,86 +705,12 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(RedArgs A) {
   }
 }
 
-// End of a round, one workgroup: the commit slots are reduced (pivots
-// committed, end of the last pivot, first column kept, columns kept), the
-// offsets of the kept segments are written for the next walk, and the
-// state advances.  The window start F is the first column not yet final;
-// the window end never moves back; the width doubles (up to the ring's
-// capacity) while almost every column of a round becomes final and halves
-// (down to the base width) when many stay.  The control block is read once
-// and written once, by one thread.
-__global__ __launch_bounds__(kAdvanceThreads) void k_advance(RedArgs A) {
-  constexpr int kWaves = kAdvanceThreads / 64;
-  __shared__ int64_t itmp[kWaves];
-  __shared__ uint64_t utmp[kWaves];
-  RedCtl* ctl = A.ctl;
-  if (ctl->done || ctl->need_more) {
-    if (A.publish && threadIdx.x == 0) *A.publish = *ctl;
-    return;
-  }
-  const int tid = threadIdx.x;
-  const int nb = A.nblocks;
-  int64_t piv = 0, kept = 0;
-  uint64_t end = 0, stay = kNoValue;
-  if (tid < nb) {
-    const uint64_t* cs = A.cslot + 4 * (int64_t)tid;
-    piv = (int64_t)cs[0];
-    end = cs[1];
-    stay = cs[2];
-    kept = (int64_t)cs[3];
-  }
-  int64_t all_kept = 0;
-  const int64_t before = block_excl_i64<kWaves>(kept, itmp, &all_kept);
-  if (tid < nb) A.kpre[tid] = before;
-  if (tid == 0) A.kpre[nb] = all_kept;
-  piv = block_sum_i64<kWaves>(piv, itmp);
-  end = block_max_u64<kWaves>(end, utmp);
-  stay = block_min_u64<kWaves>(stay, utmp);
-  if (tid != 0) return;
-  const RedCtl c = *ctl;
-  const int64_t n = A.n, E = A.E, Wcap = A.Wcap;
-  const int64_t pivots = c.pivots + piv;
-  const int64_t E_eff = (int64_t)end > c.E_eff ? (int64_t)end : c.E_eff;
-  const int64_t F = stay == kNoValue ? c.Wend : (int64_t)stay;
-  int64_t Wend = c.Wend, width = c.width;
-  int32_t done = 0, need_more = 0, err = c.err;
-  if (pivots >= n - 1) {
-    // Every later column reduces to zero; only columns before the last
-    // pivot still need finishing (for the exact addition count).
-    if (F >= E_eff) done = 1;
-  } else {
-    const int64_t lim = c.E_lim;
-    if (all_kept < width / 256)
-      width = 2 * width < Wcap ? 2 * width : Wcap;
-    else if (all_kept > width / 16)
-      width = width / 2 > c.width_min ? width / 2 : c.width_min;
-    const int64_t want = F + width < lim ? F + width : lim;
-    Wend = want > Wend ? want : Wend;
-    if (F >= lim) {
-      if (lim < E) {
-        need_more = 1;  // the host sorts the next distance range
-      } else {
-        done = 1;
-        err |= 2;
-      }
-    }
-  }
-  RedCtl u = c;
-  u.pivots = pivots;
-  u.E_eff = E_eff;
-  u.width = width;
-  u.done = done;
-  u.need_more = need_more;
-  u.err = err;
-  u.fresh_lo = c.Wend;
-  u.fresh_hi = Wend;
-  u.nA = all_kept;
-  u.F = F;
-  u.Wend = Wend;
-  u.maxWend = Wend > c.maxWend ? Wend : c.maxWend;
-  u.round = c.round + 1;
-  *ctl = u;
-  if (A.publish) *A.publish = u;
+// The state entering round `rounds` on its own, one wave (the walk of that
+// round would form the same), also left in pinned host memory when
+// `publish` is given.
+__global__ __launch_bounds__(64) void k_advance(RedArgs A, int64_t rounds, RedCtl* publish) {
+  __shared__ int64_t pre[kMaxWalkBlocks + 1];
+  (void)advance_wave(A, A.ctl + ((rounds - 1) & 1), true, A.ctl + (rounds & 1), publish, pre);
 }
 
 // Sum of the walk blocks' counter slots into the control block.
@@ -638,7 +768,8 @@ __global__ __launch_bounds__(256) void k_reduce_init(RedArgs A, int64_t E_lim, i
     c.fresh_lo = 0;
     c.fresh_hi = c.Wend;
     c.done = (A.n <= 1 || E_lim == 0) ? 1 : 0;
-    *A.ctl = c;
+    A.ctl[0] = c;
+    *A.werr = 0;
   }
 }
 
@@ -705,8 +836,8 @@ int64_t walk_segment(int64_t Wcap) {
 // copies it in 16-byte pieces), or 0 when n is too large for 16 bits.
 int64_t part16_len(int64_t n) { return n <= kPart16MaxN ? (n + 7) / 8 * 8 : 0; }
 
-hipError_t launch_reduce_extend(const RedArgs& a, int64_t E_lim, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_extend, dim3(1), dim3(1), 0, s, a.ctl, E_lim);
+hipError_t launch_reduce_extend(const RedArgs& a, int64_t E_lim, int64_t rounds, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_extend, dim3(1), dim3(1), 0, s, reduce_state(a, rounds), E_lim);
   return hipGetLastError();
 }
 
@@ -721,36 +852,45 @@ hipError_t launch_reduce_init(const RedArgs& a, int64_t E_lim, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_walk,
-                               RedCtl* publish) {
+hipError_t launch_reduce_round(const RedArgs& a, hipStream_t s, hipEvent_t* ev_walk, int64_t k,
+                               bool advanced) {
   // The LDS table copy of the largest n (64 KB) is beyond the default
   // dynamic LDS limit of a workgroup.
   static const hipError_t attr = hipFuncSetAttribute(
       (const void*)k_walk<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
       (int)(2 * kPart16MaxN));
   if (attr != hipSuccess) return attr;
+  if (k == 0 && !advanced) return hipErrorInvalidValue;  // round 0 starts from the init state
   const int wb = walk_blocks(a.Wcap);
   if (ev_walk) (void)hipEventRecord(ev_walk[0], s);
   const int64_t n16 = a.part16 ? part16_len(a.n) : 0;
+  const int adv = advanced ? 1 : 0;
   if (a.part16)
-    hipLaunchKernelGGL(k_walk<true>, dim3((unsigned)wb), dim3(kWalkThreads), 2 * n16, s, a, n16);
+    hipLaunchKernelGGL(k_walk<true>, dim3((unsigned)wb), dim3(kWalkThreads), 2 * n16, s, a, n16,
+                       k, adv);
   else
-    hipLaunchKernelGGL(k_walk<false>, dim3((unsigned)wb), dim3(kWalkThreads), 0, s, a, n16);
+    hipLaunchKernelGGL(k_walk<false>, dim3((unsigned)wb), dim3(kWalkThreads), 0, s, a, n16, k,
+                       adv);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (ev_walk) (void)hipEventRecord(ev_walk[1], s);
-  hipLaunchKernelGGL(k_commit, dim3((unsigned)wb), dim3(kCommitThreads), 0, s, a);
-  RedArgs adv = a;
-  adv.publish = publish;
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(kAdvanceThreads), 0, s, adv);
+  hipLaunchKernelGGL(k_commit, dim3((unsigned)wb), dim3(kCommitThreads), 0, s, a, k);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_finish(const RedArgs& a, hipStream_t s) {
+hipError_t launch_reduce_advance(const RedArgs& a, int64_t rounds, RedCtl* publish,
+                                 hipStream_t s) {
+  if (rounds < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, a, rounds, publish);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_finish(const RedArgs& a, int64_t rounds, hipStream_t s) {
+  RedCtl* ctl = reduce_state(a, rounds);
   hipLaunchKernelGGL(k_walk_stats, dim3(1), dim3(256), 0, s, a.wstat,
-                     (int64_t)walk_blocks(a.Wcap), a.ctl);
+                     (int64_t)walk_blocks(a.Wcap), ctl);
   hipLaunchKernelGGL(k_overshoot, dim3(scan_blocks(a.Wcap)), dim3(256), 0, s, a.ring, a.Wcap,
-                     a.ctl);
+                     ctl);
   return hipGetLastError();
 }
 
