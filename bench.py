@@ -56,6 +56,12 @@ def parse():
     ap.add_argument("--no-h1", action="store_true")
     ap.add_argument("--h1-only", action="store_true",
                     help="only run the H1 leg (no CPU oracle) and print its JSON")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the batched leg (10,000 clouds, with its roofline) and print "
+                         "its JSON")
+    ap.add_argument("--batched-launches", type=int, default=0, metavar="K",
+                    help="only make K batched launches of the 10,000-cloud workload (after one "
+                         "untimed), nothing else: the command profiled for the batched kernel")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--paper-scaling", action="store_true",
                     help="only run the paper's experiment: N uniform points in [0,1]^2 (on a "
@@ -266,8 +272,10 @@ def bench_batched(torch, ph0, synth, reps=3):
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) / k
     table = ph0.default_tuning()
+    roof = batched_roofline(torch, ph0, x, offsets, pts, out, ws, reps)
     return {
         "workload": "10000 clouds, N uniform in [32,512], d=3 int16, circles or 2-4 blobs, seed 0",
+        "roofline": roof,
         "tuning": ("autotuned table: chunk_mult %s, blocks_per_cu %d"
                    % (list(table.chunk_mult), table.blocks_per_cu)) if table else "built-in",
         "clouds_per_s": 10000 / t_batched,
@@ -277,6 +285,49 @@ def bench_batched(torch, ph0, synth, reps=3):
         "speedup_vs_plain": (10000 / t_batched) * t_plain,
         "edges_total": int(np.sum(np.diff(offsets) * (np.diff(offsets) - 1) // 2)),
     }
+
+
+def batched_roofline(torch, ph0, x, offsets, pts, out, ws, reps):
+    """Roofline of the batched launch on the method's own bytes: every cloud
+    sorts at least its keys up to its last pivot (E_eff of them, from the
+    single-cloud path's statistics), 8 B written and P passes of 8 B read +
+    8 B written each, P = ceil(b / 8) for the b distance bits of the cloud's
+    coordinate ranges (as the kernel sorts).  The launch is timed with events
+    on the stream it runs on."""
+    import numpy as np
+
+    alg = 0
+    e_eff = 0
+    pws = ph0.alloc_workspace(512, 3, pts.dtype, "cuda:0")
+    pout = torch.empty((512, 2), dtype=torch.int32, device="cuda:0")
+    for c in range(len(offsets) - 1):
+        lo, hi = int(offsets[c]), int(offsets[c + 1])
+        _, st = ph0.ph0_barcodes_device(x[lo:hi], out=pout[: hi - lo], workspace=pws,
+                                        with_stats=True)
+        span = pts[lo:hi].astype(np.int64)
+        bound = int(((span.max(0) - span.min(0)) ** 2).sum())
+        passes = (max(bound, 1).bit_length() + 7) // 8
+        alg += 8 * st["E_eff"] * (1 + 2 * passes)
+        e_eff += st["E_eff"]
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(reps):
+        ev0.record(stream)
+        ph0.ph0_barcodes_batched_device(x, offsets, out=out, workspace=ws)
+        ev1.record(stream)
+        ev1.synchronize()
+        best = min(best, ev0.elapsed_time(ev1) / 1e3)
+    achieved = alg / best / 1e9
+    traffic = measured_traffic("batched", "batch10000_d3_i16")
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(achieved / 8000.0, 5), "traffic": traffic,
+            "basis": "8 B x E_eff x (1 + 2P) per cloud over the whole launch (best of %d, "
+                     "events on its stream); sum E_eff = %d" % (reps, e_eff),
+            "algorithmic_bytes": int(alg), "launch_s": round(best, 6)}
+    if traffic is not None:
+        roof["traffic_gbs"] = round(traffic / best / 1e9, 1)
+    return roof
 
 
 H1_N = 256
@@ -375,7 +426,8 @@ def bench_serving(ph0, synth, count, warm=200):
     }
 
 
-KERNEL_SOURCES = {"reduce_walk": "reduce.hip", "radix_pass": "radix.hip"}
+KERNEL_SOURCES = {"reduce_walk": "reduce.hip", "radix_pass": "radix.hip",
+                  "batched": "batched.hip"}
 
 
 def measured_traffic(kernel, workload):
@@ -466,6 +518,21 @@ def main():
     if args.h1_only:
         print(json.dumps({"mode": "h1", **bench_h1(torch, ph0, synth, False,
                                                   reps=max(args.steps, 1))}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"mode": "batched", **bench_batched(torch, ph0, synth)}), flush=True)
+        return
+    if args.batched_launches:
+        bpts, boffs = synth.batch_clouds(count=10000, seed=0)
+        bx = torch.from_numpy(bpts).to("cuda:0")
+        bout = torch.empty((bpts.shape[0], 2), dtype=torch.int32, device="cuda:0")
+        bws = torch.empty(ph0.ph0_batched_workspace_bytes(boffs, 3, bpts.dtype),
+                          dtype=torch.uint8, device="cuda:0")
+        for _ in range(args.batched_launches + 1):
+            ph0.ph0_barcodes_batched_device(bx, boffs, out=bout, workspace=bws)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "batched-launches", "launches": args.batched_launches + 1}),
+              flush=True)
         return
     pts = synth.workload(args.workload, seed=args.seed)
     n, d = pts.shape

@@ -146,13 +146,17 @@ int ph0_key_layout(int64_t n, int32_t d, ph0_dtype dt, int32_t* index_bits,
 
 /* Speed-only tuning of the batched path (never changes results).  A zero
  * field takes the built-in value; the built-in values (chunk_mult 6, 6, 8,
- * 48; two workgroups per CU) are those the package's autotuner
- * (paper_2203_02527_amd/autotune.py) measured best on MI355X, which writes
- * them to a table the Python binding passes by default. */
+ * 48; two workgroups per CU; 8-bit digits; 8 waves per cloud) are those the
+ * package's autotuner (paper_2203_02527_amd/autotune.py) measured best on
+ * MI355X, which writes them to a table the Python binding passes by
+ * default.  digit_bits outside 0..8 or waves_per_cloud other than 0, 8 or 16
+ * is EINVAL. */
 typedef struct {
-  int32_t chunk_mult[4];  /* first sorted chunk holds about chunk_mult * n edges,
-                             per cloud size bucket n <= 64, <= 128, <= 256, <= 512 */
-  int32_t blocks_per_cu;  /* workgroups launched per compute unit (1 or 2) */
+  int32_t chunk_mult[4];    /* first sorted chunk holds about chunk_mult * n edges,
+                               per cloud size bucket n <= 64, <= 128, <= 256, <= 512 */
+  int32_t blocks_per_cu;    /* workgroups launched per compute unit (1 or 2) */
+  int32_t digit_bits;       /* digit width of the chunk's radix passes (1..8) */
+  int32_t waves_per_cloud;  /* waves of the workgroup that runs a cloud (8 or 16) */
 } ph0_batch_tuning;
 
 /* Device workspace for ph0_barcodes_batched_device on these clouds.
@@ -181,8 +185,9 @@ int ph0_barcodes_batched_device(const void* d_points, ph0_dtype dt, const int64_
  * ph0_barcodes_batched_device, copies out and frees everything before it
  * returns.  tune_json (NULL = built-in table) is a JSON object with only the
  * members "chunk_mult" (up to four non-negative integers, per size bucket as
- * in ph0_batch_tuning) and "blocks_per_cu" (a non-negative integer); zero
- * means built-in.  Any other member, or malformed text, is EINVAL before any
+ * in ph0_batch_tuning), "blocks_per_cu", "digit_bits" and "waves_per_cloud"
+ * (non-negative integers, ranges as in ph0_batch_tuning); zero means
+ * built-in.  Any other member, or malformed text, is EINVAL before any
  * device call.  `st` may be NULL.  Errors as ph0_barcodes_batched_device, and
  * ENOMEM when the device allocation fails. */
 int ph0_barcodes_batched(const void* points, ph0_dtype dt, const int64_t* offsets,

@@ -25,8 +25,6 @@ namespace ph0 {
 
 namespace {
 
-constexpr int kThreads = 512;
-constexpr int kWaves = kThreads / 64;
 constexpr int kMaxN = kBatchMaxN;
 constexpr int kMaxPts = kBatchMaxPts;
 constexpr int kBins = 1024;
@@ -34,6 +32,9 @@ constexpr int kWindow = 2048;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kActiveB = 0, kFinal = 1;
 
+// Per-workgroup LDS; kWaves waves per workgroup (the radix pass keeps one
+// digit histogram per wave).
+template <int kWaves>
 struct Shared {
   int16_t pts[kMaxPts];
   int16_t part[kMaxN];
@@ -52,6 +53,7 @@ struct Shared {
   uint64_t s_bound;
 };
 
+template <int kWaves>
 __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* tmp, uint32_t* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t x = v;
@@ -94,7 +96,8 @@ __device__ inline void edge_advance(int* j, int* i, int step) {
   *j = jj;
 }
 
-__device__ inline uint64_t sqdist(const Shared& S, int d, int i, int j) {
+template <class SH>
+__device__ inline uint64_t sqdist(const SH& S, int d, int i, int j) {
   uint64_t s = 0;
   for (int k = 0; k < d; ++k) {
     const int64_t df = (int64_t)S.pts[i * d + k] - (int64_t)S.pts[j * d + k];
@@ -103,9 +106,12 @@ __device__ inline uint64_t sqdist(const Shared& S, int d, int i, int j) {
   return s;
 }
 
-// One stable LSD pass of `cnt` keys in src -> dst on digit (key >> shift).
-__device__ void block_radix_pass(Shared& S, const uint64_t* src, uint64_t* dst, int64_t cnt,
-                                 int shift, int bits) {
+// One stable LSD pass of `cnt` keys in src -> dst on digit (key >> shift)
+// of `bits` <= 8 bits.
+template <int kThreads>
+__device__ void block_radix_pass(Shared<kThreads / 64>& S, const uint64_t* src, uint64_t* dst,
+                                 int64_t cnt, int shift, int bits) {
+  constexpr int kWaves = kThreads / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t nb = 1u << bits, dmask = nb - 1u;
   if (tid < 256) S.digit_base[tid] = 0;
@@ -115,7 +121,7 @@ __device__ void block_radix_pass(Shared& S, const uint64_t* src, uint64_t* dst, 
   __syncthreads();
   {
     const uint32_t v = tid < 256 ? S.digit_base[tid] : 0;
-    const uint32_t ex = block_excl_scan(v, S.scan_tmp, nullptr);
+    const uint32_t ex = block_excl_scan<kWaves>(v, S.scan_tmp, nullptr);
     if (tid < 256) S.digit_base[tid] = ex;
   }
   __syncthreads();
@@ -161,8 +167,9 @@ __device__ inline uint32_t benc(int round, int pos) {
 // Reduce the sorted chunk keys[0..cnt) (grades in gr) against the LDS table.
 // `round` runs on across the chunks of one cloud: the per-row minima are
 // tagged with it, so a value left by an earlier round never matches.
-__device__ void reduce_chunk(Shared& S, const uint64_t* keys, const uint32_t* gr, int64_t cnt,
-                             int n, int ib, int* err, int& round) {
+template <int kThreads>
+__device__ void reduce_chunk(Shared<kThreads / 64>& S, const uint64_t* keys, const uint32_t* gr,
+                             int64_t cnt, int n, int ib, int* err, int& round) {
   const int tid = threadIdx.x;
   const uint64_t imask = (1ull << ib) - 1ull;
   int64_t next = 0;
@@ -279,7 +286,7 @@ __device__ void reduce_chunk(Shared& S, const uint64_t* keys, const uint32_t* gr
         kpos = S.wpos[s];
       }
       uint32_t tot;
-      const uint32_t ex = block_excl_scan(k ? 1u : 0u, S.scan_tmp, &tot);
+      const uint32_t ex = block_excl_scan<kThreads / 64>(k ? 1u : 0u, S.scan_tmp, &tot);
       __syncthreads();
       if (k) {
         const int dsts = (int)(keep + ex);
@@ -308,10 +315,11 @@ __device__ void reduce_chunk(Shared& S, const uint64_t* keys, const uint32_t* gr
   __syncthreads();
 }
 
-template <typename T>
+template <typename T, int kThreads>
 __global__ __launch_bounds__(kThreads) void k_batched(BatchArgs A) {
+  constexpr int kWaves = kThreads / 64;
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  Shared& S = *reinterpret_cast<Shared*>(smem);
+  Shared<kWaves>& S = *reinterpret_cast<Shared<kWaves>*>(smem);
   const int tid = threadIdx.x;
   const int d = A.d;
   uint64_t* bufA = A.scratch + (int64_t)blockIdx.x * 2 * A.emax;
@@ -433,7 +441,7 @@ __global__ __launch_bounds__(kThreads) void k_batched(BatchArgs A) {
           key = (dl << (2 * ib)) | ((uint64_t)j << ib) | (uint64_t)i;
         }
         uint32_t tot;
-        const uint32_t ex = block_excl_scan(in ? 1u : 0u, S.scan_tmp, &tot);
+        const uint32_t ex = block_excl_scan<kWaves>(in ? 1u : 0u, S.scan_tmp, &tot);
         if (in) bufA[cnt + ex] = key;
         cnt += tot;
       }
@@ -441,9 +449,10 @@ __global__ __launch_bounds__(kThreads) void k_batched(BatchArgs A) {
       // LSD passes over the distance bits that vary inside the chunk.
       uint64_t* src = bufA;
       uint64_t* dst = bufB;
-      for (int sh = 0; sh < dbits; sh += 8) {
-        const int bits = dbits - sh < 8 ? dbits - sh : 8;
-        block_radix_pass(S, src, dst, cnt, 2 * ib + sh, bits);
+      const int db = A.digit_bits;
+      for (int sh = 0; sh < dbits; sh += db) {
+        const int bits = dbits - sh < db ? dbits - sh : db;
+        block_radix_pass<kThreads>(S, src, dst, cnt, 2 * ib + sh, bits);
         uint64_t* t = src;
         src = dst;
         dst = t;
@@ -455,13 +464,13 @@ __global__ __launch_bounds__(kThreads) void k_batched(BatchArgs A) {
         uint32_t f = 0;
         if (p < cnt) f = (p == 0) || ((src[p] >> (2 * ib)) != (src[p - 1] >> (2 * ib)));
         uint32_t tot;
-        const uint32_t ex = block_excl_scan(f, S.scan_tmp, &tot);
+        const uint32_t ex = block_excl_scan<kWaves>(f, S.scan_tmp, &tot);
         if (p < cnt) gr[p] = run + ex + f;
         run += tot;
       }
       distinct = run;
       __syncthreads();
-      reduce_chunk(S, src, gr, cnt, n, ib, &err, round);
+      reduce_chunk<kThreads>(S, src, gr, cnt, n, ib, &err, round);
       bin_lo = bin_hi;
     }
     if (err) A.errs[c] = err;
@@ -495,23 +504,30 @@ __global__ __launch_bounds__(kThreads) void k_batched(BatchArgs A) {
 
 }  // namespace
 
-size_t batched_shared_bytes() { return sizeof(Shared); }
+size_t batched_shared_bytes(int threads) {
+  return threads == 1024 ? sizeof(Shared<16>) : sizeof(Shared<8>);
+}
+
+namespace {
+template <typename T, int kThreads>
+hipError_t launch_batched_t(const BatchArgs& a, int blocks, hipStream_t s) {
+  const size_t shm = sizeof(Shared<kThreads / 64>);
+  const hipError_t e = hipFuncSetAttribute((const void*)k_batched<T, kThreads>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_batched<T, kThreads>), dim3(blocks), dim3(kThreads), shm, s, a);
+  return hipGetLastError();
+}
+}  // namespace
 
 hipError_t launch_batched(const BatchArgs& a, int blocks, hipStream_t s) {
-  const size_t shm = sizeof(Shared);
-  hipError_t e;
-  if (a.elem_bytes == 1) {
-    e = hipFuncSetAttribute((const void*)k_batched<int8_t>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batched<int8_t>, dim3(blocks), dim3(kThreads), shm, s, a);
-  } else {
-    e = hipFuncSetAttribute((const void*)k_batched<int16_t>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batched<int16_t>, dim3(blocks), dim3(kThreads), shm, s, a);
-  }
-  return hipGetLastError();
+  if (a.digit_bits < 1 || a.digit_bits > 8 || (a.threads != 512 && a.threads != 1024))
+    return hipErrorInvalidValue;
+  if (a.elem_bytes == 1)
+    return a.threads == 1024 ? launch_batched_t<int8_t, 1024>(a, blocks, s)
+                             : launch_batched_t<int8_t, 512>(a, blocks, s);
+  return a.threads == 1024 ? launch_batched_t<int16_t, 1024>(a, blocks, s)
+                           : launch_batched_t<int16_t, 512>(a, blocks, s);
 }
 
 }  // namespace ph0

@@ -53,6 +53,8 @@ constexpr int32_t kChunkMult[4] = {6, 6, 8, 48};
 // Built-in workgroups per compute unit of the batched kernel (two fit the
 // 160 KB of LDS of a CU).
 constexpr int32_t kBlocksPerCu = 2;
+constexpr int32_t kDigitBits = 8;      // batched radix digit width
+constexpr int32_t kWavesPerCloud = 8;  // batched workgroup: 512 threads
 // Edge count from which the single-cloud path recomputes keys per distance
 // range instead of storing all of them (below it, the extra passes and host
 // round trips cost more than the stored keys).
@@ -851,6 +853,12 @@ int plan_batch(const int64_t* offsets, int64_t nclouds, int32_t d, ph0_dtype dt,
   if (d < 1) return fail(PH0_EINVAL, "d must be >= 1");
   if (dt != PH0_I8 && dt != PH0_I16) return fail(PH0_EINVAL, "dtype must be PH0_I8 or PH0_I16");
   if (offsets[0] != 0) return fail(PH0_EINVAL, "offsets[0] must be 0");
+  if (tune && (tune->digit_bits < 0 || tune->digit_bits > 8))
+    return fail(PH0_EINVAL, "tuning: digit_bits must be 0..8 (got %d)", tune->digit_bits);
+  if (tune && tune->waves_per_cloud != 0 && tune->waves_per_cloud != 8 &&
+      tune->waves_per_cloud != 16)
+    return fail(PH0_EINVAL, "tuning: waves_per_cloud must be 0, 8 or 16 (got %d)",
+                tune->waves_per_cloud);
   P->nclouds = nclouds;
   std::vector<std::pair<int64_t, int32_t>> bysize;
   for (int64_t c = 0; c < nclouds; ++c) {
@@ -1095,6 +1103,8 @@ int batched_run(const void* d_points, ph0_dtype dt, const int64_t* offsets, int6
     A.errs = reinterpret_cast<int32_t*>(ws + P.errs);
     for (int b = 0; b < 4; ++b)
       A.chunk_mult[b] = tune && tune->chunk_mult[b] > 0 ? tune->chunk_mult[b] : kChunkMult[b];
+    A.digit_bits = tune && tune->digit_bits > 0 ? tune->digit_bits : kDigitBits;
+    A.threads = 64 * (tune && tune->waves_per_cloud > 0 ? tune->waves_per_cloud : kWavesPerCloud);
     HIPCHK(launch_batched(A, (int)P.blocks, s));
   }
   tm.mark();
@@ -1352,9 +1362,10 @@ int ph0_h1_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, ph0_
 namespace {
 
 // Tuning text of ph0_barcodes_batched: a JSON object whose only members are
-// "chunk_mult" (an array of up to four non-negative integers) and
-// "blocks_per_cu" (a non-negative integer), e.g.
-//   {"chunk_mult": [6, 6, 8, 48], "blocks_per_cu": 2}
+// "chunk_mult" (an array of up to four non-negative integers),
+// "blocks_per_cu", "digit_bits" and "waves_per_cloud" (non-negative
+// integers), e.g.
+//   {"chunk_mult": [6, 6, 8, 48], "blocks_per_cu": 2, "digit_bits": 8, "waves_per_cloud": 8}
 // Anything else is rejected, so a misspelt key cannot pass silently.
 struct JsonCursor {
   const char* p;
@@ -1414,6 +1425,12 @@ int parse_tuning(const char* text, ph0_batch_tuning* t) {
     } else if (!strcmp(k, "blocks_per_cu")) {
       if (!c.integer(&t->blocks_per_cu))
         return fail(PH0_EINVAL, "tuning: blocks_per_cu must be a non-negative integer");
+    } else if (!strcmp(k, "digit_bits")) {
+      if (!c.integer(&t->digit_bits))
+        return fail(PH0_EINVAL, "tuning: digit_bits must be a non-negative integer");
+    } else if (!strcmp(k, "waves_per_cloud")) {
+      if (!c.integer(&t->waves_per_cloud))
+        return fail(PH0_EINVAL, "tuning: waves_per_cloud must be a non-negative integer");
     } else {
       return fail(PH0_EINVAL, "tuning: unknown key \"%s\"", k);
     }

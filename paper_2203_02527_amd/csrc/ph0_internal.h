@@ -246,8 +246,11 @@ struct BatchArgs {
                             // size buckets b: n <= 64, <= 128, <= 256, <= 512
   int64_t single_n = 0;     // > 0: one cloud of single_n rows, one workgroup, no queue,
                             // offsets or order; its status always goes to errs[0]
+  int32_t digit_bits = 8;   // digit width of the chunk's radix passes (1..8)
+  int32_t threads = 512;    // workgroup size: 512 or 1024 (8 or 16 waves per cloud)
 };
-size_t batched_shared_bytes();
+// LDS bytes of one batched workgroup of `threads` threads.
+size_t batched_shared_bytes(int threads);
 hipError_t launch_batched(const BatchArgs& a, int blocks, hipStream_t s);
 
 // H1: reduction of the edge-by-triangle boundary matrix (h1.hip).

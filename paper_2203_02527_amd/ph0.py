@@ -331,14 +331,18 @@ def ph0_sorted_keys_device(points, workspace=None, stream=None):
 
 
 class ph0_batch_tuning(ctypes.Structure):
-    _fields_ = [("chunk_mult", ctypes.c_int32 * 4), ("blocks_per_cu", ctypes.c_int32)]
+    _fields_ = [("chunk_mult", ctypes.c_int32 * 4), ("blocks_per_cu", ctypes.c_int32),
+                ("digit_bits", ctypes.c_int32), ("waves_per_cloud", ctypes.c_int32)]
 
 
-def make_tuning(chunk_mult=(0, 0, 0, 0), blocks_per_cu=0) -> ph0_batch_tuning:
+def make_tuning(chunk_mult=(0, 0, 0, 0), blocks_per_cu=0, digit_bits=0,
+                waves_per_cloud=0) -> ph0_batch_tuning:
     t = ph0_batch_tuning()
     for k, v in enumerate(chunk_mult):
         t.chunk_mult[k] = int(v)
     t.blocks_per_cu = int(blocks_per_cu)
+    t.digit_bits = int(digit_bits)
+    t.waves_per_cloud = int(waves_per_cloud)
     return t
 
 
@@ -353,8 +357,9 @@ def default_tuning():
         from . import autotune
 
         t = autotune.load()
-        _default_tuning = (False,) if t is None else (True, make_tuning(t["chunk_mult"],
-                                                                      t["blocks_per_cu"]))
+        _default_tuning = (False,) if t is None else (
+            True, make_tuning(t["chunk_mult"], t["blocks_per_cu"], t.get("digit_bits", 0),
+                              t.get("waves_per_cloud", 0)))
     return _default_tuning[1] if _default_tuning[0] else None
 
 
@@ -426,7 +431,8 @@ def _default_tune_json():
     t = default_tuning()
     if t is None:
         return None
-    return json.dumps({"chunk_mult": list(t.chunk_mult), "blocks_per_cu": t.blocks_per_cu})
+    return json.dumps({"chunk_mult": list(t.chunk_mult), "blocks_per_cu": t.blocks_per_cu,
+                       "digit_bits": t.digit_bits, "waves_per_cloud": t.waves_per_cloud})
 
 
 def ph0_barcodes_batched(points: np.ndarray, offsets, tune_json=None, with_stats=False):

@@ -68,9 +68,15 @@ def test_tuning_table_loader(tmp_path):
     good = tmp_path / "good.json"
     good.write_text('{"chunk_mult": [8, 12, 16, 24], "blocks_per_cu": 1}')
     assert autotune.load(str(good))["chunk_mult"] == [8, 12, 16, 24]
+    ok = tmp_path / "ok.json"
+    ok.write_text('{"chunk_mult": [8, 12, 16, 24], "blocks_per_cu": 2, "waves_per_cloud": 16, '
+                  '"digit_bits": 6}')
+    assert autotune.load(str(ok))["digit_bits"] == 6
     for bad in ('{"chunk_mult": [8, 12, 16], "blocks_per_cu": 1}',
                 '{"chunk_mult": [8, 12, 16, 0], "blocks_per_cu": 1}',
-                '{"chunk_mult": [8, 12, 16, 24], "blocks_per_cu": 3}'):
+                '{"chunk_mult": [8, 12, 16, 24], "blocks_per_cu": 3}',
+                '{"chunk_mult": [8, 12, 16, 24], "blocks_per_cu": 2, "waves_per_cloud": 12}',
+                '{"chunk_mult": [8, 12, 16, 24], "blocks_per_cu": 2, "digit_bits": 9}'):
         p = tmp_path / "bad.json"
         p.write_text(bad)
         with pytest.raises(ValueError):
@@ -98,7 +104,8 @@ def test_batched_host_entry_rejects_bad_tuning_text_before_device_use():
     offsets = np.array([0, 2, 6], np.int64)
     for bad in ('', '[]', '{"chunk_mult": [1, 2, 3, 4, 5]}', '{"chunk_mult": [-1]}',
                 '{"blocks": 1}', '{"blocks_per_cu": 1,}', '{"blocks_per_cu": 1} x',
-                '{"chunk_mult": [1, 2', '{"chunk_mult"'):
+                '{"chunk_mult": [1, 2', '{"chunk_mult"', '{"digit_bits": 9}',
+                '{"waves_per_cloud": 12}', '{"waves_per_cloud": -8}'):
         with pytest.raises(ph0.Ph0Error) as ei:
             ph0.ph0_barcodes_batched(pts, offsets, tune_json=bad)
         assert ei.value.code == -1, bad

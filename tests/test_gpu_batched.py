@@ -100,6 +100,11 @@ def test_results_do_not_depend_on_tuning(torch):
         t = ph0.make_tuning(chunk_mult=(mult,) * 4)
         got = _run(torch, pts, offsets, tuning=t)
         np.testing.assert_array_equal(got, ref)
+    # digit width of the chunk sort and waves per cloud
+    for bits, waves in ((5, 8), (7, 8), (8, 16), (6, 16)):
+        t = ph0.make_tuning(chunk_mult=(2,) * 4, digit_bits=bits, waves_per_cloud=waves)
+        got = _run(torch, pts, offsets, tuning=t)
+        np.testing.assert_array_equal(got, ref)
 
 
 def test_full_batch_workload(torch):
@@ -122,6 +127,8 @@ def test_autotuner_finds_valid_table(torch, tmp_path):
     t = autotune.tune(clouds=40, reps=1, log=lambda m: None)
     assert len(t["chunk_mult"]) == 4 and all(m in autotune.MULTS for m in t["chunk_mult"])
     assert t["blocks_per_cu"] in autotune.BLOCKS_PER_CU
+    assert t["waves_per_cloud"] in autotune.WAVES_PER_CLOUD
+    assert t["digit_bits"] in autotune.DIGIT_BITS
     p = tmp_path / "t.json"
     import json
 
