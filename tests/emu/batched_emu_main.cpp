@@ -19,8 +19,8 @@ int main(int argc, char** argv) {
   if (argc != 3) return 2;
   FILE* f = fopen(argv[1], "rb");
   if (!f) return 2;
-  int64_t hdr[8];  // nclouds, d, elem_bytes, blocks, chunk_mult[4]
-  if (fread(hdr, 8, 8, f) != 8) return 2;
+  int64_t hdr[10];  // nclouds, d, elem_bytes, blocks, chunk_mult[4], digit_bits, threads
+  if (fread(hdr, 8, 10, f) != 10) return 2;
   const int64_t nclouds = hdr[0], d = hdr[1], eb = hdr[2], blocks = hdr[3];
   std::vector<int64_t> offsets(nclouds + 1);
   if (fread(offsets.data(), 8, nclouds + 1, f) != (size_t)(nclouds + 1)) return 2;
@@ -73,6 +73,8 @@ int main(int argc, char** argv) {
   A.queue = &queue;
   A.errs = errs.data();
   for (int b = 0; b < 4; ++b) A.chunk_mult[b] = (int32_t)hdr[4 + b];
+  A.digit_bits = (int32_t)hdr[8];
+  A.threads = (int32_t)hdr[9];
   if (!order.empty() && launch_batched(A, (int)blocks, nullptr) != hipSuccess) return 3;
 
   FILE* g = fopen(argv[2], "wb");

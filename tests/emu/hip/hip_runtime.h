@@ -31,7 +31,7 @@ struct dim3 {
 typedef int hipError_t;
 typedef void* hipStream_t;
 typedef void* hipEvent_t;
-enum { hipSuccess = 0, hipErrorUnknown = 1 };
+enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorUnknown = 999 };
 enum { hipFuncAttributeMaxDynamicSharedMemorySize = 8 };
 
 namespace emu {

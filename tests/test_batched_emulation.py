@@ -10,7 +10,8 @@ and runs two workgroups on clouds that cover the kernel's edge cases: n = 0,
 1 and 2, all distances zero, heavy ties, the largest fused cloud (n = 512),
 wide int16 coordinates, with the built-in chunk multipliers, with 1 (many
 chunks per cloud) and with 1000 (every edge in the first chunk: the most
-scratch a cloud uses).  Every barcode must equal the oracle's, and the run must end (a
+scratch a cloud uses), and with 1024-thread workgroups sorting on 5-bit
+digits.  Every barcode must equal the oracle's, and the run must end (a
 loop that does not end fails the test by its time limit).  CPU only."""
 import os
 import re
@@ -66,7 +67,9 @@ def checked_source() -> str:
                 t = "Chk<%s, %s>" % (t, dim)
             out.append("%s%s %s;" % (ind, t, name))
     src = src[:a] + "\n".join(out) + src[b:]
-    src = src.replace("struct Shared {", CHECKED + "struct Shared {", 1)
+    head = "template <int kWaves>\nstruct Shared {"
+    assert head in src
+    src = src.replace(head, CHECKED + head, 1)
     old = "extern __shared__ __attribute__((aligned(16))) char smem[];"
     assert old in src
     src = src.replace(old, "char* smem = emu_block_smem();")
@@ -106,15 +109,15 @@ def emulator(tmp_path_factory):
     return exe, d
 
 
-def _run(emulator, clouds, chunk_mult, blocks=2):
+def _run(emulator, clouds, chunk_mult, blocks=2, digit_bits=8, threads=512):
     exe, d = emulator
     offsets = np.zeros(len(clouds) + 1, np.int64)
     offsets[1:] = np.cumsum([c.shape[0] for c in clouds])
     pts = np.ascontiguousarray(np.concatenate(clouds, axis=0))
     inp, outp = d / "in.bin", d / "out.bin"
     with open(inp, "wb") as f:
-        np.array([len(clouds), pts.shape[1], pts.dtype.itemsize, blocks, *chunk_mult],
-                 np.int64).tofile(f)
+        np.array([len(clouds), pts.shape[1], pts.dtype.itemsize, blocks, *chunk_mult,
+                  digit_bits, threads], np.int64).tofile(f)
         offsets.tofile(f)
         pts.tofile(f)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
@@ -129,10 +132,13 @@ def _run(emulator, clouds, chunk_mult, blocks=2):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("chunk_mult", [(6, 6, 8, 48), (1, 1, 1, 1), (1000, 1000, 1000, 1000)])
-def test_fused_kernel_edge_cases_on_cpu(emulator, chunk_mult):
+@pytest.mark.parametrize("chunk_mult,digit_bits,threads", [
+    ((6, 6, 8, 48), 8, 512), ((1, 1, 1, 1), 8, 512), ((1000, 1000, 1000, 1000), 8, 512),
+    ((1, 1, 1, 1), 5, 1024)])
+def test_fused_kernel_edge_cases_on_cpu(emulator, chunk_mult, digit_bits, threads):
     clouds = _clouds()
-    bars, errs, offsets, pts = _run(emulator, clouds, chunk_mult)
+    bars, errs, offsets, pts = _run(emulator, clouds, chunk_mult, digit_bits=digit_bits,
+                                    threads=threads)
     assert not errs.any(), errs
     for c in range(len(clouds)):
         lo, hi = int(offsets[c]), int(offsets[c + 1])
