@@ -359,13 +359,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_waves(
   __shared__ __attribute__((aligned(16))) int8_t xs[2][kTile][kRow];
   __shared__ __attribute__((aligned(16))) int32_t nrm[2][kTile];
   __shared__ uint32_t lh[kHist ? kHistBins : 1];
-  __shared__ __attribute__((aligned(16))) uint32_t half_cnt[kTile][2];  // kept keys per (row, half of the tile's i)
+  // Kept keys of each wave's rows in the tile: hcp[wave][r] holds the count
+  // of accumulator r's lower half-wave row in its low 16 bits and that of
+  // its upper half-wave row in its high 16 bits (32 i each).
+  __shared__ __attribute__((aligned(16))) uint32_t hcp[4][16];
   __shared__ __attribute__((aligned(16))) uint32_t rbase[kTile];  // emit: colex base of each row's kept keys
   // emit: each wave's queue of kept keys (delta << 32 | r << 6 | lane) for
   // one half of its accumulators, and where each r's entries start
   constexpr int kQueue = MODE == kKeysEmit ? 512 : 1;
   __shared__ uint64_t q_keys[4][kQueue];
-  __shared__ uint32_t q_start[4][16];
+  __shared__ __attribute__((aligned(16))) uint32_t q_start[4][16];
+  // Kept keys of tile row jl (0..63) in the i-half `sub` (the wave jl / 32 * 2 + sub).
+  auto row_count = [&](int jl, int sub) -> uint32_t {
+    const int o = jl & 31, r = 4 * (o >> 3) + (o & 3);
+    return (hcp[(jl >> 5) * 2 + sub][r] >> (16 * ((o >> 2) & 1))) & 0xFFFFu;
+  };
   if (kHist) hist_zero(lh);
   const int hs = kHist && kp.hist_shift_dev ? *kp.hist_shift_dev : kp.hist_shift;
 
@@ -429,17 +437,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_waves(
     const int64_t i0 = (int64_t)cur.I * kTile, j0 = (int64_t)cur.J * kTile;
     const bool seg_first = cur.I == cur.I0, seg_last = cur.I + 1 == cur.I1;
     v16i c;
+    if constexpr (!ahead) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) c[r] = 0;
+      for (int r = 0; r < 16; ++r) c[r] = 0;
+    }
     __syncthreads();  // the previous tile's readers of LDS are done
     if constexpr (MODE == kKeysEmit) {
       // The row's next output position: its segment base, advanced by the
-      // previous tile's kept keys (still in half_cnt).
+      // previous tile's kept keys (still in hcp).
       if (threadIdx.x < kTile) {
         if (seg_first)
           row_acc = ahead ? pre_rb : kp.cnt[count_slot(cur, threadIdx.x)];
         else
-          row_acc += half_cnt[threadIdx.x][0] + half_cnt[threadIdx.x][1];
+          row_acc += row_count(threadIdx.x, 0) + row_count(threadIdx.x, 1);
         rbase[threadIdx.x] = row_acc;
       }
     }
@@ -460,13 +470,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_waves(
         side_load(nxt);
       }
       __syncthreads();
-      const int kpad = segs1 * 16;
-      for (int kk = 0; kk < kpad; kk += 32) {
-        const v4i a = *reinterpret_cast<const v4i*>(
-            &xs[1][jsub * 32 + (lane & 31)][kk + 16 * (lane >> 5)]);
-        const v4i b = *reinterpret_cast<const v4i*>(
-            &xs[0][isub * 32 + (lane & 31)][kk + 16 * (lane >> 5)]);
-        c = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+      // d <= 64: one or two 32-deep products, the first from a zero accumulator.
+      const v16i zero = {};
+      const v4i a0 = *reinterpret_cast<const v4i*>(&xs[1][jsub * 32 + (lane & 31)][16 * (lane >> 5)]);
+      const v4i b0 = *reinterpret_cast<const v4i*>(&xs[0][isub * 32 + (lane & 31)][16 * (lane >> 5)]);
+      c = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, zero, 0, 0, 0);
+      if (segs1 > 2) {
+        const v4i a1 =
+            *reinterpret_cast<const v4i*>(&xs[1][jsub * 32 + (lane & 31)][32 + 16 * (lane >> 5)]);
+        const v4i b1 =
+            *reinterpret_cast<const v4i*>(&xs[0][isub * 32 + (lane & 31)][32 + 16 * (lane >> 5)]);
+        c = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, c, 0, 0, 0);
       }
     }
     for (int k0 = 0; k0 < (ahead ? 0 : d); k0 += KMAX) {
@@ -531,6 +545,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_waves(
 #pragma unroll
       for (int hf = 0; hf < 2; ++hf) {
         uint32_t wq = 0;  // emit: this wave's queued keys of this half
+        uint32_t pk[8], qs[8];  // packed row counts and queue starts of r = 8 hf + 0..7
 #pragma unroll
         for (int qq = 0; qq < 2; ++qq) {
           const int q = 2 * hf + qq;
@@ -552,12 +567,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_waves(
             } else {
               const bool kept = valid && delta - dlo32 < span32;
               const uint64_t m = __ballot(kept);
-              const uint32_t hc = half ? (uint32_t)__popc((uint32_t)(m >> 32))
-                                       : (uint32_t)__popc((uint32_t)m);
-              if ((lane & 31) == 0) {
-                half_cnt[jl][isub] = hc;
-                if (MODE == kKeysEmit && lane == 0) q_start[wave][r] = wq;
-              }
+              pk[r - 8 * hf] = (uint32_t)__popc((uint32_t)m) |
+                               ((uint32_t)__popc((uint32_t)(m >> 32)) << 16);
+              qs[r - 8 * hf] = wq;
               if constexpr (MODE == kKeysEmit) {
                 if (kept) {
                   const uint32_t at =
@@ -570,8 +582,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_waves(
             }
           }
         }
+        if constexpr (!kHist) {
+          if (lane == 0) {
+            uint4* hp = reinterpret_cast<uint4*>(&hcp[wave][8 * hf]);
+            hp[0] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+            hp[1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
+            if (MODE == kKeysEmit) {
+              uint4* qp = reinterpret_cast<uint4*>(&q_start[wave][8 * hf]);
+              qp[0] = make_uint4(qs[0], qs[1], qs[2], qs[3]);
+              qp[1] = make_uint4(qs[4], qs[5], qs[6], qs[7]);
+            }
+          }
+        }
         if constexpr (MODE == kKeysEmit) {
-          __syncthreads();  // every wave's half_cnt of this half is in LDS
+          __syncthreads();  // every wave's counts of this half are in LDS
           for (uint32_t e = lane; e < wq; e += 64) {
             const uint64_t qk = q_keys[wave][e];
             const uint32_t meta = (uint32_t)qk;
@@ -580,9 +604,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_waves(
             const int jl = row0 + 4 * h;
             // rank among the kept keys of its half-row in this wave
             uint32_t rank = e - q_start[wave][r];
-            if (h) rank -= half_cnt[row0][isub];
+            if (h) rank -= hcp[wave][r] & 0xFFFFu;
             // after the lower i-half's keys of the row (the other wave)
-            const uint32_t pos = rbase[jl] + (isub ? half_cnt[jl][0] : 0u) + rank;
+            const uint32_t pos = rbase[jl] + (isub ? row_count(jl, 0) : 0u) + rank;
             const uint64_t jj = (uint64_t)(j0 + jl), ii = (uint64_t)(i0 + isub * 32 + (ln & 31));
             kp.keys[pos] = ((qk >> 32) << (2 * ib)) | (jj << ib) | ii;
           }
@@ -591,8 +615,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(keys_waves(
       if constexpr (MODE == kKeysCount) {
         __syncthreads();
         if (threadIdx.x < kTile) {
-          row_acc = (seg_first ? 0u : row_acc) + half_cnt[threadIdx.x][0] +
-                    half_cnt[threadIdx.x][1];
+          row_acc = (seg_first ? 0u : row_acc) + row_count(threadIdx.x, 0) +
+                    row_count(threadIdx.x, 1);
           if (seg_last) kp.cnt[count_slot(cur, threadIdx.x)] = row_acc;
         }
       }
