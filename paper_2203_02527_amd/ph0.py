@@ -187,9 +187,10 @@ def ph0_barcodes(points: np.ndarray, with_stats: bool = False):
         raise ValueError("points must be N x d")
     n, d = x.shape
     out = np.empty((n, 2), np.uint32)
+    # No statistics asked: NULL, so that small clouds take the one-workgroup route.
     st = ph0_stats()
     _check(lib().ph0_barcodes(x.ctypes.data_as(_P), _dtype_code(x.dtype), n, d,
-                              out.ctypes.data_as(_P), ctypes.byref(st)))
+                              out.ctypes.data_as(_P), ctypes.byref(st) if with_stats else None))
     return (out, st.to_dict()) if with_stats else out
 
 
@@ -238,10 +239,11 @@ def ph0_barcodes_device(points, out=None, workspace=None, stream=None, with_stat
         out = torch.empty((n, 2), dtype=torch.int32, device=x.device)
     if workspace is None:
         workspace = alloc_workspace(n, d, x.dtype, x.device)
+    # No statistics asked: NULL, so that small clouds take the one-workgroup route.
     st = ph0_stats()
     _check(lib().ph0_barcodes_device(_ptr(x), _dtype_code(x.dtype), n, d, _ptr(out),
                                      _ptr(workspace), workspace.numel(), _stream_ptr(stream),
-                                     ctypes.byref(st)))
+                                     ctypes.byref(st) if with_stats else None))
     return (out, st.to_dict()) if with_stats else out
 
 
