@@ -657,9 +657,10 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   ra.ctl = static_cast<RedCtl*>(at(L.ctl));
   RedCtl* hc = rb->hc;
   HIPCHK(launch_reduce_init(ra, E_lim, s));
-  // Rounds go out in bursts, each followed by an event; the burst's last
-  // round leaves a copy of the control block in pinned host memory.  The host inspects a burst's copy while the
-  // next burst already runs, so the GPU never waits for the host; rounds
+  // Rounds go out in bursts; each burst ends with the one-wave advance,
+  // which also leaves the state in pinned host memory, and an event.  The
+  // host inspects a burst's state while the next burst already runs, so the
+  // GPU never waits for the host; rounds
   // issued after the end find `done` (or an empty range) and return at once.
   // Every round finalizes at least the first unfinished column (it either
   // reduces to zero or commits), so the window start must advance.
