@@ -99,7 +99,7 @@ int64_t ring_for(int64_t n, int64_t E) {
 
 struct Layout {
   int64_t n, E, Wcap, width, tiles;
-  size_t keysA, keysB, counts, hist, err, part, surv, scount, fdslot, wstat, cslot, osum, killer,
+  size_t keysA, keysB, counts, hist, err, part, surv, surv_ra, scount, fdslot, wstat, cslot, osum, killer,
       lowc, touch, act0, act1, werr, part16, ra, rr, rrlo, rst, ctl, dbv, minmax, hshift, kcnt,
       kcnt_tot, norms, total;
 };
@@ -127,6 +127,7 @@ Layout make_layout(int64_t n, int32_t d) {
   L.part = take(4 * (size_t)n);
   const size_t wb = (size_t)walk_blocks(L.Wcap), segs = wb * (size_t)walk_segment(L.Wcap);
   L.surv = take(8 * segs);
+  L.surv_ra = take(8 * segs);
   L.scount = take(4 * wb);
   L.fdslot = take(8 * wb);
   L.wstat = take(8 * 3 * wb);
@@ -642,6 +643,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   ra.act[1] = static_cast<int64_t*>(at(L.act1));
   ra.part = static_cast<int32_t*>(at(L.part));
   ra.surv = static_cast<int64_t*>(at(L.surv));
+  ra.surv_ra = static_cast<uint64_t*>(at(L.surv_ra));
   ra.scount = static_cast<uint32_t*>(at(L.scount));
   ra.fdslot = static_cast<uint64_t*>(at(L.fdslot));
   ra.wstat = static_cast<uint64_t*>(at(L.wstat));

@@ -169,6 +169,8 @@ struct RedArgs {
   int64_t* act[2];  // kept columns, one segment per commit workgroup (by round parity)
   Ring ring;
   int64_t* surv;    // nblocks x seg: each walk workgroup's survivors
+  uint64_t* surv_ra;  // nblocks x seg: beside each survivor, its low r (high half)
+                      // and other row a (low half)
   uint32_t* scount; // nblocks: survivors per walk workgroup
   uint64_t* fdslot; // nblocks: each walk workgroup's smallest survivor whose low repeats
                     // an earlier survivor's low

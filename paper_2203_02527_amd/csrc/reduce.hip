@@ -428,6 +428,19 @@ void k_walk(RedArgs A, int64_t n16, int64_t k, int advanced) {
       s_view[4] = v.F;
       s_view[5] = (int64_t)(v.done | (v.need_more << 1));
     }
+  } else {
+    // Meanwhile the other waves empty the hash tables and copy the table
+    // (the previous commit's, read-only in this round) into LDS.
+    const int t2 = tid - 64;
+    constexpr int kOthers = kWalkThreads - 64;
+    for (int h = t2; h < kHashSlots; h += kOthers) {
+      s_hkey[0][h] = s_hkey[1][h] = kHashEmpty;
+      s_hval[0][h] = s_hval[1][h] = kRelNone;
+    }
+    if (kLds) {
+      const uint4* src = reinterpret_cast<const uint4*>(A.part16);
+      for (int64_t h = t2; h < n16 / 8; h += kOthers) s_tab4[h] = src[h];
+    }
   }
   __syncthreads();
   RoundView c;
@@ -443,6 +456,7 @@ void k_walk(RedArgs A, int64_t n16, int64_t k, int advanced) {
   const int64_t nA = c.nA, round = c.round, fresh_lo = c.fresh_lo, F = c.F;
   const int64_t items = nA + (c.fresh_hi - fresh_lo);
   int64_t* my_surv = A.surv + blockIdx.x * A.seg;
+  uint64_t* my_ra = A.surv_ra + blockIdx.x * A.seg;
   if ((int64_t)blockIdx.x * kWalkThreads >= items) {  // nothing for this block
     if (tid == 0) {
       A.scount[blockIdx.x] = 0;
@@ -450,15 +464,6 @@ void k_walk(RedArgs A, int64_t n16, int64_t k, int advanced) {
     }
     return;
   }
-  for (int h = tid; h < kHashSlots; h += kWalkThreads) {
-    s_hkey[0][h] = s_hkey[1][h] = kHashEmpty;
-    s_hval[0][h] = s_hval[1][h] = kRelNone;
-  }
-  if (kLds) {
-    const uint4* src = reinterpret_cast<const uint4*>(A.part16);
-    for (int64_t h = tid; h < n16 / 8; h += kWalkThreads) s_tab4[h] = src[h];
-  }
-  __syncthreads();
   const uint16_t* s_tab = reinterpret_cast<const uint16_t*>(s_tab4);
   const int32_t* __restrict__ part = A.part;
   auto lookup = [&](int row) -> int {
@@ -589,7 +594,11 @@ void k_walk(RedArgs A, int64_t n16, int64_t k, int advanced) {
       before += w < wave ? s_wave[w] : 0u;
       total += s_wave[w];
     }
-    if (survivor) my_surv[nsurv + before + __popcll(m & ((1ull << lane) - 1ull))] = p;
+    if (survivor) {
+      const uint32_t at = nsurv + before + __popcll(m & ((1ull << lane) - 1ull));
+      my_surv[at] = p;
+      my_ra[at] = ((uint64_t)(uint32_t)r << 32) | (uint32_t)a;
+    }
     nsurv += total;
     __syncthreads();
     if (survivor) {  // empty the slots for the next pass (every used slot has a survivor)
@@ -646,8 +655,10 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(RedArgs A, int64_t k)
   const int nb = (int)gridDim.x;
   uint64_t* slot = A.cslot + 4 * (int64_t)blockIdx.x;
   const RedCtl* ctl = A.ctl + (k & 1);  // the state the walk of this round used
-  if (ctl->done || ctl->need_more) return;
+  const int32_t idle = ctl->done | ctl->need_more;
+  const int64_t round = ctl->round;
   const uint32_t cnt = A.scount[blockIdx.x];
+  if (idle) return;
   if (cnt == 0) {
     if (tid == 0) {
       slot[0] = 0;
@@ -657,30 +668,47 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(RedArgs A, int64_t k)
     }
     return;
   }
-  const int64_t round = ctl->round;
-  uint64_t fd = kNoValue;
-  for (int b = tid; b < nb; b += kCommitThreads) fd = A.fdslot[b] < fd ? A.fdslot[b] : fd;
-  fd = block_min_u64<kWaves>(fd, utmp);
   const Ring ring = A.ring;
   const int64_t Wcap = A.Wcap;
   const int64_t* my = A.surv + blockIdx.x * A.seg;
+  const uint64_t* my_ra = A.surv_ra + blockIdx.x * A.seg;
   int64_t* kept_out = A.act[round & 1] + blockIdx.x * A.seg;
+  // A survivor's inputs, all loaded at once: its position and rows (from the
+  // walk), then its rows' minima.
+  struct Item {
+    int64_t p;
+    int32_t r, a;
+    uint64_t lc, tc;
+  };
+  auto load = [&](uint32_t i) -> Item {
+    Item it = {0, 0, 0, kNoValue, kNoValue};
+    if (i < cnt) {
+      it.p = my[i];
+      const uint64_t ra = my_ra[i];
+      it.r = (int32_t)(ra >> 32);
+      it.a = (int32_t)(uint32_t)ra;
+      it.lc = A.lowc[it.r];
+      it.tc = A.touch[it.r];
+    }
+    return it;
+  };
+  Item it = load(tid);  // in flight while the smallest repeat is found
+  uint64_t fd = kNoValue;
+  for (int b = tid; b < nb; b += kCommitThreads) fd = A.fdslot[b] < fd ? A.fdslot[b] : fd;
+  fd = block_min_u64<kWaves>(fd, utmp);
   uint64_t stay_min = kNoValue;
   int64_t npiv = 0, last = -1, nkept = 0;
   for (uint32_t i0 = 0; i0 < cnt; i0 += kCommitThreads) {
     const uint32_t i = i0 + tid;
     bool keep = false;
-    int64_t p = 0;
+    const int64_t p = it.p;
     if (i < cnt) {
-      p = my[i];
       const int64_t kk = p & (Wcap - 1);
-      const int32_t r = ring.r[kk];
       const uint64_t e = enc(round, p);
-      if ((uint64_t)p < fd || (A.lowc[r] == e && A.touch[r] > e)) {
-        const int32_t a = ring.a[kk];
-        A.part[r] = a;  // the stored column {a, r}
-        if (A.part16) A.part16[r] = (uint16_t)a;
-        A.killer[r] = p;
+      if ((uint64_t)p < fd || (it.lc == e && it.tc > e)) {
+        A.part[it.r] = it.a;  // the stored column {a, r}
+        if (A.part16) A.part16[it.r] = (uint16_t)it.a;
+        A.killer[it.r] = p;
         ring.st[kk] = (ring.st[kk] & ~3) | kCommitted;
         ++npiv;
         last = p > last ? p : last;
@@ -689,6 +717,7 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(RedArgs A, int64_t k)
         stay_min = (uint64_t)p < stay_min ? (uint64_t)p : stay_min;
       }
     }
+    if (i0 + kCommitThreads < cnt) it = load(i + kCommitThreads);
     int64_t total;
     const int64_t at = block_excl_i64<kWaves>(keep ? 1 : 0, itmp, &total);
     if (keep) kept_out[nkept + at] = p;
