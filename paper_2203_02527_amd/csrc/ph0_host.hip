@@ -73,10 +73,15 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 int index_bits(int64_t n) { return n <= 1 ? 0 : 64 - __builtin_clzll((uint64_t)(n - 1)); }
 
 // Base number of columns in flight per reduction round; a power of two.
+// Window positions are kept as 32-bit offsets from the window start, so the
+// ring (at most kWindowGrowth base windows) stays below 2^31 columns.
+constexpr int64_t kMaxWindow = int64_t(1) << 26;
+
 int64_t window_for(int64_t n, int64_t E) {
   int64_t w = g_window.load();
   if (w <= 0) w = std::max<int64_t>(65536, 16 * n);
   w = std::min<int64_t>(w, std::max<int64_t>(E, 1));
+  w = std::min<int64_t>(w, kMaxWindow);
   int64_t p = 1;
   while (p < w) p <<= 1;
   return p;
@@ -87,6 +92,7 @@ int64_t window_for(int64_t n, int64_t E) {
 // that almost all reduce to zero) then takes fewer rounds (N=16384: 25 -> 20
 // rounds for about 10% more column walks past the last pivot).
 constexpr int64_t kWindowGrowth = 16;
+static_assert(kWindowGrowth * kMaxWindow < (int64_t(1) << 31), "ring offsets fit 31 bits");
 
 // Capacity of the per-column ring (indexed by column & (capacity - 1)): the
 // largest window, a power of two.
@@ -131,7 +137,7 @@ Layout make_layout(int64_t n, int32_t d) {
   L.scount = take(4 * wb);
   L.fdslot = take(8 * wb);
   L.wstat = take(8 * 3 * wb);
-  L.cslot = take(8 * 4 * wb);
+  L.cslot = take(4 * 4 * wb);
   L.werr = take(4);
   L.killer = take(8 * (size_t)n);
   L.lowc = take(8 * (size_t)n);
@@ -647,7 +653,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   ra.scount = static_cast<uint32_t*>(at(L.scount));
   ra.fdslot = static_cast<uint64_t*>(at(L.fdslot));
   ra.wstat = static_cast<uint64_t*>(at(L.wstat));
-  ra.cslot = static_cast<uint64_t*>(at(L.cslot));
+  ra.cslot = static_cast<uint32_t*>(at(L.cslot));
   ra.killer = static_cast<int64_t*>(at(L.killer));
   ra.lowc = static_cast<uint64_t*>(at(L.lowc));
   ra.touch = static_cast<uint64_t*>(at(L.touch));

@@ -176,8 +176,9 @@ struct RedArgs {
                     // an earlier survivor's low
   uint64_t* wstat;  // 3 x nblocks: each walk workgroup's additions, root-find steps and
                     // table words, summed by the finish step
-  uint64_t* cslot;  // 4 x nblocks: each commit workgroup's pivots, end of its last
-                    // pivot, first kept column and number kept
+  uint32_t* cslot;  // 4 x nblocks: each commit workgroup's pivots, columns kept, and, as
+                    // offsets from the round's window start F, the end of its last
+                    // pivot (0: none) and its first kept column (~0u: none)
   RedCtl* ctl;       // [2]: the round states, by parity of the rounds launched
   int32_t* werr;     // a walk met a stored row below its low (folded into err)
 };

@@ -121,6 +121,24 @@ __device__ inline uint64_t wave_max_u64(uint64_t v) {
   return v;
 }
 
+__device__ inline uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t w = __shfl_down(v, o, 64);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t w = __shfl_down(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
 __device__ inline int64_t wave_sum_i64(int64_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += (int64_t)shfl64_down((uint64_t)v, o);
@@ -211,26 +229,6 @@ __device__ inline RoundView uniform_view(RoundView v) {
   return v;
 }
 
-__device__ inline RoundView round_view(const RedCtl* c) {
-  RoundView v;
-  v.nA = c->nA;
-  v.round = c->round;
-  v.fresh_lo = c->fresh_lo;
-  v.fresh_hi = c->fresh_hi;
-  v.F = c->F;
-  v.done = c->done;
-  v.need_more = c->need_more;
-  return v;
-}
-
-// dst = src, by thread 0.
-__device__ inline void copy_state(RedCtl* dst, const RedCtl* src) {
-  static_assert(sizeof(RedCtl) % 8 == 0, "the state is copied in 8-byte words");
-  const uint64_t* s = reinterpret_cast<const uint64_t*>(src);
-  uint64_t* d = reinterpret_cast<uint64_t*>(dst);
-  for (int w = 0; w < (int)(sizeof(RedCtl) / 8); ++w) d[w] = s[w];
-}
-
 // The state entering the next round, formed by one wave (lane l reduces
 // the commit slots 8l .. 8l + 7 of the round just committed: pivots, end of
 // the last pivot, first kept column, columns kept) from the state `c`
@@ -245,42 +243,78 @@ __device__ inline void copy_state(RedCtl* dst, const RedCtl* src) {
 // same view back.
 __device__ RoundView advance_wave(const RedArgs& A, const RedCtl* c, bool compute, RedCtl* out,
                                   RedCtl* publish, int64_t* pre) {
-  const int lane = threadIdx.x & 63;
-  const RoundView cv = round_view(c);
-  if (cv.done || cv.need_more) {
-    if (compute && lane == 0) {
-      if (out) copy_state(out, c);
-      if (publish) copy_state(publish, c);
-    }
-    return cv;
-  }
-  if (!compute && cv.nA == 0) return cv;  // no kept columns to place
+  constexpr int kWords = (int)(sizeof(RedCtl) / 8);
+  static_assert(sizeof(RedCtl) % 8 == 0 && kWords <= 64, "the state is one 8-byte word per lane");
   constexpr int kPer = kMaxWalkBlocks / 64;
+  const int lane = threadIdx.x & 63;
   const int nb = A.nblocks;
-  int64_t piv = 0, lane_kept = 0;
-  uint64_t end = 0, stay = kNoValue;
-  int64_t kept[kPer];
+  // Everything read is requested at once (one memory round trip): lane w
+  // holds word w of the state, each lane the commit slots it reduces, and
+  // the walk error word.  Loads and reductions run whatever the state says
+  // (selects, no branches), so that no load is moved behind a wait.
+  const uint64_t word = reinterpret_cast<const uint64_t*>(c)[lane < kWords ? lane : 0];
+  const int32_t werr = __hip_atomic_load(A.werr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint4* slots = reinterpret_cast<const uint4*>(A.cslot);
+  uint4 sl[kPer];
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
     const int b = lane * kPer + q;
-    kept[q] = 0;
-    if (b < nb) {
-      const uint64_t* cs = A.cslot + 4 * (int64_t)b;
-      kept[q] = (int64_t)cs[3];
-      if (compute) {
-        piv += (int64_t)cs[0];
-        end = cs[1] > end ? cs[1] : end;
-        stay = cs[2] < stay ? cs[2] : stay;
-      }
-    }
-    lane_kept += kept[q];
+    sl[q] = slots[b < nb ? b : 0];
   }
+  uint32_t kept[kPer];
+  int64_t piv = 0, lane_kept = 0;
+  uint32_t end_off = 0, stay_off = ~0u;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const bool ok = lane * kPer + q < nb;
+    kept[q] = ok ? sl[q].y : 0u;
+    lane_kept += kept[q];
+    piv += ok ? sl[q].x : 0u;
+    const uint32_t eq = ok ? sl[q].z : 0u;
+    const uint32_t sq = ok ? sl[q].w : ~0u;
+    end_off = eq > end_off ? eq : end_off;
+    stay_off = sq < stay_off ? sq : stay_off;
+  }
+  // Fields of the state, the same in every lane: an 8-byte one, and a
+  // 4-byte one (either half of a word).
+  auto word_at = [&](size_t off) -> uint64_t {
+    const int w = (int)(off / 8);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)word, w);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(word >> 32), w);
+    return ((uint64_t)hi << 32) | lo;
+  };
+  auto field = [&](size_t off) -> int64_t { return (int64_t)word_at(off); };
+  auto field32 = [&](size_t off) -> int32_t {
+    return (int32_t)(uint32_t)(word_at(off) >> (8 * (off % 8)));
+  };
+  static_assert(offsetof(RedCtl, done) % 8 == 0 && offsetof(RedCtl, err) == offsetof(RedCtl, done) + 4 &&
+                    offsetof(RedCtl, need_more) % 8 == 0,
+                "done and err share a word, need_more starts one");
   int64_t incl = lane_kept;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     const int64_t y = (int64_t)shfl64_up((uint64_t)incl, o);
     if (lane >= o) incl += y;
   }
+  piv = uniform64(wave_sum_i64(piv));
+  end_off = __builtin_amdgcn_readfirstlane(wave_max_u32(end_off));
+  stay_off = __builtin_amdgcn_readfirstlane(wave_min_u32(stay_off));
+  RoundView cv;
+  cv.nA = field(offsetof(RedCtl, nA));
+  cv.round = field(offsetof(RedCtl, round));
+  cv.fresh_lo = field(offsetof(RedCtl, fresh_lo));
+  cv.fresh_hi = field(offsetof(RedCtl, fresh_hi));
+  cv.F = field(offsetof(RedCtl, F));
+  cv.done = field32(offsetof(RedCtl, done));
+  cv.need_more = field32(offsetof(RedCtl, need_more));
+  if (cv.done || cv.need_more) {
+    if (compute && lane < kWords) {
+      if (out) reinterpret_cast<uint64_t*>(out)[lane] = word;
+      if (publish) reinterpret_cast<uint64_t*>(publish)[lane] = word;
+    }
+    return cv;
+  }
+  if (!compute && cv.nA == 0) return cv;  // no kept columns to place
   int64_t run = incl - lane_kept;
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
@@ -291,27 +325,27 @@ __device__ RoundView advance_wave(const RedArgs& A, const RedCtl* c, bool comput
   const int64_t all_kept = uniform64((int64_t)shfl64_idx((uint64_t)incl, 63));
   if (lane == 0) pre[nb] = all_kept;
   if (!compute) return cv;
-  piv = uniform64(wave_sum_i64(piv));
-  end = (uint64_t)uniform64((int64_t)wave_max_u64(end));
-  stay = (uint64_t)uniform64((int64_t)wave_min_u64(stay));
   const int64_t n = A.n, E = A.E, Wcap = A.Wcap;
-  const int64_t c_Wend = c->Wend, c_E_eff = c->E_eff;
-  const int64_t pivots = c->pivots + piv;
-  const int64_t E_eff = (int64_t)end > c_E_eff ? (int64_t)end : c_E_eff;
-  const int64_t F = stay == kNoValue ? c_Wend : (int64_t)stay;
-  int64_t Wend = c_Wend, width = c->width;
+  const int64_t c_Wend = field(offsetof(RedCtl, Wend));
+  const int64_t c_E_eff = field(offsetof(RedCtl, E_eff));
+  const int64_t pivots = field(offsetof(RedCtl, pivots)) + piv;
+  const int64_t end = end_off ? cv.F + (int64_t)end_off : 0;
+  const int64_t E_eff = end > c_E_eff ? end : c_E_eff;
+  const int64_t F = stay_off == ~0u ? c_Wend : cv.F + (int64_t)stay_off;
+  int64_t Wend = c_Wend, width = field(offsetof(RedCtl, width));
   int32_t done = 0, need_more = 0;
-  int32_t err = c->err | __hip_atomic_load(A.werr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  int32_t err = field32(offsetof(RedCtl, err)) | werr;
   if (pivots >= n - 1) {
     // Every later column reduces to zero; only columns before the last
     // pivot still need finishing (for the exact addition count).
     if (F >= E_eff) done = 1;
   } else {
-    const int64_t lim = c->E_lim;
+    const int64_t lim = field(offsetof(RedCtl, E_lim));
+    const int64_t width_min = field(offsetof(RedCtl, width_min));
     if (all_kept < width / 256)
       width = 2 * width < Wcap ? 2 * width : Wcap;
     else if (all_kept > width / 16)
-      width = width / 2 > c->width_min ? width / 2 : c->width_min;
+      width = width / 2 > width_min ? width / 2 : width_min;
     const int64_t want = F + width < lim ? F + width : lim;
     Wend = want > Wend ? want : Wend;
     if (F >= lim) {
@@ -331,25 +365,29 @@ __device__ RoundView advance_wave(const RedArgs& A, const RedCtl* c, bool comput
   v.F = F;
   v.done = done;
   v.need_more = need_more;
-  if (lane == 0) {
-    const int64_t maxWend = Wend > c->maxWend ? Wend : c->maxWend;
-    for (int t = 0; t < 2; ++t) {
-      RedCtl* o = t ? publish : out;
-      if (!o) continue;
-      copy_state(o, c);
-      o->pivots = pivots;
-      o->E_eff = E_eff;
-      o->width = width;
-      o->done = done;
-      o->need_more = need_more;
-      o->err = err;
-      o->fresh_lo = v.fresh_lo;
-      o->fresh_hi = v.fresh_hi;
-      o->nA = v.nA;
-      o->F = F;
-      o->Wend = Wend;
-      o->maxWend = maxWend;
-      o->round = v.round;
+  if (out || publish) {
+    // The new state, word w from lane w: the fields the advance sets
+    // replace the old ones, the rest carry over.
+    const int64_t c_maxWend = field(offsetof(RedCtl, maxWend));
+    const int64_t maxWend = Wend > c_maxWend ? Wend : c_maxWend;
+    auto at = [&](size_t off) { return lane == (int)(off / 8); };
+    uint64_t o = word;
+    if (at(offsetof(RedCtl, F))) o = (uint64_t)F;
+    if (at(offsetof(RedCtl, Wend))) o = (uint64_t)Wend;
+    if (at(offsetof(RedCtl, width))) o = (uint64_t)width;
+    if (at(offsetof(RedCtl, maxWend))) o = (uint64_t)maxWend;
+    if (at(offsetof(RedCtl, fresh_lo))) o = (uint64_t)v.fresh_lo;
+    if (at(offsetof(RedCtl, fresh_hi))) o = (uint64_t)v.fresh_hi;
+    if (at(offsetof(RedCtl, nA))) o = (uint64_t)v.nA;
+    if (at(offsetof(RedCtl, pivots))) o = (uint64_t)pivots;
+    if (at(offsetof(RedCtl, E_eff))) o = (uint64_t)E_eff;
+    if (at(offsetof(RedCtl, round))) o = (uint64_t)v.round;
+    if (at(offsetof(RedCtl, done))) o = ((uint64_t)(uint32_t)err << 32) | (uint32_t)done;
+    if (at(offsetof(RedCtl, need_more)))
+      o = (o & 0xFFFFFFFF00000000ull) | (uint32_t)need_more;
+    if (lane < kWords) {
+      if (out) reinterpret_cast<uint64_t*>(out)[lane] = o;
+      if (publish) reinterpret_cast<uint64_t*>(publish)[lane] = o;
     }
   }
   return v;
@@ -438,8 +476,25 @@ void k_walk(RedArgs A, int64_t n16, int64_t k, int advanced) {
       s_hval[0][h] = s_hval[1][h] = kRelNone;
     }
     if (kLds) {
+      // Four 16-byte pieces in flight per thread.
       const uint4* src = reinterpret_cast<const uint4*>(A.part16);
-      for (int64_t h = t2; h < n16 / 8; h += kOthers) s_tab4[h] = src[h];
+      const int64_t pieces = n16 / 8;
+      for (int64_t h0 = t2; h0 < pieces; h0 += 4 * kOthers) {
+        uint4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t h = h0 + u * kOthers;
+          v[u] = src[h < pieces ? h : 0];
+        }
+        // A piece past the end rewrites piece 0 with its own value (the
+        // store is unconditional so that the loads are not moved after a
+        // branch, one wait each).
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t h = h0 + u * kOthers;
+          s_tab4[h < pieces ? h : 0] = v[u];
+        }
+      }
     }
   }
   __syncthreads();
@@ -633,9 +688,9 @@ void k_walk(RedArgs A, int64_t n16, int64_t k, int advanced) {
     // The block's own slots (the grid is the same every round), summed once
     // at the finish.
     uint64_t* mine = A.wstat + 3 * (int64_t)blockIdx.x;
-    mine[0] += s_cnt[0];
-    mine[1] += s_cnt[1];
-    mine[2] += s_cnt[2];
+    atomicAdd((unsigned long long*)&mine[0], s_cnt[0]);  // no value returned: no wait
+    atomicAdd((unsigned long long*)&mine[1], s_cnt[1]);
+    atomicAdd((unsigned long long*)&mine[2], s_cnt[2]);
     if (s_bad) atomicOr(A.werr, 1);
   }
 }
@@ -653,19 +708,16 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(RedArgs A, int64_t k)
   __shared__ int64_t itmp[kWaves];
   const int tid = threadIdx.x;
   const int nb = (int)gridDim.x;
-  uint64_t* slot = A.cslot + 4 * (int64_t)blockIdx.x;
+  // Slot: pivots, columns kept, and as offsets from F the end of the last
+  // pivot (0: none) and the first kept column (~0u: none).
+  uint4* slot = reinterpret_cast<uint4*>(A.cslot) + blockIdx.x;
   const RedCtl* ctl = A.ctl + (k & 1);  // the state the walk of this round used
   const int32_t idle = ctl->done | ctl->need_more;
-  const int64_t round = ctl->round;
+  const int64_t round = ctl->round, F = ctl->F;
   const uint32_t cnt = A.scount[blockIdx.x];
   if (idle) return;
   if (cnt == 0) {
-    if (tid == 0) {
-      slot[0] = 0;
-      slot[1] = 0;
-      slot[2] = kNoValue;
-      slot[3] = 0;
-    }
+    if (tid == 0) *slot = make_uint4(0u, 0u, 0u, ~0u);
     return;
   }
   const Ring ring = A.ring;
@@ -727,10 +779,10 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(RedArgs A, int64_t k)
   const uint64_t last_end = block_max_u64<kWaves>((uint64_t)(last + 1), utmp);
   stay_min = block_min_u64<kWaves>(stay_min, utmp);
   if (tid == 0) {
-    slot[0] = (uint64_t)npiv;
-    slot[1] = last_end;
-    slot[2] = stay_min;
-    slot[3] = (uint64_t)nkept;
+    // Offsets below the ring's capacity (< 2^31).
+    *slot = make_uint4((uint32_t)npiv, (uint32_t)nkept,
+                       npiv ? (uint32_t)((int64_t)last_end - F) : 0u,
+                       stay_min == kNoValue ? ~0u : (uint32_t)((int64_t)stay_min - F));
   }
 }
 
