@@ -105,8 +105,8 @@ int64_t ring_for(int64_t n, int64_t E) {
 
 struct Layout {
   int64_t n, E, Wcap, width, tiles;
-  size_t keysA, keysB, counts, hist, err, part, surv, surv_ra, scount, fdslot, wstat, cslot, osum, killer,
-      lowc, touch, act0, act1, werr, part16, ra, rr, rrlo, rst, ctl, dbv, minmax, hshift, kcnt,
+  size_t keysA, keysB, counts, hist, err, part, surv, surv_ra, surv_x, scount, fdslot, wstat, cslot, osum, killer,
+      lowc, touch, act0, act1, actra0, actra1, actx0, actx1, werr, part16, rst, ctl, dbv, minmax, hshift, kcnt,
       kcnt_tot, norms, total;
 };
 
@@ -134,6 +134,7 @@ Layout make_layout(int64_t n, int32_t d) {
   const size_t wb = (size_t)walk_blocks(L.Wcap), segs = wb * (size_t)walk_segment(L.Wcap);
   L.surv = take(8 * segs);
   L.surv_ra = take(8 * segs);
+  L.surv_x = take(8 * segs);
   L.scount = take(4 * wb);
   L.fdslot = take(8 * wb);
   L.wstat = take(8 * 3 * wb);
@@ -144,10 +145,11 @@ Layout make_layout(int64_t n, int32_t d) {
   L.touch = take(8 * (size_t)n);
   L.act0 = take(8 * segs);
   L.act1 = take(8 * segs);
+  L.actra0 = take(8 * segs);
+  L.actra1 = take(8 * segs);
+  L.actx0 = take(8 * segs);
+  L.actx1 = take(8 * segs);
   L.part16 = take(2 * (size_t)std::max<int64_t>(part16_len(n), 8));
-  L.ra = take(4 * (size_t)L.Wcap);
-  L.rr = take(4 * (size_t)L.Wcap);
-  L.rrlo = take(4 * (size_t)L.Wcap);
   L.rst = take(4 * (size_t)L.Wcap);
   L.ctl = take(2 * sizeof(RedCtl));  // the two round states
   L.dbv = take(4 * (size_t)n);
@@ -647,9 +649,14 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   ra.werr = static_cast<int32_t*>(at(L.werr));
   ra.act[0] = static_cast<int64_t*>(at(L.act0));
   ra.act[1] = static_cast<int64_t*>(at(L.act1));
+  ra.act_ra[0] = static_cast<uint64_t*>(at(L.actra0));
+  ra.act_ra[1] = static_cast<uint64_t*>(at(L.actra1));
+  ra.act_x[0] = static_cast<uint64_t*>(at(L.actx0));
+  ra.act_x[1] = static_cast<uint64_t*>(at(L.actx1));
   ra.part = static_cast<int32_t*>(at(L.part));
   ra.surv = static_cast<int64_t*>(at(L.surv));
   ra.surv_ra = static_cast<uint64_t*>(at(L.surv_ra));
+  ra.surv_x = static_cast<uint64_t*>(at(L.surv_x));
   ra.scount = static_cast<uint32_t*>(at(L.scount));
   ra.fdslot = static_cast<uint64_t*>(at(L.fdslot));
   ra.wstat = static_cast<uint64_t*>(at(L.wstat));
@@ -658,9 +665,6 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   ra.lowc = static_cast<uint64_t*>(at(L.lowc));
   ra.touch = static_cast<uint64_t*>(at(L.touch));
   ra.part16 = part16_len(n) ? static_cast<uint16_t*>(at(L.part16)) : nullptr;
-  ra.ring.a = static_cast<int32_t*>(at(L.ra));
-  ra.ring.r = static_cast<int32_t*>(at(L.rr));
-  ra.ring.rlo = static_cast<int32_t*>(at(L.rrlo));
   ra.ring.st = static_cast<int32_t*>(at(L.rst));
   ra.ctl = static_cast<RedCtl*>(at(L.ctl));
   RedCtl* hc = rb->hc;

@@ -48,15 +48,15 @@ struct RedCtl {
   int32_t pad;
 };
 
-// Per-column state of the reduction window, a ring indexed by p % Wcap.
+// Per-column record of the reduction window, a ring indexed by p % Wcap:
+// the status of the last walk (low 2 bits) | additions so far << 2.  (The
+// rows of a column still active travel with it in the survivor and kept
+// lists.)
 struct Ring {
-  int32_t* a;    // smaller nonzero row of the partially reduced column
-  int32_t* r;    // its low (larger nonzero row)
-  int32_t* rlo;  // root of row a in the pivot forest seen last round
-  int32_t* st;   // status (low 2 bits) | additions so far << 2
+  int32_t* st;
 };
 
-enum : int32_t { kActive = 0, kZero = 1, kCommitted = 2 };
+enum : int32_t { kActive = 0, kZero = 1 };
 
 // ---- launchers (each enqueues on `s`, returns hipError_t) ----
 
@@ -167,10 +167,14 @@ struct RedArgs {
   uint64_t* lowc;   // n: round-tagged smallest survivor with low r
   uint64_t* touch;  // n: round-tagged smallest survivor whose other row has root r
   int64_t* act[2];  // kept columns, one segment per commit workgroup (by round parity)
+  uint64_t* act_ra[2];  // beside each: its low r (high half) and other row a (low half)
+  uint64_t* act_x[2];   // beside each: root of a last seen (high half), additions so far
   Ring ring;
   int64_t* surv;    // nblocks x seg: each walk workgroup's survivors
   uint64_t* surv_ra;  // nblocks x seg: beside each survivor, its low r (high half)
                       // and other row a (low half)
+  uint64_t* surv_x;   // nblocks x seg: beside each survivor, the root of a (high half)
+                      // and its additions so far (low half)
   uint32_t* scount; // nblocks: survivors per walk workgroup
   uint64_t* fdslot; // nblocks: each walk workgroup's smallest survivor whose low repeats
                     // an earlier survivor's low

@@ -53,8 +53,8 @@
 //     workgroups from the values the row-minimum atomics return; each
 //     workgroup leaves its candidate in a slot of its own;
 //   * the commit workgroup of a walk workgroup's survivors commits or keeps
-//     them, writes the kept ones to a segment of its own and its totals to a
-//     slot of its own.
+//     them, writes the kept ones (with their state) to a segment of its own
+//     and its totals to a slot of its own.
 // Where the host looks at the state (the end of a burst of rounds), one
 // wave advances it on its own and leaves a copy in host memory.
 #include <algorithm>
@@ -230,9 +230,9 @@ __device__ inline RoundView uniform_view(RoundView v) {
 }
 
 // The state entering the next round, formed by one wave (lane l reduces
-// the commit slots 8l .. 8l + 7 of the round just committed: pivots, end of
-// the last pivot, first kept column, columns kept) from the state `c`
-// entering that round; lane 0 stores it to `out` and `publish` when given.
+// the commit slots 8l .. 8l + 7 of the round just committed: pivots,
+// columns kept, end of the last pivot, first kept column) from the state
+// `c` entering that round; stored to `out` and `publish` when given.
 // pre[0..nblocks] (LDS) receives the kept columns before each commit
 // segment and their total.  With `compute` false, `c` is the state already
 // (only pre is formed).  A state that is done or waits for more columns
@@ -425,11 +425,12 @@ __device__ inline int hash_insert(uint32_t* keys, uint32_t* vals, int row, uint3
 // so far, one lane per column.  A column stops on a free row (a survivor) or
 // becomes zero.  For a survivor {a, r} the root of a in the pivot forest
 // (follow part[] down to a free row) is found, and the round-tagged minima
-// for row r (lowc) and that root (touch) are lowered.  A survivor's state
-// goes back to the ring; a zero column only leaves its addition count there
-// (for the overshoot sum).  Each workgroup lists its survivors in its own
-// segment of `surv`, and leaves in fdslot[block] the smallest survivor it
-// saw whose low repeats an earlier survivor's low.
+// for row r (lowc) and that root (touch) are lowered.  Every walked column
+// leaves its addition count in the ring (for the overshoot sum).  Each
+// workgroup lists its survivors, with their rows, root and addition count,
+// in its own segment of `surv` (the commit passes the kept ones on to the
+// next walk the same way), and leaves in fdslot[block] the smallest
+// survivor it saw whose low repeats an earlier survivor's low.
 // kLds: the table is read from the workgroup's LDS copy of part16 (0xFFFF =
 // free), else from part in global memory.
 template <bool kLds>
@@ -512,6 +513,7 @@ void k_walk(RedArgs A, int64_t n16, int64_t k, int advanced) {
   const int64_t items = nA + (c.fresh_hi - fresh_lo);
   int64_t* my_surv = A.surv + blockIdx.x * A.seg;
   uint64_t* my_ra = A.surv_ra + blockIdx.x * A.seg;
+  uint64_t* my_x = A.surv_x + blockIdx.x * A.seg;
   if ((int64_t)blockIdx.x * kWalkThreads >= items) {  // nothing for this block
     if (tid == 0) {
       A.scount[blockIdx.x] = 0;
@@ -528,7 +530,10 @@ void k_walk(RedArgs A, int64_t n16, int64_t k, int advanced) {
     }
     return part[row];
   };
-  const int64_t* kept_cols = A.act[(round - 1) & 1];  // the previous commit's segments
+  // The previous commit's segments: kept columns and their states.
+  const int64_t* kept_cols = A.act[(round - 1) & 1];
+  const uint64_t* kept_ra = A.act_ra[(round - 1) & 1];
+  const uint64_t* kept_x = A.act_x[(round - 1) & 1];
   const uint64_t* __restrict__ skeys = A.skeys;
   const int ib = A.ib;
   const Ring ring = A.ring;
@@ -543,7 +548,7 @@ void k_walk(RedArgs A, int64_t n16, int64_t k, int advanced) {
     const int64_t t = t0 + tid;
     bool survivor = false;
     int64_t p = 0;
-    int32_t a = 0, r = 0, rlo = 0;
+    int32_t a = 0, r = 0, rlo = 0, steps = 0;
     int hs_low = 0, hs_root = 0;  // this survivor's hash slots
     if (t < items) {
       int32_t prev_steps;
@@ -557,12 +562,13 @@ void k_walk(RedArgs A, int64_t n16, int64_t k, int advanced) {
           else
             hi = mid;
         }
-        p = kept_cols[lo * seg + (t - s_pre[lo])];
-        const int64_t kk = p & (Wcap - 1);
-        a = ring.a[kk];
-        r = ring.r[kk];
-        rlo = ring.rlo[kk];
-        prev_steps = ring.st[kk] >> 2;
+        const int64_t at = lo * seg + (t - s_pre[lo]);
+        p = kept_cols[at];
+        const uint64_t ra = kept_ra[at], x = kept_x[at];
+        r = (int32_t)(ra >> 32);
+        a = (int32_t)(uint32_t)ra;
+        rlo = (int32_t)(x >> 32);
+        prev_steps = (int32_t)(uint32_t)x;
       } else {
         p = fresh_lo + (t - nA);
         const uint64_t key = skeys[p];
@@ -593,9 +599,10 @@ void k_walk(RedArgs A, int64_t n16, int64_t k, int advanced) {
         a = lo2;
       }
       adds += moved;
+      steps = prev_steps + moved;
       const int64_t kk = p & (Wcap - 1);
       if (zero) {
-        ring.st[kk] = kZero | ((prev_steps + moved) << 2);
+        ring.st[kk] = kZero | (steps << 2);
       } else {
         // Root of row a in the current forest: follow stored columns down.
         int v = moved ? a : rlo;
@@ -615,10 +622,7 @@ void k_walk(RedArgs A, int64_t n16, int64_t k, int advanced) {
         hs_low = hash_insert(s_hkey[0], s_hval[0], r, rel);
         hs_root = hash_insert(s_hkey[1], s_hval[1], rlo, rel);
         survivor = true;
-        ring.a[kk] = a;
-        ring.r[kk] = r;
-        ring.rlo[kk] = rlo;
-        ring.st[kk] = kActive | ((prev_steps + moved) << 2);
+        ring.st[kk] = kActive | (steps << 2);
       }
     }
     // Append this pass's survivors to the block's segment; the lane holding
@@ -653,6 +657,7 @@ void k_walk(RedArgs A, int64_t n16, int64_t k, int advanced) {
       const uint32_t at = nsurv + before + __popcll(m & ((1ull << lane) - 1ull));
       my_surv[at] = p;
       my_ra[at] = ((uint64_t)(uint32_t)r << 32) | (uint32_t)a;
+      my_x[at] = ((uint64_t)(uint32_t)rlo << 32) | (uint32_t)steps;
     }
     nsurv += total;
     __syncthreads();
@@ -720,27 +725,28 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(RedArgs A, int64_t k)
     if (tid == 0) *slot = make_uint4(0u, 0u, 0u, ~0u);
     return;
   }
-  const Ring ring = A.ring;
-  const int64_t Wcap = A.Wcap;
-  const int64_t* my = A.surv + blockIdx.x * A.seg;
-  const uint64_t* my_ra = A.surv_ra + blockIdx.x * A.seg;
-  int64_t* kept_out = A.act[round & 1] + blockIdx.x * A.seg;
-  // A survivor's inputs, all loaded at once: its position and rows (from the
-  // walk), then its rows' minima.
+  const int64_t my0 = blockIdx.x * A.seg;
+  const int64_t* my = A.surv + my0;
+  const uint64_t* my_ra = A.surv_ra + my0;
+  const uint64_t* my_x = A.surv_x + my0;
+  int64_t* kept_out = A.act[round & 1] + my0;
+  uint64_t* kept_ra = A.act_ra[round & 1] + my0;
+  uint64_t* kept_x = A.act_x[round & 1] + my0;
+  // A survivor's inputs, all loaded at once: its position, rows and state
+  // (from the walk), then its rows' minima.
   struct Item {
     int64_t p;
-    int32_t r, a;
-    uint64_t lc, tc;
+    uint64_t ra, x, lc, tc;
   };
   auto load = [&](uint32_t i) -> Item {
     Item it = {0, 0, 0, kNoValue, kNoValue};
     if (i < cnt) {
       it.p = my[i];
-      const uint64_t ra = my_ra[i];
-      it.r = (int32_t)(ra >> 32);
-      it.a = (int32_t)(uint32_t)ra;
-      it.lc = A.lowc[it.r];
-      it.tc = A.touch[it.r];
+      it.ra = my_ra[i];
+      it.x = my_x[i];
+      const int32_t r = (int32_t)(it.ra >> 32);
+      it.lc = A.lowc[r];
+      it.tc = A.touch[r];
     }
     return it;
   };
@@ -754,14 +760,14 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(RedArgs A, int64_t k)
     const uint32_t i = i0 + tid;
     bool keep = false;
     const int64_t p = it.p;
+    const uint64_t ra = it.ra, x = it.x;
     if (i < cnt) {
-      const int64_t kk = p & (Wcap - 1);
       const uint64_t e = enc(round, p);
       if ((uint64_t)p < fd || (it.lc == e && it.tc > e)) {
-        A.part[it.r] = it.a;  // the stored column {a, r}
-        if (A.part16) A.part16[it.r] = (uint16_t)it.a;
-        A.killer[it.r] = p;
-        ring.st[kk] = (ring.st[kk] & ~3) | kCommitted;
+        const int32_t r = (int32_t)(ra >> 32), a = (int32_t)(uint32_t)ra;
+        A.part[r] = a;  // the stored column {a, r}
+        if (A.part16) A.part16[r] = (uint16_t)a;
+        A.killer[r] = p;
         ++npiv;
         last = p > last ? p : last;
       } else {
@@ -772,7 +778,11 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(RedArgs A, int64_t k)
     if (i0 + kCommitThreads < cnt) it = load(i + kCommitThreads);
     int64_t total;
     const int64_t at = block_excl_i64<kWaves>(keep ? 1 : 0, itmp, &total);
-    if (keep) kept_out[nkept + at] = p;
+    if (keep) {
+      kept_out[nkept + at] = p;
+      kept_ra[nkept + at] = ra;
+      kept_x[nkept + at] = x;
+    }
     nkept += total;
   }
   npiv = block_sum_i64<kWaves>(npiv, itmp);
