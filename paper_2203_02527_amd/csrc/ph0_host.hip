@@ -646,6 +646,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   ra.width = L.width;
   ra.seg = walk_segment(L.Wcap);
   ra.nblocks = walk_blocks(L.Wcap);
+  ra.count = st != nullptr;  // the addition counts are statistics: formed only when asked
   ra.werr = static_cast<int32_t*>(at(L.werr));
   ra.act[0] = static_cast<int64_t*>(at(L.act0));
   ra.act[1] = static_cast<int64_t*>(at(L.act1));

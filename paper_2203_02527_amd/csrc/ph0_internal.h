@@ -157,6 +157,9 @@ struct RedArgs {
   const uint64_t* skeys;
   int ib;
   int32_t nblocks;     // walk_blocks(Wcap)
+  int32_t count;       // nonzero: the walks keep their counters (additions, root-find
+                       // steps, table words) and the finish sums them and the
+                       // overshoot; zero: those statistics are not formed
   int64_t n, E, Wcap;  // Wcap: ring capacity, a power of two
   int64_t width;       // base window width (<= Wcap)
   int64_t seg;         // walk_segment(Wcap): entries per workgroup segment

@@ -438,10 +438,8 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu(8,
 void k_walk(RedArgs A, int64_t n16, int64_t k, int advanced) {
   extern __shared__ uint4 s_tab4[];  // kLds: n16 / 8 entries of 8 table rows
   __shared__ uint32_t s_wave[kWalkWaves];
-  __shared__ uint64_t s_u64[kWalkWaves];
   __shared__ int64_t s_view[6];
-  __shared__ unsigned long long s_cnt[3];
-  __shared__ int s_bad;
+  __shared__ uint64_t s_red[kWalkWaves][4];
   __shared__ int64_t s_pre[kMaxWalkBlocks + 1];  // kept columns before each commit segment
   // Row-minimum hash tables: [0] by low r (lowc), [1] by root rlo (touch).
   __shared__ uint32_t s_hkey[2][kHashSlots];
@@ -669,34 +667,47 @@ void k_walk(RedArgs A, int64_t n16, int64_t k, int advanced) {
     }
     __syncthreads();
   }
-  fd = block_min_u64<kWalkWaves>(fd, s_u64);
-  if (tid == 0) {
-    A.scount[blockIdx.x] = nsurv;
-    A.fdslot[blockIdx.x] = fd;
+  // One block reduction, one barrier: the smallest repeat, a corrupt-table
+  // flag and (when counting) the counters, per wave into LDS, then summed
+  // by the first thread into the block's own slots (the grid is the same
+  // every round; the counter slots are summed once at the finish).
+  fd = wave_min_u64(fd);
+  const uint64_t wbad = __ballot(bad != 0);
+  uint64_t wadds = 0, wfinds = 0, wwords = 0;
+  if (A.count) {
+    wadds = (uint64_t)wave_sum_i64(adds);
+    wfinds = (uint64_t)wave_sum_i64(finds);
+    wwords = (uint64_t)wave_sum_i64(words);
   }
-  // Counters: wave sums -> block totals in LDS -> the block's own slots.
-  if (tid < 3) s_cnt[tid] = 0;
-  if (tid == 0) s_bad = 0;
-  __syncthreads();
-  const int64_t wadds = wave_sum_i64(adds);
-  const int64_t wfinds = wave_sum_i64(finds);
-  const int64_t wwords = wave_sum_i64(words);
-  if (__ballot(bad != 0)) bad = 1;
-  if ((tid & 63) == 0) {
-    if (wadds) atomicAdd(&s_cnt[0], (unsigned long long)wadds);
-    if (wfinds) atomicAdd(&s_cnt[1], (unsigned long long)wfinds);
-    if (wwords) atomicAdd(&s_cnt[2], (unsigned long long)wwords);
-    if (bad) s_bad = 1;
+  if (lane == 0) {
+    s_red[wave][0] = fd;
+    s_red[wave][1] = wadds;
+    s_red[wave][2] = wfinds;
+    s_red[wave][3] = wwords | (wbad ? 1ull << 63 : 0ull);
   }
   __syncthreads();
-  if (tid == 0) {
-    // The block's own slots (the grid is the same every round), summed once
-    // at the finish.
-    uint64_t* mine = A.wstat + 3 * (int64_t)blockIdx.x;
-    atomicAdd((unsigned long long*)&mine[0], s_cnt[0]);  // no value returned: no wait
-    atomicAdd((unsigned long long*)&mine[1], s_cnt[1]);
-    atomicAdd((unsigned long long*)&mine[2], s_cnt[2]);
-    if (s_bad) atomicOr(A.werr, 1);
+  if (wave == 0) {  // lane w takes wave w's entry
+    const bool has = lane < kWalkWaves;
+    const uint64_t m = wave_min_u64(has ? s_red[lane][0] : kNoValue);
+    const uint64_t w3 = has ? s_red[lane][3] : 0ull;
+    const bool anybad = __ballot(w3 >> 63) != 0;
+    uint64_t c0 = 0, c1 = 0, c2 = 0;
+    if (A.count) {
+      c0 = (uint64_t)wave_sum_i64(has ? (int64_t)s_red[lane][1] : 0);
+      c1 = (uint64_t)wave_sum_i64(has ? (int64_t)s_red[lane][2] : 0);
+      c2 = (uint64_t)wave_sum_i64((int64_t)(w3 & ~(1ull << 63)));
+    }
+    if (lane == 0) {
+      A.scount[blockIdx.x] = nsurv;
+      A.fdslot[blockIdx.x] = m;
+      if (A.count) {
+        uint64_t* mine = A.wstat + 3 * (int64_t)blockIdx.x;
+        atomicAdd((unsigned long long*)&mine[0], c0);  // no value returned: no wait
+        atomicAdd((unsigned long long*)&mine[1], c1);
+        atomicAdd((unsigned long long*)&mine[2], c2);
+      }
+      if (anybad) atomicOr(A.werr, 1);
+    }
   }
 }
 
@@ -709,7 +720,8 @@ void k_walk(RedArgs A, int64_t n16, int64_t k, int advanced) {
 // kept.
 __global__ __launch_bounds__(kCommitThreads) void k_commit(RedArgs A, int64_t k) {
   constexpr int kWaves = kCommitThreads / 64;
-  __shared__ uint64_t utmp[kWaves];
+  __shared__ uint64_t s_fd[kWaves];
+  __shared__ uint64_t s_tot[kWaves][3];
   __shared__ int64_t itmp[kWaves];
   const int tid = threadIdx.x;
   const int nb = (int)gridDim.x;
@@ -753,7 +765,12 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(RedArgs A, int64_t k)
   Item it = load(tid);  // in flight while the smallest repeat is found
   uint64_t fd = kNoValue;
   for (int b = tid; b < nb; b += kCommitThreads) fd = A.fdslot[b] < fd ? A.fdslot[b] : fd;
-  fd = block_min_u64<kWaves>(fd, utmp);
+  fd = wave_min_u64(fd);
+  if ((tid & 63) == 0) s_fd[tid >> 6] = fd;
+  __syncthreads();
+  fd = s_fd[0];
+#pragma unroll
+  for (int w = 1; w < kWaves; ++w) fd = s_fd[w] < fd ? s_fd[w] : fd;
   uint64_t stay_min = kNoValue;
   int64_t npiv = 0, last = -1, nkept = 0;
   for (uint32_t i0 = 0; i0 < cnt; i0 += kCommitThreads) {
@@ -785,10 +802,28 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(RedArgs A, int64_t k)
     }
     nkept += total;
   }
-  npiv = block_sum_i64<kWaves>(npiv, itmp);
-  const uint64_t last_end = block_max_u64<kWaves>((uint64_t)(last + 1), utmp);
-  stay_min = block_min_u64<kWaves>(stay_min, utmp);
+  // The three totals in one barrier.
+  {
+    const int64_t wn = wave_sum_i64(npiv);
+    const uint64_t we = wave_max_u64((uint64_t)(last + 1));
+    const uint64_t wst = wave_min_u64(stay_min);
+    if ((tid & 63) == 0) {
+      s_tot[tid >> 6][0] = (uint64_t)wn;
+      s_tot[tid >> 6][1] = we;
+      s_tot[tid >> 6][2] = wst;
+    }
+  }
+  __syncthreads();
+  uint64_t last_end = 0;
   if (tid == 0) {
+    npiv = 0;
+    stay_min = kNoValue;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      npiv += (int64_t)s_tot[w][0];
+      last_end = s_tot[w][1] > last_end ? s_tot[w][1] : last_end;
+      stay_min = s_tot[w][2] < stay_min ? s_tot[w][2] : stay_min;
+    }
     // Offsets below the ring's capacity (< 2^31).
     *slot = make_uint4((uint32_t)npiv, (uint32_t)nkept,
                        npiv ? (uint32_t)((int64_t)last_end - F) : 0u,
@@ -977,6 +1012,7 @@ hipError_t launch_reduce_advance(const RedArgs& a, int64_t rounds, RedCtl* publi
 }
 
 hipError_t launch_reduce_finish(const RedArgs& a, int64_t rounds, hipStream_t s) {
+  if (!a.count) return hipSuccess;
   RedCtl* ctl = reduce_state(a, rounds);
   hipLaunchKernelGGL(k_walk_stats, dim3(1), dim3(256), 0, s, a.wstat,
                      (int64_t)walk_blocks(a.Wcap), ctl);
