@@ -70,6 +70,7 @@ constexpr uint16_t kFree16 = 0xFFFF;  // a free row in the 16-bit table mirror
 constexpr int kWalkThreads = 1024;
 constexpr int kWalkWaves = kWalkThreads / 64;
 constexpr int kCommitThreads = 256;
+static_assert(kCommitThreads <= kWalkThreads, "a commit pass fits one walk segment");
 constexpr int kHashBits = 11;  // log2 of the LDS hash slots (2 x kWalkThreads)
 
 // Row minima carry the round in their top bits, so that a value left by an
@@ -729,42 +730,61 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(RedArgs A, int64_t k)
   // pivot (0: none) and the first kept column (~0u: none).
   uint4* slot = reinterpret_cast<uint4*>(A.cslot) + blockIdx.x;
   const RedCtl* ctl = A.ctl + (k & 1);  // the state the walk of this round used
-  const int32_t idle = ctl->done | ctl->need_more;
-  const int64_t round = ctl->round, F = ctl->F;
-  const uint32_t cnt = A.scount[blockIdx.x];
-  if (idle) return;
-  if (cnt == 0) {
-    if (tid == 0) *slot = make_uint4(0u, 0u, 0u, ~0u);
-    return;
-  }
   const int64_t my0 = blockIdx.x * A.seg;
   const int64_t* my = A.surv + my0;
   const uint64_t* my_ra = A.surv_ra + my0;
   const uint64_t* my_x = A.surv_x + my0;
-  int64_t* kept_out = A.act[round & 1] + my0;
-  uint64_t* kept_ra = A.act_ra[round & 1] + my0;
-  uint64_t* kept_x = A.act_x[round & 1] + my0;
-  // A survivor's inputs, all loaded at once: its position, rows and state
-  // (from the walk), then its rows' minima.
+  // A survivor's inputs: its position, rows and state (from the walk), then
+  // its rows' minima.  The first pass's list entries (a segment holds at
+  // least kCommitThreads) and the walk slots are requested with the state,
+  // before the survivor count is known.
   struct Item {
     int64_t p;
     uint64_t ra, x, lc, tc;
   };
-  auto load = [&](uint32_t i) -> Item {
-    Item it = {0, 0, 0, kNoValue, kNoValue};
+  Item it;
+  it.p = my[tid];
+  it.ra = my_ra[tid];
+  it.x = my_x[tid];
+  static_assert(kMaxWalkBlocks <= 2 * kCommitThreads, "two walk slots per thread");
+  const uint64_t fd0 = A.fdslot[tid < nb ? tid : 0];
+  const uint64_t fd1 = A.fdslot[tid + kCommitThreads < nb ? tid + kCommitThreads : 0];
+  const int32_t done = ctl->done, need_more = ctl->need_more;
+  const int64_t round = ctl->round, F = ctl->F;
+  const uint32_t cnt = A.scount[blockIdx.x];
+  // All of the above arrive together: a branch on the first would
+  // otherwise hold back the loads of the others.
+  asm volatile("" ::"s"(done), "s"(need_more), "s"(round), "s"(F), "s"(cnt));
+  uint64_t fd = tid < nb ? fd0 : kNoValue;
+  fd = tid + kCommitThreads < nb && fd1 < fd ? fd1 : fd;
+  if (done | need_more) return;
+  if (cnt == 0) {
+    if (tid == 0) *slot = make_uint4(0u, 0u, 0u, ~0u);
+    return;
+  }
+  int64_t* kept_out = A.act[round & 1] + my0;
+  uint64_t* kept_ra = A.act_ra[round & 1] + my0;
+  uint64_t* kept_x = A.act_x[round & 1] + my0;
+  auto minima = [&](uint32_t i, Item& t) {
+    t.lc = kNoValue;
+    t.tc = kNoValue;
     if (i < cnt) {
-      it.p = my[i];
-      it.ra = my_ra[i];
-      it.x = my_x[i];
-      const int32_t r = (int32_t)(it.ra >> 32);
-      it.lc = A.lowc[r];
-      it.tc = A.touch[r];
+      const int32_t r = (int32_t)(t.ra >> 32);
+      t.lc = A.lowc[r];
+      t.tc = A.touch[r];
     }
-    return it;
   };
-  Item it = load(tid);  // in flight while the smallest repeat is found
-  uint64_t fd = kNoValue;
-  for (int b = tid; b < nb; b += kCommitThreads) fd = A.fdslot[b] < fd ? A.fdslot[b] : fd;
+  auto load = [&](uint32_t i) -> Item {
+    Item t = {0, 0, 0, kNoValue, kNoValue};
+    if (i < cnt) {
+      t.p = my[i];
+      t.ra = my_ra[i];
+      t.x = my_x[i];
+    }
+    minima(i, t);
+    return t;
+  };
+  minima(tid, it);  // in flight while the smallest repeat is found
   fd = wave_min_u64(fd);
   if ((tid & 63) == 0) s_fd[tid >> 6] = fd;
   __syncthreads();
