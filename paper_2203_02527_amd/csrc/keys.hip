@@ -112,6 +112,77 @@ __global__ void k_coord_range_wide(const T* __restrict__ x, int64_t n, int32_t d
   }
 }
 
+// Squared norms and per-dimension coordinate ranges of int8 points in one
+// pass, for rows made of 16-byte pieces (d = 16 * 2^k <= kRangeLds, 16-byte
+// aligned).  The pieces of a row sit in adjacent lanes, which sum the row's
+// norm; each thread keeps the running range of its piece's 16 dimensions
+// (two rows per step, their loads issued together), folded into LDS and
+// then one global atomic pair per dimension and workgroup.
+constexpr int kPrepMaxBlocks = 64;
+
+__global__ __launch_bounds__(256) void k_prep_i8(const int8_t* __restrict__ x, int64_t n,
+                                                 int32_t d, int32_t* __restrict__ minmax,
+                                                 int32_t* __restrict__ norms) {
+  __shared__ int32_t lo[kRangeLds], hi[kRangeLds];
+  const int segs = d >> 4, seg = threadIdx.x & (segs - 1);
+  const int rows = 256 / segs;  // rows per workgroup step
+  for (int k = threadIdx.x; k < d; k += blockDim.x) {
+    lo[k] = 0x7FFFFFFF;
+    hi[k] = (int32_t)0x80000000;
+  }
+  __syncthreads();
+  int32_t mn[16], mx[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    mn[i] = 127;
+    mx[i] = -128;
+  }
+  // Every lane runs the same steps (the bound depends on the workgroup
+  // only), so the row sums below see whole rows; rows past n load row n - 1
+  // and are not counted.
+  auto take = [&](const int4 v, bool ok, int64_t row) {
+    const int32_t w[4] = {v.x, v.y, v.z, v.w};
+    int32_t sq = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int32_t e = (int32_t)(int8_t)(w[q] >> (8 * b));
+        sq += e * e;
+        const int i = 4 * q + b;
+        mn[i] = ok && e < mn[i] ? e : mn[i];
+        mx[i] = ok && e > mx[i] ? e : mx[i];
+      }
+    for (int o = 1; o < segs; o <<= 1) sq += __shfl_xor(sq, o, 64);
+    if (ok && seg == 0) norms[row] = sq;
+  };
+  const int64_t step = (int64_t)gridDim.x * rows;
+  for (int64_t r0 = blockIdx.x * (int64_t)rows; r0 < n; r0 += 2 * step) {
+    const int64_t ra = r0 + threadIdx.x / segs, rb = ra + step;
+    const bool oka = ra < n, okb = rb < n;
+    const int4 va = *reinterpret_cast<const int4*>(x + (oka ? ra : n - 1) * d + seg * 16);
+    const int4 vb = *reinterpret_cast<const int4*>(x + (okb ? rb : n - 1) * d + seg * 16);
+    take(va, oka, ra);
+    take(vb, okb, rb);
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    atomicMin(&lo[seg * 16 + i], mn[i]);
+    atomicMax(&hi[seg * 16 + i], mx[i]);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < d; k += blockDim.x) {
+    atomicMin(&minmax[k], lo[k]);
+    atomicMax(&minmax[d + k], hi[k]);
+  }
+}
+
+// lo[0..d) = INT_MAX, hi[0..d) = INT_MIN.
+__global__ void k_range_init(int32_t* __restrict__ minmax, int32_t d) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < 2 * d; k += gridDim.x * blockDim.x)
+    minmax[k] = k < d ? 0x7FFFFFFF : (int32_t)0x80000000;
+}
+
 // ---- vector ALU path ----
 constexpr int kChunk = 32;  // dimensions staged per LDS round
 
@@ -692,12 +763,18 @@ hipError_t launch_gather(const Gather& g, hipStream_t s) {
 }
 
 hipError_t launch_coord_range(const void* pts, int elem_bytes, int64_t n, int32_t d,
-                              int32_t* minmax, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t*>(minmax),
-                     0x7FFFFFFFu, (int64_t)d);
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s,
-                     reinterpret_cast<uint32_t*>(minmax + d), 0x80000000u, (int64_t)d);
-  if (d <= kRangeLds) {
+                              int32_t* minmax, hipStream_t s, int32_t* norms, bool* norms_done) {
+  if (norms_done) *norms_done = false;
+  hipLaunchKernelGGL(k_range_init, dim3(grid_for(2 * (int64_t)d, 256, 64)), dim3(256), 0, s,
+                     minmax, d);
+  const int segs = d / 16;
+  if (norms && norms_done && elem_bytes == 1 && n > 0 && d % 16 == 0 && d <= kRangeLds &&
+      (segs & (segs - 1)) == 0 && reinterpret_cast<uintptr_t>(pts) % 16 == 0) {
+    const int rows = 256 / segs;
+    hipLaunchKernelGGL(k_prep_i8, dim3(grid_for(n, 4 * rows, kPrepMaxBlocks)), dim3(256), 0, s,
+                       static_cast<const int8_t*>(pts), n, d, minmax, norms);
+    *norms_done = true;
+  } else if (d <= kRangeLds) {
     const int g = grid_for(n * d, 256 * 16, 1024);
     if (elem_bytes == 1)
       hipLaunchKernelGGL(k_coord_range<int8_t>, dim3(g), dim3(256), 0, s,

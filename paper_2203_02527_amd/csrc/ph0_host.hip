@@ -442,7 +442,9 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   const uint32_t* h = reinterpret_cast<const uint32_t*>(back + ranges_bytes);
   int32_t* mm = static_cast<int32_t*>(at(L.minmax));
   int32_t* dshift = static_cast<int32_t*>(at(L.hshift));
-  HIPCHK(launch_coord_range(d_points, eb, n, d, mm, s));
+  int32_t* norms = static_cast<int32_t*>(at(L.norms));
+  bool norms_done = false;  // the range pass also formed the squared norms
+  HIPCHK(launch_coord_range(d_points, eb, n, d, mm, s, norms, &norms_done));
   HIPCHK(launch_dist_shift(mm, d, dshift, s));
   const bool mfma = (eb == 1) && d >= 8 && d <= 32768;
   S.keys_path = mfma ? 1 : 0;
@@ -452,7 +454,6 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   uint32_t* counts = static_cast<uint32_t*>(at(L.counts));
   uint32_t* hist = static_cast<uint32_t*>(at(L.hist));
   int32_t* serr = static_cast<int32_t*>(at(L.err));
-  int32_t* norms = static_cast<int32_t*>(at(L.norms));
 
   // Large problems never store all keys: a sampled histogram picks the
   // distance ranges, and each range's keys are recomputed and written, in
@@ -467,6 +468,7 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     KeyPass kp;
     kp.mode = kKeysHist;
     kp.norms = norms;
+    kp.norms_ready = norms_done;
     kp.hist = hist;
     kp.hist_shift_dev = dshift;
     kp.sample = sample;

@@ -82,10 +82,14 @@ struct Gather {
 };
 hipError_t launch_gather(const Gather& g, hipStream_t s);
 
-// Per-dimension coordinate range -> bound on the squared distance.
+// Per-dimension coordinate range -> bound on the squared distance.  When
+// `norms` and `norms_done` are given and the points allow it (int8, rows of
+// 16 * 2^k <= 1024 bytes, 16-byte aligned), the same pass also leaves the
+// squared norms |x_i|^2 in norms[0..n) and sets *norms_done.
 hipError_t launch_coord_range(const void* pts, int elem_bytes, int64_t n, int32_t d,
                               int32_t* minmax /* 2*d: lo[0..d) then hi[0..d) */,
-                              hipStream_t s);
+                              hipStream_t s, int32_t* norms = nullptr,
+                              bool* norms_done = nullptr);
 
 // Step 1: keys of all edges at colex positions, and the histogram of
 // delta >> hist_shift over kHistBins bins (added into `hist`).  `norms`
