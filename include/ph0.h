@@ -295,11 +295,12 @@ int ph0_h1_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, ph0_
                   void* hip_stream, ph0_h1_stats* st);
 
 /* Base reduction window (columns reduced side by side per round, rounded up
- * to a power of two); 0 restores the built-in choice, max(65536, 16 n) capped
- * at E.  A round widens the window up to 16 times the base while almost every
- * column of the previous round became final, and narrows it back when many
- * stay.  Affects speed and workspace size only, never results.
- * Process-wide. */
+ * to a power of two); 0 restores the built-in choice, max(65536, 4 n) capped
+ * at E.  Values above 2^26 columns are taken as 2^26 (window positions are
+ * kept as 32-bit offsets).  A round widens the window up to 16 times the base
+ * while almost every column of the previous round became final, and narrows
+ * it back when many stay.  Affects speed and workspace size only, never
+ * results.  Process-wide. */
 int ph0_set_window(int64_t columns);
 
 
