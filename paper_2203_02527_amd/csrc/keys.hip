@@ -177,10 +177,17 @@ __global__ __launch_bounds__(256) void k_prep_i8(const int8_t* __restrict__ x, i
   }
 }
 
-// lo[0..d) = INT_MAX, hi[0..d) = INT_MIN.
-__global__ void k_range_init(int32_t* __restrict__ minmax, int32_t d) {
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < 2 * d; k += gridDim.x * blockDim.x)
-    minmax[k] = k < d ? 0x7FFFFFFF : (int32_t)0x80000000;
+// lo[0..d) = INT_MAX, hi[0..d) = INT_MIN, and zero[0..zero_len) = 0.
+__global__ void k_range_init(int32_t* __restrict__ minmax, int32_t d, uint32_t* __restrict__ zero,
+                             int64_t zero_len) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < 2 * (int64_t)d + zero_len;
+       k += stride) {
+    if (k < 2 * (int64_t)d)
+      minmax[k] = k < d ? 0x7FFFFFFF : (int32_t)0x80000000;
+    else
+      zero[k - 2 * (int64_t)d] = 0u;
+  }
 }
 
 // ---- vector ALU path ----
@@ -763,10 +770,12 @@ hipError_t launch_gather(const Gather& g, hipStream_t s) {
 }
 
 hipError_t launch_coord_range(const void* pts, int elem_bytes, int64_t n, int32_t d,
-                              int32_t* minmax, hipStream_t s, int32_t* norms, bool* norms_done) {
+                              int32_t* minmax, hipStream_t s, int32_t* norms, bool* norms_done,
+                              uint32_t* zero, int64_t zero_len) {
   if (norms_done) *norms_done = false;
-  hipLaunchKernelGGL(k_range_init, dim3(grid_for(2 * (int64_t)d, 256, 64)), dim3(256), 0, s,
-                     minmax, d);
+  if (!zero) zero_len = 0;
+  hipLaunchKernelGGL(k_range_init, dim3(grid_for(2 * (int64_t)d + zero_len, 256, 64)), dim3(256),
+                     0, s, minmax, d, zero, zero_len);
   const int segs = d / 16;
   if (norms && norms_done && elem_bytes == 1 && n > 0 && d % 16 == 0 && d <= kRangeLds &&
       (segs & (segs - 1)) == 0 && reinterpret_cast<uintptr_t>(pts) % 16 == 0) {

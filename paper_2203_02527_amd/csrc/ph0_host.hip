@@ -443,8 +443,13 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   int32_t* mm = static_cast<int32_t*>(at(L.minmax));
   int32_t* dshift = static_cast<int32_t*>(at(L.hshift));
   int32_t* norms = static_cast<int32_t*>(at(L.norms));
+  uint32_t* hist = static_cast<uint32_t*>(at(L.hist));
+  int32_t* serr = static_cast<int32_t*>(at(L.err));
   bool norms_done = false;  // the range pass also formed the squared norms
-  HIPCHK(launch_coord_range(d_points, eb, n, d, mm, s, norms, &norms_done));
+  // The launch that initialises the ranges also clears the histogram and
+  // the error word that follows it.
+  HIPCHK(launch_coord_range(d_points, eb, n, d, mm, s, norms, &norms_done, hist,
+                            kHistBins + 1));
   HIPCHK(launch_dist_shift(mm, d, dshift, s));
   const bool mfma = (eb == 1) && d >= 8 && d <= 32768;
   S.keys_path = mfma ? 1 : 0;
@@ -452,8 +457,6 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   uint64_t* keysA = static_cast<uint64_t*>(at(L.keysA));
   uint64_t* keysB = static_cast<uint64_t*>(at(L.keysB));
   uint32_t* counts = static_cast<uint32_t*>(at(L.counts));
-  uint32_t* hist = static_cast<uint32_t*>(at(L.hist));
-  int32_t* serr = static_cast<int32_t*>(at(L.err));
 
   // Large problems never store all keys: a sampled histogram picks the
   // distance ranges, and each range's keys are recomputed and written, in
@@ -462,7 +465,6 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
   const int64_t nbk = (n + 63) / 64;
   const int64_t sample = std::max<int64_t>(1, nbk * (nbk + 1) / 2 / 2048);
   bool keys_full = false;  // keysA holds every key at its colex position
-  HIPCHK(launch_fill_u32(hist, 0u, kHistBins + 1, s));  // the histogram and serr
   tm.mark();  // 1
   if (recompute) {
     KeyPass kp;

@@ -85,11 +85,13 @@ hipError_t launch_gather(const Gather& g, hipStream_t s);
 // Per-dimension coordinate range -> bound on the squared distance.  When
 // `norms` and `norms_done` are given and the points allow it (int8, rows of
 // 16 * 2^k <= 1024 bytes, 16-byte aligned), the same pass also leaves the
-// squared norms |x_i|^2 in norms[0..n) and sets *norms_done.
+// squared norms |x_i|^2 in norms[0..n) and sets *norms_done.  The launch
+// that initialises the ranges also clears zero[0..zero_len) when given.
 hipError_t launch_coord_range(const void* pts, int elem_bytes, int64_t n, int32_t d,
                               int32_t* minmax /* 2*d: lo[0..d) then hi[0..d) */,
                               hipStream_t s, int32_t* norms = nullptr,
-                              bool* norms_done = nullptr);
+                              bool* norms_done = nullptr, uint32_t* zero = nullptr,
+                              int64_t zero_len = 0);
 
 // Step 1: keys of all edges at colex positions, and the histogram of
 // delta >> hist_shift over kHistBins bins (added into `hist`).  `norms`
@@ -140,6 +142,11 @@ int64_t key_count_len(int64_t n, bool mfma);
 // scan_totals_len(len) words of scratch.
 int64_t scan_totals_len(int64_t len);
 hipError_t launch_scan_u32(uint32_t* v, int64_t len, uint32_t* totals, hipStream_t s);
+// Exclusive scans, in place, of `cols` arrays of `len` counts laid end to end
+// (v + c * len), one workgroup each, in one launch; totals[c] receives each
+// array's total.  For short arrays (a few tens of thousands of counts).
+hipError_t launch_scan_columns(uint32_t* v, int64_t len, int cols, uint32_t* totals,
+                               hipStream_t s);
 
 // Step 2: one stable LSD pass in -> out by digit (key >> shift) & ((1<<bits)-1).
 // `counts` holds radix_count_entries(count) words of scratch.

@@ -121,6 +121,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_count(const uint64_t* __rest
 
 // One 1024-thread workgroup per digit: exclusive scan, in place, of that
 // digit's tile counts (tile order); the digit's total goes to totals[digit].
+// (Also any set of short count arrays laid end to end.)
 constexpr int kDigitScanThreads = 1024;
 __global__ __launch_bounds__(kDigitScanThreads) void k_radix_digit_scan(
     uint32_t* __restrict__ counts, int64_t ntiles, uint32_t* __restrict__ totals) {
@@ -306,6 +307,14 @@ hipError_t launch_radix_pass(const uint64_t* in, uint64_t* out, int64_t count, i
   hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)tiles), dim3(kThreads), 0, s, in, out,
                      count, shift, bits, tiles, (const uint32_t*)counts,
                      (const uint32_t*)totals, err, f, out_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_columns(uint32_t* v, int64_t len, int cols, uint32_t* totals,
+                               hipStream_t s) {
+  if (len <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_radix_digit_scan, dim3((unsigned)cols), dim3(kDigitScanThreads), 0, s, v,
+                     len, totals);
   return hipGetLastError();
 }
 

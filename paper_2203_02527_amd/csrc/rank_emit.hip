@@ -16,6 +16,7 @@ namespace ph0 {
 namespace {
 
 constexpr int kGroup = 256;  // positions per group (one workgroup pass)
+constexpr int64_t kShortScan = 65536;  // group counts scanned by one workgroup per array
 
 // Marks the pivot columns: bit p of the bitmap, and the pivot row of p.
 __global__ void k_pivot_marks(const int64_t* __restrict__ killer, int64_t n,
@@ -184,8 +185,14 @@ hipError_t launch_grades_and_bars(const uint64_t* skeys, int64_t E_eff, int shif
   const int g = grid_for(E_eff, kGroup, 4096);
   hipLaunchKernelGGL(k_grade_count, dim3(g), dim3(kGroup), 0, s, skeys, E_eff, shift, bitmap, cc,
                      cp);
-  if ((e = launch_scan_u32(cc, ng + 1, tot_c, s)) != hipSuccess) return e;
-  if ((e = launch_scan_u32(cp, ng + 1, tot_p, s)) != hipSuccess) return e;
+  // The two count arrays are adjacent (cp = cc + ng + 1): short ones are
+  // scanned together, one workgroup each; long ones block-wise.
+  if (ng + 1 <= kShortScan) {
+    if ((e = launch_scan_columns(cc, ng + 1, 2, tot_c, s)) != hipSuccess) return e;
+  } else {
+    if ((e = launch_scan_u32(cc, ng + 1, tot_c, s)) != hipSuccess) return e;
+    if ((e = launch_scan_u32(cp, ng + 1, tot_p, s)) != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_grade_emit, dim3(g), dim3(kGroup), 0, s, skeys, E_eff, shift, bitmap,
                      prow, cc, cp, dbv, bars, n);
   *distinct = cc + ng;
