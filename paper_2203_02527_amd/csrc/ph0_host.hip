@@ -268,7 +268,8 @@ struct KernelClock {
 // reduction loop inspects one burst's copy while the next burst runs.
 struct CtlReadback {
   RedCtl* hc = nullptr;      // [2]
-  uint32_t* words = nullptr;  // [3]: radix error flag, distinct grades, pivot columns
+  uint32_t* words = nullptr;  // [4]: radix error flag, distinct grades, pivot columns,
+                              // keys in a distance range
   void* buf = nullptr;        // coordinate ranges and histogram, grown on demand
   size_t buf_bytes = 0;
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -578,10 +579,13 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     if (e == hipSuccess) e = launch_fill_u32(kcnt + kcnt_len, 0u, 1, s);
     if (e == hipSuccess)
       e = launch_scan_u32(kcnt, kcnt_len + 1, static_cast<uint32_t*>(at(L.kcnt_tot)), s);
-    uint32_t total = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&total, kcnt + kcnt_len, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) {  // the total, into pinned memory
+      Gather g;
+      g.add(kcnt + kcnt_len, &rb->words[3], 4);
+      e = launch_gather(g, s);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    *cnt = total;
+    *cnt = e == hipSuccess ? (int64_t)rb->words[3] : 0;
     return e;
   };
   auto next_chunk = [&]() -> hipError_t {
