@@ -589,7 +589,10 @@ int run(const void* d_points, ph0_dtype dt, int64_t n, int32_t d, const Outputs&
     return e;
   };
   auto next_chunk = [&]() -> hipError_t {
-    const int64_t target = std::max<int64_t>(L.E / 16, 8 * n) << std::min(chunks, 20);
+    // The second range is as large as the first (a last pivot just past the
+    // first range is the common case), later ones double.
+    const int64_t target = std::max<int64_t>(L.E / 16, 8 * n)
+                           << std::min(std::max(chunks - 1, 0), 20);
     int b = bin_next;
     int64_t cnt = 0;
     while (b < kHistBins && (cnt == 0 || cnt < target))
