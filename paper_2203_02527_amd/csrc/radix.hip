@@ -218,6 +218,35 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(uint32_t* __restrict__ 
   }
 }
 
+// k_scan_apply for a scan of at most kScanDirectBlocks blocks: each block
+// sums the raw totals of the blocks before it itself (no separate scan of
+// the totals).
+constexpr int64_t kScanDirectBlocks = 1024;
+__global__ __launch_bounds__(kThreads) void k_scan_apply_direct(uint32_t* __restrict__ v,
+                                                                int64_t len,
+                                                                const uint32_t* __restrict__ sums) {
+  __shared__ uint32_t tmp[4];
+  uint32_t before = 0;
+  for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kThreads) before += sums[b];
+  uint32_t all = 0;
+  (void)block_exclusive_scan(before, tmp, &all);
+  constexpr int kPer = kScanBlock / kThreads;
+  const int64_t p0 = blockIdx.x * (int64_t)kScanBlock + threadIdx.x * kPer;
+  uint32_t x[kPer];
+  uint32_t s = 0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    x[q] = p0 + q < len ? v[p0 + q] : 0;
+    s += x[q];
+  }
+  uint32_t run = all + block_exclusive_scan(s, tmp);
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    if (p0 + q < len) v[p0 + q] = run;
+    run += x[q];
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint64_t* __restrict__ in,
                                                             uint64_t* __restrict__ out,
                                                             int64_t count, int shift, int bits,
@@ -329,6 +358,11 @@ hipError_t launch_scan_u32(uint32_t* v, int64_t len, uint32_t* totals, hipStream
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)nblocks), dim3(kThreads), 0, s, v, len, totals);
+  if (nblocks <= kScanDirectBlocks) {  // two launches: the apply sums the totals before it
+    hipLaunchKernelGGL(k_scan_apply_direct, dim3((unsigned)nblocks), dim3(kThreads), 0, s, v, len,
+                       (const uint32_t*)totals);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kThreads), 0, s, totals, nblocks);
   hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblocks), dim3(kThreads), 0, s, v, len, totals);
   return hipGetLastError();
