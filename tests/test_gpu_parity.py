@@ -241,6 +241,16 @@ def test_recomputed_ranges_outlier_forces_whole_sort(torch):
     assert st["keys_path"] == 0 and st["E_eff"] > st["E"] // 2
 
 
+def test_recomputed_ranges_long_grade_scan(torch):
+    # The last pivot past 2^24 sorted edges: the grade pass holds more
+    # per-256-position group counts (about 68,000) than one workgroup scans,
+    # so they go through the block-wise scan.
+    x = _cloud(44, 5900, 3, -100, 100, np.int16)
+    x[4321] = (16000, 16000, 16000)
+    st = _check_full(torch, x)
+    assert st["E_eff"] > 256 * 65536
+
+
 def test_recomputed_ranges_massive_ties(torch):
     st = _check_full(torch, _cloud(42, 3100, 2, 0, 6, np.int8))
     assert st["E"] >= 1 << 22
