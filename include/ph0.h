@@ -112,6 +112,26 @@ int ph0_barcodes_device(const void* d_points, ph0_dtype dt, int64_t n, int32_t d
                         ph0_bar* d_out, void* d_workspace, size_t ws_bytes,
                         void* hip_stream, ph0_stats* st);
 
+/* Real-valued points (the paper's workload, Section 4.1: points drawn
+ * uniformly from the unit square).  The barcode is defined on exact integer
+ * distances, so the coordinates are first put on the int16 grid
+ * q = rint((x - lo) * 32767 / (hi - lo)), computed in double precision (one
+ * subtraction, one multiplication by the host-computed factor
+ * 32767 / (hi - lo), rounding half to even), and the grid cloud's barcode is
+ * returned: the same as ph0_barcodes_device on those int16 points (its
+ * grades are indices of the grid's distinct squared distances).  The order
+ * of two real distances is kept except where they differ by less than the
+ * grid's resolution.  d_points: n*d row-major floats in device memory;
+ * every coordinate must lie in [lo, hi] (finite lo < hi), else EINVAL (the
+ * call checks on the device and waits for that check).  d_workspace: at
+ * least ph0_workspace_bytes_f32() bytes, not allocated by the call.  `st`
+ * as in ph0_barcodes_device; EINVAL / ERANGE as ph0_barcodes_device on the
+ * grid cloud. */
+int ph0_workspace_bytes_f32(int64_t n, int32_t d, size_t* bytes);
+int ph0_barcodes_f32_device(const float* d_points, int64_t n, int32_t d, double lo, double hi,
+                            ph0_bar* d_out, void* d_workspace, size_t ws_bytes,
+                            void* hip_stream, ph0_stats* st);
+
 /* Per-vertex detail of the same computation (device pointers, any may be NULL):
  *   d_death_by_vertex[n] grade at which vertex r dies, PH0_INF for vertex 0
  *   d_killer_pos[n]      sorted position of the edge whose column became the

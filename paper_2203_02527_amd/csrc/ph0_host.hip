@@ -8,6 +8,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <cmath>
+
 #include <cstring>
 
 #include <algorithm>
@@ -1033,6 +1035,50 @@ int ph0_key_layout(int64_t n, int32_t d, ph0_dtype dt, int32_t* ibits, int32_t* 
   if (2 * ib + db > 64)
     return fail(PH0_ERANGE, "full-range coordinates need %d + 2 x %d > 64 key bits", db, ib);
   return PH0_OK;
+}
+
+int ph0_workspace_bytes_f32(int64_t n, int32_t d, size_t* bytes) {
+  size_t b = 0;
+  const int rc = ph0_workspace_bytes(n, d, PH0_I16, &b);
+  if (rc) return rc;
+  if (!bytes) return fail(PH0_EINVAL, "bytes pointer is NULL");
+  // The points on the int16 grid, the off-grid flag, then the int16 call's workspace.
+  *bytes = align_up(2 * (size_t)n * (size_t)d) + align_up(4) + b;
+  return PH0_OK;
+}
+
+int ph0_barcodes_f32_device(const float* d_points, int64_t n, int32_t d, double lo, double hi,
+                            ph0_bar* d_out, void* d_ws, size_t ws_bytes, void* hip_stream,
+                            ph0_stats* st) {
+  if (!d_points) return fail(PH0_EINVAL, "points pointer is NULL");
+  if (!d_out) return fail(PH0_EINVAL, "output pointer is NULL");
+  if (!d_ws) return fail(PH0_EINVAL, "workspace pointer is NULL");
+  if (!(std::isfinite(lo) && std::isfinite(hi) && lo < hi))
+    return fail(PH0_EINVAL, "the coordinate interval needs finite lo < hi");
+  size_t need = 0;
+  int rc = ph0_workspace_bytes_f32(n, d, &need);
+  if (rc) return rc;
+  if (ws_bytes < need)
+    return fail(PH0_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  char* ws = static_cast<char*>(d_ws);
+  int16_t* q = reinterpret_cast<int16_t*>(ws);
+  const size_t qb = align_up(2 * (size_t)n * (size_t)d);
+  int32_t* qerr = reinterpret_cast<int32_t*>(ws + qb);
+  char* rest = ws + qb + align_up(4);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  CtlReadback* rb = pinned_ctl();
+  if (!rb) return fail(PH0_ENOMEM, "pinned host allocation failed");
+  HIPCHK(launch_quantize_f32(d_points, n * (int64_t)d, lo, 32767.0 / (hi - lo), q, qerr, s));
+  {
+    Gather g;
+    g.add(qerr, &rb->words[3], 4);
+    HIPCHK(launch_gather(g, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  if (rb->words[3]) return fail(PH0_EINVAL, "a coordinate is outside [lo, hi] or not finite");
+  Outputs o;
+  o.bars = d_out;
+  return run(q, PH0_I16, n, d, o, rest, ws_bytes - (size_t)(rest - ws), s, st, kStopAll);
 }
 
 int ph0_set_window(int64_t columns) {

@@ -82,6 +82,13 @@ struct Gather {
 };
 hipError_t launch_gather(const Gather& g, hipStream_t s);
 
+// Real coordinates onto the int16 grid 0..32767: q[k] = rint((x[k] - lo) *
+// scale) in fp64; *err (cleared first) becomes nonzero when a value falls off
+// the grid (a coordinate outside [lo, hi] for scale = 32767 / (hi - lo), or
+// not finite).
+hipError_t launch_quantize_f32(const float* x, int64_t count, double lo, double scale, int16_t* q,
+                               int32_t* err, hipStream_t s);
+
 // Per-dimension coordinate range -> bound on the squared distance.  When
 // `norms` and `norms_done` are given and the points allow it (int8, rows of
 // 16 * 2^k <= 1024 bytes, 16-byte aligned), the same pass also leaves the

@@ -98,6 +98,9 @@ _SIGS = {
     "ph0_workspace_bytes": ([_I64, _I32, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "ph0_key_layout": ([_I64, _I32, ctypes.c_int, ctypes.POINTER(_I32), ctypes.POINTER(_I32)], ctypes.c_int),
     "ph0_set_window": ([_I64], ctypes.c_int),
+    "ph0_workspace_bytes_f32": ([_I64, _I32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "ph0_barcodes_f32_device": ([_P, _I64, _I32, ctypes.c_double, ctypes.c_double, _P, _P,
+                                 ctypes.c_size_t, _P, ctypes.POINTER(ph0_stats)], ctypes.c_int),
     "ph0_barcodes": ([_P, ctypes.c_int, _I64, _I32, _P, ctypes.POINTER(ph0_stats)], ctypes.c_int),
     "ph0_barcodes_device": ([_P, ctypes.c_int, _I64, _I32, _P, _P, ctypes.c_size_t, _P,
                              ctypes.POINTER(ph0_stats)], ctypes.c_int),
@@ -244,6 +247,33 @@ def ph0_barcodes_device(points, out=None, workspace=None, stream=None, with_stat
     _check(lib().ph0_barcodes_device(_ptr(x), _dtype_code(x.dtype), n, d, _ptr(out),
                                      _ptr(workspace), workspace.numel(), _stream_ptr(stream),
                                      ctypes.byref(st) if with_stats else None))
+    return (out, st.to_dict()) if with_stats else out
+
+
+def ph0_workspace_bytes_f32(n: int, d: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().ph0_workspace_bytes_f32(n, d, ctypes.byref(b)))
+    return b.value
+
+
+def ph0_barcodes_f32_device(points, lo: float, hi: float, out=None, workspace=None, stream=None,
+                            with_stats=False):
+    """Real-valued points (float32 device tensor, N x d, every coordinate in
+    [lo, hi]): the barcode of their int16 grid cloud (see include/ph0.h).
+    Returns the N x 2 int32 bars as ph0_barcodes_device does."""
+    torch = _torch()
+    x = _points_dev(points)
+    if x.dtype != torch.float32:
+        raise TypeError("points must be float32, got %s" % x.dtype)
+    n, d = x.shape
+    if out is None:
+        out = torch.empty((n, 2), dtype=torch.int32, device=x.device)
+    if workspace is None:
+        workspace = torch.empty(ph0_workspace_bytes_f32(n, d), dtype=torch.uint8, device=x.device)
+    st = ph0_stats()
+    _check(lib().ph0_barcodes_f32_device(_ptr(x), n, d, float(lo), float(hi), _ptr(out),
+                                         _ptr(workspace), workspace.numel(), _stream_ptr(stream),
+                                         ctypes.byref(st) if with_stats else None))
     return (out, st.to_dict()) if with_stats else out
 
 

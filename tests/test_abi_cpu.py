@@ -1,5 +1,6 @@
 """The C-ABI library loads, exports every declared symbol, and its argument
 checks (which run before any device call) behave as documented.  CPU only."""
+import ctypes
 import os
 import re
 
@@ -37,6 +38,27 @@ def test_workspace_bytes_and_arguments():
         assert ei.value.code == -1
     with pytest.raises(TypeError):
         ph0.ph0_workspace_bytes(5, 3, np.int32)
+
+
+def test_f32_workspace_bytes_and_arguments():
+    # The real-valued entry holds the int16 grid copy and a flag beside the
+    # int16 workspace; its argument checks run before any device work.
+    base = ph0.ph0_workspace_bytes(3000, 2, np.int16)
+    ws = ph0.ph0_workspace_bytes_f32(3000, 2)
+    assert base + 2 * 3000 * 2 <= ws <= base + 2 * 3000 * 2 + 1024
+    for n, d in [(0, 2), (70000, 2), (5, 0)]:
+        with pytest.raises(ph0.Ph0Error) as ei:
+            ph0.ph0_workspace_bytes_f32(n, d)
+        assert ei.value.code == -1
+    lib = ph0.lib()
+    dummy = ctypes.c_void_p(16)  # never dereferenced: the checks fail first
+    for lo, hi in [(1.0, 1.0), (2.0, 1.0), (float("nan"), 1.0), (0.0, float("inf"))]:
+        rc = lib.ph0_barcodes_f32_device(dummy, 10, 2, lo, hi, dummy, dummy, 1 << 30, None, None)
+        assert rc == -1 and b"finite lo < hi" in ph0.ph0_last_error().encode()
+    rc = lib.ph0_barcodes_f32_device(dummy, 10, 2, 0.0, 1.0, dummy, dummy, 16, None, None)
+    assert rc == -1 and b"workspace too small" in ph0.ph0_last_error().encode()
+    rc = lib.ph0_barcodes_f32_device(None, 10, 2, 0.0, 1.0, dummy, dummy, 1 << 30, None, None)
+    assert rc == -1
 
 
 def test_key_layout_bit_budget():

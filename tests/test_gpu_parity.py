@@ -251,6 +251,38 @@ def test_recomputed_ranges_long_grade_scan(torch):
     assert st["E_eff"] > 256 * 65536
 
 
+def _grid(u, lo, hi):
+    # The int16 grid of the real-valued entry, in the same fp64 operations.
+    return np.rint((u.astype(np.float64) - lo) * (32767.0 / (hi - lo))).astype(np.int16)
+
+
+@pytest.mark.parametrize("n", [50, 700, 3000])
+def test_real_valued_points_on_the_grid(torch, n):
+    # The paper's workload (uniform points in the unit square) through the
+    # real-valued entry: the barcode of the grid cloud, against the oracle.
+    u = np.random.default_rng(100 + n).random((n, 2)).astype(np.float32)
+    ref = oracle.barcode(_grid(u, 0.0, 1.0)).canonical
+    bars = ph0.ph0_barcodes_f32_device(_dev(torch, u), 0.0, 1.0)
+    np.testing.assert_array_equal(bars.cpu().numpy().view(np.uint32)[:, 1], ref)
+    bars2, st = ph0.ph0_barcodes_f32_device(_dev(torch, u), 0.0, 1.0, with_stats=True)
+    np.testing.assert_array_equal(bars2.cpu().numpy(), bars.cpu().numpy())
+    assert st["n"] == n
+
+
+def test_real_valued_points_other_interval_and_bad_values(torch):
+    rng = np.random.default_rng(7)
+    v = (rng.random((400, 3)) * 5.0 - 2.0).astype(np.float32)  # in [-2, 3)
+    ref = oracle.barcode(_grid(v, -2.0, 3.0)).canonical
+    bars = ph0.ph0_barcodes_f32_device(_dev(torch, v), -2.0, 3.0)
+    np.testing.assert_array_equal(bars.cpu().numpy().view(np.uint32)[:, 1], ref)
+    for bad in (3.5, -2.25, np.nan, np.inf):
+        w = v.copy()
+        w[17, 1] = bad
+        with pytest.raises(ph0.Ph0Error) as ei:
+            ph0.ph0_barcodes_f32_device(_dev(torch, w), -2.0, 3.0)
+        assert ei.value.code == -1 and "outside" in str(ei.value)
+
+
 def test_recomputed_ranges_massive_ties(torch):
     st = _check_full(torch, _cloud(42, 3100, 2, 0, 6, np.int8))
     assert st["E"] >= 1 << 22
