@@ -756,37 +756,6 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t v, int64_t count, hipStream_t s
   return hipGetLastError();
 }
 
-namespace {
-
-// Real coordinates onto the int16 grid: q = rint((x - lo) * scale) in fp64
-// (one subtraction, one multiplication, round half to even); a value off
-// [0, 32767] (a coordinate outside [lo, hi], or not finite) sets *err and
-// stores 0.
-__global__ void k_quantize_f32(const float* __restrict__ x, int64_t count, double lo,
-                               double scale, int16_t* __restrict__ q, int32_t* err) {
-  bool bad = false;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    const double r = rint(((double)x[k] - lo) * scale);
-    const bool ok = r >= 0.0 && r <= 32767.0;  // false for NaN
-    q[k] = ok ? (int16_t)r : (int16_t)0;
-    bad |= !ok;
-  }
-  if (bad) atomicOr(err, 1);
-}
-
-}  // namespace
-
-hipError_t launch_quantize_f32(const float* x, int64_t count, double lo, double scale, int16_t* q,
-                               int32_t* err, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t*>(err), 0u,
-                     (int64_t)1);
-  if (count > 0)
-    hipLaunchKernelGGL(k_quantize_f32, dim3(grid_for(count, 256 * 8, 2048)), dim3(256), 0, s, x,
-                       count, lo, scale, q, err);
-  return hipGetLastError();
-}
-
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count, 256, 4096)), dim3(256), 0, s, p, v, count);
