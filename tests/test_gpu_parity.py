@@ -269,6 +269,23 @@ def test_real_valued_points_on_the_grid(torch, n):
     assert st["n"] == n
 
 
+def test_real_valued_points_degenerate_clouds(torch):
+    # One point, two points, identical points, both interval ends, and
+    # points near half-way between grid values (the same fp64 rounding on
+    # both sides).
+    clouds = [
+        np.array([[0.25, 0.75]], np.float32),
+        np.array([[0.0, 0.0], [1.0, 1.0]], np.float32),
+        np.full((40, 2), 0.5, np.float32),
+        np.array([[0.5 / 32767, 0.0], [1.5 / 32767, 0.0], [2.5 / 32767, 1.0], [0.0, 1.0]],
+                 np.float32),
+    ]
+    for u in clouds:
+        ref = oracle.barcode(_grid(u, 0.0, 1.0)).canonical
+        bars = ph0.ph0_barcodes_f32_device(_dev(torch, u), 0.0, 1.0)
+        np.testing.assert_array_equal(bars.cpu().numpy().view(np.uint32)[:, 1], ref)
+
+
 def test_real_valued_points_other_interval_and_bad_values(torch):
     rng = np.random.default_rng(7)
     v = (rng.random((400, 3)) * 5.0 - 2.0).astype(np.float32)  # in [-2, 3)
